@@ -1,0 +1,317 @@
+"""Test infrastructure, not product code.
+
+ctypes front end of the plain FP64 CPU oracle (``nmc_oracle.c``) of the
+implicit neutrino-matter coupling solve (paper Sec. 3.5).  Only ``tests/``,
+``__graft_entry__.smoke()`` and the CPU-baseline leg of ``bench.py`` may import
+this package.  It shares no code with the HIP library.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from dataclasses import dataclass, field
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liboracle_nmc.so")
+SRC = os.path.join(HERE, "nmc_oracle.c")
+
+MAX_NQ = 64
+MAX_NS = 3
+NU_E, NU_E_BAR, NU_X = 0, 1, 2
+EMAB, ISO, NES, PAIR = 1, 2, 4, 8
+ALL_PHYSICS = EMAB | ISO | NES | PAIR
+OK, MAX_OUTER, MAX_INNER, NONFINITE, EOS_DOMAIN = 0, 1, 2, 3, 4
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (-O2 -ffp-contract=off, OpenMP over points)."""
+    if force or not os.path.exists(LIB_PATH):
+        tmp = LIB_PATH + ".tmp"
+        cmd = ["gcc", "-O2", "-ffp-contract=off", "-fopenmp", "-std=c99", "-Wall",
+               "-shared", "-fPIC", SRC, "-o", tmp, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, LIB_PATH)
+    return LIB_PATH
+
+
+class _Model(C.Structure):
+    _fields_ = [
+        ("nq", C.c_int), ("ns", C.c_int), ("species", C.c_int * MAX_NS),
+        ("eps", C.c_double * MAX_NQ), ("w2", C.c_double * MAX_NQ), ("w3", C.c_double * MAX_NQ),
+        ("flags", C.c_uint),
+        ("chi_ref", C.c_double), ("eps_ref", C.c_double), ("chi_power", C.c_double),
+        ("sigma_ratio", C.c_double),
+        ("eos_a", C.c_double), ("eos_b", C.c_double), ("mu_a", C.c_double), ("mu_ye0", C.c_double),
+        ("mu_b", C.c_double), ("mu_t0", C.c_double),
+        ("kcoup", C.c_double), ("rho11_min", C.c_double),
+    ]
+
+
+class _Params(C.Structure):
+    _fields_ = [
+        ("tol_inner", C.c_double), ("tol_outer", C.c_double),
+        ("m_inner", C.c_int), ("m_outer", C.c_int), ("max_inner", C.c_int), ("max_outer", C.c_int),
+        ("fixed_matter", C.c_int),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            build()
+        L = C.CDLL(LIB_PATH)
+        dp = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
+        ip = np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS")
+        vp = C.c_void_p
+        L.ora_grid_loguniform.argtypes = [C.c_int, C.c_double, C.c_double, dp, dp, dp]
+        L.ora_grid_zoom.argtypes = [C.c_int, C.c_double, C.c_double, dp, dp, dp, dp]
+        L.ora_model_defaults.argtypes = [C.POINTER(_Model)]
+        for f in ("ora_fermi_dirac", "ora_fermi_dirac_complement"):
+            getattr(L, f).argtypes = [C.c_double] * 3
+            getattr(L, f).restype = C.c_double
+        for f in ("ora_eos_energy", "ora_eos_temperature", "ora_eos_mu"):
+            getattr(L, f).argtypes = [C.POINTER(_Model), C.c_double, C.c_double, C.c_double]
+            getattr(L, f).restype = C.c_double
+        L.ora_kernels.argtypes = [C.POINTER(_Model), dp, C.c_double, C.c_double, dp, dp, dp, dp]
+        L.ora_rates.argtypes = [C.POINTER(_Model), dp, C.c_double, C.c_double, C.c_double, C.c_double,
+                                dp, dp, dp, dp]
+        L.ora_anderson.argtypes = [C.c_int, C.c_int, dp, dp, dp]
+        L.ora_anderson.restype = C.c_int
+        L.ora_solve_batch.argtypes = [C.POINTER(_Model), C.POINTER(_Params), dp, C.c_long, C.c_double,
+                                      dp, dp, dp, dp, dp, vp, vp, vp,
+                                      dp, dp, dp, dp, dp, ip, ip, ip, C.c_int]
+        L.ora_residual.argtypes = [C.POINTER(_Model), dp, C.c_double, C.c_double, C.c_double,
+                                   dp, dp, C.c_double, C.c_double, dp, dp, C.c_double, C.c_double, dp]
+        L.ora_jacobian.argtypes = [C.POINTER(_Model), dp, C.c_double, C.c_double, C.c_double,
+                                   dp, C.c_double, C.c_double, dp]
+        L.ora_newton.argtypes = [C.POINTER(_Model), dp, C.c_double, C.c_double, C.c_double,
+                                 dp, dp, C.c_double, C.c_double, dp, dp,
+                                 C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_double, C.c_int]
+        L.ora_newton.restype = C.c_int
+        L.ora_adjoint_batch.argtypes = [C.POINTER(_Model), dp, C.c_long, C.c_double, dp, vp,
+                                        dp, dp, dp, dp, dp, vp, C.c_int]
+        L.ora_adjoint_batch.restype = C.c_int
+        L.ora_init_state.argtypes = [C.POINTER(_Model), C.c_long, dp, vp, dp, dp, dp, dp,
+                                     C.c_double, C.c_double, C.c_double, dp, dp, vp]
+        _lib = L
+    return _lib
+
+
+def _vp(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+# ---------------------------------------------------------------------------
+# grids
+
+def grid_loguniform(n_elem: int, eps_lo: float = 1.0, eps_hi: float = 300.0):
+    nq = 2 * n_elem
+    eps, w2, w3 = np.zeros(nq), np.zeros(nq), np.zeros(nq)
+    if lib().ora_grid_loguniform(n_elem, eps_lo, eps_hi, eps, w2, w3) != 0:
+        raise ValueError("bad grid")
+    return eps, w2, w3
+
+
+def grid_zoom(n_elem: int, zoom: float, width: float = 300.0):
+    nq = 2 * n_elem
+    edges, eps, w2, w3 = np.zeros(n_elem + 1), np.zeros(nq), np.zeros(nq), np.zeros(nq)
+    if lib().ora_grid_zoom(n_elem, zoom, width, edges, eps, w2, w3) != 0:
+        raise ValueError("bad grid")
+    return edges, eps, w2, w3
+
+
+# ---------------------------------------------------------------------------
+# model
+
+@dataclass
+class Model:
+    n_elem: int = 16
+    eps_lo: float = 1.0
+    eps_hi: float = 300.0
+    species: tuple = (NU_E, NU_E_BAR, NU_X)
+    flags: int = ALL_PHYSICS
+    overrides: dict = field(default_factory=dict)
+
+    def __post_init__(self):
+        m = _Model()
+        lib().ora_model_defaults(C.byref(m))
+        eps, w2, w3 = grid_loguniform(self.n_elem, self.eps_lo, self.eps_hi)
+        self.set_grid(eps, w2, w3, m)
+
+    def set_grid(self, eps, w2, w3, m=None):
+        m = m if m is not None else self.c
+        m.nq = len(eps)
+        m.ns = len(self.species)
+        for i, s in enumerate(self.species):
+            m.species[i] = s
+        for i in range(len(eps)):
+            m.eps[i], m.w2[i], m.w3[i] = eps[i], w2[i], w3[i]
+        m.flags = self.flags
+        for k, v in self.overrides.items():
+            setattr(m, k, v)
+        self.c = m
+
+    @property
+    def nq(self):
+        return self.c.nq
+
+    @property
+    def ns(self):
+        return self.c.ns
+
+    @property
+    def eps(self):
+        return np.array(self.c.eps[: self.nq])
+
+    @property
+    def w2(self):
+        return np.array(self.c.w2[: self.nq])
+
+    @property
+    def w3(self):
+        return np.array(self.c.w3[: self.nq])
+
+    def ref(self):
+        return C.byref(self.c)
+
+    def default_theta(self, a_nes: float, a_pair: float):
+        return np.concatenate([np.ones(self.nq), [a_nes, a_pair]])
+
+    # thermodynamics
+    def fd(self, eps, mu, T):
+        return lib().ora_fermi_dirac(eps, mu, T)
+
+    def fd_complement(self, eps, mu, T):
+        return lib().ora_fermi_dirac_complement(eps, mu, T)
+
+    def eos_energy(self, T, ye, rho11):
+        return lib().ora_eos_energy(self.ref(), T, ye, rho11)
+
+    def eos_temperature(self, e, ye, rho11):
+        return lib().ora_eos_temperature(self.ref(), e, ye, rho11)
+
+    def eos_mu(self, ye, T, rho11):
+        return lib().ora_eos_mu(self.ref(), ye, T, rho11)
+
+    def kernels(self, theta, rho11, T):
+        nq = self.nq
+        out = [np.zeros(nq * nq) for _ in range(4)]
+        lib().ora_kernels(self.ref(), _f64(theta), rho11, T, *out)
+        return [o.reshape(nq, nq) for o in out]  # phi_in, phi_out, phi_pro, phi_ann
+
+    def rates(self, theta, rho11, chi0, T, mu, D):
+        nn = self.ns * self.nq
+        eta, chi, kap = np.zeros(nn), np.zeros(nn), np.zeros(nn)
+        lib().ora_rates(self.ref(), _f64(theta), rho11, chi0, T, mu, _f64(D).ravel(), eta, chi, kap)
+        shp = (self.ns, self.nq)
+        return eta.reshape(shp), chi.reshape(shp), kap.reshape(shp)
+
+    def residual(self, theta, dtau, rho11, chi0, Dstar, Istar, ye_star, e_star, D, I, ye, e):
+        nn = self.ns * self.nq
+        R = np.zeros(2 * nn + 2)
+        lib().ora_residual(self.ref(), _f64(theta), dtau, rho11, chi0, _f64(Dstar).ravel(),
+                           _f64(Istar).ravel(), ye_star, e_star, _f64(D).ravel(), _f64(I).ravel(),
+                           ye, e, R)
+        return R
+
+    def jacobian(self, theta, dtau, rho11, chi0, D, ye, e):
+        n = self.ns * self.nq + 2
+        J = np.zeros(n * n)
+        lib().ora_jacobian(self.ref(), _f64(theta), dtau, rho11, chi0, _f64(D).ravel(), ye, e, J)
+        return J.reshape(n, n)
+
+    def newton(self, theta, dtau, rho11, chi0, Dstar, Istar, ye_star, e_star, D0=None, I0=None,
+               ye0=None, e0=None, tol=1e-14, max_it=100):
+        D = _f64(Dstar if D0 is None else D0).ravel().copy()
+        I = _f64(Istar if I0 is None else I0).ravel().copy()
+        ye = C.c_double(ye_star if ye0 is None else ye0)
+        e = C.c_double(e_star if e0 is None else e0)
+        it = lib().ora_newton(self.ref(), _f64(theta), dtau, rho11, chi0, _f64(Dstar).ravel(),
+                              _f64(Istar).ravel(), ye_star, e_star, D, I, C.byref(ye), C.byref(e),
+                              tol, max_it)
+        shp = (self.ns, self.nq)
+        return D.reshape(shp), I.reshape(shp), ye.value, e.value, it
+
+    def init_state(self, T, rho11, ye, uD, uI, a=1.0, b=0.1, c=0.1, mu=None):
+        T, rho11, ye = _f64(T), _f64(rho11), _f64(ye)
+        P = len(T)
+        nn = self.ns * self.nq
+        D0, I0, e0 = np.zeros(P * nn), np.zeros(P * nn), np.zeros(P)
+        mu_arr = None if mu is None else _f64(mu)
+        lib().ora_init_state(self.ref(), P, T, _vp(mu_arr), rho11, ye, _f64(uD).ravel(), _f64(uI).ravel(),
+                             a, b, c, D0, I0, _vp(e0))
+        shp = (P, self.ns, self.nq)
+        return D0.reshape(shp), I0.reshape(shp), e0
+
+
+@dataclass
+class Params:
+    tol_inner: float = 1e-10
+    tol_outer: float = 1e-10
+    m_inner: int = 3
+    m_outer: int = 3
+    max_inner: int = 100
+    max_outer: int = 50
+    fixed_matter: bool = False
+
+    def c(self):
+        return _Params(self.tol_inner, self.tol_outer, self.m_inner, self.m_outer, self.max_inner,
+                       self.max_outer, int(self.fixed_matter))
+
+
+def anderson(Qh, Fh):
+    """One Anderson step over a history (oldest first); returns (x_new, columns used)."""
+    Qh, Fh = _f64(Qh), _f64(Fh)
+    mem, n = Qh.shape
+    out = np.zeros(n)
+    ncol = lib().ora_anderson(n, mem, Qh.ravel(), Fh.ravel(), out)
+    return out, ncol
+
+
+def solve_batch(model: Model, params: Params, theta, dtau, D0, I0, rho11, ye0, e0, chi0=None,
+                T_fixed=None, mu_fixed=None, nthreads: int = 0):
+    """Batched forward solve (Algorithm neutrinoMatterCoupling), one point per item."""
+    D0 = _f64(D0)
+    P = D0.shape[0]
+    nn = model.ns * model.nq
+    D, I = np.zeros(P * nn), np.zeros(P * nn)
+    ye, e, T = np.zeros(P), np.zeros(P), np.zeros(P)
+    no, ni, st = np.zeros(P, np.int32), np.zeros(P, np.int32), np.zeros(P, np.int32)
+    chi0 = None if chi0 is None else _f64(chi0)
+    T_fixed = None if T_fixed is None else _f64(T_fixed)
+    mu_fixed = None if mu_fixed is None else _f64(mu_fixed)
+    pc = params.c()
+    rc = lib().ora_solve_batch(model.ref(), C.byref(pc), _f64(theta), P, dtau, D0.ravel(),
+                               _f64(I0).ravel(), _f64(rho11), _f64(ye0), _f64(e0), _vp(chi0),
+                               _vp(T_fixed), _vp(mu_fixed), D, I, ye, e, T, no, ni, st, nthreads)
+    if rc != 0:
+        raise ValueError("oracle rejected the arguments")
+    shp = (P, model.ns, model.nq)
+    return dict(D=D.reshape(shp), I=I.reshape(shp), ye=ye, e=e, T=T, n_outer=no, n_inner=ni, status=st)
+
+
+def adjoint_batch(model: Model, theta, dtau, rho11, D, ye, e, gbar, chi0=None, per_point=False,
+                  nthreads: int = 0):
+    P = len(rho11)
+    nt = model.nq + 2
+    g = np.zeros(nt)
+    gpp = np.zeros(P * nt) if per_point else None
+    chi0 = None if chi0 is None else _f64(chi0)
+    rc = lib().ora_adjoint_batch(model.ref(), _f64(theta), P, dtau, _f64(rho11), _vp(chi0),
+                                 _f64(D).ravel(), _f64(ye), _f64(e), _f64(gbar).ravel(), g, _vp(gpp),
+                                 nthreads)
+    if rc != 0:
+        raise RuntimeError("singular Jacobian in the oracle adjoint")
+    return (g, gpp.reshape(P, nt)) if per_point else g
+

@@ -1,0 +1,950 @@
+/*
+ * Test infrastructure, not product code: the plain FP64 CPU oracle of the
+ * implicit neutrino-matter coupling solve.  Only tests, the smoke check and the
+ * CPU-baseline leg of the benchmark load it.  It shares no code, header, table
+ * or helper with the HIP library.
+ *
+ * Built with -O2 -ffp-contract=off so every multiply and add rounds as written.
+ * Loops are plain; nothing is blocked, fused or reordered beyond what the
+ * paper's definitions state.  Citations name sections, equations and
+ * algorithms of the paper (arXiv 2601.00976).
+ *
+ * Parity pins (tests/test_oracle_*.py): grid and weights (Table energyGrids,
+ * Eq. energy_integration_weights), Fermi-Dirac and EOS closed forms, kernel
+ * in-out invariance and detailed balance (Eqs. inOutInvarianceNES ...
+ * detailedBalancePair), number / lepton-number conservation of the collision
+ * contractions, the emission-absorption closed form (Eqs. implicitNumberNodal,
+ * implicitNumberFluxNodal, emissivityEmAbNodal), the equilibrium fixed point,
+ * the large-dtau equilibrium limit, Newton on tiny problems, Anderson finite
+ * termination on linear maps, and finite differences for the Jacobian and the
+ * adjoint.  Exact iteration counts and intermediate iterates are parity
+ * unpinned.
+ */
+#include "nmc_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define MAXN (2 * ORA_MAX_NS * ORA_MAX_NQ)
+#define MAXMEM 8
+
+/* ------------------------------------------------------------------------ */
+/* Energy grid: Sec. 3.1.2 (nodes eps_q = eps_e + dEps_e xi_q on the reference
+ * interval (-1/2, 1/2), Legendre-Gauss points, weights summing to one) and
+ * Eq. energy_integration_weights (W2 = 4 pi w eps^2 dEps / h^3; the constant
+ * 4 pi / h^3 is carried by the coupling constants instead). */
+
+static void lg2(double* xi, double* w) {
+  /* 2-point Legendre-Gauss rule on (-1/2, 1/2): xi = -/+ 1/(2 sqrt 3), w = 1/2 */
+  xi[0] = -0.5 / sqrt(3.0);
+  xi[1] = 0.5 / sqrt(3.0);
+  w[0] = 0.5;
+  w[1] = 0.5;
+}
+
+static void fill_nodes(int n_elem, const double* edges, double* eps, double* w2, double* w3) {
+  double xi[2], w[2];
+  lg2(xi, w);
+  for (int e = 0; e < n_elem; ++e) {
+    double lo = edges[e], hi = edges[e + 1];
+    double c = 0.5 * (lo + hi), d = hi - lo;
+    for (int q = 0; q < 2; ++q) {
+      int g = e * 2 + q; /* global energy index (Sec. 3.1.2) */
+      eps[g] = c + d * xi[q];
+      w2[g] = w[q] * eps[g] * eps[g] * d;
+      w3[g] = w2[g] * eps[g];
+    }
+  }
+}
+
+int ora_grid_loguniform(int n_elem, double eps_lo, double eps_hi, double* eps, double* w2, double* w3) {
+  /* geometric element edges eps_lo * (eps_hi/eps_lo)^(e/n_elem) */
+  if (n_elem < 1 || 2 * n_elem > ORA_MAX_NQ || !(eps_lo > 0) || !(eps_hi > eps_lo)) return -1;
+  double edges[ORA_MAX_NQ + 1];
+  for (int e = 0; e <= n_elem; ++e) edges[e] = eps_lo * pow(eps_hi / eps_lo, (double)e / n_elem);
+  edges[n_elem] = eps_hi;
+  fill_nodes(n_elem, edges, eps, w2, w3);
+  return 0;
+}
+
+int ora_grid_zoom(int n_elem, double zoom, double width, double* edges, double* eps, double* w2, double* w3) {
+  /* Table energyGrids: dEps_{e+1} = zoom * dEps_e on [0, width] */
+  if (n_elem < 1 || 2 * n_elem > ORA_MAX_NQ || !(zoom > 0) || !(width > 0)) return -1;
+  double d1;
+  if (zoom == 1.0) d1 = width / n_elem;
+  else d1 = width * (zoom - 1.0) / (pow(zoom, n_elem) - 1.0);
+  edges[0] = 0.0;
+  double d = d1;
+  for (int e = 0; e < n_elem; ++e) {
+    edges[e + 1] = edges[e] + d;
+    d *= zoom;
+  }
+  fill_nodes(n_elem, edges, eps, w2, w3);
+  return 0;
+}
+
+void ora_model_defaults(ora_model* m) {
+  memset(m, 0, sizeof(*m));
+  m->flags = ORA_EMAB | ORA_ISO | ORA_NES | ORA_PAIR;
+  m->chi_ref = 10.0;   /* km^-1 per rho11 */
+  m->eps_ref = 10.0;   /* MeV */
+  m->chi_power = 2.0;
+  m->sigma_ratio = 0.5;
+  m->eos_a = 1.5;
+  m->eos_b = 3.0;
+  m->mu_a = 20.0;
+  m->mu_ye0 = 0.3;
+  m->mu_b = 5.0;
+  m->mu_t0 = 5.0;
+  {
+    const double hc = 1.239841984e-10;    /* MeV cm */
+    const double m_u = 1.66053906660e-24; /* g */
+    const double pi = 3.14159265358979323846;
+    m->kcoup = 4.0 * pi / (hc * hc * hc) * m_u / 1.0e11;
+  }
+  m->rho11_min = 1.0e-4; /* 1e7 g/cm^3 */
+}
+
+/* ------------------------------------------------------------------------ */
+/* Thermodynamics.  Fermi-Dirac equilibrium: App. B, Eq. FermiDiracDistribution,
+ * evaluated at the node energy (pointwise nodal values). */
+
+double ora_fermi_dirac(double eps, double mu, double T) {
+  double x = (eps - mu) / T;
+  if (x > 0.0) {
+    double t = exp(-x);
+    return t / (1.0 + t);
+  }
+  return 1.0 / (1.0 + exp(x));
+}
+
+double ora_fermi_dirac_complement(double eps, double mu, double T) {
+  double x = (eps - mu) / T;
+  if (x > 0.0) return 1.0 / (1.0 + exp(-x));
+  double t = exp(x);
+  return t / (1.0 + t);
+}
+
+/* synthetic closed-form EOS: e = a T (1 + Ye) + b Ye^(4/3) rho11^(1/3) [MeV/baryon] */
+double ora_eos_energy(const ora_model* m, double T, double ye, double rho11) {
+  return m->eos_a * T * (1.0 + ye) + m->eos_b * pow(ye, 4.0 / 3.0) * cbrt(rho11);
+}
+
+double ora_eos_temperature(const ora_model* m, double e, double ye, double rho11) {
+  return (e - m->eos_b * pow(ye, 4.0 / 3.0) * cbrt(rho11)) / (m->eos_a * (1.0 + ye));
+}
+
+/* mu_nu_e = mu_a (Ye - ye0) rho11^(1/3) + mu_b ln(T / T0) [MeV] */
+double ora_eos_mu(const ora_model* m, double ye, double T, double rho11) {
+  return m->mu_a * (ye - m->mu_ye0) * cbrt(rho11) + m->mu_b * log(T / m->mu_t0);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Species bookkeeping: lepton numbers g = (+1, -1, 0) (Sec. 2.2), energy
+ * multiplicity d = (1, 1, 4) for the heavy-lepton stand-in, chemical-potential
+ * sign (+1, -1, 0), pair partner (nu_e <-> anti-nu_e, nu_x <-> nu_x) and
+ * emission/absorption only for the electron flavours (Table opacities). */
+
+static double sp_g(int id) { return id == ORA_NU_E ? 1.0 : (id == ORA_NU_E_BAR ? -1.0 : 0.0); }
+static double sp_d(int id) { return id == ORA_NU_X ? 4.0 : 1.0; }
+static double sp_musign(int id) { return id == ORA_NU_E ? 1.0 : (id == ORA_NU_E_BAR ? -1.0 : 0.0); }
+static int sp_emab(int id) { return id != ORA_NU_X; }
+static int sp_partner_id(int id) { return id == ORA_NU_E ? ORA_NU_E_BAR : (id == ORA_NU_E_BAR ? ORA_NU_E : ORA_NU_X); }
+
+static int partner_index(const ora_model* m, int s) {
+  int want = sp_partner_id(m->species[s]);
+  for (int t = 0; t < m->ns; ++t)
+    if (m->species[t] == want) return t;
+  return -1;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Energy-coupling kernels (Eqs. nesRatesNodal, pairRatesNodal) built so that
+ * in-out invariance (Eqs. inOutInvarianceNES, inOutInvariancePair) and detailed
+ * balance (Eqs. detailedBalanceNES, detailedBalancePair) hold exactly with the
+ * pointwise Fermi-Dirac equilibrium:
+ *   S(e,e')   = A e e' exp(-|e-e'|/T)
+ *   Phi_in    = S exp(-(e-e')/(2T)),  Phi_out = S exp(+(e-e')/(2T))
+ *   Phi_ann   = A_p e e' exp(-|e-e'|/T),  Phi_pro = Phi_ann exp(-(e+e')/T)
+ * Every exponent is written as exp(-(non-negative)/T). */
+
+static void kernels_unit(const ora_model* m, double T, double a_nes, double a_pair, double* phi_in,
+                         double* phi_out, double* phi_pro, double* phi_ann) {
+  int nq = m->nq;
+  for (int q = 0; q < nq; ++q) {
+    for (int p = 0; p < nq; ++p) {
+      double eq = m->eps[q], ep = m->eps[p];
+      double dlt = eq - ep;
+      double adl = fabs(dlt);
+      double ee = eq * ep;
+      phi_in[q * nq + p] = a_nes * ee * exp(-(adl + 0.5 * dlt) / T);
+      phi_out[q * nq + p] = a_nes * ee * exp(-(adl - 0.5 * dlt) / T);
+      phi_ann[q * nq + p] = a_pair * ee * exp(-adl / T);
+      phi_pro[q * nq + p] = a_pair * ee * exp(-(adl + eq + ep) / T);
+    }
+  }
+}
+
+void ora_kernels(const ora_model* m, const double* theta, double rho11, double T, double* phi_in,
+                 double* phi_out, double* phi_pro, double* phi_ann) {
+  double a_nes = (m->flags & ORA_NES) ? theta[m->nq] * rho11 : 0.0;
+  double a_pair = (m->flags & ORA_PAIR) ? theta[m->nq + 1] * rho11 : 0.0;
+  kernels_unit(m, T, a_nes, a_pair, phi_in, phi_out, phi_pro, phi_ann);
+}
+
+/* per-point opacity state, recomputed once per outer iteration
+ * (ComputeOpacities in Algorithm neutrinoMatterCoupling) */
+typedef struct {
+  double T, mu;
+  double deq[ORA_MAX_NS * ORA_MAX_NQ];
+  double chia[ORA_MAX_NS * ORA_MAX_NQ];
+  double sig[ORA_MAX_NS * ORA_MAX_NQ];
+  double phi_in[ORA_MAX_NQ * ORA_MAX_NQ];
+  double phi_out[ORA_MAX_NQ * ORA_MAX_NQ];
+  double phi_pro[ORA_MAX_NQ * ORA_MAX_NQ];
+  double phi_ann[ORA_MAX_NQ * ORA_MAX_NQ];
+} opac;
+
+static void compute_opacities(const ora_model* m, const double* theta, double rho11, double chi0, double T,
+                              double mu, opac* o) {
+  int nq = m->nq, ns = m->ns;
+  o->T = T;
+  o->mu = mu;
+  for (int s = 0; s < ns; ++s) {
+    int id = m->species[s];
+    double mus = sp_musign(id) * mu;
+    for (int q = 0; q < nq; ++q) {
+      double shape = chi0 * pow(m->eps[q] / m->eps_ref, m->chi_power);
+      /* Eq. emissivityEmAbNodal: eta^EmAb = chi^EmAb * D^Eq */
+      o->deq[s * nq + q] = ora_fermi_dirac(m->eps[q], mus, T);
+      o->chia[s * nq + q] = ((m->flags & ORA_EMAB) && sp_emab(id)) ? theta[q] * shape : 0.0;
+      o->sig[s * nq + q] = (m->flags & ORA_ISO) ? m->sigma_ratio * shape : 0.0;
+    }
+  }
+  ora_kernels(m, theta, rho11, T, o->phi_in, o->phi_out, o->phi_pro, o->phi_ann);
+}
+
+/* Eqs. emissivityNodal, opacityNodal, transportOpacityNodal, nesRatesNodal,
+ * pairRatesNodal: eta, chi, kappa at every (species, node) for moments D. */
+static void rates(const ora_model* m, const opac* o, const double* D, double* eta, double* chi, double* kappa) {
+  int nq = m->nq, ns = m->ns;
+  for (int s = 0; s < ns; ++s) {
+    int sb = partner_index(m, s);
+    for (int q = 0; q < nq; ++q) {
+      double eta_nes = 0.0, out_nes = 0.0, eta_pair = 0.0, ann_pair = 0.0;
+      if (m->flags & ORA_NES) {
+        for (int p = 0; p < nq; ++p) {
+          eta_nes += m->w2[p] * o->phi_in[q * nq + p] * D[s * nq + p];
+          out_nes += m->w2[p] * o->phi_out[q * nq + p] * (1.0 - D[s * nq + p]);
+        }
+      }
+      if ((m->flags & ORA_PAIR) && sb >= 0) {
+        for (int p = 0; p < nq; ++p) {
+          eta_pair += m->w2[p] * o->phi_pro[q * nq + p] * (1.0 - D[sb * nq + p]);
+          ann_pair += m->w2[p] * o->phi_ann[q * nq + p] * D[sb * nq + p];
+        }
+      }
+      double chi_nes = eta_nes + out_nes;
+      double chi_pair = eta_pair + ann_pair;
+      int i = s * nq + q;
+      eta[i] = o->chia[i] * o->deq[i] + eta_nes + eta_pair;
+      chi[i] = o->chia[i] + chi_nes + chi_pair;
+      kappa[i] = chi[i] + o->sig[i];
+    }
+  }
+}
+
+void ora_rates(const ora_model* m, const double* theta, double rho11, double chi0, double T, double mu,
+               const double* D, double* eta, double* chi, double* kappa) {
+  opac* o = (opac*)malloc(sizeof(opac));
+  compute_opacities(m, theta, rho11, chi0, T, mu, o);
+  rates(m, o, D, eta, chi, kappa);
+  free(o);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Anderson acceleration step (Algorithm neutrinoMatterCoupling, the least
+ * squares problems for alpha / beta with sum-to-one constraint).  The
+ * constrained problem over the last `mem` residuals is solved in its
+ * equivalent difference form: with dF_i = F_{i+1} - F_i, dQ_i likewise,
+ *   gamma = argmin || F_last - sum_i gamma_i dF_i ||_2,
+ *   x_new = Q_last - sum_i gamma_i dQ_i.
+ * Normal equations by Cholesky; a pivot <= 1e-14 * trace drops the oldest
+ * column and retries; with no column left the step is Picard.  Returns the
+ * number of difference columns used. */
+int ora_anderson(int n, int mem, const double* Qh, const double* Fh, double* out) {
+  const double* Qlast = Qh + (size_t)(mem - 1) * n;
+  const double* Flast = Fh + (size_t)(mem - 1) * n;
+  int first = 0; /* oldest difference column in use */
+  int ncol = mem - 1;
+  double gamma[MAXMEM];
+  while (ncol > 0) {
+    double G[MAXMEM][MAXMEM], b[MAXMEM], L[MAXMEM][MAXMEM];
+    for (int i = 0; i < ncol; ++i) {
+      int ci = first + i;
+      for (int j = 0; j <= i; ++j) {
+        int cj = first + j;
+        double acc = 0.0;
+        for (int k = 0; k < n; ++k) {
+          double di = Fh[(size_t)(ci + 1) * n + k] - Fh[(size_t)ci * n + k];
+          double dj = Fh[(size_t)(cj + 1) * n + k] - Fh[(size_t)cj * n + k];
+          acc += di * dj;
+        }
+        G[i][j] = acc;
+        G[j][i] = acc;
+      }
+      double acc = 0.0;
+      for (int k = 0; k < n; ++k) {
+        double di = Fh[(size_t)(ci + 1) * n + k] - Fh[(size_t)ci * n + k];
+        acc += di * Flast[k];
+      }
+      b[i] = acc;
+    }
+    double tr = 0.0;
+    for (int i = 0; i < ncol; ++i) tr += G[i][i];
+    int ok = 1;
+    for (int i = 0; i < ncol && ok; ++i) {
+      for (int j = 0; j <= i; ++j) {
+        double s = G[i][j];
+        for (int k = 0; k < j; ++k) s -= L[i][k] * L[j][k];
+        if (i == j) {
+          if (!(s > 1e-14 * tr)) {
+            ok = 0;
+            break;
+          }
+          L[i][i] = sqrt(s);
+        } else {
+          L[i][j] = s / L[j][j];
+        }
+      }
+    }
+    if (!ok) {
+      first += 1;
+      ncol -= 1;
+      continue;
+    }
+    double y[MAXMEM];
+    for (int i = 0; i < ncol; ++i) {
+      double s = b[i];
+      for (int k = 0; k < i; ++k) s -= L[i][k] * y[k];
+      y[i] = s / L[i][i];
+    }
+    for (int i = ncol - 1; i >= 0; --i) {
+      double s = y[i];
+      for (int k = i + 1; k < ncol; ++k) s -= L[k][i] * gamma[k];
+      gamma[i] = s / L[i][i];
+    }
+    break;
+  }
+  for (int k = 0; k < n; ++k) {
+    double v = Qlast[k];
+    for (int i = 0; i < ncol; ++i) {
+      int ci = first + i;
+      double dq = Qh[(size_t)(ci + 1) * n + k] - Qh[(size_t)ci * n + k];
+      v -= gamma[i] * dq;
+    }
+    out[k] = v;
+  }
+  return ncol;
+}
+
+/* push (Q, F) into a history of at most `cap` entries (oldest first) */
+static void hist_push(double* Qh, double* Fh, int* count, int cap, int n, const double* Q, const double* F) {
+  if (*count == cap) {
+    memmove(Qh, Qh + n, sizeof(double) * (size_t)n * (cap - 1));
+    memmove(Fh, Fh + n, sizeof(double) * (size_t)n * (cap - 1));
+    *count = cap - 1;
+  }
+  memcpy(Qh + (size_t)(*count) * n, Q, sizeof(double) * n);
+  memcpy(Fh + (size_t)(*count) * n, F, sizeof(double) * n);
+  *count += 1;
+}
+
+/* matter right-hand side (Eqs. implicitFluidNodal, eulerianEnergyLG,
+ * eulerianNumberLG at v = 0; the energy per baryon and the lepton fraction
+ * change by the neutrino energy and lepton number absorbed, divided by the
+ * baryon density, K = kcoup / rho11) */
+static void matter_rhs(const ora_model* m, double rho11, const double* D, const double* Dstar, double ye_star,
+                       double e_star, double* yq) {
+  int nq = m->nq, ns = m->ns;
+  double K = m->kcoup / rho11;
+  double dn = 0.0, de = 0.0;
+  for (int s = 0; s < ns; ++s) {
+    int id = m->species[s];
+    for (int q = 0; q < nq; ++q) {
+      double dd = D[s * nq + q] - Dstar[s * nq + q];
+      dn += sp_g(id) * m->w2[q] * dd;
+      de += sp_d(id) * m->w3[q] * dd;
+    }
+  }
+  yq[0] = ye_star - K * dn;
+  yq[1] = e_star - K * de;
+}
+
+static int all_finite(const double* x, int n) {
+  for (int i = 0; i < n; ++i)
+    if (!isfinite(x[i])) return 0;
+  return 1;
+}
+
+/* weighted norm ||D_s||_W2 of one species (Algorithm innerConverged) */
+static double wnorm(const ora_model* m, const double* v) {
+  double acc = 0.0;
+  for (int q = 0; q < m->nq; ++q) acc += m->w2[q] * v[q] * v[q];
+  return sqrt(acc);
+}
+
+typedef struct {
+  double M[MAXN], Mnew[MAXN], Q[MAXN], F[MAXN];
+  double Qh[MAXMEM * MAXN], Fh[MAXMEM * MAXN];
+  double eta[ORA_MAX_NS * ORA_MAX_NQ], chi[ORA_MAX_NS * ORA_MAX_NQ], kap[ORA_MAX_NS * ORA_MAX_NQ];
+  opac o;
+} work;
+
+/* Algorithm neutrinoMatterCoupling for one spatial point (Sec. 3.5.3). */
+static int solve_point(const ora_model* m, const ora_params* prm, const double* theta, double dtau,
+                       const double* Dst, const double* Ist, double rho11, double ye_st, double e_st, double chi0,
+                       int have_T, double T_in, int have_mu, double mu_in, double* D, double* I, double* ye_out,
+                       double* e_out, double* T_out, int* n_outer, int* n_inner, work* w) {
+  int nq = m->nq, ns = m->ns, nn = ns * nq, n = 2 * nn;
+  double ystar[2] = {ye_st, e_st};
+  double y[2] = {ye_st, e_st};
+  double qh[MAXMEM * 2], fh[MAXMEM * 2];
+  int ocount = 0;
+  int status = ORA_OK, inner_failed = 0, outer_conv = 0, fatal = 0;
+  int total_inner = 0, k;
+  double T_last = (prm->fixed_matter && have_T) ? T_in : ora_eos_temperature(m, e_st, ye_st, rho11);
+
+  /* initial guesses: y^[1] = y*, M^[1,1] = M* */
+  for (int i = 0; i < nn; ++i) {
+    w->M[i] = Dst[i];
+    w->M[nn + i] = Ist[i];
+  }
+
+  for (k = 1; k <= prm->max_outer; ++k) {
+    /* ComputeOpacities(y^[k]) */
+    double T, mu;
+    /* with matter held fixed the caller may prescribe T and mu directly */
+    T = (prm->fixed_matter && have_T) ? T_in : ora_eos_temperature(m, y[1], y[0], rho11);
+    mu = (prm->fixed_matter && have_mu) ? mu_in : ora_eos_mu(m, y[0], T, rho11);
+    if (!(T > 0.0) || !(y[0] >= 0.0) || !isfinite(T) || !isfinite(mu)) {
+      status = ORA_EOS_DOMAIN;
+      fatal = 1;
+      break;
+    }
+    T_last = T;
+    compute_opacities(m, theta, rho11, chi0, T, mu, &w->o);
+
+    /* inner loop over moments with matter held fixed; M^[k,1] = M^[k-1,*] */
+    double dref0[ORA_MAX_NS];
+    for (int s = 0; s < ns; ++s) dref0[s] = wnorm(m, w->M + s * nq);
+    int icount = 0, conv = 0, l;
+    for (l = 1; l <= prm->max_inner; ++l) {
+      /* ComputeRates and moment right-hand side, Eq. implicitMomentsNodal at
+       * v = 0 (lambda = 1): Q_D = (D* + dtau eta) / (1 + dtau chi),
+       * Q_I = I* / (1 + dtau kappa) */
+      rates(m, &w->o, w->M, w->eta, w->chi, w->kap);
+      for (int i = 0; i < nn; ++i) {
+        w->Q[i] = (Dst[i] + dtau * w->eta[i]) / (1.0 + dtau * w->chi[i]);
+        w->Q[nn + i] = Ist[i] / (1.0 + dtau * w->kap[i]);
+      }
+      for (int i = 0; i < n; ++i) w->F[i] = w->Q[i] - w->M[i];
+      hist_push(w->Qh, w->Fh, &icount, prm->m_inner, n, w->Q, w->F);
+      ora_anderson(n, icount, w->Qh, w->Fh, w->Mnew);
+      if (!all_finite(w->Mnew, n)) {
+        status = ORA_NONFINITE;
+        fatal = 1;
+        break;
+      }
+      /* Algorithm innerConverged: per species, sqrt(max over moments of
+       * sum_q W2 dM^2) <= tol * ||D_s||, reference guarded by the new norm */
+      conv = 1;
+      for (int s = 0; s < ns; ++s) {
+        double sd = 0.0, si = 0.0;
+        for (int q = 0; q < nq; ++q) {
+          int i = s * nq + q;
+          double dd = w->Mnew[i] - w->M[i];
+          double di = w->Mnew[nn + i] - w->M[nn + i];
+          sd += m->w2[q] * dd * dd;
+          si += m->w2[q] * di * di;
+        }
+        double dm = sqrt(sd > si ? sd : si);
+        double dnew = wnorm(m, w->Mnew + s * nq);
+        double dref = dref0[s] > dnew ? dref0[s] : dnew;
+        if (!(dm <= prm->tol_inner * dref)) conv = 0;
+      }
+      memcpy(w->M, w->Mnew, sizeof(double) * n);
+      if (conv) break;
+    }
+    if (fatal) {
+      total_inner += (l > prm->max_inner ? prm->max_inner : l);
+      break;
+    }
+    total_inner += (l > prm->max_inner ? prm->max_inner : l);
+    if (!conv) inner_failed = 1;
+
+    if (prm->fixed_matter) {
+      outer_conv = 1;
+      break;
+    }
+
+    /* matter right-hand side and residual; outer Anderson step */
+    double yq[2], f[2], ynew[2];
+    matter_rhs(m, rho11, w->M, Dst, ye_st, e_st, yq);
+    f[0] = yq[0] - y[0];
+    f[1] = yq[1] - y[1];
+    hist_push(qh, fh, &ocount, prm->m_outer, 2, yq, f);
+    ora_anderson(2, ocount, qh, fh, ynew);
+    if (!isfinite(ynew[0]) || !isfinite(ynew[1])) {
+      status = ORA_NONFINITE;
+      fatal = 1;
+      break;
+    }
+    /* Algorithm outerConverged: componentwise against y* */
+    int oc = fabs(ynew[0] - y[0]) <= prm->tol_outer * fabs(ystar[0]) &&
+             fabs(ynew[1] - y[1]) <= prm->tol_outer * fabs(ystar[1]);
+    y[0] = ynew[0];
+    y[1] = ynew[1];
+    if (oc) {
+      outer_conv = 1;
+      break;
+    }
+  }
+  if (k > prm->max_outer) k = prm->max_outer;
+  if (!fatal) {
+    if (!outer_conv) status = ORA_MAX_OUTER;
+    else if (inner_failed) status = ORA_MAX_INNER;
+  }
+
+  for (int i = 0; i < nn; ++i) {
+    D[i] = w->M[i];
+    I[i] = w->M[nn + i];
+  }
+  if (prm->fixed_matter) {
+    *ye_out = ye_st;
+    *e_out = e_st;
+    *T_out = T_last;
+  } else {
+    /* output matter state recomputed from the final moments so that lepton
+     * number and energy balance hold to rounding */
+    double yq[2];
+    matter_rhs(m, rho11, w->M, Dst, ye_st, e_st, yq);
+    *ye_out = yq[0];
+    *e_out = yq[1];
+    *T_out = ora_eos_temperature(m, yq[1], yq[0], rho11);
+  }
+  *n_outer = k;
+  *n_inner = total_inner;
+  return status;
+}
+
+int ora_solve_batch(const ora_model* m, const ora_params* prm, const double* theta, long P, double dtau,
+                    const double* D0, const double* I0, const double* rho11, const double* ye0,
+                    const double* e0, const double* chi0, const double* T_fixed, const double* mu_fixed,
+                    double* D, double* I, double* ye, double* e, double* T,
+                    int* n_outer, int* n_inner, int* status, int nthreads) {
+  if (m->nq < 1 || m->nq > ORA_MAX_NQ || m->ns < 1 || m->ns > ORA_MAX_NS) return -1;
+  if (prm->m_inner < 1 || prm->m_inner > MAXMEM || prm->m_outer < 1 || prm->m_outer > MAXMEM) return -1;
+  if (prm->max_inner < 1 || prm->max_outer < 1) return -1;
+  if ((m->flags & ORA_PAIR))
+    for (int s = 0; s < m->ns; ++s)
+      if (partner_index(m, s) < 0) return -1;
+  int nn = m->ns * m->nq;
+#ifdef _OPENMP
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel
+#endif
+  {
+    work* w = (work*)malloc(sizeof(work));
+#ifdef _OPENMP
+#pragma omp for schedule(dynamic, 16)
+#endif
+    for (long p = 0; p < P; ++p) {
+      double c0 = chi0 ? chi0[p] : m->chi_ref * rho11[p];
+      if (rho11[p] < m->rho11_min) {
+        /* neutrino-matter coupling is disabled at low density (Sec. 7.2):
+         * the state passes through unchanged */
+        for (int i = 0; i < nn; ++i) {
+          D[p * nn + i] = D0[p * nn + i];
+          I[p * nn + i] = I0[p * nn + i];
+        }
+        ye[p] = ye0[p];
+        e[p] = e0[p];
+        T[p] = (prm->fixed_matter && T_fixed) ? T_fixed[p] : ora_eos_temperature(m, e0[p], ye0[p], rho11[p]);
+        n_outer[p] = 0;
+        n_inner[p] = 0;
+        status[p] = ORA_OK;
+        continue;
+      }
+      status[p] = solve_point(m, prm, theta, dtau, D0 + p * nn, I0 + p * nn, rho11[p], ye0[p], e0[p], c0,
+                              T_fixed != NULL, T_fixed ? T_fixed[p] : 0.0, mu_fixed != NULL,
+                              mu_fixed ? mu_fixed[p] : 0.0, D + p * nn, I + p * nn, ye + p, e + p, T + p,
+                              n_outer + p, n_inner + p, w);
+    }
+    free(w);
+  }
+  return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Residual of the implicit system (definition of the result): Eqs.
+ * implicitNumberNodal, implicitNumberFluxNodal at v = 0 and Eq.
+ * implicitFluidNodal.  Layout: [R_D (ns*nq), R_I (ns*nq), R_Ye, R_e]. */
+void ora_residual(const ora_model* m, const double* theta, double dtau, double rho11, double chi0,
+                  const double* Dstar, const double* Istar, double ye_star, double e_star,
+                  const double* D, const double* I, double ye, double e, double* R) {
+  int nn = m->ns * m->nq;
+  double T = ora_eos_temperature(m, e, ye, rho11);
+  double mu = ora_eos_mu(m, ye, T, rho11);
+  double* eta = (double*)malloc(sizeof(double) * 3 * nn);
+  double *chi = eta + nn, *kap = eta + 2 * nn;
+  ora_rates(m, theta, rho11, chi0, T, mu, D, eta, chi, kap);
+  for (int i = 0; i < nn; ++i) {
+    R[i] = D[i] - Dstar[i] - dtau * (eta[i] - chi[i] * D[i]);
+    R[nn + i] = I[i] - Istar[i] + dtau * kap[i] * I[i];
+  }
+  double yq[2];
+  matter_rhs(m, rho11, D, Dstar, ye_star, e_star, yq);
+  R[2 * nn] = ye - yq[0];
+  R[2 * nn + 1] = e - yq[1];
+  free(eta);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Analytic Jacobian of the reduced residual x = (D, Ye, e):
+ *   R_D = D (1 + dtau chi) - D* - dtau eta,
+ *   R_Y = Ye - Ye* + K sum g W2 (D - D*),  R_e = e - e* + K sum d W3 (D - D*),
+ * with T = T(e, Ye) and mu = mu(Ye, T).  The flux block drops out because no
+ * output of the reduced system depends on I when v = 0. */
+
+typedef struct {
+  double dPin[ORA_MAX_NQ * ORA_MAX_NQ], dPout[ORA_MAX_NQ * ORA_MAX_NQ];
+  double dPpro[ORA_MAX_NQ * ORA_MAX_NQ], dPann[ORA_MAX_NQ * ORA_MAX_NQ];
+  opac o;
+} jwork;
+
+static void jacobian_core(const ora_model* m, const double* theta, double dtau, double rho11, double chi0,
+                          const double* D, double ye, double e, double* J, jwork* w) {
+  int nq = m->nq, ns = m->ns, nn = ns * nq, n = nn + 2;
+  double T = ora_eos_temperature(m, e, ye, rho11);
+  double mu = ora_eos_mu(m, ye, T, rho11);
+  opac* o = &w->o;
+  compute_opacities(m, theta, rho11, chi0, T, mu, o);
+  /* d Phi / dT = Phi * c / T^2 with c the non-negative exponent numerator */
+  for (int q = 0; q < nq; ++q)
+    for (int p = 0; p < nq; ++p) {
+      double dlt = m->eps[q] - m->eps[p], adl = fabs(dlt);
+      int i = q * nq + p;
+      w->dPin[i] = o->phi_in[i] * (adl + 0.5 * dlt) / (T * T);
+      w->dPout[i] = o->phi_out[i] * (adl - 0.5 * dlt) / (T * T);
+      w->dPann[i] = o->phi_ann[i] * adl / (T * T);
+      w->dPpro[i] = o->phi_pro[i] * (adl + m->eps[q] + m->eps[p]) / (T * T);
+    }
+  double eta[ORA_MAX_NS * ORA_MAX_NQ], chi[ORA_MAX_NS * ORA_MAX_NQ], kap[ORA_MAX_NS * ORA_MAX_NQ];
+  rates(m, o, D, eta, chi, kap);
+  memset(J, 0, sizeof(double) * n * n);
+  double r3 = cbrt(rho11);
+  double dT_de = 1.0 / (m->eos_a * (1.0 + ye));
+  double dT_dye = -(4.0 / 3.0) * m->eos_b * cbrt(ye) * r3 / (m->eos_a * (1.0 + ye)) - T / (1.0 + ye);
+  double dmu_dye = m->mu_a * r3 + m->mu_b / T * dT_dye;
+  double dmu_de = m->mu_b / T * dT_de;
+  int nes = (m->flags & ORA_NES) != 0, pair = (m->flags & ORA_PAIR) != 0;
+  for (int s = 0; s < ns; ++s) {
+    int id = m->species[s];
+    int sb = partner_index(m, s);
+    double sgn = sp_musign(id);
+    for (int q = 0; q < nq; ++q) {
+      int i = s * nq + q;
+      double Dq = D[i];
+      J[i * n + i] += 1.0 + dtau * chi[i];
+      if (nes)
+        for (int p = 0; p < nq; ++p) {
+          double a_in = m->w2[p] * o->phi_in[q * nq + p];
+          double a_out = m->w2[p] * o->phi_out[q * nq + p];
+          /* d eta_nes / dD_s' = W Phi_in ; d chi_nes / dD_s' = W (Phi_in - Phi_out) */
+          J[i * n + s * nq + p] += dtau * (Dq * (a_in - a_out) - a_in);
+        }
+      if (pair && sb >= 0)
+        for (int p = 0; p < nq; ++p) {
+          double a_pro = m->w2[p] * o->phi_pro[q * nq + p];
+          double a_ann = m->w2[p] * o->phi_ann[q * nq + p];
+          /* d eta_pair / dDbar' = -W Phi_pro ; d chi_pair / dDbar' = W (Phi_ann - Phi_pro) */
+          J[i * n + sb * nq + p] += dtau * (Dq * (a_ann - a_pro) + a_pro);
+        }
+      /* temperature and chemical-potential derivatives */
+      double f = o->deq[i];
+      double fc = ora_fermi_dirac_complement(m->eps[q], sgn * mu, T);
+      double ddeq_dT = f * fc * (m->eps[q] - sgn * mu) / (T * T);
+      double ddeq_dmu = f * fc / T * sgn;
+      double deta_dT = o->chia[i] * ddeq_dT, dchi_dT = 0.0;
+      if (nes)
+        for (int p = 0; p < nq; ++p) {
+          double t_in = m->w2[p] * w->dPin[q * nq + p] * D[s * nq + p];
+          double t_out = m->w2[p] * w->dPout[q * nq + p] * (1.0 - D[s * nq + p]);
+          deta_dT += t_in;
+          dchi_dT += t_in + t_out;
+        }
+      if (pair && sb >= 0)
+        for (int p = 0; p < nq; ++p) {
+          double t_pro = m->w2[p] * w->dPpro[q * nq + p] * (1.0 - D[sb * nq + p]);
+          double t_ann = m->w2[p] * w->dPann[q * nq + p] * D[sb * nq + p];
+          deta_dT += t_pro;
+          dchi_dT += t_pro + t_ann;
+        }
+      double dR_dT = dtau * (Dq * dchi_dT - deta_dT);
+      double dR_dmu = -dtau * o->chia[i] * ddeq_dmu;
+      J[i * n + nn] += dR_dT * dT_dye + dR_dmu * dmu_dye;
+      J[i * n + nn + 1] += dR_dT * dT_de + dR_dmu * dmu_de;
+    }
+  }
+  double K = m->kcoup / rho11;
+  for (int s = 0; s < ns; ++s) {
+    int id = m->species[s];
+    for (int q = 0; q < nq; ++q) {
+      J[nn * n + s * nq + q] = K * sp_g(id) * m->w2[q];
+      J[(nn + 1) * n + s * nq + q] = K * sp_d(id) * m->w3[q];
+    }
+  }
+  J[nn * n + nn] = 1.0;
+  J[(nn + 1) * n + nn + 1] = 1.0;
+}
+
+int ora_jacobian(const ora_model* m, const double* theta, double dtau, double rho11, double chi0,
+                 const double* D, double ye, double e, double* J) {
+  jwork* w = (jwork*)malloc(sizeof(jwork));
+  jacobian_core(m, theta, dtau, rho11, chi0, D, ye, e, J, w);
+  free(w);
+  return 0;
+}
+
+/* dense LU with partial pivoting, in place; solves A x = b (trans = 0) or
+ * A^T x = b (trans = 1) */
+static int lu_factor(double* A, int n, int* piv) {
+  for (int k = 0; k < n; ++k) {
+    int pr = k;
+    double best = fabs(A[k * n + k]);
+    for (int i = k + 1; i < n; ++i)
+      if (fabs(A[i * n + k]) > best) {
+        best = fabs(A[i * n + k]);
+        pr = i;
+      }
+    piv[k] = pr;
+    if (best == 0.0) return -1;
+    if (pr != k)
+      for (int j = 0; j < n; ++j) {
+        double t = A[k * n + j];
+        A[k * n + j] = A[pr * n + j];
+        A[pr * n + j] = t;
+      }
+    for (int i = k + 1; i < n; ++i) {
+      A[i * n + k] /= A[k * n + k];
+      double l = A[i * n + k];
+      for (int j = k + 1; j < n; ++j) A[i * n + j] -= l * A[k * n + j];
+    }
+  }
+  return 0;
+}
+
+static void lu_solve(const double* A, int n, const int* piv, double* x, int trans) {
+  if (!trans) {
+    for (int k = 0; k < n; ++k) {
+      double t = x[k];
+      x[k] = x[piv[k]];
+      x[piv[k]] = t;
+    }
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < i; ++j) x[i] -= A[i * n + j] * x[j];
+    for (int i = n - 1; i >= 0; --i) {
+      for (int j = i + 1; j < n; ++j) x[i] -= A[i * n + j] * x[j];
+      x[i] /= A[i * n + i];
+    }
+  } else {
+    /* (P^T L U)^T y = b  ->  U^T z = b, L^T w = z, y = P^T w */
+    for (int i = 0; i < n; ++i) {
+      for (int j = 0; j < i; ++j) x[i] -= A[j * n + i] * x[j];
+      x[i] /= A[i * n + i];
+    }
+    for (int i = n - 1; i >= 0; --i)
+      for (int j = i + 1; j < n; ++j) x[i] -= A[j * n + i] * x[j];
+    for (int k = n - 1; k >= 0; --k) {
+      double t = x[k];
+      x[k] = x[piv[k]];
+      x[piv[k]] = t;
+    }
+  }
+}
+
+/* Dense Newton on the reduced (D, Ye, e) system, then I from its closed form
+ * I = I* / (1 + dtau kappa).  Used only to pin the fixed-point solution on
+ * tiny problems. */
+int ora_newton(const ora_model* m, const double* theta, double dtau, double rho11, double chi0,
+               const double* Dstar, const double* Istar, double ye_star, double e_star,
+               double* D, double* I, double* ye, double* e, double tol, int max_it) {
+  int nn = m->ns * m->nq, n = nn + 2;
+  double* J = (double*)malloc(sizeof(double) * n * n);
+  double* R = (double*)malloc(sizeof(double) * (2 * nn + 2));
+  double* dx = (double*)malloc(sizeof(double) * n);
+  int* piv = (int*)malloc(sizeof(int) * n);
+  jwork* w = (jwork*)malloc(sizeof(jwork));
+  int it, rc = -1;
+  for (it = 0; it < max_it; ++it) {
+    ora_residual(m, theta, dtau, rho11, chi0, Dstar, Istar, ye_star, e_star, D, I, *ye, *e, R);
+    for (int i = 0; i < nn; ++i) dx[i] = -R[i];
+    dx[nn] = -R[2 * nn];
+    dx[nn + 1] = -R[2 * nn + 1];
+    jacobian_core(m, theta, dtau, rho11, chi0, D, *ye, *e, J, w);
+    if (lu_factor(J, n, piv) != 0) break;
+    lu_solve(J, n, piv, dx, 0);
+    double step = 0.0, scale = 0.0;
+    for (int i = 0; i < nn; ++i) {
+      D[i] += dx[i];
+      step += m->w2[i % m->nq] * dx[i] * dx[i];
+      scale += m->w2[i % m->nq] * D[i] * D[i];
+    }
+    *ye += dx[nn];
+    *e += dx[nn + 1];
+    if (sqrt(step) <= tol * sqrt(scale) && fabs(dx[nn]) <= tol * fabs(*ye) && fabs(dx[nn + 1]) <= tol * fabs(*e)) {
+      rc = it + 1;
+      break;
+    }
+  }
+  /* flux moments from their closed form at the converged D and T */
+  {
+    double T = ora_eos_temperature(m, *e, *ye, rho11);
+    double mu = ora_eos_mu(m, *ye, T, rho11);
+    double* eta = (double*)malloc(sizeof(double) * 3 * nn);
+    ora_rates(m, theta, rho11, chi0, T, mu, D, eta, eta + nn, eta + 2 * nn);
+    for (int i = 0; i < nn; ++i) I[i] = Istar[i] / (1.0 + dtau * eta[2 * nn + i]);
+    free(eta);
+  }
+  free(J);
+  free(R);
+  free(dx);
+  free(piv);
+  free(w);
+  return rc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Implicit-function-theorem adjoint.  At the converged x (R(x, theta) = 0):
+ *   R_x^T lambda = L_x^T,  dL/dtheta = -lambda^T R_theta,
+ * with L = gE (e* - e) + gY (Ye - Ye*) per point, theta = (s_1..s_nq, a_nes,
+ * a_pair).  s_q scales chi^EmAb only; a_nes and a_pair scale the NES and pair
+ * kernels linearly (A = a * rho11). */
+int ora_adjoint_batch(const ora_model* m, const double* theta, long P, double dtau, const double* rho11,
+                      const double* chi0, const double* D, const double* ye, const double* e,
+                      const double* gbar, double* grad_theta, double* grad_pp, int nthreads) {
+  int nq = m->nq, ns = m->ns, nn = ns * nq, n = nn + 2, nt = nq + 2;
+  double* gsum = (double*)calloc((size_t)nt, sizeof(double));
+  int bad = 0;
+#ifdef _OPENMP
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel
+#endif
+  {
+    double* J = (double*)malloc(sizeof(double) * n * n);
+    double* lam = (double*)malloc(sizeof(double) * n);
+    int* piv = (int*)malloc(sizeof(int) * n);
+    jwork* w = (jwork*)malloc(sizeof(jwork));
+    double* gl = (double*)calloc((size_t)nt, sizeof(double));
+    opac* ou = (opac*)malloc(sizeof(opac));
+#ifdef _OPENMP
+#pragma omp for schedule(dynamic, 16)
+#endif
+    for (long p = 0; p < P; ++p) {
+      double c0 = chi0 ? chi0[p] : m->chi_ref * rho11[p];
+      const double* Dp = D + p * nn;
+      jacobian_core(m, theta, dtau, rho11[p], c0, Dp, ye[p], e[p], J, w);
+      if (lu_factor(J, n, piv) != 0) {
+#ifdef _OPENMP
+#pragma omp atomic write
+#endif
+        bad = 1;
+        continue;
+      }
+      for (int i = 0; i < n; ++i) lam[i] = 0.0;
+      lam[nn] = gbar[2 * p + 1];   /* dL/dYe */
+      lam[nn + 1] = -gbar[2 * p];  /* dL/de (L_E = e* - e) */
+      lu_solve(J, n, piv, lam, 1);
+      double T = w->o.T, mu = w->o.mu;
+      /* unit-amplitude kernels for the a_nes / a_pair derivatives */
+      kernels_unit(m, T, rho11[p], rho11[p], ou->phi_in, ou->phi_out, ou->phi_pro, ou->phi_ann);
+      double gp[ORA_MAX_NQ + 2];
+      for (int j = 0; j < nt; ++j) gp[j] = 0.0;
+      for (int s = 0; s < ns; ++s) {
+        int id = m->species[s];
+        int sb = partner_index(m, s);
+        for (int q = 0; q < nq; ++q) {
+          int i = s * nq + q;
+          double Dq = Dp[i];
+          if ((m->flags & ORA_EMAB) && sp_emab(id)) {
+            double shape = c0 * pow(m->eps[q] / m->eps_ref, m->chi_power);
+            gp[q] -= lam[i] * dtau * shape * (Dq - w->o.deq[i]);
+          }
+          if (m->flags & ORA_NES) {
+            double en = 0.0, on = 0.0;
+            for (int r = 0; r < nq; ++r) {
+              en += m->w2[r] * ou->phi_in[q * nq + r] * Dp[s * nq + r];
+              on += m->w2[r] * ou->phi_out[q * nq + r] * (1.0 - Dp[s * nq + r]);
+            }
+            gp[nq] -= lam[i] * dtau * (Dq * (en + on) - en);
+          }
+          if ((m->flags & ORA_PAIR) && sb >= 0) {
+            double ep = 0.0, an = 0.0;
+            for (int r = 0; r < nq; ++r) {
+              ep += m->w2[r] * ou->phi_pro[q * nq + r] * (1.0 - Dp[sb * nq + r]);
+              an += m->w2[r] * ou->phi_ann[q * nq + r] * Dp[sb * nq + r];
+            }
+            gp[nq + 1] -= lam[i] * dtau * (Dq * (ep + an) - ep);
+          }
+        }
+      }
+      (void)mu;
+      if (grad_pp)
+        for (int j = 0; j < nt; ++j) grad_pp[p * nt + j] = gp[j];
+      for (int j = 0; j < nt; ++j) gl[j] += gp[j];
+    }
+#ifdef _OPENMP
+#pragma omp critical
+#endif
+    for (int j = 0; j < nt; ++j) gsum[j] += gl[j];
+    free(J);
+    free(lam);
+    free(piv);
+    free(w);
+    free(gl);
+    free(ou);
+  }
+  for (int j = 0; j < nt; ++j) grad_theta[j] += gsum[j];
+  free(gsum);
+  return bad ? -2 : 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Initial state from raw draws: e* from the EOS, D* = clip(D_eq (a + b uD),
+ * 0, 1 - 1e-12), I* = c D* uI.  If mu is NULL it follows from the EOS. */
+int ora_init_state(const ora_model* m, long P, const double* T, const double* mu, const double* rho11,
+                   const double* ye, const double* uD, const double* uI, double a, double b, double c,
+                   double* D0, double* I0, double* e0) {
+  int nq = m->nq, ns = m->ns, nn = ns * nq;
+  for (long p = 0; p < P; ++p) {
+    double mup = mu ? mu[p] : ora_eos_mu(m, ye[p], T[p], rho11[p]);
+    if (e0) e0[p] = ora_eos_energy(m, T[p], ye[p], rho11[p]);
+    for (int s = 0; s < ns; ++s) {
+      double mus = sp_musign(m->species[s]) * mup;
+      for (int q = 0; q < nq; ++q) {
+        long i = p * nn + s * nq + q;
+        double d = ora_fermi_dirac(m->eps[q], mus, T[p]) * (a + b * uD[i]);
+        if (d < 0.0) d = 0.0;
+        if (d > 1.0 - 1e-12) d = 1.0 - 1e-12;
+        D0[i] = d;
+        I0[i] = c * d * uI[i];
+      }
+    }
+  }
+  return 0;
+}

@@ -1,0 +1,117 @@
+/*
+ * Test infrastructure, not product code.
+ *
+ * Plain, slow, obviously-correct FP64 CPU oracle for the implicit (backward
+ * Euler) neutrino-matter coupling solve of the two-moment DG-IMEX scheme
+ * (paper Sec. 3.5, Eqs. implicitNumberNodal ... implicitFluidNodal and
+ * Algorithms neutrinoMatterCoupling / innerConverged / outerConverged).
+ *
+ * It shares no code with the HIP library: only tests, the smoke check and the
+ * CPU-baseline leg of the benchmark may load it.  Every routine cites the
+ * passage it follows; readings of silent or garbled passages are listed in the
+ * design notes of the repository.
+ */
+#ifndef NMC_ORACLE_H
+#define NMC_ORACLE_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ORA_MAX_NQ 64
+#define ORA_MAX_NS 3
+
+/* species identities */
+#define ORA_NU_E 0
+#define ORA_NU_E_BAR 1
+#define ORA_NU_X 2
+
+/* physics flags */
+#define ORA_EMAB 1u
+#define ORA_ISO 2u
+#define ORA_NES 4u
+#define ORA_PAIR 8u
+
+/* per-point status */
+#define ORA_OK 0
+#define ORA_MAX_OUTER 1
+#define ORA_MAX_INNER 2
+#define ORA_NONFINITE 3
+#define ORA_EOS_DOMAIN 4
+
+typedef struct {
+  int nq, ns;
+  int species[ORA_MAX_NS];
+  double eps[ORA_MAX_NQ]; /* node energies [MeV] */
+  double w2[ORA_MAX_NQ];  /* w_q eps_q^2 dEps [MeV^3] (4 pi / h^3 factored out) */
+  double w3[ORA_MAX_NQ];  /* w2 * eps [MeV^4] */
+  unsigned flags;
+  double chi_ref, eps_ref, chi_power, sigma_ratio;
+  double eos_a, eos_b, mu_a, mu_ye0, mu_b, mu_t0;
+  double kcoup; /* (4 pi/(hc)^3) * m_u / 1e11 [MeV^-3]; K = kcoup / rho11 */
+  double rho11_min; /* coupling disabled below this density (Sec. 7.2) */
+} ora_model;
+
+typedef struct {
+  double tol_inner, tol_outer;
+  int m_inner, m_outer, max_inner, max_outer, fixed_matter;
+} ora_params;
+
+/* grids */
+int ora_grid_loguniform(int n_elem, double eps_lo, double eps_hi, double* eps, double* w2, double* w3);
+int ora_grid_zoom(int n_elem, double zoom, double width, double* edges, double* eps, double* w2, double* w3);
+
+/* model default constants */
+void ora_model_defaults(ora_model* m);
+
+/* thermodynamics */
+double ora_fermi_dirac(double eps, double mu, double T);
+double ora_fermi_dirac_complement(double eps, double mu, double T);
+double ora_eos_energy(const ora_model* m, double T, double ye, double rho11);
+double ora_eos_temperature(const ora_model* m, double e, double ye, double rho11);
+double ora_eos_mu(const ora_model* m, double ye, double T, double rho11);
+
+/* opacities and kernels at (T, mu) for one point */
+void ora_kernels(const ora_model* m, const double* theta, double rho11, double T,
+                 double* phi_in, double* phi_out, double* phi_pro, double* phi_ann);
+void ora_rates(const ora_model* m, const double* theta, double rho11, double chi0, double T, double mu,
+               const double* D, double* eta, double* chi, double* kappa);
+
+/* Anderson step on generic vectors (history oldest first) */
+int ora_anderson(int n, int mem, const double* Qh, const double* Fh, double* out);
+
+/* batched forward solve (Algorithm neutrinoMatterCoupling) */
+int ora_solve_batch(const ora_model* m, const ora_params* prm, const double* theta, long P, double dtau,
+                    const double* D0, const double* I0, const double* rho11, const double* ye0,
+                    const double* e0, const double* chi0, const double* T_fixed, const double* mu_fixed,
+                    double* D, double* I, double* ye, double* e, double* T,
+                    int* n_outer, int* n_inner, int* status, int nthreads);
+
+/* implicit-system residual (definition of the result) at one point */
+void ora_residual(const ora_model* m, const double* theta, double dtau, double rho11, double chi0,
+                  const double* Dstar, const double* Istar, double ye_star, double e_star,
+                  const double* D, const double* I, double ye, double e, double* R);
+
+/* analytic Jacobian of the (D, Ye, e) residual block at one point, n = ns*nq + 2, row-major */
+int ora_jacobian(const ora_model* m, const double* theta, double dtau, double rho11, double chi0,
+                 const double* D, double ye, double e, double* J);
+
+/* dense Newton on the full residual (tiny problems) */
+int ora_newton(const ora_model* m, const double* theta, double dtau, double rho11, double chi0,
+               const double* Dstar, const double* Istar, double ye_star, double e_star,
+               double* D, double* I, double* ye, double* e, double tol, int max_it);
+
+/* implicit-function-theorem adjoint, dense LU, summed gradient */
+int ora_adjoint_batch(const ora_model* m, const double* theta, long P, double dtau, const double* rho11,
+                      const double* chi0, const double* D, const double* ye, const double* e,
+                      const double* gbar, double* grad_theta, double* grad_pp, int nthreads);
+
+/* initial state from raw draws */
+int ora_init_state(const ora_model* m, long P, const double* T, const double* mu, const double* rho11,
+                   const double* ye, const double* uD, const double* uI, double a, double b, double c,
+                   double* D0, double* I0, double* e0);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
