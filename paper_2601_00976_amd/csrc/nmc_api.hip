@@ -1,0 +1,395 @@
+// Host side of the nmc C ABI: handles, argument validation and launches.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <new>
+#include <string>
+
+#include "nmc_internal.h"
+
+struct nmc_grid {
+  int n_elem;
+  int nq;
+  double edges[nmc::kMaxNq / 2 + 1];
+  double eps[nmc::kMaxNq];
+  double w2[nmc::kMaxNq];
+  double w3[nmc::kMaxNq];
+};
+
+struct nmc_model {
+  nmc::DevModel host;
+  nmc::DevModel* dev;
+  int device;
+  int num_cu;
+};
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+  return fail(NMC_E_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+bool aligned256(const void* p) { return ((uintptr_t)p & 255u) == 0; }
+
+constexpr size_t kCounterBytes = 256;
+
+int partner_id(int id) { return id == NMC_NU_E ? NMC_NU_E_BAR : (id == NMC_NU_E_BAR ? NMC_NU_E : NMC_NU_X); }
+
+}  // namespace
+
+extern "C" {
+
+const char* nmc_error_string(int code) {
+  switch (code) {
+    case NMC_OK: return "ok";
+    case NMC_E_INVALID_ARG: return "invalid argument";
+    case NMC_E_UNSUPPORTED: return "unsupported configuration";
+    case NMC_E_HIP: return "HIP runtime error";
+    case NMC_E_WORKSPACE: return "workspace too small or misaligned";
+    default: return "unknown error";
+  }
+}
+
+const char* nmc_last_error(void) { return g_last_error.c_str(); }
+
+void nmc_model_desc_default(nmc_model_desc* d) {
+  if (!d) return;
+  memset(d, 0, sizeof(*d));
+  d->n_species = 3;
+  d->species[0] = NMC_NU_E;
+  d->species[1] = NMC_NU_E_BAR;
+  d->species[2] = NMC_NU_X;
+  d->flags = NMC_ALL_PHYSICS;
+  d->chi_ref = 10.0;
+  d->eps_ref = 10.0;
+  d->chi_power = 2.0;
+  d->sigma_ratio = 0.5;
+  d->eos_a = 1.5;
+  d->eos_b = 3.0;
+  d->mu_a = 20.0;
+  d->mu_ye0 = 0.3;
+  d->mu_b = 5.0;
+  d->mu_t0 = 5.0;
+  d->hc_mev_cm = 1.239841984e-10;
+  d->m_u_g = 1.66053906660e-24;
+  d->rho11_min = 1.0e-4;
+}
+
+void nmc_solver_params_default(nmc_solver_params* p) {
+  if (!p) return;
+  p->tol_inner = 1e-10;
+  p->tol_outer = 1e-10;
+  p->m_inner = 3;
+  p->m_outer = 3;
+  p->max_inner = 100;
+  p->max_outer = 50;
+  p->fixed_matter = 0;
+}
+
+// Energy grid: element edges, then 2 Legendre-Gauss nodes per element on the
+// reference interval (-1/2, 1/2) with weights 1/2 (Sec. 3.1.2) and the
+// integration weights of Eq. energy_integration_weights without 4 pi / h^3.
+int nmc_grid_create(const nmc_grid_desc* desc, nmc_grid** out) {
+  if (!desc || !out) return fail(NMC_E_INVALID_ARG, "grid_create: null argument");
+  *out = nullptr;
+  if (desc->nodes_per_elem != 2)
+    return fail(NMC_E_UNSUPPORTED, "grid_create: nodes_per_elem must be 2 (got %d)", desc->nodes_per_elem);
+  if (desc->n_elem < 1 || 2 * desc->n_elem > nmc::kMaxNq)
+    return fail(NMC_E_INVALID_ARG, "grid_create: n_elem must be in [1, %d] (got %d)", nmc::kMaxNq / 2, desc->n_elem);
+  if (!(desc->eps_hi > 0.0) || !isfinite(desc->eps_hi)) return fail(NMC_E_INVALID_ARG, "grid_create: bad eps_hi");
+  nmc_grid* g = new (std::nothrow) nmc_grid();
+  if (!g) return fail(NMC_E_INVALID_ARG, "grid_create: out of host memory");
+  const int ne = desc->n_elem;
+  g->n_elem = ne;
+  g->nq = 2 * ne;
+  if (desc->spacing == NMC_SPACING_LOG) {
+    if (!(desc->eps_lo > 0.0) || !(desc->eps_hi > desc->eps_lo)) {
+      delete g;
+      return fail(NMC_E_INVALID_ARG, "grid_create: LOG spacing needs 0 < eps_lo < eps_hi");
+    }
+    for (int e = 0; e <= ne; ++e) g->edges[e] = desc->eps_lo * pow(desc->eps_hi / desc->eps_lo, (double)e / ne);
+    g->edges[ne] = desc->eps_hi;
+  } else if (desc->spacing == NMC_SPACING_ZOOM) {
+    if (!(desc->zoom > 0.0) || !isfinite(desc->zoom)) {
+      delete g;
+      return fail(NMC_E_INVALID_ARG, "grid_create: ZOOM spacing needs zoom > 0");
+    }
+    const double z = desc->zoom;
+    const double d1 = (z == 1.0) ? desc->eps_hi / ne : desc->eps_hi * (z - 1.0) / (pow(z, ne) - 1.0);
+    g->edges[0] = 0.0;
+    double d = d1;
+    for (int e = 0; e < ne; ++e) {
+      g->edges[e + 1] = g->edges[e] + d;
+      d *= z;
+    }
+  } else {
+    delete g;
+    return fail(NMC_E_INVALID_ARG, "grid_create: unknown spacing %d", desc->spacing);
+  }
+  const double xi = 0.5 / sqrt(3.0);
+  for (int e = 0; e < ne; ++e) {
+    const double c = 0.5 * (g->edges[e] + g->edges[e + 1]);
+    const double w = g->edges[e + 1] - g->edges[e];
+    for (int k = 0; k < 2; ++k) {
+      const int i = 2 * e + k;
+      g->eps[i] = c + w * (k == 0 ? -xi : xi);
+      g->w2[i] = 0.5 * g->eps[i] * g->eps[i] * w;
+      g->w3[i] = g->w2[i] * g->eps[i];
+    }
+  }
+  *out = g;
+  return NMC_OK;
+}
+
+int nmc_grid_query(const nmc_grid* g, int* nq, double* eps, double* w2, double* w3) {
+  if (!g) return fail(NMC_E_INVALID_ARG, "grid_query: null grid");
+  if (nq) *nq = g->nq;
+  if (eps) memcpy(eps, g->eps, sizeof(double) * g->nq);
+  if (w2) memcpy(w2, g->w2, sizeof(double) * g->nq);
+  if (w3) memcpy(w3, g->w3, sizeof(double) * g->nq);
+  return NMC_OK;
+}
+
+int nmc_grid_destroy(nmc_grid* g) {
+  delete g;
+  return NMC_OK;
+}
+
+int nmc_model_create(const nmc_grid* g, const nmc_model_desc* d, nmc_model** out) {
+  if (!g || !d || !out) return fail(NMC_E_INVALID_ARG, "model_create: null argument");
+  *out = nullptr;
+  if (g->nq != 32 && g->nq != 64)
+    return fail(NMC_E_UNSUPPORTED, "model_create: the solver supports 32 or 64 energy nodes (grid has %d)", g->nq);
+  if (d->n_species < 1 || d->n_species > nmc::kMaxNs)
+    return fail(NMC_E_UNSUPPORTED, "model_create: n_species must be 1..3 (got %d)", d->n_species);
+  if (d->flags & ~NMC_ALL_PHYSICS) return fail(NMC_E_INVALID_ARG, "model_create: unknown physics flags");
+  nmc::DevModel m;
+  memset(&m, 0, sizeof(m));
+  m.ns = d->n_species;
+  m.nq = g->nq;
+  m.flags = d->flags;
+  for (int s = 0; s < m.ns; ++s) {
+    const int id = d->species[s];
+    if (id < NMC_NU_E || id > NMC_NU_X) return fail(NMC_E_INVALID_ARG, "model_create: bad species id %d", id);
+    for (int t = 0; t < s; ++t)
+      if (d->species[t] == id) return fail(NMC_E_INVALID_ARG, "model_create: species %d listed twice", id);
+    m.species[s] = id;
+    m.g[s] = id == NMC_NU_E ? 1.0 : (id == NMC_NU_E_BAR ? -1.0 : 0.0);
+    m.mult[s] = id == NMC_NU_X ? 4.0 : 1.0;
+    m.musign[s] = id == NMC_NU_E ? 1.0 : (id == NMC_NU_E_BAR ? -1.0 : 0.0);
+    m.emab[s] = id == NMC_NU_X ? 0.0 : 1.0;
+  }
+  for (int s = 0; s < m.ns; ++s) {
+    m.partner[s] = -1;
+    for (int t = 0; t < m.ns; ++t)
+      if (m.species[t] == partner_id(m.species[s])) m.partner[s] = t;
+    if ((m.flags & NMC_PAIR) && m.partner[s] < 0)
+      return fail(NMC_E_UNSUPPORTED, "model_create: pair processes need the partner of species %d", m.species[s]);
+  }
+  const double vals[] = {d->chi_ref, d->eps_ref, d->chi_power, d->sigma_ratio, d->eos_a, d->eos_b, d->mu_a,
+                         d->mu_ye0, d->mu_b, d->mu_t0, d->hc_mev_cm, d->m_u_g, d->rho11_min};
+  for (double v : vals)
+    if (!isfinite(v)) return fail(NMC_E_INVALID_ARG, "model_create: non-finite constant");
+  if (!(d->eps_ref > 0) || !(d->eos_a > 0) || !(d->mu_t0 > 0) || !(d->hc_mev_cm > 0) || !(d->m_u_g > 0))
+    return fail(NMC_E_INVALID_ARG, "model_create: eps_ref, eos_a, mu_t0, hc, m_u must be positive");
+  for (int q = 0; q < m.nq; ++q) {
+    m.eps[q] = g->eps[q];
+    m.w2[q] = g->w2[q];
+    m.w3[q] = g->w3[q];
+    m.shape[q] = pow(g->eps[q] / d->eps_ref, d->chi_power);
+  }
+  m.chi_ref = d->chi_ref;
+  m.sigma_ratio = d->sigma_ratio;
+  m.eos_a = d->eos_a;
+  m.eos_b = d->eos_b;
+  m.mu_a = d->mu_a;
+  m.mu_ye0 = d->mu_ye0;
+  m.mu_b = d->mu_b;
+  m.mu_t0 = d->mu_t0;
+  const double pi = 3.14159265358979323846;
+  const double hc = d->hc_mev_cm;
+  m.kcoup = 4.0 * pi / (hc * hc * hc) * d->m_u_g / 1.0e11;
+  m.rho11_min = d->rho11_min;
+
+  nmc_model* mm = new (std::nothrow) nmc_model();
+  if (!mm) return fail(NMC_E_INVALID_ARG, "model_create: out of host memory");
+  mm->host = m;
+  hipError_t e = hipGetDevice(&mm->device);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&mm->num_cu, hipDeviceAttributeMultiprocessorCount, mm->device);
+  if (e == hipSuccess) e = hipMalloc((void**)&mm->dev, sizeof(nmc::DevModel));
+  if (e == hipSuccess) e = hipMemcpy(mm->dev, &m, sizeof(m), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    if (mm->dev) (void)hipFree(mm->dev);
+    delete mm;
+    return hip_fail(e, "model_create");
+  }
+  *out = mm;
+  return NMC_OK;
+}
+
+int nmc_model_destroy(nmc_model* m) {
+  if (!m) return NMC_OK;
+  hipError_t e = m->dev ? hipFree(m->dev) : hipSuccess;
+  delete m;
+  return e == hipSuccess ? NMC_OK : hip_fail(e, "model_destroy");
+}
+
+size_t nmc_workspace_bytes(const nmc_model* m, int64_t P) {
+  if (!m || P < 0) return 0;
+  // queue counter + per-point adjoint terms and a column-partial buffer
+  const size_t nt = (size_t)m->host.nq + 2;
+  const size_t pp = ((size_t)P * nt * sizeof(double) + 255) & ~(size_t)255;
+  const size_t part = ((size_t)1024 * nt * sizeof(double) + 255) & ~(size_t)255;
+  return kCounterBytes + pp + part;
+}
+
+static int check_params(const nmc_solver_params* p) {
+  if (!p) return fail(NMC_E_INVALID_ARG, "null solver params");
+  if (!(p->tol_inner > 0.0) || !(p->tol_outer > 0.0) || !isfinite(p->tol_inner) || !isfinite(p->tol_outer))
+    return fail(NMC_E_INVALID_ARG, "tolerances must be positive and finite");
+  if (p->m_inner < 1 || p->m_inner > 3 || p->m_outer < 1 || p->m_outer > 3)
+    return fail(NMC_E_UNSUPPORTED, "Anderson memories must be in 1..3 (got %d, %d)", p->m_inner, p->m_outer);
+  if (p->max_inner < 1 || p->max_outer < 1 || p->max_inner > 100000 || p->max_outer > 100000)
+    return fail(NMC_E_INVALID_ARG, "iteration caps must be in 1..100000");
+  return NMC_OK;
+}
+
+int nmc_solve_batch(const nmc_model* m, const nmc_solver_params* prm, int64_t P, double dtau,
+                    const nmc_batch_in* in, const nmc_batch_out* out, void* ws, size_t ws_bytes,
+                    const nmc_launch* launch, void* stream) {
+  if (!m || !in || !out) return fail(NMC_E_INVALID_ARG, "solve_batch: null handle or descriptor");
+  int rc = check_params(prm);
+  if (rc) return rc;
+  if (P < 0 || P > (int64_t(1) << 30)) return fail(NMC_E_INVALID_ARG, "solve_batch: P out of range (%lld)", (long long)P);
+  if (!(dtau > 0.0) || !isfinite(dtau)) return fail(NMC_E_INVALID_ARG, "solve_batch: dtau must be positive");
+  if (P == 0) return NMC_OK;
+  if (!in->D0 || !in->I0 || !in->rho11 || !in->ye0 || !in->e0 || !in->theta)
+    return fail(NMC_E_INVALID_ARG, "solve_batch: null input array");
+  if (!out->D || !out->I || !out->ye || !out->e || !out->T || !out->n_outer || !out->n_inner || !out->status)
+    return fail(NMC_E_INVALID_ARG, "solve_batch: null output array");
+  if ((in->T_fixed || in->mu_fixed) && !prm->fixed_matter)
+    return fail(NMC_E_INVALID_ARG, "solve_batch: T_fixed / mu_fixed need fixed_matter");
+  nmc_launch L = {0, 1, 1};
+  if (launch) L = *launch;
+  if (L.chunk < 1 || L.chunk > 4096 || L.blocks_per_cu < 0 || L.blocks_per_cu > 64)
+    return fail(NMC_E_INVALID_ARG, "solve_batch: bad launch configuration");
+  if (L.persistent) {
+    if (!ws || !aligned256(ws) || ws_bytes < kCounterBytes)
+      return fail(NMC_E_WORKSPACE, "solve_batch: persistent launch needs a 256-byte aligned workspace");
+  }
+  nmc::FwdArgs a;
+  memset(&a, 0, sizeof(a));
+  a.mdl = m->dev;
+  a.prm.tol_inner = prm->tol_inner;
+  a.prm.tol_outer = prm->tol_outer;
+  a.prm.m_inner = prm->m_inner;
+  a.prm.m_outer = prm->m_outer;
+  a.prm.max_inner = prm->max_inner;
+  a.prm.max_outer = prm->max_outer;
+  a.prm.fixed_matter = prm->fixed_matter ? 1 : 0;
+  a.P = P;
+  a.dtau = dtau;
+  a.D0 = in->D0;
+  a.I0 = in->I0;
+  a.rho11 = in->rho11;
+  a.ye0 = in->ye0;
+  a.e0 = in->e0;
+  a.chi0 = in->chi0;
+  a.T_fixed = in->T_fixed;
+  a.mu_fixed = in->mu_fixed;
+  a.theta = in->theta;
+  a.D = out->D;
+  a.I = out->I;
+  a.ye = out->ye;
+  a.e = out->e;
+  a.T = out->T;
+  a.n_outer = out->n_outer;
+  a.n_inner = out->n_inner;
+  a.status = out->status;
+  a.chunk = L.chunk;
+  hipStream_t s = (hipStream_t)stream;
+  if (L.persistent) {
+    a.queue = (int*)ws;
+    hipError_t e = nmc::launch_reset_counter(a.queue, s);
+    if (e != hipSuccess) return hip_fail(e, "solve_batch: counter reset");
+  }
+  hipError_t e = nmc::launch_forward(a, m->host.nq, m->host.ns, L, m->num_cu, s);
+  if (e == hipErrorInvalidValue) return fail(NMC_E_UNSUPPORTED, "solve_batch: no kernel for nq=%d ns=%d", m->host.nq, m->host.ns);
+  if (e != hipSuccess) return hip_fail(e, "solve_batch: launch");
+  return NMC_OK;
+}
+
+int nmc_init_state(const nmc_model* m, int64_t P, const double* T, const double* mu, const double* rho11,
+                   const double* ye, const double* uD, const double* uI, double a, double b, double c, double* D0,
+                   double* I0, double* e0, void* stream) {
+  if (!m) return fail(NMC_E_INVALID_ARG, "init_state: null model");
+  if (P < 0 || P > (int64_t(1) << 30)) return fail(NMC_E_INVALID_ARG, "init_state: P out of range");
+  if (P == 0) return NMC_OK;
+  if (!T || !rho11 || !ye || !uD || !uI || !D0 || !I0) return fail(NMC_E_INVALID_ARG, "init_state: null array");
+  if (!isfinite(a) || !isfinite(b) || !isfinite(c)) return fail(NMC_E_INVALID_ARG, "init_state: non-finite coefficient");
+  hipError_t e = nmc::launch_init_state(m->dev, m->host.ns, m->host.nq, P, T, mu, rho11, ye, uD, uI, a, b, c, D0, I0,
+                                        e0, (hipStream_t)stream);
+  return e == hipSuccess ? NMC_OK : hip_fail(e, "init_state: launch");
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+namespace nmc {
+namespace {
+
+// one thread per (point, species, node)
+__global__ void init_state_kernel(const DevModel* __restrict__ md, int ns, int nq, int64_t P,
+                                  const double* __restrict__ T, const double* __restrict__ mu,
+                                  const double* __restrict__ rho11, const double* __restrict__ ye,
+                                  const double* __restrict__ uD, const double* __restrict__ uI, double a, double b,
+                                  double c, double* __restrict__ D0, double* __restrict__ I0, double* __restrict__ e0) {
+  const int64_t n = P * ns * nq;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t p = i / (ns * nq);
+    const int s = (int)((i / nq) % ns);
+    const int q = (int)(i % nq);
+    const double r3 = cbrt(rho11[p]);
+    const double Tp = T[p];
+    const double mup = mu ? mu[p] : md->mu_a * (ye[p] - md->mu_ye0) * r3 + md->mu_b * log(Tp / md->mu_t0);
+    const double x = (md->eps[q] - md->musign[s] * mup) / Tp;
+    const double ex = exp(-fabs(x));
+    const double f = x > 0.0 ? ex / (1.0 + ex) : 1.0 / (1.0 + ex);
+    double d = f * (a + b * uD[i]);
+    d = d < 0.0 ? 0.0 : d;
+    d = d > 1.0 - 1e-12 ? 1.0 - 1e-12 : d;
+    D0[i] = d;
+    I0[i] = c * d * uI[i];
+    if (e0 && s == 0 && q == 0) e0[p] = md->eos_a * Tp * (1.0 + ye[p]) + md->eos_b * pow(ye[p], 4.0 / 3.0) * r3;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_init_state(const DevModel* mdl, int ns, int nq, int64_t P, const double* T, const double* mu,
+                             const double* rho11, const double* ye, const double* uD, const double* uI, double a,
+                             double b, double c, double* D0, double* I0, double* e0, hipStream_t s) {
+  const int64_t n = P * ns * nq;
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(init_state_kernel, dim3((unsigned)blocks), dim3(256), 0, s, mdl, ns, nq, P, T, mu, rho11, ye,
+                     uD, uI, a, b, c, D0, I0, e0);
+  return hipGetLastError();
+}
+
+}  // namespace nmc

@@ -1,0 +1,74 @@
+// Internal declarations of the nmc library (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/nmc.h"
+
+namespace nmc {
+
+constexpr int kMaxNq = 64;
+constexpr int kMaxNs = 3;
+
+// Model table resident in device memory; every field is read with uniform
+// addresses inside the kernels, so it is served by the scalar cache.
+struct DevModel {
+  int ns, nq;
+  unsigned flags;
+  int pad0;
+  int species[kMaxNs];
+  int partner[kMaxNs];  // index of the pair partner in the species list, or -1
+  double g[kMaxNs];       // lepton number of the species
+  double mult[kMaxNs];    // energy multiplicity (4 for the heavy-lepton stand-in)
+  double musign[kMaxNs];  // chemical potential = musign * mu_nu_e
+  double emab[kMaxNs];    // 1 if the species has emission/absorption
+  double eps[kMaxNq];     // node energies [MeV]
+  double w2[kMaxNq];      // w eps^2 dEps [MeV^3]
+  double w3[kMaxNq];      // w2 eps [MeV^4]
+  double shape[kMaxNq];   // (eps / eps_ref)^chi_power
+  double chi_ref, sigma_ratio;
+  double eos_a, eos_b, mu_a, mu_ye0, mu_b, mu_t0;
+  double kcoup;           // K * rho11 [MeV^-3]
+  double rho11_min;
+};
+
+struct SolverParams {
+  double tol_inner, tol_outer;
+  int m_inner, m_outer, max_inner, max_outer, fixed_matter;
+};
+
+struct FwdArgs {
+  const DevModel* mdl;
+  SolverParams prm;
+  int64_t P;
+  double dtau;
+  const double *D0, *I0, *rho11, *ye0, *e0, *chi0, *T_fixed, *mu_fixed, *theta;
+  double *D, *I, *ye, *e, *T;
+  int32_t *n_outer, *n_inner, *status;
+  int* queue;  // work-queue counter (persistent mode) or nullptr
+  int chunk;   // points per grab
+};
+
+struct AdjArgs {
+  const DevModel* mdl;
+  int64_t P;
+  double dtau;
+  const double *rho11, *chi0, *theta;
+  const double *D, *ye, *e;
+  const int32_t *status, *n_outer;
+  const double* gbar;
+  double* grad_pp;     // (P, nq + 2) per-point terms, always written
+};
+
+// launchers (defined in the kernel translation units)
+hipError_t launch_forward(const FwdArgs& a, int nq, int ns, const nmc_launch& L, int num_cu, hipStream_t s);
+hipError_t launch_reset_counter(int* counter, hipStream_t s);
+hipError_t launch_init_state(const DevModel* mdl, int ns, int nq, int64_t P, const double* T, const double* mu,
+                             const double* rho11, const double* ye, const double* uD, const double* uI, double a,
+                             double b, double c, double* D0, double* I0, double* e0, hipStream_t s);
+hipError_t launch_adjoint(const AdjArgs& a, int nq, int ns, hipStream_t s);
+hipError_t launch_reduce_columns(const double* grad_pp, int64_t P, int ncol, double* partial, double* grad_theta,
+                                 hipStream_t s);
+
+}  // namespace nmc

@@ -1,0 +1,214 @@
+"""Python front end of the MI355X coupling solver (``libnmc.so``).
+
+Thin wrappers: shape and dtype checks plus argument marshalling.  Every step
+of the solve runs in the HIP kernels behind the C ABI of ``include/nmc.h``;
+torch provides device memory and the current stream.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+
+import torch
+
+from . import native as N
+
+DEFAULT_A_NES = 1.0e-10   # NES kernel amplitude per rho11 [1/(km MeV^5)]
+DEFAULT_A_PAIR = 1.0e-10  # pair kernel amplitude per rho11 [1/(km MeV^5)]
+
+
+def _stream_handle(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _req(t: torch.Tensor, name: str, shape, dtype=torch.float64):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must live on the GPU")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t
+
+
+class Grid:
+    """Energy grid (2 Legendre-Gauss nodes per element)."""
+
+    def __init__(self, n_elem: int = 16, eps_lo: float = 1.0, eps_hi: float = 300.0, zoom: float | None = None):
+        d = N.GridDesc(n_elem, 2, eps_lo, eps_hi, N.SPACING_ZOOM if zoom else N.SPACING_LOG, zoom or 0.0)
+        h = C.c_void_p()
+        N.check(N.lib().nmc_grid_create(C.byref(d), C.byref(h)))
+        self._h = h
+        nq = C.c_int()
+        N.check(N.lib().nmc_grid_query(h, C.byref(nq), None, None, None))
+        self.nq = nq.value
+        import numpy as np
+        eps, w2, w3 = (np.zeros(self.nq) for _ in range(3))
+        N.check(N.lib().nmc_grid_query(h, None, eps.ctypes.data_as(C.c_void_p), w2.ctypes.data_as(C.c_void_p),
+                                       w3.ctypes.data_as(C.c_void_p)))
+        self.eps, self.w2, self.w3 = eps, w2, w3
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and N._lib is not None:
+            N.lib().nmc_grid_destroy(h)
+            self._h = None
+
+
+class Model:
+    """Species set, physics flags and synthetic microphysics constants on a grid."""
+
+    def __init__(self, grid: Grid, species=(N.NU_E, N.NU_E_BAR, N.NU_X), flags: int = N.ALL_PHYSICS, **overrides):
+        d = N.ModelDesc()
+        N.lib().nmc_model_desc_default(C.byref(d))
+        d.n_species = len(species)
+        for i, s in enumerate(species):
+            d.species[i] = s
+        d.flags = flags
+        for k, v in overrides.items():
+            setattr(d, k, v)
+        h = C.c_void_p()
+        N.check(N.lib().nmc_model_create(grid._h, C.byref(d), C.byref(h)))
+        self._h = h
+        self.grid = grid
+        self.ns = len(species)
+        self.nq = grid.nq
+        self.flags = flags
+        self.desc = d
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and N._lib is not None:
+            N.lib().nmc_model_destroy(h)
+            self._h = None
+
+    def workspace_bytes(self, P: int) -> int:
+        return int(N.lib().nmc_workspace_bytes(self._h, P))
+
+    def default_theta(self, a_nes: float = DEFAULT_A_NES, a_pair: float = DEFAULT_A_PAIR, device="cuda"):
+        th = torch.ones(self.nq + 2, dtype=torch.float64, device=device)
+        th[self.nq] = a_nes
+        th[self.nq + 1] = a_pair
+        return th
+
+
+@dataclass
+class Params:
+    tol_inner: float = 1e-10
+    tol_outer: float = 1e-10
+    m_inner: int = 3
+    m_outer: int = 3
+    max_inner: int = 100
+    max_outer: int = 50
+    fixed_matter: bool = False
+
+    def c(self):
+        return N.SolverParams(self.tol_inner, self.tol_outer, self.m_inner, self.m_outer, self.max_inner,
+                              self.max_outer, int(self.fixed_matter))
+
+
+@dataclass
+class LaunchConfig:
+    blocks_per_cu: int = 0
+    chunk: int = 1
+    persistent: bool = True
+
+    def c(self):
+        return N.Launch(self.blocks_per_cu, self.chunk, int(self.persistent))
+
+
+class Workspace:
+    """Device workspace for solve calls (allocated once, reused)."""
+
+    def __init__(self, model: Model, P: int, device="cuda"):
+        nb = max(model.workspace_bytes(P), 256)
+        self.buf = torch.empty(nb + 256, dtype=torch.uint8, device=device)
+        off = (-self.buf.data_ptr()) % 256
+        self.ptr = self.buf.data_ptr() + off
+        self.nbytes = nb
+
+
+def alloc_outputs(model: Model, P: int, device="cuda"):
+    f64 = dict(dtype=torch.float64, device=device)
+    i32 = dict(dtype=torch.int32, device=device)
+    return dict(D=torch.empty(P, model.ns, model.nq, **f64), I=torch.empty(P, model.ns, model.nq, **f64),
+                ye=torch.empty(P, **f64), e=torch.empty(P, **f64), T=torch.empty(P, **f64),
+                n_outer=torch.empty(P, **i32), n_inner=torch.empty(P, **i32), status=torch.empty(P, **i32))
+
+
+def _batch_in(model, P, D0, I0, rho11, ye0, e0, theta, chi0, T_fixed, mu_fixed):
+    ns, nq = model.ns, model.nq
+    _req(D0, "D0", (P, ns, nq))
+    _req(I0, "I0", (P, ns, nq))
+    for n, t in (("rho11", rho11), ("ye0", ye0), ("e0", e0)):
+        _req(t, n, (P,))
+    _req(theta, "theta", (nq + 2,))
+    for n, t in (("chi0", chi0), ("T_fixed", T_fixed), ("mu_fixed", mu_fixed)):
+        if t is not None:
+            _req(t, n, (P,))
+    return N.BatchIn(*[None if t is None else t.data_ptr()
+                       for t in (D0, I0, rho11, ye0, e0, chi0, T_fixed, mu_fixed, theta)])
+
+
+def _batch_out(model, P, out):
+    ns, nq = model.ns, model.nq
+    _req(out["D"], "D", (P, ns, nq))
+    _req(out["I"], "I", (P, ns, nq))
+    for n in ("ye", "e", "T"):
+        _req(out[n], n, (P,))
+    for n in ("n_outer", "n_inner", "status"):
+        _req(out[n], n, (P,), torch.int32)
+    return N.BatchOut(*[out[n].data_ptr() for n in ("D", "I", "ye", "e", "T", "n_outer", "n_inner", "status")])
+
+
+def solve(model: Model, params: Params, dtau: float, D0, I0, rho11, ye0, e0, theta, chi0=None, T_fixed=None,
+          mu_fixed=None, out=None, workspace: Workspace | None = None, launch: LaunchConfig | None = None,
+          stream=None):
+    """Enqueue one batched implicit solve on the current (or given) stream.
+
+    Returns the output dict (tensors on the GPU; not synchronized)."""
+    P = D0.shape[0]
+    if out is None:
+        out = alloc_outputs(model, P, D0.device)
+    bi = _batch_in(model, P, D0, I0, rho11, ye0, e0, theta, chi0, T_fixed, mu_fixed)
+    bo = _batch_out(model, P, out)
+    launch = launch or LaunchConfig()
+    if workspace is None:
+        workspace = Workspace(model, P, D0.device)
+    pc, lc = params.c(), launch.c()
+    N.check(N.lib().nmc_solve_batch(model._h, C.byref(pc), P, float(dtau), C.byref(bi), C.byref(bo),
+                                    C.c_void_p(workspace.ptr), workspace.nbytes, C.byref(lc),
+                                    _stream_handle(stream)))
+    return out
+
+
+def init_state(model: Model, T, rho11, ye, uD, uI, a=1.0, b=0.1, c=0.1, mu=None, stream=None):
+    """Initial state on the GPU from raw draws (EOS energy, perturbed equilibrium)."""
+    P = T.shape[0]
+    ns, nq = model.ns, model.nq
+    for n, t in (("T", T), ("rho11", rho11), ("ye", ye)):
+        _req(t, n, (P,))
+    _req(uD, "uD", (P, ns, nq))
+    _req(uI, "uI", (P, ns, nq))
+    if mu is not None:
+        _req(mu, "mu", (P,))
+    D0 = torch.empty(P, ns, nq, dtype=torch.float64, device=T.device)
+    I0 = torch.empty_like(D0)
+    e0 = torch.empty(P, dtype=torch.float64, device=T.device)
+    N.check(N.lib().nmc_init_state(model._h, P, T.data_ptr(), None if mu is None else mu.data_ptr(),
+                                   rho11.data_ptr(), ye.data_ptr(), uD.data_ptr(), uI.data_ptr(), float(a),
+                                   float(b), float(c), D0.data_ptr(), I0.data_ptr(), e0.data_ptr(),
+                                   _stream_handle(stream)))
+    return D0, I0, e0
+
+
+def to_device(draws, device="cuda"):
+    """Move a workloads.Draws bundle to the GPU as float64 tensors."""
+    f = lambda x: None if x is None else torch.as_tensor(x, dtype=torch.float64, device=device).contiguous()
+    return dict(T=f(draws.T), rho11=f(draws.rho11), ye=f(draws.ye), uD=f(draws.uD), uI=f(draws.uI),
+                mu=f(draws.mu), chi0=f(draws.chi0))

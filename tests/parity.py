@@ -1,0 +1,59 @@
+"""Shared helpers of the GPU parity tests (test infrastructure)."""
+from __future__ import annotations
+
+import numpy as np
+
+import oracle as O
+from paper_2601_00976_amd import solver as S
+from paper_2601_00976_amd import workloads as W
+
+A_NES = S.DEFAULT_A_NES
+A_PAIR = S.DEFAULT_A_PAIR
+
+
+def oracle_model(ns_species, flags, n_elem=16, **ov):
+    return O.Model(n_elem=n_elem, species=tuple(ns_species), flags=flags, overrides=ov)
+
+
+def run_oracle(draws: W.Draws, species, flags, dtau, params: O.Params, theta, n_elem=16, **ov):
+    m = oracle_model(species, flags, n_elem, **ov)
+    D0, I0, e0 = m.init_state(draws.T, draws.rho11, draws.ye, draws.uD, draws.uI, draws.a, draws.b, draws.c,
+                              mu=draws.mu)
+    fixedT = params.fixed_matter and draws.mu is not None
+    r = O.solve_batch(m, params, theta, dtau, D0, I0, draws.rho11, draws.ye, e0, chi0=draws.chi0,
+                      T_fixed=draws.T if fixedT else None, mu_fixed=draws.mu if fixedT else None)
+    r["D0"], r["I0"], r["e0"] = D0, I0, e0
+    return m, r
+
+
+def run_gpu(draws: W.Draws, species, flags, dtau, params: S.Params, theta_np, n_elem=16, launch=None, **ov):
+    import torch
+    g = S.Grid(n_elem=n_elem)
+    m = S.Model(g, species=tuple(species), flags=flags, **ov)
+    t = S.to_device(draws)
+    D0, I0, e0 = S.init_state(m, t["T"], t["rho11"], t["ye"], t["uD"], t["uI"], draws.a, draws.b, draws.c,
+                              mu=t["mu"])
+    theta = torch.as_tensor(theta_np, dtype=torch.float64, device="cuda")
+    fixedT = params.fixed_matter and draws.mu is not None
+    out = S.solve(m, params, dtau, D0, I0, t["rho11"], t["ye"], e0, theta, chi0=t["chi0"],
+                  T_fixed=t["T"] if fixedT else None, mu_fixed=t["mu"] if fixedT else None, launch=launch)
+    torch.cuda.synchronize()
+    res = {k: v.cpu().numpy() for k, v in out.items()}
+    res["D0"], res["I0"], res["e0"] = D0.cpu().numpy(), I0.cpu().numpy(), e0.cpu().numpy()
+    return m, res
+
+
+def wnorm(x, w2):
+    return np.sqrt(np.sum(w2 * x * x, axis=-1))
+
+
+def parity_errors(ref, got, w2):
+    """Per point and species W-weighted relative errors of D and I (reference
+    ||D||), and relative errors of Ye and e."""
+    dref = wnorm(ref["D"], w2)
+    scale = np.where(dref > 0, dref, 1.0)
+    eD = wnorm(got["D"] - ref["D"], w2) / scale
+    eI = wnorm(got["I"] - ref["I"], w2) / scale
+    eY = np.abs(got["ye"] - ref["ye"]) / np.abs(ref["ye"])
+    eE = np.abs(got["e"] - ref["e"]) / np.abs(ref["e"])
+    return eD, eI, eY, eE
