@@ -1,0 +1,228 @@
+"""Benchmark: batched implicit neutrino-matter coupling solves on one MI355X.
+
+Workload: the synthetic supernova-like radial profile, 2^16 spatial points,
+3 species (nu_e, anti-nu_e, nu_x), 32 energy nodes (16 geometric elements x 2
+Legendre-Gauss nodes on 1-300 MeV), full physics (emission/absorption,
+isoenergetic scattering, NES and pair kernels), FP64, Anderson memory 3,
+tolerance 1e-10.  One bench step = one replay of a captured HIP graph that
+restores the initial state and runs 10 chained implicit steps (each the
+persistent work-queue kernel over all points, output feeding the next step).
+
+Metric: implicit point-solves per second (points below 1e7 g/cm^3, where the
+coupling is switched off and the state passes through, are not counted).
+The JSON line also carries the roofline of the solve kernel (FP64 vector ALU
+bound; algorithmic FLOPs per launch / kernel time from HIP events captured
+around each launch in the graph) and the CPU oracle timed on a bounded
+sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+NQ, NS, N_ELEM = 32, 3, 16
+P_POINTS = 1 << 16
+STEPS_PER_GRAPH = 10
+PEAK_FP64_TFLOPS = 78.6   # MI355X FP64 vector, published
+PEAK_HBM_GBS = 8000.0
+
+
+def flops_per_point(n_inner, n_outer, nq=NQ, ns=NS):
+    """Algorithmic FLOPs of one point-solve (FMA = 2): per inner iteration the
+    four energy-coupling mat-vecs of every species (8 ns nq^2) and pointwise
+    plus Anderson work (40 ns nq); per outer iteration the kernel build and
+    matter update (4 nq^2 + 30 ns nq)."""
+    return n_inner * (8 * ns * nq * nq + 40 * ns * nq) + n_outer * (4 * nq * nq + 30 * ns * nq)
+
+
+def bytes_per_point(nq=NQ, ns=NS):
+    """Algorithmic HBM bytes of one point-solve: read D*, I* and 5 scalars,
+    write D, I, 3 scalars and 3 int32 counters."""
+    return 2 * ns * nq * 8 + 5 * 8 + 2 * ns * nq * 8 + 3 * 8 + 3 * 4
+
+
+def cpu_baseline(repeats: int, threads: int):
+    """The oracle (as it stands) on the same workload: the 10-step chain over
+    all 2^16 profile points, repeated `repeats` times from the initial state."""
+    import numpy as np
+
+    import oracle as O
+    from paper_2601_00976_amd import solver as S
+    from paper_2601_00976_amd import workloads as W
+
+    O.build(force=False)
+    d = W.radial_profile(P=P_POINTS)
+    m = O.Model(n_elem=N_ELEM)
+    theta = m.default_theta(S.DEFAULT_A_NES, S.DEFAULT_A_PAIR)
+    D0, I0, e0 = m.init_state(d.T, d.rho11, d.ye, d.uD, d.uI)
+    solved = 0
+    t0 = time.perf_counter()
+    for _ in range(repeats):
+        D, I, ye, e = D0, I0, d.ye.copy(), e0
+        for _ in range(STEPS_PER_GRAPH):
+            r = O.solve_batch(m, O.Params(), theta, W.DTAU_KM, D, I, d.rho11, ye, e, nthreads=threads)
+            D, I, ye, e = r["D"], r["I"], r["ye"], r["e"]
+            solved += int(np.sum(r["n_outer"] > 0))
+    dt = time.perf_counter() - t0
+    return dict(value=solved / dt, unit="point-solves/s", cores=threads, kind="oracle",
+                sample=f"all {P_POINTS} profile points, {STEPS_PER_GRAPH} chained steps x {repeats}, "
+                       f"{solved} solves in {dt:.1f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--cpu-repeats", type=int, default=3, help="repeats of the 10-step chain in the oracle baseline")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
+    ap.add_argument("--chunk", type=int, default=None)
+    ap.add_argument("--blocks-per-cu", type=int, default=None)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: the per-point solve needs no communication, and this "
+              "build measures the single-GPU kernel (see the sharding notes in DESIGN.md).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2601_00976_amd import autotune as AT
+    from paper_2601_00976_amd import solver as S
+    from paper_2601_00976_amd import workloads as W
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+
+    grid = S.Grid(N_ELEM)
+    model = S.Model(grid)
+    params = S.Params()
+    draws = W.radial_profile(P=P_POINTS)
+    t = S.to_device(draws, dev)
+    D0, I0, e0 = S.init_state(model, t["T"], t["rho11"], t["ye"], t["uD"], t["uI"])
+    theta = model.default_theta()
+    launch = AT.best_launch(model, P_POINTS)
+    if args.chunk is not None:
+        launch.chunk = args.chunk
+    if args.blocks_per_cu is not None:
+        launch.blocks_per_cu = args.blocks_per_cu
+
+    # working state (solved in place step after step) and per-step counters
+    work = dict(D=D0.clone(), I=I0.clone(), ye=t["ye"].clone(), e=e0.clone())
+    outs = [S.alloc_outputs(model, P_POINTS, dev) for _ in range(STEPS_PER_GRAPH)]
+    for o in outs:
+        o["D"], o["I"], o["ye"], o["e"] = work["D"], work["I"], work["ye"], work["e"]
+    ws = S.Workspace(model, P_POINTS, dev)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(STEPS_PER_GRAPH)]
+
+    def one_pass(record=False):
+        work["D"].copy_(D0)
+        work["I"].copy_(I0)
+        work["ye"].copy_(t["ye"])
+        work["e"].copy_(e0)
+        for i in range(STEPS_PER_GRAPH):
+            if record:
+                ev[i][0].record()
+            S.solve(model, params, W.DTAU_KM, work["D"], work["I"], t["rho11"], work["ye"], work["e"], theta,
+                    out=outs[i], workspace=ws, launch=launch)
+            if record:
+                ev[i][1].record()
+
+    # eager warm-up (also caches the occupancy query outside capture)
+    one_pass()
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        one_pass()
+    for _ in range(args.warmup):
+        g.replay()
+    torch.cuda.synchronize()
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        g.replay()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_per_step = 1e3 * wall / args.steps
+
+    # solve-kernel duration: HIP events around every launch of the same
+    # 10-step chain, run eagerly on the launch stream (events recorded inside
+    # a captured graph are not timeable on ROCm)
+    kern_ms = 0.0
+    n_timed = max(2, min(args.steps, 5))
+    for _ in range(n_timed):
+        one_pass(record=True)
+        torch.cuda.synchronize()
+        kern_ms += sum(a.elapsed_time(b) for a, b in ev)
+
+    # accounting from the (deterministic) per-step iteration counts
+    n_in = np.stack([o["n_inner"].cpu().numpy() for o in outs]).astype(np.float64)
+    n_out = np.stack([o["n_outer"].cpu().numpy() for o in outs]).astype(np.float64)
+    status = np.stack([o["status"].cpu().numpy() for o in outs])
+    solved = int(np.sum(n_out > 0))
+    flops = float(np.sum(flops_per_point(n_in, n_out)))
+    value = solved / (ms_per_step * 1e-3)
+    kern_s_per_launch = kern_ms * 1e-3 / (n_timed * STEPS_PER_GRAPH)
+    flops_per_launch = flops / STEPS_PER_GRAPH
+    achieved = flops_per_launch / kern_s_per_launch / 1e12
+    hbm_bytes_per_launch = bytes_per_point() * P_POINTS
+    traffic = AT.stored_traffic("fwd_kernel_nq32_ns3")
+
+    line = {
+        "metric": "implicit point-solves/sec at 32 energy nodes, 3 species (FP64)",
+        "value": value,
+        "unit": "point-solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "radial-profile, 2^16 points, 3 species, 32 energy nodes, full physics, "
+                        "10 chained implicit steps per captured graph",
+            "points": P_POINTS, "solved_point_steps_per_step": solved, "species": NS, "energy_nodes": NQ,
+            "implicit_steps_per_step": STEPS_PER_GRAPH, "dtau_km": W.DTAU_KM, "tol": params.tol_inner,
+            "anderson_memory": params.m_inner, "launch": {"chunk": launch.chunk,
+                                                          "blocks_per_cu": launch.blocks_per_cu,
+                                                          "persistent": launch.persistent},
+            "iterations": {"inner_min": int(n_in[n_out > 0].min()), "inner_median": float(np.median(n_in[n_out > 0])),
+                           "inner_max": int(n_in.max()), "outer_max": int(n_out.max())},
+            "status_counts": np.bincount(status.ravel(), minlength=5).tolist(),
+        },
+        "roofline": {
+            "kernel": "fwd_kernel<3,32> (persistent point solve)",
+            "bound": "alu",
+            "achieved": achieved,
+            "peak": PEAK_FP64_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP64_TFLOPS,
+            "traffic": traffic,
+            "kernel_ms_per_launch": kern_s_per_launch * 1e3,
+            "flops_per_launch": flops_per_launch,
+            "algorithmic_hbm_gbs": hbm_bytes_per_launch / kern_s_per_launch / 1e9,
+        },
+    }
+    adj = AT.adjoint_ratio(model, params, theta, D0, I0, t, e0, ws) if hasattr(AT, "adjoint_ratio") else None
+    if adj is not None:
+        line["adjoint_forward_ratio"] = adj
+    if not args.no_cpu:
+        threads = int(os.environ.get("OMP_NUM_THREADS") or os.cpu_count() or 1)
+        line["cpu_baseline"] = cpu_baseline(args.cpu_repeats, threads)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,103 @@
+"""Launch-shape autotuner for the persistent solve kernel.
+
+The knobs are the points taken per work-queue grab (`chunk`), the resident
+work-groups per compute unit of the persistent grid (`blocks_per_cu`, 0 =
+occupancy limit) and persistent versus one-work-group-per-chunk launches.
+`tune()` times candidate shapes on a real batch and stores the winner in a
+JSON cache next to this file, keyed by (energy nodes, species, device name);
+`best_launch()` reads the cache and falls back to the persistent default.
+"""
+from __future__ import annotations
+
+import glob
+import hashlib
+import json
+import os
+import re
+
+from . import solver as S
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CACHE = os.path.join(HERE, "autotune_cache.json")
+ROOT = os.path.dirname(HERE)
+
+
+def _key(model) -> str:
+    import torch
+    name = torch.cuda.get_device_name(0) if torch.cuda.is_available() else "cpu"
+    return f"nq{model.nq}-ns{model.ns}-{name}"
+
+
+def _load():
+    if os.path.exists(CACHE):
+        with open(CACHE) as f:
+            return json.load(f)
+    return {}
+
+
+def best_launch(model, P: int) -> S.LaunchConfig:
+    ent = _load().get(_key(model))
+    if ent:
+        return S.LaunchConfig(**ent["launch"])
+    return S.LaunchConfig(blocks_per_cu=0, chunk=1, persistent=True)
+
+
+def candidates():
+    for persistent in (True, False):
+        for chunk in (1, 2, 4):
+            for bpc in ((0, 4, 6) if persistent else (0,)):
+                yield S.LaunchConfig(blocks_per_cu=bpc, chunk=chunk, persistent=persistent)
+
+
+def tune(model, params, dtau, D0, I0, rho11, ye0, e0, theta, repeats: int = 3, write: bool = True):
+    """Time every candidate launch shape on the given batch (outputs are
+    bitwise identical across shapes) and cache the fastest."""
+    import torch
+    P = D0.shape[0]
+    ws = S.Workspace(model, P, D0.device)
+    out = S.alloc_outputs(model, P, D0.device)
+    results = []
+    for L in candidates():
+        S.solve(model, params, dtau, D0, I0, rho11, ye0, e0, theta, out=out, workspace=ws, launch=L)
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(repeats):
+            S.solve(model, params, dtau, D0, I0, rho11, ye0, e0, theta, out=out, workspace=ws, launch=L)
+        b.record()
+        torch.cuda.synchronize()
+        results.append((a.elapsed_time(b) / repeats, L))
+    results.sort(key=lambda r: r[0])
+    best = results[0][1]
+    if write:
+        cache = _load()
+        cache[_key(model)] = {"launch": {"blocks_per_cu": best.blocks_per_cu, "chunk": best.chunk,
+                                         "persistent": bool(best.persistent)},
+                              "ms": results[0][0], "P": P}
+        with open(CACHE, "w") as f:
+            json.dump(cache, f, indent=1, sort_keys=True)
+    return results
+
+
+def kernel_source_hash() -> str:
+    """Hash of the HIP sources, used to tell whether stored counter
+    measurements still describe the current kernels."""
+    h = hashlib.sha256()
+    for p in sorted(glob.glob(os.path.join(HERE, "csrc", "*"))):
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def stored_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed counter summary,
+    or None when the summary is missing or was taken on other sources."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}.txt")
+    if not os.path.exists(path):
+        return None
+    txt = open(path).read()
+    m_hash = re.search(r"^source_hash:\s*(\S+)", txt, re.M)
+    m_val = re.search(r"^hbm_bytes_per_launch:\s*([0-9.eE+-]+)", txt, re.M)
+    if not m_hash or not m_val or m_hash.group(1) != kernel_source_hash():
+        return None
+    return float(m_val.group(1))

@@ -609,8 +609,13 @@ hipError_t launch_fwd_t(const FwdArgs& a, const nmc_launch& L, int num_cu, hipSt
   if (a.queue) {
     int bpc = L.blocks_per_cu;
     if (bpc <= 0) {
-      int occ = 0;
-      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, kLanes, 0) != hipSuccess || occ <= 0) occ = 8;
+      // occupancy of this kernel variant, queried once per process
+      static int occ = 0;
+      if (occ <= 0) {
+        int o = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, kern, kLanes, 0) != hipSuccess || o <= 0) o = 8;
+        occ = o;
+      }
       bpc = occ;
     }
     grid = (int64_t)bpc * num_cu;
