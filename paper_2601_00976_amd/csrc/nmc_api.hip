@@ -302,6 +302,7 @@ int nmc_solve_batch(const nmc_model* m, const nmc_solver_params* prm, int64_t P,
   a.prm.max_inner = prm->max_inner;
   a.prm.max_outer = prm->max_outer;
   a.prm.fixed_matter = prm->fixed_matter ? 1 : 0;
+  a.tol_inner2 = prm->tol_inner * prm->tol_inner;
   a.P = P;
   a.dtau = dtau;
   a.D0 = in->D0;
@@ -328,7 +329,8 @@ int nmc_solve_batch(const nmc_model* m, const nmc_solver_params* prm, int64_t P,
     hipError_t e = nmc::launch_reset_counter(a.queue, s);
     if (e != hipSuccess) return hip_fail(e, "solve_batch: counter reset");
   }
-  hipError_t e = nmc::launch_forward(a, m->host.nq, m->host.ns, L, m->num_cu, s);
+  const bool coupled = (m->host.flags & (NMC_NES | NMC_PAIR)) != 0;
+  hipError_t e = nmc::launch_forward(a, m->host.nq, m->host.ns, coupled, L, m->num_cu, s);
   if (e == hipErrorInvalidValue) return fail(NMC_E_UNSUPPORTED, "solve_batch: no kernel for nq=%d ns=%d", m->host.nq, m->host.ns);
   if (e != hipSuccess) return hip_fail(e, "solve_batch: launch");
   return NMC_OK;

@@ -80,7 +80,10 @@ __device__ __forceinline__ double sum_halves(double v) {
 }
 
 // Per-half sums of V lane values through LDS: s0[k] = sum over lanes 0..31,
-// s1[k] = sum over lanes 32..63.  Fixed summation order (deterministic).
+// s1[k] = sum over lanes 32..63.  Four lanes share each of the 2V sums; lane
+// r of a group adds the entries r, r + 4, ..., r + 28 of its half, starting
+// at a group-dependent rotation so that the 16 lanes of every LDS access
+// cycle hit 16 different banks.  Fixed summation order (deterministic).
 template <int V>
 __device__ __forceinline__ void half_sums(const double (&v)[V], double (&s0)[V], double (&s1)[V], double* red,
                                           double* redout) {
@@ -94,8 +97,12 @@ __device__ __forceinline__ void half_sums(const double (&v)[V], double (&s0)[V],
   double acc = 0.0;
   if (sidx < 2 * V) {
     const int hh = sidx / V, k = sidx - hh * V;
-    const double* b = red + k * kLanes + hh * 32 + r * 8;
-    acc = ((b[0] + b[1]) + (b[2] + b[3])) + ((b[4] + b[5]) + (b[6] + b[7]));
+    const double* b = red + k * kLanes + hh * 32;
+    const int rot = sidx & 3;
+    double part[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) part[i] = b[(r + 4 * ((i + rot) & 7)) & 31];
+    acc = ((part[0] + part[1]) + (part[2] + part[3])) + ((part[4] + part[5]) + (part[6] + part[7]));
   }
   acc += dpp<0xB1>(acc);  // quad_perm [1,0,3,2]
   acc += dpp<0x4E>(acc);  // quad_perm [2,3,0,1]
@@ -108,23 +115,252 @@ __device__ __forceinline__ void half_sums(const double (&v)[V], double (&s0)[V],
   }
 }
 
+// Register-only reductions (no LDS round trip).  Within a 16-lane row the
+// butterfly xor 1, xor 2 (quad_perm), half-row mirror and row mirror leaves
+// the row total in every lane, bitwise identical across the row.
+__device__ __forceinline__ double row_allsum(double v) {
+  v += dpp<0xB1>(v);   // quad_perm [1,0,3,2]
+  v += dpp<0x4E>(v);   // quad_perm [2,3,0,1]
+  v += dpp<0x141>(v);  // row_half_mirror
+  v += dpp<0x140>(v);  // row_mirror
+  return v;
+}
+
+// a from lanes 0..31 and b from lanes 32..63 halved into one register:
+// lanes 0..31 get a(l) + a(l + 32), lanes 32..63 get b(l - 32) + b(l)
+__device__ __forceinline__ double halve32(double a, double b) {
+  auto x = __builtin_amdgcn_permlane32_swap(lo32(a), lo32(b), false, false);
+  auto y = __builtin_amdgcn_permlane32_swap(hi32(a), hi32(b), false, false);
+  return mk64(x[0], y[0]) + mk64(x[1], y[1]);
+}
+
+// rows (0, 2) keep a summed with the partner row, rows (1, 3) keep b
+__device__ __forceinline__ double halve16(double a, double b) {
+  auto x = __builtin_amdgcn_permlane16_swap(lo32(a), lo32(b), false, false);
+  auto y = __builtin_amdgcn_permlane16_swap(hi32(a), hi32(b), false, false);
+  return mk64(x[0], y[0]) + mk64(x[1], y[1]);
+}
+
+// Sums of 4 values over all 64 lanes, returned in every lane.
+__device__ __forceinline__ void wave_sums4(const double (&v)[4], double (&out)[4]) {
+  // lanes 0..31: (v0, v1) over the wave halves; lanes 32..63: (v2, v3)
+  const double h01 = halve32(v[0], v[2]);
+  const double h23 = halve32(v[1], v[3]);
+  // row r now carries slot r summed over 4 lanes per column
+  const double r = row_allsum(halve16(h01, h23));
+  // rows (0,0,2,2) and (1,1,3,3), then both halves
+  double f, sc;
+  swap16(r, f, sc);
+  double f0, f1, s0, s1;
+  swap32(f, f0, f1);
+  swap32(sc, s0, s1);
+  out[0] = f0;
+  out[1] = s0;
+  out[2] = f1;
+  out[3] = s1;
+}
+
+// Per-half sums of 2 K values (K = 1..3): s0 over lanes 0..31, s1 over lanes
+// 32..63, returned in every lane.
+template <int K>
+__device__ __forceinline__ void half_sums_reg(const double (&v)[2 * K], double (&s0)[2 * K], double (&s1)[2 * K]) {
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    // rows (0, 2): slot k over the row pair; rows (1, 3): slot K + k
+    const double r = row_allsum(halve16(v[k], v[K + k]));
+    double f, sc;
+    swap16(r, f, sc);  // f: slot k of this half, sc: slot K + k
+    double a0, a1, b0, b1;
+    swap32(f, a0, a1);
+    swap32(sc, b0, b1);
+    s0[k] = a0;
+    s1[k] = a1;
+    s0[K + k] = b0;
+    s1[K + k] = b1;
+  }
+}
+
 __device__ __forceinline__ bool wave_any(bool b) { return __builtin_amdgcn_ballot_w64(b) != 0; }
 
-// Per-wave LDS scratch of the point solver.
+// Opaque copies: values derived from these are recomputed where they are
+// used instead of being hoisted out of the outer loop (hoisted invariants
+// end up spilled, which costs far more than recomputing them).
+__device__ __forceinline__ int opaque(int x) {
+  asm volatile("" : "+v"(x));
+  return x;
+}
+template <class T>
+__device__ __forceinline__ const T* opaque_ptr(const T* p) {
+  asm volatile("" : "+s"(p));
+  return p;
+}
+
+// Four columns of the contraction for every species and both matrices in one
+// asm block: acc1[t] += bcast(x[t], L0 + jj) * m1[jj], acc2[t] += bcast(x[t], L0 + jj) * m2[jj].
+// The leading s_nop 1 provides the two wait states a DPP source needs after
+// a VALU write, whatever the compiler schedules before the block.
 template <int NS>
-struct WaveLds {
-  double mst[NS][kLanes];     // owned moment of the old state (D* or I*)
-  double hist[4][NS][kLanes];  // Anderson history: Q_prev, F_prev, dQ_old, dF_old
-  double red[2 * NS * kLanes];  // reduction staging
-  double redout[16];
+struct Fmac4;
+
+template <>
+struct Fmac4<1> {
+  template <int L0>
+  __device__ __forceinline__ static void run(double (&a1)[1], double (&a2)[1], const double (&x)[1], double m10,
+                                             double m11, double m12, double m13, double m20, double m21, double m22,
+                                             double m23) {
+    asm volatile(
+        "s_nop 1\n"
+        "v_fmac_f64_dpp %0, %2, %3 row_newbcast:%11 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %1, %2, %7 row_newbcast:%11 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %0, %2, %4 row_newbcast:%12 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %1, %2, %8 row_newbcast:%12 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %0, %2, %5 row_newbcast:%13 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %1, %2, %9 row_newbcast:%13 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %0, %2, %6 row_newbcast:%14 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %1, %2, %10 row_newbcast:%14 row_mask:0xf bank_mask:0xf\n"
+        : "+v"(a1[0]), "+v"(a2[0])
+        : "v"(x[0]), "v"(m10), "v"(m11), "v"(m12), "v"(m13), "v"(m20), "v"(m21), "v"(m22), "v"(m23), "i"(L0),
+          "i"(L0 + 1), "i"(L0 + 2), "i"(L0 + 3));
+  }
 };
 
-template <int NS, int NQ>
+template <>
+struct Fmac4<2> {
+  template <int L0>
+  __device__ __forceinline__ static void run(double (&a1)[2], double (&a2)[2], const double (&x)[2], double m10,
+                                             double m11, double m12, double m13, double m20, double m21, double m22,
+                                             double m23) {
+    asm volatile(
+        "s_nop 1\n"
+        "v_fmac_f64_dpp %0, %4, %6 row_newbcast:%14 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %1, %5, %6 row_newbcast:%14 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %2, %4, %10 row_newbcast:%14 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %3, %5, %10 row_newbcast:%14 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %0, %4, %7 row_newbcast:%15 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %1, %5, %7 row_newbcast:%15 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %2, %4, %11 row_newbcast:%15 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %3, %5, %11 row_newbcast:%15 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %0, %4, %8 row_newbcast:%16 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %1, %5, %8 row_newbcast:%16 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %2, %4, %12 row_newbcast:%16 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %3, %5, %12 row_newbcast:%16 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %0, %4, %9 row_newbcast:%17 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %1, %5, %9 row_newbcast:%17 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %2, %4, %13 row_newbcast:%17 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %3, %5, %13 row_newbcast:%17 row_mask:0xf bank_mask:0xf\n"
+        : "+v"(a1[0]), "+v"(a1[1]), "+v"(a2[0]), "+v"(a2[1])
+        : "v"(x[0]), "v"(x[1]), "v"(m10), "v"(m11), "v"(m12), "v"(m13), "v"(m20), "v"(m21), "v"(m22), "v"(m23),
+          "i"(L0), "i"(L0 + 1), "i"(L0 + 2), "i"(L0 + 3));
+  }
+};
+
+template <>
+struct Fmac4<3> {
+  template <int L0>
+  __device__ __forceinline__ static void run(double (&a1)[3], double (&a2)[3], const double (&x)[3], double m10,
+                                             double m11, double m12, double m13, double m20, double m21, double m22,
+                                             double m23) {
+    asm volatile(
+        "s_nop 1\n"
+        "v_fmac_f64_dpp %0, %6, %9 row_newbcast:%17 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %1, %7, %9 row_newbcast:%17 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %2, %8, %9 row_newbcast:%17 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %3, %6, %13 row_newbcast:%17 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %4, %7, %13 row_newbcast:%17 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %5, %8, %13 row_newbcast:%17 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %0, %6, %10 row_newbcast:%18 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %1, %7, %10 row_newbcast:%18 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %2, %8, %10 row_newbcast:%18 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %3, %6, %14 row_newbcast:%18 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %4, %7, %14 row_newbcast:%18 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %5, %8, %14 row_newbcast:%18 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %0, %6, %11 row_newbcast:%19 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %1, %7, %11 row_newbcast:%19 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %2, %8, %11 row_newbcast:%19 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %3, %6, %15 row_newbcast:%19 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %4, %7, %15 row_newbcast:%19 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %5, %8, %15 row_newbcast:%19 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %0, %6, %12 row_newbcast:%20 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %1, %7, %12 row_newbcast:%20 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %2, %8, %12 row_newbcast:%20 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %3, %6, %16 row_newbcast:%20 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %4, %7, %16 row_newbcast:%20 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %5, %8, %16 row_newbcast:%20 row_mask:0xf bank_mask:0xf\n"
+        : "+v"(a1[0]), "+v"(a1[1]), "+v"(a1[2]), "+v"(a2[0]), "+v"(a2[1]), "+v"(a2[2])
+        : "v"(x[0]), "v"(x[1]), "v"(x[2]), "v"(m10), "v"(m11), "v"(m12), "v"(m13), "v"(m20), "v"(m21), "v"(m22),
+          "v"(m23), "i"(L0), "i"(L0 + 1), "i"(L0 + 2), "i"(L0 + 3));
+  }
+};
+
+// reciprocal of x >= 1 (finite): hardware estimate refined by two Newton steps
+__device__ __forceinline__ double rcp_ge1(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = __builtin_fma(-x, r, 1.0);
+  r = __builtin_fma(r, e, r);
+  e = __builtin_fma(-x, r, 1.0);
+  return __builtin_fma(r, e, r);
+}
+
+// Per-wave LDS scratch of the point solver: per-lane arrays, reduction
+// staging, and the uniform per-point state of the outer (matter) loop, kept
+// here so that it does not occupy VGPRs across the inner loop.
+// Per-node model tables copied into LDS once per work-group (lane-indexed
+// reads of them are then LDS hits); the uniform scalars of the model stay in
+// the global table, where the scalar cache serves them.
+struct ModelLds {
+  double eps[32], w2[32], w3[32], shape[32];
+  double theta[34];  // per-node EmAb scales, a_nes, a_pair
+};
+
+__device__ __forceinline__ void load_model(const DevModel* __restrict__ md, const double* __restrict__ theta,
+                                           ModelLds& m) {
+  const int l = threadIdx.x;
+  if (l < 32) {
+    m.eps[l] = md->eps[l];
+    m.w2[l] = md->w2[l];
+    m.w3[l] = md->w3[l];
+    m.shape[l] = md->shape[l];
+  }
+  if (l < 34) m.theta[l] = theta[l];
+  __syncthreads();
+}
+
+template <int NS>
+struct WaveLds {
+  static constexpr int kStride = 33;  // padded row stride of the 32 x 32 build tile
+  ModelLds m;
+  double mst[NS][kLanes];   // owned moment of the old state (D* or I*)
+  double base[NS][kLanes];  // D* + dtau chi^EmAb D_eq (number lanes) or I* (flux lanes)
+  double den0[NS][kLanes];  // 1 + dtau chi^EmAb (number lanes) or 1 + dtau (chi^EmAb + sigma^Iso)
+  union {
+    struct {
+      double hist[4][NS][kLanes];   // Anderson history: Q_prev, F_prev, dQ_old, dF_old
+      double red[2 * NS * kLanes];  // reduction staging
+      double redout[16];
+    } it;                       // live during an inner loop
+    double tile[32 * kStride];  // kernel-row assembly, live while building
+  } u;
+  // per-node factors of the current temperature (kernel build)
+  double P2[32], R2[32], G[32];
+  int n2[32];
+  // uniform per-point state
+  double dref[NS];                      // ||D_s^[k,1]||_W^2 of the current inner loop
+  double y[2];                          // matter iterate (Ye, e)
+  double oq[2], of[2], odq[2], odf[2];  // outer Anderson history
+  double T_last, r3, K, An, Ap;
+};
+
+__device__ __forceinline__ double ye43(double ye) { return ye * cbrt(ye); }
+
+template <int NS, int NQ, bool COUPLED>
 struct PointSolver {
   static_assert(NQ == 32, "lane layout is for 32 energy nodes");
 
   // Energy-coupling contraction: a1[t] = sum_j M1[j] X_t[j], a2[t] = sum_j M2[j] X_t[j]
-  // where X_t = W D_t on number lanes and W (1 - D_t) on flux lanes.
+  // where X_t = W D_t on number lanes and W (1 - D_t) on flux lanes.  Column
+  // j of the vector lives in lane (j mod 16) of every 16-lane row of
+  // XR[t][j / 16]; v_fmac_f64_dpp with row_newbcast broadcasts it into the
+  // FMA, so no separate move is issued.
   __device__ __forceinline__ static void contract(const double (&M1)[NQ], const double (&M2)[NQ],
                                                   const double (&XR)[NS][2], double (&a1)[NS], double (&a2)[NS]) {
 #pragma unroll
@@ -132,66 +368,128 @@ struct PointSolver {
       a1[t] = 0.0;
       a2[t] = 0.0;
     }
-    static_for<0, 2>([&](auto c) {
-      static_for<0, 16>([&](auto i) {
-        constexpr int C = decltype(c)::value, I = decltype(i)::value, j = 16 * C + I;
+    asm volatile("s_nop 4" ::);  // DPP after a possible EXEC write
+    static_for<0, NQ / 4>([&](auto bb) {
+      constexpr int B = decltype(bb)::value, C = (4 * B) / 16, L0 = (4 * B) % 16, j = 4 * B;
+      double x[NS];
 #pragma unroll
-        for (int t = 0; t < NS; ++t) {
-          const double b = row_bcast<I>(XR[t][C]);
-          a1[t] = __builtin_fma(M1[j], b, a1[t]);
-          a2[t] = __builtin_fma(M2[j], b, a2[t]);
-        }
-      });
+      for (int t = 0; t < NS; ++t) x[t] = XR[t][C];
+      Fmac4<NS>::template run<L0>(a1, a2, x, M1[j], M1[j + 1], M1[j + 2], M1[j + 3], M2[j], M2[j + 1], M2[j + 2],
+                                  M2[j + 3]);
     });
   }
 
   // Kernel rows at temperature T (Eqs. nesRatesNodal, pairRatesNodal with the
   // kernels of Eqs. inOutInvarianceNES ... detailedBalancePair).  With
-  // a = exp(-|e_q - e_j| / (2T)) and G_x = exp(-2 e_x / T):
-  //   Phi_in  = A e_q e_j (a^3 if e_q > e_j else a),  Phi_out = A e_q e_j (a if e_q > e_j else a^3),
-  //   Phi_ann = A' e_q e_j a^2,                       Phi_pro = A' e_q e_j G_max(q,j).
-  // Every factor is <= 1, so nothing overflows at low temperature.
-  __device__ __forceinline__ static void build_rows(int h, double epsq, double invT, double An, double Ap,
+  // b = exp(-(e_hi - e_lo) / (2T)) for e_hi >= e_lo and G_x = exp(-2 e_x / T):
+  //   Phi_in[hi][lo] = A e e' b^3,  Phi_in[lo][hi] = A e e' b,  Phi_out = Phi_in^T,
+  //   Phi_ann = A' e e' b^2,  Phi_pro = A' e e' G_hi  (both symmetric).
+  // b is assembled from per-node exponent splits x = e log2(e) / (2T) =
+  // n + f, P = 2^f, R = 2^-f:  b = ldexp(P_lo R_hi, n_lo - n_hi), so every
+  // factor stays <= 1 and nothing overflows at low temperature.  The 528
+  // unordered node pairs are spread over the 64 lanes by the model's pair
+  // schedule and written into a padded LDS tile, three times: Phi_in
+  // (number lanes load row q, flux lanes column q = row q of Phi_out),
+  // Phi_ann (number lanes load row q), Phi_pro (flux lanes load row q).
+  __device__ __forceinline__ static void build_rows(int h, int q, double invT, double An, double Ap, WaveLds<NS>& S,
                                                     double (&M1)[NQ], double (&M2)[NQ]) {
-    double ER[2], GR[2];
-    swap16(epsq, ER[0], ER[1]);
-    const double Gq = exp(-2.0 * epsq * invT);
-    swap16(Gq, GR[0], GR[1]);
-    const double hinv = 0.5 * invT;
-    static_for<0, 2>([&](auto c) {
-      static_for<0, 16>([&](auto i) {
-        constexpr int C = decltype(c)::value, I = decltype(i)::value, j = 16 * C + I;
-        const double ej = row_bcast<I>(ER[C]);
-        const double Gj = row_bcast<I>(GR[C]);
-        const double dl = epsq - ej;
-        const double av = exp(-fabs(dl) * hinv);
-        const double a2 = av * av;
-        const double a3 = a2 * av;
-        const double ee = epsq * ej;
-        const bool above = dl > 0.0;
-        M1[j] = An * ee * ((above != (h != 0)) ? a3 : av);
-        M2[j] = Ap * ee * (h ? (above ? Gq : Gj) : a2);
-      });
-    });
+    constexpr int ST = WaveLds<NS>::kStride;
+    const int lane = threadIdx.x;
+    const ModelLds& m = S.m;
+    if (lane < 32) {
+      const double e = m.eps[lane];
+      const double x = e * (0.5 * invT) * 1.4426950408889634;  // log2(e)
+      const double n = floor(x);
+      const double P = exp2(x - n);
+      S.P2[lane] = P;
+      S.R2[lane] = rcp_ge1(P);
+      S.n2[lane] = (int)n;
+      S.G[lane] = exp(-2.0 * e * invT);
+    }
+    double* T0 = S.u.tile;
+    __syncthreads();
+    // pair slot i of lane (h, q): nodes (q, q + d mod 32), d = h + 2 i; the
+    // d = 16 pairs are taken by q < 16 only, so every unordered pair
+    // (diagonal included) is written exactly once
+    constexpr int kSlots = 9;
+    // b = exp(-(eps_hi - eps_lo) / (2T)) of a node pair, from the split exponentials
+    auto half_boltz = [&](int lo, int hi) { return ldexp(S.P2[lo] * S.R2[hi], S.n2[lo] - S.n2[hi]); };
+    // pass 1: Phi_in
+#pragma unroll
+    for (int i = 0; i < kSlots; ++i) {
+      const int d = h + 2 * i;
+      const int j = (q + d) & 31;
+      const int lo = q < j ? q : j, hi = q < j ? j : q;
+      if (d < 16 || (d == 16 && q < 16)) {
+        const double b = half_boltz(lo, hi);
+        const double ee = An * (m.eps[lo] * m.eps[hi]);
+        T0[hi * ST + lo] = ee * (b * b * b);
+        T0[lo * ST + hi] = ee * b;
+      }
+    }
+    __syncthreads();
+    {
+      // number lanes: row q; flux lanes: column q
+      const int step = h ? ST : 1;
+      const double* p = T0 + (h ? q : q * ST);
+#pragma unroll
+      for (int j = 0; j < NQ; ++j) M1[j] = p[j * step];
+    }
+    __syncthreads();
+    // pass 2: Phi_ann
+#pragma unroll
+    for (int i = 0; i < kSlots; ++i) {
+      const int d = h + 2 * i;
+      const int j = (q + d) & 31;
+      const int lo = q < j ? q : j, hi = q < j ? j : q;
+      if (d < 16 || (d == 16 && q < 16)) {
+        const double b = half_boltz(lo, hi);
+        const double ann = Ap * (m.eps[lo] * m.eps[hi]) * (b * b);
+        T0[hi * ST + lo] = ann;
+        T0[lo * ST + hi] = ann;
+      }
+    }
+    __syncthreads();
+    if (h == 0) {
+      const double* p = T0 + q * ST;
+#pragma unroll
+      for (int j = 0; j < NQ; ++j) M2[j] = p[j];
+    }
+    __syncthreads();
+    // pass 3: Phi_pro
+#pragma unroll
+    for (int i = 0; i < kSlots; ++i) {
+      const int d = h + 2 * i;
+      const int j = (q + d) & 31;
+      const int lo = q < j ? q : j, hi = q < j ? j : q;
+      if (d < 16 || (d == 16 && q < 16)) {
+        const double pro = Ap * (m.eps[lo] * m.eps[hi]) * S.G[hi];
+        T0[hi * ST + lo] = pro;
+        T0[lo * ST + hi] = pro;
+      }
+    }
+    __syncthreads();
+    if (h != 0) {
+      const double* p = T0 + q * ST;
+#pragma unroll
+      for (int j = 0; j < NQ; ++j) M2[j] = p[j];
+    }
+    __syncthreads();
   }
 
   __device__ static void solve(const FwdArgs& a, int64_t p, WaveLds<NS>& S) {
-    const DevModel* __restrict__ md = a.mdl;
-    const SolverParams& prm = a.prm;
+    const DevModel* __restrict__ md0 = a.mdl;
+    const DevModel* __restrict__ md = md0;
+    const ModelLds& mt = S.m;
     const int lane = threadIdx.x;
-    const int h = lane >> 5;  // 0: number lanes, 1: flux lanes
-    const int q = lane & 31;
-    const double epsq = md->eps[q], w2q = md->w2[q], w3q = md->w3[q], shq = md->shape[q];
+    const int h0 = lane >> 5;  // 0: number lanes, 1: flux lanes
+    const int q0 = lane & 31;
+    const int h = h0, q = q0;
     const double dtau = a.dtau;
-    const unsigned flags = md->flags;
-    double* red = S.red;
-    double* redout = S.redout;
+    const int64_t base = p * (int64_t)(NS * NQ);
 
     const double rho = a.rho11[p];
-    const double ye_st = a.ye0[p], e_st = a.e0[p];
-    const int64_t base = p * (int64_t)(NS * NQ);
-    const double r3 = cbrt(rho);
-    const bool fixedT = prm.fixed_matter && a.T_fixed;
+    const bool fixedT = a.prm.fixed_matter && a.T_fixed;
 
     // the moment a lane owns: D* on number lanes, I* on flux lanes; D* on
     // every lane (flux lanes form W (1 - D) from it)
@@ -210,10 +508,11 @@ struct PointSolver {
         else a.I[base + t * NQ + q] = M[t];
       }
       if (lane == 0) {
+        const double ye_st = a.ye0[p], e_st = a.e0[p];
         a.ye[p] = ye_st;
         a.e[p] = e_st;
         a.T[p] = fixedT ? a.T_fixed[p]
-                        : (e_st - md->eos_b * pow(ye_st, 4.0 / 3.0) * r3) / (md->eos_a * (1.0 + ye_st));
+                        : (e_st - md->eos_b * ye43(ye_st) * cbrt(rho)) / (md->eos_a * (1.0 + ye_st));
         a.n_outer[p] = 0;
         a.n_inner[p] = 0;
         a.status[p] = NMC_STATUS_OK;
@@ -223,85 +522,95 @@ struct PointSolver {
 #pragma unroll
     for (int t = 0; t < NS; ++t) S.mst[t][lane] = M[t];
 
-    const double chi0 = a.chi0 ? a.chi0[p] : md->chi_ref * rho;
-    const double An = (flags & NMC_NES) ? a.theta[NQ] * rho : 0.0;
-    const double Ap = (flags & NMC_PAIR) ? a.theta[NQ + 1] * rho : 0.0;
-    const bool coupled = (flags & (NMC_NES | NMC_PAIR)) != 0;
-
-    // point-constant opacities: chi^EmAb = theta_q chi0 shape_q (electron
-    // flavours), sigma^Iso = sigma_ratio chi0 shape_q
-    const double shape = chi0 * shq;
-    const double sig = (flags & NMC_ISO) ? md->sigma_ratio * shape : 0.0;
-    const double emab_q = (flags & NMC_EMAB) ? a.theta[q] * shape : 0.0;
+    // point constants: rho^(1/3), coupling K, kernel amplitudes
+    S.r3 = cbrt(rho);
+    S.K = md->kcoup / rho;
+    S.An = (md->flags & NMC_NES) ? mt.theta[NQ] * rho : 0.0;
+    S.Ap = (md->flags & NMC_PAIR) ? mt.theta[NQ + 1] * rho : 0.0;
 
     // ||D_s||_W^2 of the initial moments (reference of the first inner loop)
-    double nD[NS];
     {
+      const double w2q = mt.w2[q];
       double v[NS], s0[NS], s1[NS];
 #pragma unroll
       for (int t = 0; t < NS; ++t) v[t] = h ? 0.0 : w2q * Dcur[t] * Dcur[t];
-      half_sums<NS>(v, s0, s1, red, redout);
+      half_sums<NS>(v, s0, s1, S.u.it.red, S.u.it.redout);
 #pragma unroll
-      for (int t = 0; t < NS; ++t) nD[t] = s0[t];
+      for (int t = 0; t < NS; ++t) S.dref[t] = s0[t];
     }
+    S.y[0] = a.ye0[p];
+    S.y[1] = a.e0[p];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) S.oq[i] = S.of[i] = S.odq[i] = S.odf[i] = 0.0;
+    S.T_last = 0.0;
 
-    double y0 = ye_st, y1 = e_st;  // matter iterate (Ye, e)
-    // outer Anderson history: previous (q, f) and the older difference column
-    double oq0 = 0, oq1 = 0, of0 = 0, of1 = 0, odq0 = 0, odq1 = 0, odf0 = 0, odf1 = 0;
     int status = NMC_STATUS_OK;
     bool fatal = false, inner_failed = false, outer_conv = false;
     int k, total_inner = 0;
-    double T_last = fixedT ? a.T_fixed[p] : (e_st - md->eos_b * pow(ye_st, 4.0 / 3.0) * r3) / (md->eos_a * (1.0 + ye_st));
 
     double M1[NQ], M2[NQ];
-    for (k = 1; k <= prm.max_outer; ++k) {
+    for (k = 1; k <= a.prm.max_outer; ++k) {
+      // per-iteration opaque copies keep lane invariants from being hoisted
+      // out of this loop (and spilled)
+      const DevModel* __restrict__ md = opaque_ptr(md0);
+      const int q = opaque(q0), h = opaque(h0);
       // ---- ComputeOpacities(y^[k]) --------------------------------------
-      const double T = fixedT ? a.T_fixed[p] : (y1 - md->eos_b * pow(y0, 4.0 / 3.0) * r3) / (md->eos_a * (1.0 + y0));
-      const double mu = (prm.fixed_matter && a.mu_fixed) ? a.mu_fixed[p]
-                                                         : md->mu_a * (y0 - md->mu_ye0) * r3 + md->mu_b * log(T / md->mu_t0);
+      const double r3 = S.r3;
+      const double y0 = S.y[0], y1 = S.y[1];
+      const double T = fixedT ? a.T_fixed[p] : (y1 - md->eos_b * ye43(y0) * r3) / (md->eos_a * (1.0 + y0));
+      const double mu = (a.prm.fixed_matter && a.mu_fixed)
+                            ? a.mu_fixed[p]
+                            : md->mu_a * (y0 - md->mu_ye0) * r3 + md->mu_b * log(T / md->mu_t0);
       if (!(T > 0.0) || !(y0 >= 0.0) || !isfinite(T) || !isfinite(mu)) {
         status = NMC_STATUS_EOS_DOMAIN;
         fatal = true;
         break;
       }
-      T_last = T;
+      S.T_last = T;
       const double invT = 1.0 / T;
 
       // Eq. emissivityEmAbNodal with the nodal Fermi-Dirac equilibrium: the
       // number lanes need chi^EmAb D_eq and chi^EmAb, the flux lanes
       // chi^EmAb + sigma^Iso (transport opacity, Eq. transportOpacityNodal).
-      double c1[NS], c2[NS];
+      // chi^EmAb = theta_q chi0 shape_q (electron flavours), sigma^Iso =
+      // sigma_ratio chi0 shape_q.  Stored as the constant parts of the
+      // numerator and denominator of Q.
+      {
+        const double chi0 = a.chi0 ? a.chi0[p] : md->chi_ref * rho;
+        const double shape = chi0 * mt.shape[q];
+        const double sig = (md->flags & NMC_ISO) ? md->sigma_ratio * shape : 0.0;
+        const double emab_q = (md->flags & NMC_EMAB) ? mt.theta[q] * shape : 0.0;
+        const double epsq = mt.eps[q];
 #pragma unroll
-      for (int t = 0; t < NS; ++t) {
-        const double chia = md->emab[t] * emab_q;
-        const double x = (epsq - md->musign[t] * mu) * invT;
-        const double ex = exp(-fabs(x));
-        const double deq = x > 0.0 ? ex / (1.0 + ex) : 1.0 / (1.0 + ex);
-        c1[t] = h ? 0.0 : chia * deq;
-        c2[t] = h ? chia + sig : chia;
+        for (int t = 0; t < NS; ++t) {
+          const double chia = md->emab[t] * emab_q;
+          const double x = (epsq - md->musign[t] * mu) * invT;
+          const double ex = exp(-fabs(x));
+          const double r = rcp_ge1(1.0 + ex);
+          const double deq = x > 0.0 ? ex * r : r;
+          S.base[t][lane] = h ? S.mst[t][lane] : S.mst[t][lane] + dtau * (chia * deq);
+          S.den0[t][lane] = 1.0 + dtau * (h ? chia + sig : chia);
+        }
       }
 
       // kernel rows in registers: number lanes Phi_in[q][:], Phi_ann[q][:];
       // flux lanes Phi_out[q][:], Phi_pro[q][:]
-      if (coupled) build_rows(h, epsq, invT, An, Ap, M1, M2);
+      if constexpr (COUPLED) build_rows(h, q, invT, S.An, S.Ap, S, M1, M2);
 
       // ---- inner loop over moments at fixed matter (M^[k,1] = M^[k-1,*]) --
-      double dref0[NS];
-#pragma unroll
-      for (int t = 0; t < NS; ++t) dref0[t] = sqrt(nD[t]);
+      const double w2q = mt.w2[q];
+      const double xa = h ? -w2q : w2q, xb = h ? w2q : 0.0;  // X = xa D + xb
+      const double dth = h ? 0.0 : dtau;
       double G11 = 0.0;
       bool conv = false;
       int l;
-      for (l = 1; l <= prm.max_inner; ++l) {
+      for (l = 1; l <= a.prm.max_inner; ++l) {
         // ComputeRates(M^[k,l])
         double eta_c[NS], chi_c[NS];
-        if (coupled) {
+        if constexpr (COUPLED) {
           double XR[NS][2];
 #pragma unroll
-          for (int t = 0; t < NS; ++t) {
-            const double x = h ? w2q * (1.0 - Dcur[t]) : w2q * Dcur[t];
-            swap16(x, XR[t][0], XR[t][1]);
-          }
+          for (int t = 0; t < NS; ++t) swap16(__builtin_fma(xa, Dcur[t], xb), XR[t][0], XR[t][1]);
           double a1[NS], a2[NS];
           contract(M1, M2, XR, a1, a2);
           // number lanes: a1 = eta^NES, a2 = Phi_ann W D (per partner);
@@ -326,78 +635,72 @@ struct PointSolver {
         double Q[NS], F[NS];
 #pragma unroll
         for (int t = 0; t < NS; ++t) {
-          const double num = S.mst[t][lane] + dtau * (h ? 0.0 : c1[t] + eta_c[t]);
-          const double den = 1.0 + dtau * (c2[t] + chi_c[t]);
-          Q[t] = num / den;
+          const double num = __builtin_fma(dth, eta_c[t], S.base[t][lane]);
+          const double den = __builtin_fma(dtau, chi_c[t], S.den0[t][lane]);
+          Q[t] = num * rcp_ge1(den);
           F[t] = Q[t] - M[t];
         }
 
-        // Anderson step over the last min(l, M_inner) residuals
+        // Anderson step over the last min(l, M_inner) residuals, as two
+        // difference columns (the older one weighted zero when absent)
+        const int mem = l < a.prm.m_inner ? l : a.prm.m_inner;
         double Mnew[NS];
-        const int mem = l < prm.m_inner ? l : prm.m_inner;
         if (mem == 1) {
 #pragma unroll
           for (int t = 0; t < NS; ++t) Mnew[t] = Q[t];
         } else {
+          const double use1 = (mem == 3) ? 1.0 : 0.0;
           double dQ2[NS], dF2[NS];
           double v4[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
           for (int t = 0; t < NS; ++t) {
-            dQ2[t] = Q[t] - S.hist[0][t][lane];
-            dF2[t] = F[t] - S.hist[1][t][lane];
-            const double dF1 = (mem == 3) ? S.hist[3][t][lane] : 0.0;
+            dQ2[t] = Q[t] - S.u.it.hist[0][t][lane];
+            dF2[t] = F[t] - S.u.it.hist[1][t][lane];
+            const double dF1 = use1 * S.u.it.hist[3][t][lane];
             v4[0] += dF1 * dF2[t];
             v4[1] += dF2[t] * dF2[t];
             v4[2] += dF1 * F[t];
             v4[3] += dF2[t] * F[t];
           }
-          double s0[4], s1[4];
-          half_sums<4>(v4, s0, s1, red, redout);
-          const double G12 = s0[0] + s1[0], G22 = s0[1] + s1[1];
-          const double b1 = s0[2] + s1[2], b2 = s0[3] + s1[3];
+          double gs[4];
+          wave_sums4(v4, gs);
+          const double G12 = gs[0], G22 = gs[1];
+          const double b1 = gs[2], b2 = gs[3];
+          // normal equations by LDL^T (the Cholesky pivots G11 and
+          // G22 - G12^2 / G11, without square roots); a pivot <= 1e-14 trace
+          // drops the oldest column, none left gives Picard
           double g1 = 0.0, g2 = 0.0;
           bool two = (mem == 3);
           if (two) {
             const double tr = G11 + G22;
             two = G11 > 1e-14 * tr;
             if (two) {
-              const double L11 = sqrt(G11);
-              const double L21 = G12 / L11;
-              const double p2 = G22 - L21 * L21;
+              const double r11 = 1.0 / G11;
+              const double l21 = G12 * r11;
+              const double p2 = G22 - G12 * l21;
               two = p2 > 1e-14 * tr;
               if (two) {
-                const double L22 = sqrt(p2);
-                const double z1 = b1 / L11;
-                const double z2 = (b2 - L21 * z1) / L22;
-                g2 = z2 / L22;
-                g1 = (z1 - L21 * g2) / L11;
+                g2 = (b2 - l21 * b1) / p2;
+                g1 = (b1 - G12 * g2) * r11;
               }
             }
           }
           if (!two) {
-            // newest column only; Picard when it vanishes
             g1 = 0.0;
-            if (G22 > 1e-14 * G22) {
-              const double L = sqrt(G22);
-              g2 = (b2 / L) / L;
-            } else {
-              g2 = 0.0;
-            }
+            g2 = (G22 > 1e-14 * G22) ? b2 / G22 : 0.0;
           }
 #pragma unroll
           for (int t = 0; t < NS; ++t) {
-            double mn = Q[t] - g2 * dQ2[t];
-            if (mem == 3) mn -= g1 * S.hist[2][t][lane];
-            Mnew[t] = mn;
-            S.hist[2][t][lane] = dQ2[t];
-            S.hist[3][t][lane] = dF2[t];
+            Mnew[t] = Q[t] - g2 * dQ2[t] - g1 * S.u.it.hist[2][t][lane];
+            S.u.it.hist[2][t][lane] = dQ2[t];
+            S.u.it.hist[3][t][lane] = dF2[t];
           }
           G11 = G22;
         }
 #pragma unroll
         for (int t = 0; t < NS; ++t) {
-          S.hist[0][t][lane] = Q[t];
-          S.hist[1][t][lane] = F[t];
+          S.u.it.hist[0][t][lane] = Q[t];
+          S.u.it.hist[1][t][lane] = F[t];
         }
 
         bool bad = false;
@@ -410,7 +713,8 @@ struct PointSolver {
         }
 
         // Algorithm innerConverged (weighted per species, reference guarded
-        // by the new norm)
+        // by the new norm): sqrt(max(S_D, S_I)) <= tol max(||D^[k,1]||,
+        // ||D^[k,l+1]||), compared squared
         {
           double v[2 * NS], s0[2 * NS], s1[2 * NS];
 #pragma unroll
@@ -419,16 +723,21 @@ struct PointSolver {
             v[t] = w2q * d * d;
             v[NS + t] = h ? 0.0 : w2q * Mnew[t] * Mnew[t];
           }
-          half_sums<2 * NS>(v, s0, s1, red, redout);
+          half_sums_reg<NS>(v, s0, s1);
           conv = true;
 #pragma unroll
           for (int t = 0; t < NS; ++t) {
             const double sd = s0[t], si = s1[t];
-            const double dm = sqrt(sd > si ? sd : si);
-            const double dn = sqrt(s0[NS + t]);
-            const double dref = dref0[t] > dn ? dref0[t] : dn;
-            if (!(dm <= prm.tol_inner * dref)) conv = false;
-            nD[t] = s0[NS + t];
+            const double dm2 = sd > si ? sd : si;
+            const double dn2 = s0[NS + t];
+            const double d0 = S.dref[t];
+            const double dref2 = d0 > dn2 ? d0 : dn2;
+            if (!(dm2 <= a.tol_inner2 * dref2)) conv = false;
+          }
+          if (conv) {
+            // ||D^[k,*]|| is the reference of the next inner loop
+#pragma unroll
+            for (int t = 0; t < NS; ++t) S.dref[t] = s0[NS + t];
           }
         }
 #pragma unroll
@@ -440,10 +749,19 @@ struct PointSolver {
         }
         if (conv) break;
       }
-      total_inner += (l > prm.max_inner ? prm.max_inner : l);
+      total_inner += (l > a.prm.max_inner ? a.prm.max_inner : l);
       if (fatal) break;
-      if (!conv) inner_failed = true;
-      if (prm.fixed_matter) {
+      if (!conv) {
+        inner_failed = true;
+        // reference for the next loop: the norm of the current moments
+        double v[NS], s0[NS], s1[NS];
+#pragma unroll
+        for (int t = 0; t < NS; ++t) v[t] = h ? 0.0 : w2q * M[t] * M[t];
+        half_sums<NS>(v, s0, s1, S.u.it.red, S.u.it.redout);
+#pragma unroll
+        for (int t = 0; t < NS; ++t) S.dref[t] = s0[t];
+      }
+      if (a.prm.fixed_matter) {
         outer_conv = true;
         break;
       }
@@ -451,31 +769,32 @@ struct PointSolver {
       // ---- matter right-hand side (Eq. implicitFluidNodal at v = 0) -------
       double yq0, yq1;
       {
+        const double w3 = mt.w3[q];
         double mv[2] = {0.0, 0.0}, s0[2], s1[2];
         if (h == 0) {
 #pragma unroll
           for (int t = 0; t < NS; ++t) {
             const double dd = M[t] - S.mst[t][lane];
             mv[0] += md->g[t] * w2q * dd;
-            mv[1] += md->mult[t] * w3q * dd;
+            mv[1] += md->mult[t] * w3 * dd;
           }
         }
-        half_sums<2>(mv, s0, s1, red, redout);
-        const double K = md->kcoup / rho;
-        yq0 = ye_st - K * s0[0];
-        yq1 = e_st - K * s0[1];
+        half_sums<2>(mv, s0, s1, S.u.it.red, S.u.it.redout);
+        yq0 = a.ye0[p] - S.K * s0[0];
+        yq1 = a.e0[p] - S.K * s0[1];
       }
-      const double f0 = yq0 - y0, f1 = yq1 - y1;
+      const double f0 = yq0 - S.y[0], f1 = yq1 - S.y[1];
 
-      // outer Anderson step on (Ye, e)
-      const int omem = k < prm.m_outer ? k : prm.m_outer;
+      // outer Anderson step on (Ye, e), same least-squares rule
+      const int omem = k < a.prm.m_outer ? k : a.prm.m_outer;
       double yn0, yn1;
       if (omem == 1) {
         yn0 = yq0;
         yn1 = yq1;
       } else {
-        const double dq20 = yq0 - oq0, dq21 = yq1 - oq1;
-        const double df20 = f0 - of0, df21 = f1 - of1;
+        const double dq20 = yq0 - S.oq[0], dq21 = yq1 - S.oq[1];
+        const double df20 = f0 - S.of[0], df21 = f1 - S.of[1];
+        const double odf0 = S.odf[0], odf1 = S.odf[1];
         const double G22 = df20 * df20 + df21 * df21, b2 = df20 * f0 + df21 * f1;
         double g1 = 0.0, g2 = 0.0;
         bool two = (omem == 3);
@@ -485,82 +804,73 @@ struct PointSolver {
           const double tr = G11o + G22;
           two = G11o > 1e-14 * tr;
           if (two) {
-            const double L11 = sqrt(G11o);
-            const double L21 = G12 / L11;
-            const double p2 = G22 - L21 * L21;
+            const double l21 = G12 / G11o;
+            const double p2 = G22 - G12 * l21;
             two = p2 > 1e-14 * tr;
             if (two) {
-              const double L22 = sqrt(p2);
-              const double z1 = b1 / L11;
-              const double z2 = (b2 - L21 * z1) / L22;
-              g2 = z2 / L22;
-              g1 = (z1 - L21 * g2) / L11;
+              g2 = (b2 - l21 * b1) / p2;
+              g1 = (b1 - G12 * g2) / G11o;
             }
           }
         }
         if (!two) {
           g1 = 0.0;
-          if (G22 > 1e-14 * G22) {
-            const double L = sqrt(G22);
-            g2 = (b2 / L) / L;
-          } else {
-            g2 = 0.0;
-          }
+          g2 = (G22 > 1e-14 * G22) ? b2 / G22 : 0.0;
         }
-        yn0 = yq0 - g2 * dq20;
-        yn1 = yq1 - g2 * dq21;
-        if (omem == 3) {
-          yn0 -= g1 * odq0;
-          yn1 -= g1 * odq1;
-        }
-        odq0 = dq20;
-        odq1 = dq21;
-        odf0 = df20;
-        odf1 = df21;
+        yn0 = yq0 - g2 * dq20 - g1 * S.odq[0];
+        yn1 = yq1 - g2 * dq21 - g1 * S.odq[1];
+        S.odq[0] = dq20;
+        S.odq[1] = dq21;
+        S.odf[0] = df20;
+        S.odf[1] = df21;
       }
-      oq0 = yq0;
-      oq1 = yq1;
-      of0 = f0;
-      of1 = f1;
+      S.oq[0] = yq0;
+      S.oq[1] = yq1;
+      S.of[0] = f0;
+      S.of[1] = f1;
       if (!isfinite(yn0) || !isfinite(yn1)) {
         status = NMC_STATUS_NONFINITE;
         fatal = true;
         break;
       }
       // Algorithm outerConverged: componentwise against y*
-      const bool oc = fabs(yn0 - y0) <= prm.tol_outer * fabs(ye_st) && fabs(yn1 - y1) <= prm.tol_outer * fabs(e_st);
-      y0 = yn0;
-      y1 = yn1;
+      const bool oc = fabs(yn0 - S.y[0]) <= a.prm.tol_outer * fabs(a.ye0[p]) &&
+                      fabs(yn1 - S.y[1]) <= a.prm.tol_outer * fabs(a.e0[p]);
+      S.y[0] = yn0;
+      S.y[1] = yn1;
       if (oc) {
         outer_conv = true;
         break;
       }
     }
-    if (k > prm.max_outer) k = prm.max_outer;
+    if (k > a.prm.max_outer) k = a.prm.max_outer;
     if (!fatal) {
       if (!outer_conv) status = NMC_STATUS_MAX_OUTER;
       else if (inner_failed) status = NMC_STATUS_MAX_INNER;
     }
 
     // ---- outputs --------------------------------------------------------
-    double ye_out = ye_st, e_out = e_st, T_out = T_last;
-    if (!prm.fixed_matter) {
+    const double ye_st = a.ye0[p], e_st = a.e0[p];
+    double ye_out = ye_st, e_out = e_st, T_out = S.T_last;
+    if (!a.prm.fixed_matter) {
       // final matter state from the final moments (exact lepton-number and
       // energy balance)
+      const double w2 = mt.w2[q], w3 = mt.w3[q];
       double mv[2] = {0.0, 0.0}, s0[2], s1[2];
       if (h == 0) {
 #pragma unroll
         for (int t = 0; t < NS; ++t) {
           const double dd = M[t] - S.mst[t][lane];
-          mv[0] += md->g[t] * w2q * dd;
-          mv[1] += md->mult[t] * w3q * dd;
+          mv[0] += md->g[t] * w2 * dd;
+          mv[1] += md->mult[t] * w3 * dd;
         }
       }
-      half_sums<2>(mv, s0, s1, red, redout);
-      const double K = md->kcoup / rho;
-      ye_out = ye_st - K * s0[0];
-      e_out = e_st - K * s0[1];
-      T_out = (e_out - md->eos_b * pow(ye_out, 4.0 / 3.0) * r3) / (md->eos_a * (1.0 + ye_out));
+      half_sums<2>(mv, s0, s1, S.u.it.red, S.u.it.redout);
+      ye_out = ye_st - S.K * s0[0];
+      e_out = e_st - S.K * s0[1];
+      T_out = (e_out - md->eos_b * ye43(ye_out) * S.r3) / (md->eos_a * (1.0 + ye_out));
+    } else if (status == NMC_STATUS_EOS_DOMAIN) {
+      T_out = fixedT ? a.T_fixed[p] : (e_st - md->eos_b * ye43(ye_st) * S.r3) / (md->eos_a * (1.0 + ye_st));
     }
 #pragma unroll
     for (int t = 0; t < NS; ++t) {
@@ -578,23 +888,26 @@ struct PointSolver {
   }
 };
 
-template <int NS, int NQ>
+template <int NS, int NQ, bool COUPLED>
 __global__ __launch_bounds__(kLanes, 2) void fwd_kernel(FwdArgs a) {
   __shared__ WaveLds<NS> S;
+  load_model(a.mdl, a.theta, S.m);
   if (a.queue) {
-    // persistent grid: pop chunks of points from the work queue until drained
+    // persistent grid: pop chunks of points from the work queue until
+    // drained; the next grab is issued before the current chunk is solved
+    int nxt = 0;
+    if (threadIdx.x == 0) nxt = atomicAdd(a.queue, a.chunk);
     for (;;) {
-      int b = 0;
-      if (threadIdx.x == 0) b = atomicAdd(a.queue, a.chunk);
-      const int64_t b0 = __builtin_amdgcn_readfirstlane(b);
+      const int64_t b0 = __builtin_amdgcn_readfirstlane(nxt);
       if (b0 >= a.P) break;
+      if (threadIdx.x == 0) nxt = atomicAdd(a.queue, a.chunk);
       const int64_t end = b0 + a.chunk < a.P ? b0 + a.chunk : a.P;
-      for (int64_t p = b0; p < end; ++p) PointSolver<NS, NQ>::solve(a, p, S);
+      for (int64_t p = b0; p < end; ++p) PointSolver<NS, NQ, COUPLED>::solve(a, p, S);
     }
   } else {
     const int64_t b0 = (int64_t)blockIdx.x * a.chunk;
     const int64_t end = b0 + a.chunk < a.P ? b0 + a.chunk : a.P;
-    for (int64_t p = b0; p < end; ++p) PointSolver<NS, NQ>::solve(a, p, S);
+    for (int64_t p = b0; p < end; ++p) PointSolver<NS, NQ, COUPLED>::solve(a, p, S);
   }
 }
 
@@ -602,9 +915,9 @@ __global__ void reset_counter_kernel(int* c) {
   if (threadIdx.x == 0) *c = 0;
 }
 
-template <int NS, int NQ>
+template <int NS, int NQ, bool COUPLED>
 hipError_t launch_fwd_t(const FwdArgs& a, const nmc_launch& L, int num_cu, hipStream_t s) {
-  auto kern = fwd_kernel<NS, NQ>;
+  auto kern = fwd_kernel<NS, NQ, COUPLED>;
   int64_t grid;
   if (a.queue) {
     int bpc = L.blocks_per_cu;
@@ -636,12 +949,21 @@ hipError_t launch_reset_counter(int* counter, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_forward(const FwdArgs& a, int nq, int ns, const nmc_launch& L, int num_cu, hipStream_t s) {
+hipError_t launch_forward(const FwdArgs& a, int nq, int ns, bool coupled, const nmc_launch& L, int num_cu,
+                          hipStream_t s) {
   if (nq == 32) {
-    switch (ns) {
-      case 1: return launch_fwd_t<1, 32>(a, L, num_cu, s);
-      case 2: return launch_fwd_t<2, 32>(a, L, num_cu, s);
-      case 3: return launch_fwd_t<3, 32>(a, L, num_cu, s);
+    if (coupled) {
+      switch (ns) {
+        case 1: return launch_fwd_t<1, 32, true>(a, L, num_cu, s);
+        case 2: return launch_fwd_t<2, 32, true>(a, L, num_cu, s);
+        case 3: return launch_fwd_t<3, 32, true>(a, L, num_cu, s);
+      }
+    } else {
+      switch (ns) {
+        case 1: return launch_fwd_t<1, 32, false>(a, L, num_cu, s);
+        case 2: return launch_fwd_t<2, 32, false>(a, L, num_cu, s);
+        case 3: return launch_fwd_t<3, 32, false>(a, L, num_cu, s);
+      }
     }
   }
   return hipErrorInvalidValue;

@@ -11,8 +11,9 @@ namespace nmc {
 constexpr int kMaxNq = 64;
 constexpr int kMaxNs = 3;
 
-// Model table resident in device memory; every field is read with uniform
-// addresses inside the kernels, so it is served by the scalar cache.
+// Model table resident in device memory.  The kernels copy the per-node
+// tables into LDS once per work-group and read the uniform scalars through
+// the scalar cache.
 struct DevModel {
   int ns, nq;
   unsigned flags;
@@ -41,6 +42,7 @@ struct SolverParams {
 struct FwdArgs {
   const DevModel* mdl;
   SolverParams prm;
+  double tol_inner2;  // tol_inner^2 (the inner test is evaluated squared)
   int64_t P;
   double dtau;
   const double *D0, *I0, *rho11, *ye0, *e0, *chi0, *T_fixed, *mu_fixed, *theta;
@@ -62,7 +64,8 @@ struct AdjArgs {
 };
 
 // launchers (defined in the kernel translation units)
-hipError_t launch_forward(const FwdArgs& a, int nq, int ns, const nmc_launch& L, int num_cu, hipStream_t s);
+hipError_t launch_forward(const FwdArgs& a, int nq, int ns, bool coupled, const nmc_launch& L, int num_cu,
+                          hipStream_t s);
 hipError_t launch_reset_counter(int* counter, hipStream_t s);
 hipError_t launch_init_state(const DevModel* mdl, int ns, int nq, int64_t P, const double* T, const double* mu,
                              const double* rho11, const double* ye, const double* uD, const double* uI, double a,

@@ -57,3 +57,15 @@ def parity_errors(ref, got, w2):
     eY = np.abs(got["ye"] - ref["ye"]) / np.abs(ref["ye"])
     eE = np.abs(got["e"] - ref["e"]) / np.abs(ref["e"])
     return eD, eI, eY, eE
+
+
+def reservoir_ratios(kcoup, rho11, D, ye, e, w2, w3, species=(0, 1, 2)):
+    """Neutrino-to-matter ratios of lepton number and energy per point.  The
+    output matter state is recomputed from the final moments, so a relative
+    error tol in the moments becomes tol * ratio in Ye and e."""
+    g = np.array([[1.0, 1.0, 0.0][s] for s in species])[None, :, None]
+    mult = np.array([[1.0, 1.0, 4.0][s] for s in species])[None, :, None]
+    K = kcoup / rho11
+    RY = K * np.sum(g * w2 * D, axis=(1, 2)) / np.abs(ye)
+    RE = K * np.sum(mult * w3 * D, axis=(1, 2)) / np.abs(e)
+    return RY, RE
