@@ -39,12 +39,12 @@ def best_launch(model, P: int) -> S.LaunchConfig:
     ent = _load().get(_key(model))
     if ent:
         return S.LaunchConfig(**ent["launch"])
-    return S.LaunchConfig(blocks_per_cu=0, chunk=1, persistent=True)
+    return S.LaunchConfig(blocks_per_cu=0, chunk=4, persistent=True)
 
 
 def candidates():
     for persistent in (True, False):
-        for chunk in (1, 2, 4):
+        for chunk in (1, 2, 4, 8):
             for bpc in ((0, 4, 6) if persistent else (0,)):
                 yield S.LaunchConfig(blocks_per_cu=bpc, chunk=chunk, persistent=persistent)
 

@@ -201,6 +201,21 @@ int nmc_model_create(const nmc_grid* g, const nmc_model_desc* d, nmc_model** out
     if ((m.flags & NMC_PAIR) && m.partner[s] < 0)
       return fail(NMC_E_UNSUPPORTED, "model_create: pair processes need the partner of species %d", m.species[s]);
   }
+  for (int t = 0, k = 0; t < m.ns; ++t) {
+    // t-th smallest species id
+    int best = -1;
+    for (int s = 0; s < m.ns; ++s) {
+      bool taken = false;
+      for (int u = 0; u < k; ++u) taken = taken || m.ext[u] == s;
+      if (!taken && (best < 0 || m.species[s] < m.species[best])) best = s;
+    }
+    m.ext[k] = best;
+    m.ig[k] = m.g[best];
+    m.imult[k] = m.mult[best];
+    m.imusign[k] = m.musign[best];
+    m.iemab[k] = m.emab[best];
+    ++k;
+  }
   const double vals[] = {d->chi_ref, d->eps_ref, d->chi_power, d->sigma_ratio, d->eos_a, d->eos_b, d->mu_a,
                          d->mu_ye0, d->mu_b, d->mu_t0, d->hc_mev_cm, d->m_u_g, d->rho11_min};
   for (double v : vals)

@@ -37,9 +37,12 @@ __device__ __forceinline__ void static_for(F&& f) {
   }
 }
 
+// DPP lane permutation within 16-lane rows for controls that read a valid
+// lane for every lane (quad_perm, row mirrors), so no "old" value is needed
 template <int CTRL>
 __device__ __forceinline__ double dpp(double x) {
-  return __builtin_amdgcn_update_dpp(0.0, x, CTRL, 0xF, 0xF, false);
+  const long v = __builtin_amdgcn_mov_dpp(__builtin_bit_cast(long, x), CTRL, 0xF, 0xF, false);
+  return __builtin_bit_cast(double, v);
 }
 
 // broadcast lane I of every 16-lane row to the whole row (row_newbcast:I);
@@ -325,6 +328,14 @@ __device__ __forceinline__ void load_model(const DevModel* __restrict__ md, cons
   __syncthreads();
 }
 
+// Pair partner of internal species s (species sorted by id: nu_e, anti-nu_e
+// are partners, nu_x is its own partner).  Models without pair processes
+// have zero pair kernels, so the map is irrelevant for them.
+template <int NS>
+__device__ __forceinline__ constexpr int pair_partner(int s) {
+  return NS == 3 ? (s < 2 ? 1 - s : 2) : (NS == 2 ? 1 - s : 0);
+}
+
 template <int NS>
 struct WaveLds {
   static constexpr int kStride = 33;  // padded row stride of the 32 x 32 build tile
@@ -496,16 +507,16 @@ struct PointSolver {
     double M[NS], Dcur[NS];
 #pragma unroll
     for (int t = 0; t < NS; ++t) {
-      Dcur[t] = a.D0[base + t * NQ + q];
-      M[t] = h ? a.I0[base + t * NQ + q] : Dcur[t];
+      Dcur[t] = a.D0[base + md->ext[t] * NQ + q];
+      M[t] = h ? a.I0[base + md->ext[t] * NQ + q] : Dcur[t];
     }
 
     if (rho < md->rho11_min) {
       // coupling disabled at low density (Sec. 7.2): pass the state through
 #pragma unroll
       for (int t = 0; t < NS; ++t) {
-        if (h == 0) a.D[base + t * NQ + q] = M[t];
-        else a.I[base + t * NQ + q] = M[t];
+        if (h == 0) a.D[base + md->ext[t] * NQ + q] = M[t];
+        else a.I[base + md->ext[t] * NQ + q] = M[t];
       }
       if (lane == 0) {
         const double ye_st = a.ye0[p], e_st = a.e0[p];
@@ -583,8 +594,8 @@ struct PointSolver {
         const double epsq = mt.eps[q];
 #pragma unroll
         for (int t = 0; t < NS; ++t) {
-          const double chia = md->emab[t] * emab_q;
-          const double x = (epsq - md->musign[t] * mu) * invT;
+          const double chia = md->iemab[t] * emab_q;
+          const double x = (epsq - md->imusign[t] * mu) * invT;
           const double ex = exp(-fabs(x));
           const double r = rcp_ge1(1.0 + ex);
           const double deq = x > 0.0 ? ex * r : r;
@@ -617,10 +628,7 @@ struct PointSolver {
           // flux lanes: a1 = Phi_out W (1 - D), a2 = eta^Pair (per partner)
 #pragma unroll
           for (int s = 0; s < NS; ++s) {
-            const int sb = md->partner[s];
-            double pa = a2[0];
-#pragma unroll
-            for (int t = 1; t < NS; ++t) pa = (sb == t) ? a2[t] : pa;
+            const double pa = a2[pair_partner<NS>(s)];
             const double u = h ? pa : a1[s];
             const double v = a1[s] + pa;
             eta_c[s] = sum_halves(u);  // eta^NES + eta^Pair
@@ -775,8 +783,8 @@ struct PointSolver {
 #pragma unroll
           for (int t = 0; t < NS; ++t) {
             const double dd = M[t] - S.mst[t][lane];
-            mv[0] += md->g[t] * w2q * dd;
-            mv[1] += md->mult[t] * w3 * dd;
+            mv[0] += md->ig[t] * w2q * dd;
+            mv[1] += md->imult[t] * w3 * dd;
           }
         }
         half_sums<2>(mv, s0, s1, S.u.it.red, S.u.it.redout);
@@ -861,8 +869,8 @@ struct PointSolver {
 #pragma unroll
         for (int t = 0; t < NS; ++t) {
           const double dd = M[t] - S.mst[t][lane];
-          mv[0] += md->g[t] * w2 * dd;
-          mv[1] += md->mult[t] * w3 * dd;
+          mv[0] += md->ig[t] * w2 * dd;
+          mv[1] += md->imult[t] * w3 * dd;
         }
       }
       half_sums<2>(mv, s0, s1, S.u.it.red, S.u.it.redout);
@@ -874,8 +882,8 @@ struct PointSolver {
     }
 #pragma unroll
     for (int t = 0; t < NS; ++t) {
-      if (h == 0) a.D[base + t * NQ + q] = M[t];
-      else a.I[base + t * NQ + q] = M[t];
+      if (h == 0) a.D[base + md->ext[t] * NQ + q] = M[t];
+      else a.I[base + md->ext[t] * NQ + q] = M[t];
     }
     if (lane == 0) {
       a.ye[p] = ye_out;

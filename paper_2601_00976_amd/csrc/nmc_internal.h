@@ -24,6 +24,12 @@ struct DevModel {
   double mult[kMaxNs];    // energy multiplicity (4 for the heavy-lepton stand-in)
   double musign[kMaxNs];  // chemical potential = musign * mu_nu_e
   double emab[kMaxNs];    // 1 if the species has emission/absorption
+  // Internal species order used by the solve kernels: sorted by species id,
+  // so that pair partners sit at compile-time positions (nu_e, anti-nu_e at
+  // 0, 1 and nu_x last).  ext[t] is the caller's slot of internal species t;
+  // the i* arrays are the per-species constants in internal order.
+  int ext[kMaxNs];
+  double ig[kMaxNs], imult[kMaxNs], imusign[kMaxNs], iemab[kMaxNs];
   double eps[kMaxNq];     // node energies [MeV]
   double w2[kMaxNq];      // w eps^2 dEps [MeV^3]
   double w3[kMaxNq];      // w2 eps [MeV^4]

@@ -115,7 +115,7 @@ class Params:
 @dataclass
 class LaunchConfig:
     blocks_per_cu: int = 0
-    chunk: int = 1
+    chunk: int = 4
     persistent: bool = True
 
     def c(self):
