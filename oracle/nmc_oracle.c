@@ -856,6 +856,13 @@ int ora_adjoint_batch(const ora_model* m, const double* theta, long P, double dt
 #pragma omp for schedule(dynamic, 16)
 #endif
     for (long p = 0; p < P; ++p) {
+      if (rho11[p] < m->rho11_min) {
+        /* coupling switched off (Sec. 7.2): the step passes the state
+         * through, so nothing depends on theta */
+        if (grad_pp)
+          for (int j = 0; j < nt; ++j) grad_pp[p * nt + j] = 0.0;
+        continue;
+      }
       double c0 = chi0 ? chi0[p] : m->chi_ref * rho11[p];
       const double* Dp = D + p * nn;
       jacobian_core(m, theta, dtau, rho11[p], c0, Dp, ye[p], e[p], J, w);

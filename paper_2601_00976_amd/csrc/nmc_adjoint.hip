@@ -1,7 +1,459 @@
-// Adjoint (implicit-function-theorem) kernels of the coupling solve.
-#include "nmc_internal.h"
+// Adjoint (implicit-function-theorem) kernels of the coupling solve on CDNA4.
+//
+// At the converged state x = (D, Ye, e) of a point the reduced residual
+//   R_D = D (1 + dtau chi) - D* - dtau eta          (Eq. implicitMomentsNodal, v = 0)
+//   R_Y = Ye - Ye* + K sum_s g_s sum_q W_q (D - D*)  (Eq. implicitFluidNodal)
+//   R_e = e  - e*  + K sum_s d_s sum_q W3_q (D - D*)
+// vanishes (the flux moments drop out: nothing depends on I when v = 0).
+// With J = dR/dx = [[A, B], [C, 1]] (A: moment block, B: the Ye / e columns
+// through T(e, Ye) and mu(Ye, T), C: the conservation rows) the transposed
+// system J^T lambda = dL/dx is solved by a Schur complement on the two matter
+// unknowns:
+//   Z = A^-T C^T,  (1 - B^T Z) lambda_m = (gY, -gE),  lambda_D = -Z lambda_m,
+// and dL/dtheta_j = -lambda_D^T dR_D/dtheta_j for theta = (s_1..s_nq, a_nes,
+// a_pair), L = gE (e* - e) + gY (Ye - Ye*).
+//
+// A is block diagonal over pair-coupled species: NES couples the nodes of one
+// species, pair processes couple a species with its partner, so with species
+// in id order the blocks are (nu_e, anti-nu_e) of size 64 and nu_x of size
+// 32.  Each block is factorised in registers, one wavefront per point: lane r
+// holds row r of A^T (column r of A) and the two right-hand sides.  Gaussian
+// elimination picks the pivot row by a wave-wide argmax over the lanes not yet
+// eliminated (partial pivoting without moving rows), broadcasts it through
+// LDS, and every other lane updates its row; back substitution runs over the
+// recorded pivot order.  Per-point terms go to a (P, nq + 2) array and are
+// summed over points by a fixed-order two-stage reduction.
+#include "nmc_wave.h"
 
-extern "C" int nmc_solve_batch_adjoint(const nmc_model*, int64_t, double, const nmc_batch_in*, const nmc_batch_out*,
-                                       const double*, double*, double*, void*, size_t, void*) {
-  return NMC_E_UNSUPPORTED;
+namespace nmc {
+namespace {
+
+constexpr int NQ = 32;
+
+template <int NS>
+struct AdjLds {
+  ModelLds m;
+  SplitExp E;
+  double tile[32 * kTileStride];
+  double D[NS][NQ];
+  double prow[64 + 2];  // pivot row of the current elimination step and its right-hand sides
+  // per-row results, row = (species, node)
+  double chi[NS][NQ];         // total opacity chi of the row
+  double b0[NS][NQ], b1[NS][NQ];  // dR_D / dYe, dR_D / de
+  double da[NS][NQ], dp[NS][NQ], ds[NS][NQ];  // dR_D / d a_nes, / d a_pair, / d s_q
+  double z0[NS][NQ], z1[NS][NQ];  // Z = A^-T C^T
+};
+
+__device__ __forceinline__ double wave_max(double v) {
+  v = fmax(v, dpp<0xB1>(v));
+  v = fmax(v, dpp<0x4E>(v));
+  v = fmax(v, dpp<0x141>(v));
+  v = fmax(v, dpp<0x140>(v));
+  double f, s;
+  swap16(v, f, s);
+  v = fmax(f, s);
+  swap32(v, f, s);
+  return fmax(f, s);
 }
+
+__device__ __forceinline__ double readlane_f64(double v, int lane) {
+  const uint32_t lo = __builtin_amdgcn_readlane((int)lo32(v), lane);
+  const uint32_t hi = __builtin_amdgcn_readlane((int)hi32(v), lane);
+  return mk64(lo, hi);
+}
+
+// Solves A^T z = c for one diagonal block of size N (lanes 0..N-1 active):
+// lane r enters with R = row r of A^T and c = (c0, c1) its right-hand sides
+// and leaves with (z0, z1) = entry r of the two solutions.  Returns false if
+// a pivot was zero or non-finite (the results are then not finite either).
+template <int N>
+__device__ __forceinline__ bool solve_block_transposed(double (&R)[N], double c0, double c1, double* prow,
+                                                       double& z0, double& z1) {
+  const int lane = opaque((int)threadIdx.x);
+  const bool active = lane < N;
+  bool done = !active;
+  int mystep = -1;
+  bool ok = true;
+  static_for<0, N>([&](auto kk) __attribute__((always_inline)) {
+    constexpr int k = decltype(kk)::value;
+    const double cand = done ? -1.0 : fabs(R[k]);
+    const double mx = wave_max(cand);
+    uint64_t bal = __builtin_amdgcn_ballot_w64(!done && cand == mx);
+    if (bal == 0) {
+      ok = false;
+      bal = __builtin_amdgcn_ballot_w64(!done);
+    }
+    const int pl = (int)__builtin_ctzll(bal);
+    if (lane == pl) {
+#pragma unroll
+      for (int j = k; j < N; ++j) prow[j] = R[j];
+      prow[N] = c0;
+      prow[N + 1] = c1;
+      mystep = k;
+      done = true;
+    }
+    __syncthreads();
+    const double piv = prow[k];
+    ok = ok && piv != 0.0 && isfinite(piv);
+    if (!done) {
+      const double l = R[k] / piv;
+#pragma unroll
+      for (int j = k + 1; j < N; ++j) {
+        R[j] = __builtin_fma(-l, prow[j], R[j]);
+        // keep at most a few pivot-row loads in flight (register pressure)
+        if ((j & 7) == 7) asm volatile("" ::: "memory");
+      }
+      c0 = __builtin_fma(-l, prow[N], c0);
+      c1 = __builtin_fma(-l, prow[N + 1], c1);
+    }
+    __syncthreads();
+  });
+  z0 = z1 = 0.0;
+  static_for<0, N>([&](auto kk) __attribute__((always_inline)) {
+    constexpr int k = N - 1 - decltype(kk)::value;
+    const uint64_t bal = __builtin_amdgcn_ballot_w64(mystep == k);
+    const int pl = bal ? (int)__builtin_ctzll(bal) : 0;
+    const double r = 1.0 / R[k];
+    const double zk0 = readlane_f64(c0 * r, pl), zk1 = readlane_f64(c1 * r, pl);
+    if (lane == k) {
+      z0 = zk0;
+      z1 = zk1;
+    }
+    if (mystep >= 0 && mystep < k) {
+      c0 = __builtin_fma(-R[k], zk0, c0);
+      c1 = __builtin_fma(-R[k], zk1, c1);
+    }
+  });
+  return ok;
+}
+
+template <int NS>
+struct PointAdjoint {
+  // Rows of A^T of one block of species [S0, S0 + NB): lane r = 32 si + p
+  // holds column (S0 + si, p) of A.  Entries (Jacobian of R_D):
+  //   same species (NES):  -dtau W_p [(1 - D_q) Phi_in[q][p] + D_q Phi_out[q][p]]
+  //   partner species:     +dtau W_p [D_q Phi_ann[q][p] + (1 - D_q) Phi_pro[q][p]]
+  //   diagonal:            1 + dtau chi_(s, p)
+  // with the kernels at the point's amplitudes; Phi_out[q][p] = Phi_in[p][q].
+  template <int S0, int NB>
+  __device__ __forceinline__ static void block_rows(AdjLds<NS>& S, double dtau, double an, double ap,
+                                                    double (&R)[32 * NB]) {
+    constexpr int ST = kTileStride;
+    constexpr int N = 32 * NB;
+    const int lane = opaque((int)threadIdx.x);  // laundered: lane-derived indices are not hoisted out of the point loop
+    const int h = lane >> 5, p = lane & 31;
+    const int si = NB == 2 ? h : 0;
+    const int sp = S0 + si;  // species of this lane's column
+    const double dw = dtau * S.m.w2[p];
+#pragma unroll
+    for (int r = 0; r < N; ++r) R[r] = 0.0;
+    // NES: row species = column species
+    fill_tile<kTilePhiIn>(S.m, S.E, an, h, p, S.tile);
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const double tin = S.tile[q * ST + p], tout = S.tile[p * ST + q];
+      const double d = S.D[sp][q];
+      const double v = -dw * __builtin_fma(d, tout - tin, tin);
+      if constexpr (NB == 2) {
+        R[q] += si == 0 ? v : 0.0;
+        R[32 + q] += si == 1 ? v : 0.0;
+      } else {
+        R[q] += v;
+      }
+      if ((q & 3) == 3) asm volatile("" ::: "memory");
+    }
+    __syncthreads();
+    // pair: rows of the partner species (the block's other species, or the
+    // species itself for nu_x)
+    fill_tile<kTilePhiAnn>(S.m, S.E, ap, h, p, S.tile);
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const double t = dw * S.tile[q * ST + p];
+      if constexpr (NB == 2) {
+        R[q] += si == 1 ? t * S.D[S0][q] : 0.0;
+        R[32 + q] += si == 0 ? t * S.D[S0 + 1][q] : 0.0;
+      } else {
+        R[q] += t * S.D[S0][q];
+      }
+      if ((q & 3) == 3) asm volatile("" ::: "memory");
+    }
+    __syncthreads();
+    fill_tile<kTilePhiPro>(S.m, S.E, ap, h, p, S.tile);
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const double t = dw * S.tile[q * ST + p];
+      if constexpr (NB == 2) {
+        R[q] += si == 1 ? t * (1.0 - S.D[S0][q]) : 0.0;
+        R[32 + q] += si == 0 ? t * (1.0 - S.D[S0 + 1][q]) : 0.0;
+      } else {
+        R[q] += t * (1.0 - S.D[S0][q]);
+      }
+      if ((q & 3) == 3) asm volatile("" ::: "memory");
+    }
+    __syncthreads();
+    const double diag = 1.0 + dtau * S.chi[sp][p];
+#pragma unroll
+    for (int r = 0; r < N; ++r) R[r] += (r == lane) ? diag : 0.0;
+  }
+
+  template <int S0, int NB>
+  __device__ __forceinline__ static bool block_solve(AdjLds<NS>& S, const DevModel* md, double dtau, double an,
+                                                     double ap, double K) {
+    double R[32 * NB];
+    block_rows<S0, NB>(S, dtau, an, ap, R);
+    const int lane = opaque((int)threadIdx.x);  // laundered: lane-derived indices are not hoisted out of the point loop
+    const int h = lane >> 5, p = lane & 31;
+    const int sp = S0 + (NB == 2 ? h : 0);
+    // right-hand sides: column (sp, p) of the conservation rows C
+    const double c0 = K * md->ig[sp] * S.m.w2[p];
+    const double c1 = K * md->imult[sp] * S.m.w3[p];
+    double z0, z1;
+    const bool ok = solve_block_transposed<32 * NB>(R, c0, c1, S.prow, z0, z1);
+    if (lane < 32 * NB) {
+      S.z0[sp][p] = z0;
+      S.z1[sp][p] = z1;
+    }
+    __syncthreads();
+    return ok;
+  }
+
+  __device__ static void run(const AdjArgs& a, int64_t pt, AdjLds<NS>& S) {
+    constexpr int ST = kTileStride;
+    constexpr int NT = NQ + 2;
+    const DevModel* __restrict__ md = a.mdl;
+    const int lane = opaque((int)threadIdx.x);  // laundered: lane-derived indices are not hoisted out of the point loop
+    const int h = lane >> 5, q = lane & 31;
+    double* gout = a.grad_pp + pt * NT;
+    if (a.status[pt] != NMC_STATUS_OK || a.n_outer[pt] == 0) {
+      // skipped or failed points contribute nothing
+      if (lane < NT) gout[lane] = 0.0;
+      return;
+    }
+    const int64_t base = pt * (int64_t)(NS * NQ);
+    if (lane < 32) {
+#pragma unroll
+      for (int t = 0; t < NS; ++t) S.D[t][lane] = a.D[base + md->ext[t] * NQ + lane];
+    }
+    const double rho = a.rho11[pt], ye = a.ye[pt], e = a.e[pt];
+    const double chi0 = a.chi0 ? a.chi0[pt] : md->chi_ref * rho;
+    const double dtau = a.dtau;
+    // EOS and its derivatives
+    const double r3 = cbrt(rho);
+    const double ia = 1.0 / (md->eos_a * (1.0 + ye));
+    const double T = (e - md->eos_b * ye43(ye) * r3) * ia;
+    const double mu = md->mu_a * (ye - md->mu_ye0) * r3 + md->mu_b * log(T / md->mu_t0);
+    const double invT = 1.0 / T;
+    const double dT_de = ia;
+    const double dT_dye = -(4.0 / 3.0) * md->eos_b * cbrt(ye) * r3 * ia - T / (1.0 + ye);
+    const double dmu_dye = md->mu_a * r3 + md->mu_b * invT * dT_dye;
+    const double dmu_de = md->mu_b * invT * dT_de;
+    const double K = md->kcoup / rho;
+    const unsigned flags = md->flags;
+    const double a_nes = (flags & NMC_NES) ? S.m.theta[NQ] : 0.0;
+    const double a_pair = (flags & NMC_PAIR) ? S.m.theta[NQ + 1] : 0.0;
+    split_exp_prepare(S.m, invT, S.E);
+
+    // ---- per-row contractions with unit-amplitude kernels (A = rho11) ----
+    // group 0: species h (ns >= 2) or 0 (ns = 1, lanes < 32); group 1: nu_x (ns = 3, lanes < 32)
+    constexpr int NG = NS == 3 ? 2 : 1;
+    int sg[NG], sbg[NG];
+    bool on[NG];
+    sg[0] = NS >= 2 ? h : 0;
+    on[0] = NS >= 2 || lane < 32;
+    if constexpr (NG == 2) {
+      sg[1] = 2;
+      on[1] = lane < 32;
+    }
+#pragma unroll
+    for (int g = 0; g < NG; ++g) sbg[g] = NS == 3 ? (sg[g] < 2 ? 1 - sg[g] : 2) : (NS == 2 ? 1 - sg[g] : 0);
+    const double eq = S.m.eps[q];
+    // en, on (NES in / out), an, ep (pair ann / pro) and their temperature
+    // derivatives times T^2
+    double en[NG], onn[NG], an[NG], ep[NG], dn[NG], dout[NG], dan[NG], dpr[NG];
+#pragma unroll
+    for (int g = 0; g < NG; ++g) en[g] = onn[g] = an[g] = ep[g] = dn[g] = dout[g] = dan[g] = dpr[g] = 0.0;
+    fill_tile<kTilePhiIn>(S.m, S.E, rho, h, q, S.tile);
+    __syncthreads();
+#pragma unroll 2
+    for (int p = 0; p < NQ; ++p) {
+      const double w = S.m.w2[p], dl = eq - S.m.eps[p], adl = fabs(dl);
+      const double tin = w * S.tile[q * ST + p], tout = w * S.tile[p * ST + q];
+#pragma unroll
+      for (int g = 0; g < NG; ++g) {
+        const double d = S.D[sg[g]][p];
+        en[g] = __builtin_fma(tin, d, en[g]);
+        dn[g] = __builtin_fma(tin * (adl + 0.5 * dl), d, dn[g]);
+        onn[g] = __builtin_fma(tout, 1.0 - d, onn[g]);
+        dout[g] = __builtin_fma(tout * (adl - 0.5 * dl), 1.0 - d, dout[g]);
+      }
+    }
+    __syncthreads();
+    fill_tile<kTilePhiAnn>(S.m, S.E, rho, h, q, S.tile);
+    __syncthreads();
+#pragma unroll 2
+    for (int p = 0; p < NQ; ++p) {
+      const double w = S.m.w2[p], adl = fabs(eq - S.m.eps[p]);
+      const double t = w * S.tile[q * ST + p];
+#pragma unroll
+      for (int g = 0; g < NG; ++g) {
+        const double d = S.D[sbg[g]][p];
+        an[g] = __builtin_fma(t, d, an[g]);
+        dan[g] = __builtin_fma(t * adl, d, dan[g]);
+      }
+    }
+    __syncthreads();
+    fill_tile<kTilePhiPro>(S.m, S.E, rho, h, q, S.tile);
+    __syncthreads();
+#pragma unroll 2
+    for (int p = 0; p < NQ; ++p) {
+      const double w = S.m.w2[p], epp = S.m.eps[p], adl = fabs(eq - epp);
+      const double t = w * S.tile[q * ST + p];
+#pragma unroll
+      for (int g = 0; g < NG; ++g) {
+        const double d = 1.0 - S.D[sbg[g]][p];
+        ep[g] = __builtin_fma(t, d, ep[g]);
+        dpr[g] = __builtin_fma(t * (adl + eq + epp), d, dpr[g]);
+      }
+    }
+    __syncthreads();
+    // ---- per-row Jacobian pieces ----------------------------------------
+    {
+      const double shape = chi0 * S.m.shape[q];
+      const double iT2 = invT * invT;
+#pragma unroll
+      for (int g = 0; g < NG; ++g) {
+        if (!on[g]) continue;
+        const int s = sg[g];
+        const double chia = (flags & NMC_EMAB) ? md->iemab[s] * S.m.theta[q] * shape : 0.0;
+        const double x = (eq - md->imusign[s] * mu) * invT;
+        const double ex = exp(-fabs(x));
+        const double r = 1.0 / (1.0 + ex);
+        const double f = x > 0.0 ? ex * r : r;   // Fermi-Dirac D_eq
+        const double fc = x > 0.0 ? r : ex * r;  // 1 - D_eq
+        const double ddeq_dT = f * fc * x * invT;
+        const double ddeq_dmu = f * fc * md->imusign[s] * invT;
+        const double Dq = S.D[s][q];
+        const double chi = chia + a_nes * (en[g] + onn[g]) + a_pair * (ep[g] + an[g]);
+        const double deta_dT = chia * ddeq_dT + (a_nes * dn[g] + a_pair * dpr[g]) * iT2;
+        const double dchi_dT = (a_nes * (dn[g] + dout[g]) + a_pair * (dpr[g] + dan[g])) * iT2;
+        const double dR_dT = dtau * (Dq * dchi_dT - deta_dT);
+        const double dR_dmu = -dtau * chia * ddeq_dmu;
+        S.chi[s][q] = chi;
+        S.b0[s][q] = dR_dT * dT_dye + dR_dmu * dmu_dye;
+        S.b1[s][q] = dR_dT * dT_de + dR_dmu * dmu_de;
+        S.da[s][q] = (flags & NMC_NES) ? dtau * (Dq * (en[g] + onn[g]) - en[g]) : 0.0;
+        S.dp[s][q] = (flags & NMC_PAIR) ? dtau * (Dq * (ep[g] + an[g]) - ep[g]) : 0.0;
+        S.ds[s][q] = (flags & NMC_EMAB) ? dtau * shape * md->iemab[s] * (Dq - f) : 0.0;
+      }
+    }
+    __syncthreads();
+
+    // ---- Z = A^-T C^T, block by block ------------------------------------
+    const double amp_n = a_nes * rho, amp_p = a_pair * rho;
+    bool ok;
+    if constexpr (NS == 1) {
+      ok = block_solve<0, 1>(S, md, dtau, amp_n, amp_p, K);
+    } else {
+      ok = block_solve<0, 2>(S, md, dtau, amp_n, amp_p, K);
+      if constexpr (NS == 3) ok = block_solve<2, 1>(S, md, dtau, amp_n, amp_p, K) && ok;
+    }
+
+    // ---- Schur complement on (Ye, e), multipliers and gradient ------------
+    double v4[4] = {0.0, 0.0, 0.0, 0.0};
+    if (lane < 32) {
+#pragma unroll
+      for (int t = 0; t < NS; ++t) {
+        v4[0] += S.b0[t][q] * S.z0[t][q];
+        v4[1] += S.b0[t][q] * S.z1[t][q];
+        v4[2] += S.b1[t][q] * S.z0[t][q];
+        v4[3] += S.b1[t][q] * S.z1[t][q];
+      }
+    }
+    double bz[4];
+    wave_sums4(v4, bz);
+    const double s00 = 1.0 - bz[0], s01 = -bz[1], s10 = -bz[2], s11 = 1.0 - bz[3];
+    const double g_e = a.gbar[2 * pt], g_y = a.gbar[2 * pt + 1];
+    const double r0 = g_y, r1 = -g_e;  // dL/dYe, dL/de
+    const double idet = 1.0 / (s00 * s11 - s01 * s10);
+    const double l0 = (s11 * r0 - s01 * r1) * idet;
+    const double l1 = (s00 * r1 - s10 * r0) * idet;
+    double gq = 0.0, v2[4] = {0.0, 0.0, 0.0, 0.0};
+    if (lane < 32) {
+#pragma unroll
+      for (int t = 0; t < NS; ++t) {
+        const double lam = -(S.z0[t][q] * l0 + S.z1[t][q] * l1);
+        gq -= lam * S.ds[t][q];
+        v2[0] -= lam * S.da[t][q];
+        v2[1] -= lam * S.dp[t][q];
+      }
+    }
+    double gs[4];
+    wave_sums4(v2, gs);
+    const double nan = __builtin_nan("");
+    if (lane < 32) gout[lane] = ok ? gq : nan;
+    if (lane == 32) gout[NQ] = ok ? gs[0] : nan;
+    if (lane == 33) gout[NQ + 1] = ok ? gs[1] : nan;
+    __syncthreads();
+  }
+};
+
+template <int NS>
+__global__ __launch_bounds__(kLanes) void adj_kernel(AdjArgs a) {
+  __shared__ AdjLds<NS> S;
+  load_model(a.mdl, a.theta, S.m);
+  for (int64_t p = blockIdx.x; p < a.P; p += gridDim.x) PointAdjoint<NS>::run(a, p, S);
+}
+
+// Column sums of a (P, ncol) row-major array in a fixed order: block b sums
+// its contiguous range of rows, then one block adds the block partials in
+// order into out (accumulating).
+__global__ void reduce_stage1(const double* __restrict__ x, int64_t P, int ncol, int64_t rows_per_block,
+                              double* __restrict__ partial) {
+  const int c = threadIdx.x;
+  if (c >= ncol) return;
+  const int64_t r0 = (int64_t)blockIdx.x * rows_per_block;
+  const int64_t r1 = r0 + rows_per_block < P ? r0 + rows_per_block : P;
+  double s = 0.0;
+  for (int64_t r = r0; r < r1; ++r) s += x[r * ncol + c];
+  partial[(int64_t)blockIdx.x * ncol + c] = s;
+}
+
+__global__ void reduce_stage2(const double* __restrict__ partial, int nblk, int ncol, double* __restrict__ out) {
+  const int c = threadIdx.x;
+  if (c >= ncol) return;
+  double s = 0.0;
+  for (int b = 0; b < nblk; ++b) s += partial[(int64_t)b * ncol + c];
+  out[c] += s;
+}
+
+}  // namespace
+
+hipError_t launch_adjoint(const AdjArgs& a, int nq, int ns, int num_cu, hipStream_t s) {
+  if (nq != NQ || ns < 1 || ns > 3) return hipErrorInvalidValue;
+  if (a.P == 0) return hipSuccess;
+  const int64_t want = (int64_t)num_cu * 16;
+  const unsigned grid = (unsigned)(a.P < want ? a.P : want);
+  switch (ns) {
+    case 1: hipLaunchKernelGGL(adj_kernel<1>, dim3(grid), dim3(kLanes), 0, s, a); break;
+    case 2: hipLaunchKernelGGL(adj_kernel<2>, dim3(grid), dim3(kLanes), 0, s, a); break;
+    default: hipLaunchKernelGGL(adj_kernel<3>, dim3(grid), dim3(kLanes), 0, s, a); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_columns(const double* x, int64_t P, int ncol, double* partial, double* out,
+                                 hipStream_t s) {
+  if (P == 0) return hipSuccess;
+  if (ncol > 256) return hipErrorInvalidValue;
+  const int64_t nblk = P < kReduceBlocks ? P : kReduceBlocks;
+  const int64_t rows = (P + nblk - 1) / nblk;
+  const int64_t used = (P + rows - 1) / rows;
+  hipLaunchKernelGGL(reduce_stage1, dim3((unsigned)used), dim3(256), 0, s, x, P, ncol, rows, partial);
+  hipLaunchKernelGGL(reduce_stage2, dim3(1), dim3(256), 0, s, partial, (int)used, ncol, out);
+  return hipGetLastError();
+}
+
+}  // namespace nmc

@@ -269,7 +269,7 @@ size_t nmc_workspace_bytes(const nmc_model* m, int64_t P) {
   // queue counter + per-point adjoint terms and a column-partial buffer
   const size_t nt = (size_t)m->host.nq + 2;
   const size_t pp = ((size_t)P * nt * sizeof(double) + 255) & ~(size_t)255;
-  const size_t part = ((size_t)1024 * nt * sizeof(double) + 255) & ~(size_t)255;
+  const size_t part = ((size_t)nmc::kReduceBlocks * nt * sizeof(double) + 255) & ~(size_t)255;
   return kCounterBytes + pp + part;
 }
 
@@ -348,6 +348,45 @@ int nmc_solve_batch(const nmc_model* m, const nmc_solver_params* prm, int64_t P,
   hipError_t e = nmc::launch_forward(a, m->host.nq, m->host.ns, coupled, L, m->num_cu, s);
   if (e == hipErrorInvalidValue) return fail(NMC_E_UNSUPPORTED, "solve_batch: no kernel for nq=%d ns=%d", m->host.nq, m->host.ns);
   if (e != hipSuccess) return hip_fail(e, "solve_batch: launch");
+  return NMC_OK;
+}
+
+int nmc_solve_batch_adjoint(const nmc_model* m, int64_t P, double dtau, const nmc_batch_in* in,
+                            const nmc_batch_out* fwd, const double* gbar, double* grad_theta, double* grad_pp,
+                            void* ws, size_t ws_bytes, void* stream) {
+  if (!m || !in || !fwd) return fail(NMC_E_INVALID_ARG, "adjoint: null model, inputs or forward outputs");
+  if (P < 0 || P > (int64_t(1) << 30)) return fail(NMC_E_INVALID_ARG, "adjoint: P out of range");
+  if (!(dtau > 0.0) || !isfinite(dtau)) return fail(NMC_E_INVALID_ARG, "adjoint: dtau must be positive and finite");
+  if (!grad_theta) return fail(NMC_E_INVALID_ARG, "adjoint: null grad_theta");
+  if (m->host.nq != 32) return fail(NMC_E_UNSUPPORTED, "adjoint: implemented for 32 energy nodes (model has %d)", m->host.nq);
+  if (P == 0) return NMC_OK;
+  if (!in->rho11 || !in->theta || !fwd->D || !fwd->ye || !fwd->e || !fwd->status || !fwd->n_outer || !gbar)
+    return fail(NMC_E_INVALID_ARG, "adjoint: null array");
+  if (!ws || !aligned256(ws) || ws_bytes < nmc_workspace_bytes(m, P))
+    return fail(NMC_E_WORKSPACE, "adjoint: workspace must be 256-byte aligned and at least nmc_workspace_bytes");
+  const int nt = m->host.nq + 2;
+  const size_t pp = ((size_t)P * nt * sizeof(double) + 255) & ~(size_t)255;
+  char* w = (char*)ws + kCounterBytes;
+  nmc::AdjArgs a;
+  memset(&a, 0, sizeof(a));
+  a.mdl = m->dev;
+  a.P = P;
+  a.dtau = dtau;
+  a.rho11 = in->rho11;
+  a.chi0 = in->chi0;
+  a.theta = in->theta;
+  a.D = fwd->D;
+  a.ye = fwd->ye;
+  a.e = fwd->e;
+  a.status = fwd->status;
+  a.n_outer = fwd->n_outer;
+  a.gbar = gbar;
+  a.grad_pp = grad_pp ? grad_pp : (double*)w;
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = nmc::launch_adjoint(a, m->host.nq, m->host.ns, m->num_cu, s);
+  if (e != hipSuccess) return hip_fail(e, "adjoint: launch");
+  e = nmc::launch_reduce_columns(a.grad_pp, P, nt, (double*)(w + pp), grad_theta, s);
+  if (e != hipSuccess) return hip_fail(e, "adjoint: reduction");
   return NMC_OK;
 }
 

@@ -19,326 +19,16 @@
 // combined with v_permlane32_swap; moment vectors are redistributed with
 // v_permlane16_swap.  Weighted norms and Anderson inner products are reduced
 // through LDS.
-#include <type_traits>
-#include <utility>
-
-#include "nmc_internal.h"
+#include "nmc_wave.h"
 
 namespace nmc {
 namespace {
 
-constexpr int kLanes = 64;
-
-template <int I, int N, class F>
-__device__ __forceinline__ void static_for(F&& f) {
-  if constexpr (I < N) {
-    f(std::integral_constant<int, I>{});
-    static_for<I + 1, N>(f);
-  }
-}
-
-// DPP lane permutation within 16-lane rows for controls that read a valid
-// lane for every lane (quad_perm, row mirrors), so no "old" value is needed
-template <int CTRL>
-__device__ __forceinline__ double dpp(double x) {
-  const long v = __builtin_amdgcn_mov_dpp(__builtin_bit_cast(long, x), CTRL, 0xF, 0xF, false);
-  return __builtin_bit_cast(double, v);
-}
-
-// broadcast lane I of every 16-lane row to the whole row (row_newbcast:I);
-// every lane is written, so no "old" operand is needed
-template <int I>
-__device__ __forceinline__ double row_bcast(double x) {
-  const long v = __builtin_amdgcn_mov_dpp(__builtin_bit_cast(long, x), 0x150 + I, 0xF, 0xF, false);
-  return __builtin_bit_cast(double, v);
-}
-
-__device__ __forceinline__ uint32_t lo32(double x) { return (uint32_t)__builtin_bit_cast(uint64_t, x); }
-__device__ __forceinline__ uint32_t hi32(double x) { return (uint32_t)(__builtin_bit_cast(uint64_t, x) >> 32); }
-__device__ __forceinline__ double mk64(uint32_t lo, uint32_t hi) {
-  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
-}
-
-// v_permlane16_swap(v, v): first = rows (0,0,2,2) of v, second = rows (1,1,3,3)
-__device__ __forceinline__ void swap16(double v, double& first, double& second) {
-  auto a = __builtin_amdgcn_permlane16_swap(lo32(v), lo32(v), false, false);
-  auto b = __builtin_amdgcn_permlane16_swap(hi32(v), hi32(v), false, false);
-  first = mk64(a[0], b[0]);
-  second = mk64(a[1], b[1]);
-}
-
-// v_permlane32_swap(v, v): first = lanes 0..31 of v in both halves, second = lanes 32..63
-__device__ __forceinline__ void swap32(double v, double& first, double& second) {
-  auto a = __builtin_amdgcn_permlane32_swap(lo32(v), lo32(v), false, false);
-  auto b = __builtin_amdgcn_permlane32_swap(hi32(v), hi32(v), false, false);
-  first = mk64(a[0], b[0]);
-  second = mk64(a[1], b[1]);
-}
-
-// lower-half value + upper-half value, identical bits in every lane
-__device__ __forceinline__ double sum_halves(double v) {
-  double f, s;
-  swap32(v, f, s);
-  return f + s;
-}
-
-// Per-half sums of V lane values through LDS: s0[k] = sum over lanes 0..31,
-// s1[k] = sum over lanes 32..63.  Four lanes share each of the 2V sums; lane
-// r of a group adds the entries r, r + 4, ..., r + 28 of its half, starting
-// at a group-dependent rotation so that the 16 lanes of every LDS access
-// cycle hit 16 different banks.  Fixed summation order (deterministic).
-template <int V>
-__device__ __forceinline__ void half_sums(const double (&v)[V], double (&s0)[V], double (&s1)[V], double* red,
-                                          double* redout) {
-  static_assert(2 * V <= 16, "at most 16 sums");
-  const int l = threadIdx.x;
-  __syncthreads();
-#pragma unroll
-  for (int k = 0; k < V; ++k) red[k * kLanes + l] = v[k];
-  __syncthreads();
-  const int sidx = l >> 2, r = l & 3;
-  double acc = 0.0;
-  if (sidx < 2 * V) {
-    const int hh = sidx / V, k = sidx - hh * V;
-    const double* b = red + k * kLanes + hh * 32;
-    const int rot = sidx & 3;
-    double part[8];
-#pragma unroll
-    for (int i = 0; i < 8; ++i) part[i] = b[(r + 4 * ((i + rot) & 7)) & 31];
-    acc = ((part[0] + part[1]) + (part[2] + part[3])) + ((part[4] + part[5]) + (part[6] + part[7]));
-  }
-  acc += dpp<0xB1>(acc);  // quad_perm [1,0,3,2]
-  acc += dpp<0x4E>(acc);  // quad_perm [2,3,0,1]
-  if (r == 0 && sidx < 2 * V) redout[sidx] = acc;
-  __syncthreads();
-#pragma unroll
-  for (int k = 0; k < V; ++k) {
-    s0[k] = redout[k];
-    s1[k] = redout[V + k];
-  }
-}
-
-// Register-only reductions (no LDS round trip).  Within a 16-lane row the
-// butterfly xor 1, xor 2 (quad_perm), half-row mirror and row mirror leaves
-// the row total in every lane, bitwise identical across the row.
-__device__ __forceinline__ double row_allsum(double v) {
-  v += dpp<0xB1>(v);   // quad_perm [1,0,3,2]
-  v += dpp<0x4E>(v);   // quad_perm [2,3,0,1]
-  v += dpp<0x141>(v);  // row_half_mirror
-  v += dpp<0x140>(v);  // row_mirror
-  return v;
-}
-
-// a from lanes 0..31 and b from lanes 32..63 halved into one register:
-// lanes 0..31 get a(l) + a(l + 32), lanes 32..63 get b(l - 32) + b(l)
-__device__ __forceinline__ double halve32(double a, double b) {
-  auto x = __builtin_amdgcn_permlane32_swap(lo32(a), lo32(b), false, false);
-  auto y = __builtin_amdgcn_permlane32_swap(hi32(a), hi32(b), false, false);
-  return mk64(x[0], y[0]) + mk64(x[1], y[1]);
-}
-
-// rows (0, 2) keep a summed with the partner row, rows (1, 3) keep b
-__device__ __forceinline__ double halve16(double a, double b) {
-  auto x = __builtin_amdgcn_permlane16_swap(lo32(a), lo32(b), false, false);
-  auto y = __builtin_amdgcn_permlane16_swap(hi32(a), hi32(b), false, false);
-  return mk64(x[0], y[0]) + mk64(x[1], y[1]);
-}
-
-// Sums of 4 values over all 64 lanes, returned in every lane.
-__device__ __forceinline__ void wave_sums4(const double (&v)[4], double (&out)[4]) {
-  // lanes 0..31: (v0, v1) over the wave halves; lanes 32..63: (v2, v3)
-  const double h01 = halve32(v[0], v[2]);
-  const double h23 = halve32(v[1], v[3]);
-  // row r now carries slot r summed over 4 lanes per column
-  const double r = row_allsum(halve16(h01, h23));
-  // rows (0,0,2,2) and (1,1,3,3), then both halves
-  double f, sc;
-  swap16(r, f, sc);
-  double f0, f1, s0, s1;
-  swap32(f, f0, f1);
-  swap32(sc, s0, s1);
-  out[0] = f0;
-  out[1] = s0;
-  out[2] = f1;
-  out[3] = s1;
-}
-
-// Per-half sums of 2 K values (K = 1..3): s0 over lanes 0..31, s1 over lanes
-// 32..63, returned in every lane.
-template <int K>
-__device__ __forceinline__ void half_sums_reg(const double (&v)[2 * K], double (&s0)[2 * K], double (&s1)[2 * K]) {
-#pragma unroll
-  for (int k = 0; k < K; ++k) {
-    // rows (0, 2): slot k over the row pair; rows (1, 3): slot K + k
-    const double r = row_allsum(halve16(v[k], v[K + k]));
-    double f, sc;
-    swap16(r, f, sc);  // f: slot k of this half, sc: slot K + k
-    double a0, a1, b0, b1;
-    swap32(f, a0, a1);
-    swap32(sc, b0, b1);
-    s0[k] = a0;
-    s1[k] = a1;
-    s0[K + k] = b0;
-    s1[K + k] = b1;
-  }
-}
-
-__device__ __forceinline__ bool wave_any(bool b) { return __builtin_amdgcn_ballot_w64(b) != 0; }
-
-// Opaque copies: values derived from these are recomputed where they are
-// used instead of being hoisted out of the outer loop (hoisted invariants
-// end up spilled, which costs far more than recomputing them).
-__device__ __forceinline__ int opaque(int x) {
-  asm volatile("" : "+v"(x));
-  return x;
-}
-template <class T>
-__device__ __forceinline__ const T* opaque_ptr(const T* p) {
-  asm volatile("" : "+s"(p));
-  return p;
-}
-
-// Four columns of the contraction for every species and both matrices in one
-// asm block: acc1[t] += bcast(x[t], L0 + jj) * m1[jj], acc2[t] += bcast(x[t], L0 + jj) * m2[jj].
-// The leading s_nop 1 provides the two wait states a DPP source needs after
-// a VALU write, whatever the compiler schedules before the block.
-template <int NS>
-struct Fmac4;
-
-template <>
-struct Fmac4<1> {
-  template <int L0>
-  __device__ __forceinline__ static void run(double (&a1)[1], double (&a2)[1], const double (&x)[1], double m10,
-                                             double m11, double m12, double m13, double m20, double m21, double m22,
-                                             double m23) {
-    asm volatile(
-        "s_nop 1\n"
-        "v_fmac_f64_dpp %0, %2, %3 row_newbcast:%11 row_mask:0xf bank_mask:0xf\n"
-        "v_fmac_f64_dpp %1, %2, %7 row_newbcast:%11 row_mask:0xf bank_mask:0xf\n"
-        "v_fmac_f64_dpp %0, %2, %4 row_newbcast:%12 row_mask:0xf bank_mask:0xf\n"
-        "v_fmac_f64_dpp %1, %2, %8 row_newbcast:%12 row_mask:0xf bank_mask:0xf\n"
-        "v_fmac_f64_dpp %0, %2, %5 row_newbcast:%13 row_mask:0xf bank_mask:0xf\n"
-        "v_fmac_f64_dpp %1, %2, %9 row_newbcast:%13 row_mask:0xf bank_mask:0xf\n"
-        "v_fmac_f64_dpp %0, %2, %6 row_newbcast:%14 row_mask:0xf bank_mask:0xf\n"
-        "v_fmac_f64_dpp %1, %2, %10 row_newbcast:%14 row_mask:0xf bank_mask:0xf\n"
-        : "+v"(a1[0]), "+v"(a2[0])
-        : "v"(x[0]), "v"(m10), "v"(m11), "v"(m12), "v"(m13), "v"(m20), "v"(m21), "v"(m22), "v"(m23), "i"(L0),
-          "i"(L0 + 1), "i"(L0 + 2), "i"(L0 + 3));
-  }
-};
-
-template <>
-struct Fmac4<2> {
-  template <int L0>
-  __device__ __forceinline__ static void run(double (&a1)[2], double (&a2)[2], const double (&x)[2], double m10,
-                                             double m11, double m12, double m13, double m20, double m21, double m22,
-                                             double m23) {
-    asm volatile(
-        "s_nop 1\n"
-        "v_fmac_f64_dpp %0, %4, %6 row_newbcast:%14 row_mask:0xf bank_mask:0xf\n"
-        "v_fmac_f64_dpp %1, %5, %6 row_newbcast:%14 row_mask:0xf bank_mask:0xf\n"
-        "v_fmac_f64_dpp %2, %4, %10 row_newbcast:%14 row_mask:0xf bank_mask:0xf\n"
-        "v_fmac_f64_dpp %3, %5, %10 row_newbcast:%14 row_mask:0xf bank_mask:0xf\n"
-        "v_fmac_f64_dpp %0, %4, %7 row_newbcast:%15 row_mask:0xf bank_mask:0xf\n"
-        "v_fmac_f64_dpp %1, %5, %7 row_newbcast:%15 row_mask:0xf bank_mask:0xf\n"
-        "v_fmac_f64_dpp %2, %4, %11 row_newbcast:%15 row_mask:0xf bank_mask:0xf\n"
-        "v_fmac_f64_dpp %3, %5, %11 row_newbcast:%15 row_mask:0xf bank_mask:0xf\n"
-        "v_fmac_f64_dpp %0, %4, %8 row_newbcast:%16 row_mask:0xf bank_mask:0xf\n"
-        "v_fmac_f64_dpp %1, %5, %8 row_newbcast:%16 row_mask:0xf bank_mask:0xf\n"
-        "v_fmac_f64_dpp %2, %4, %12 row_newbcast:%16 row_mask:0xf bank_mask:0xf\n"
-        "v_fmac_f64_dpp %3, %5, %12 row_newbcast:%16 row_mask:0xf bank_mask:0xf\n"
-        "v_fmac_f64_dpp %0, %4, %9 row_newbcast:%17 row_mask:0xf bank_mask:0xf\n"
-        "v_fmac_f64_dpp %1, %5, %9 row_newbcast:%17 row_mask:0xf bank_mask:0xf\n"
-        "v_fmac_f64_dpp %2, %4, %13 row_newbcast:%17 row_mask:0xf bank_mask:0xf\n"
-        "v_fmac_f64_dpp %3, %5, %13 row_newbcast:%17 row_mask:0xf bank_mask:0xf\n"
-        : "+v"(a1[0]), "+v"(a1[1]), "+v"(a2[0]), "+v"(a2[1])
-        : "v"(x[0]), "v"(x[1]), "v"(m10), "v"(m11), "v"(m12), "v"(m13), "v"(m20), "v"(m21), "v"(m22), "v"(m23),
-          "i"(L0), "i"(L0 + 1), "i"(L0 + 2), "i"(L0 + 3));
-  }
-};
-
-template <>
-struct Fmac4<3> {
-  template <int L0>
-  __device__ __forceinline__ static void run(double (&a1)[3], double (&a2)[3], const double (&x)[3], double m10,
-                                             double m11, double m12, double m13, double m20, double m21, double m22,
-                                             double m23) {
-    asm volatile(
-        "s_nop 1\n"
-        "v_fmac_f64_dpp %0, %6, %9 row_newbcast:%17 row_mask:0xf bank_mask:0xf\n"
-        "v_fmac_f64_dpp %1, %7, %9 row_newbcast:%17 row_mask:0xf bank_mask:0xf\n"
-        "v_fmac_f64_dpp %2, %8, %9 row_newbcast:%17 row_mask:0xf bank_mask:0xf\n"
-        "v_fmac_f64_dpp %3, %6, %13 row_newbcast:%17 row_mask:0xf bank_mask:0xf\n"
-        "v_fmac_f64_dpp %4, %7, %13 row_newbcast:%17 row_mask:0xf bank_mask:0xf\n"
-        "v_fmac_f64_dpp %5, %8, %13 row_newbcast:%17 row_mask:0xf bank_mask:0xf\n"
-        "v_fmac_f64_dpp %0, %6, %10 row_newbcast:%18 row_mask:0xf bank_mask:0xf\n"
-        "v_fmac_f64_dpp %1, %7, %10 row_newbcast:%18 row_mask:0xf bank_mask:0xf\n"
-        "v_fmac_f64_dpp %2, %8, %10 row_newbcast:%18 row_mask:0xf bank_mask:0xf\n"
-        "v_fmac_f64_dpp %3, %6, %14 row_newbcast:%18 row_mask:0xf bank_mask:0xf\n"
-        "v_fmac_f64_dpp %4, %7, %14 row_newbcast:%18 row_mask:0xf bank_mask:0xf\n"
-        "v_fmac_f64_dpp %5, %8, %14 row_newbcast:%18 row_mask:0xf bank_mask:0xf\n"
-        "v_fmac_f64_dpp %0, %6, %11 row_newbcast:%19 row_mask:0xf bank_mask:0xf\n"
-        "v_fmac_f64_dpp %1, %7, %11 row_newbcast:%19 row_mask:0xf bank_mask:0xf\n"
-        "v_fmac_f64_dpp %2, %8, %11 row_newbcast:%19 row_mask:0xf bank_mask:0xf\n"
-        "v_fmac_f64_dpp %3, %6, %15 row_newbcast:%19 row_mask:0xf bank_mask:0xf\n"
-        "v_fmac_f64_dpp %4, %7, %15 row_newbcast:%19 row_mask:0xf bank_mask:0xf\n"
-        "v_fmac_f64_dpp %5, %8, %15 row_newbcast:%19 row_mask:0xf bank_mask:0xf\n"
-        "v_fmac_f64_dpp %0, %6, %12 row_newbcast:%20 row_mask:0xf bank_mask:0xf\n"
-        "v_fmac_f64_dpp %1, %7, %12 row_newbcast:%20 row_mask:0xf bank_mask:0xf\n"
-        "v_fmac_f64_dpp %2, %8, %12 row_newbcast:%20 row_mask:0xf bank_mask:0xf\n"
-        "v_fmac_f64_dpp %3, %6, %16 row_newbcast:%20 row_mask:0xf bank_mask:0xf\n"
-        "v_fmac_f64_dpp %4, %7, %16 row_newbcast:%20 row_mask:0xf bank_mask:0xf\n"
-        "v_fmac_f64_dpp %5, %8, %16 row_newbcast:%20 row_mask:0xf bank_mask:0xf\n"
-        : "+v"(a1[0]), "+v"(a1[1]), "+v"(a1[2]), "+v"(a2[0]), "+v"(a2[1]), "+v"(a2[2])
-        : "v"(x[0]), "v"(x[1]), "v"(x[2]), "v"(m10), "v"(m11), "v"(m12), "v"(m13), "v"(m20), "v"(m21), "v"(m22),
-          "v"(m23), "i"(L0), "i"(L0 + 1), "i"(L0 + 2), "i"(L0 + 3));
-  }
-};
-
-// reciprocal of x >= 1 (finite): hardware estimate refined by two Newton steps
-__device__ __forceinline__ double rcp_ge1(double x) {
-  double r = __builtin_amdgcn_rcp(x);
-  double e = __builtin_fma(-x, r, 1.0);
-  r = __builtin_fma(r, e, r);
-  e = __builtin_fma(-x, r, 1.0);
-  return __builtin_fma(r, e, r);
-}
-
 // Per-wave LDS scratch of the point solver: per-lane arrays, reduction
 // staging, and the uniform per-point state of the outer (matter) loop, kept
 // here so that it does not occupy VGPRs across the inner loop.
-// Per-node model tables copied into LDS once per work-group (lane-indexed
-// reads of them are then LDS hits); the uniform scalars of the model stay in
-// the global table, where the scalar cache serves them.
-struct ModelLds {
-  double eps[32], w2[32], w3[32], shape[32];
-  double theta[34];  // per-node EmAb scales, a_nes, a_pair
-};
-
-__device__ __forceinline__ void load_model(const DevModel* __restrict__ md, const double* __restrict__ theta,
-                                           ModelLds& m) {
-  const int l = threadIdx.x;
-  if (l < 32) {
-    m.eps[l] = md->eps[l];
-    m.w2[l] = md->w2[l];
-    m.w3[l] = md->w3[l];
-    m.shape[l] = md->shape[l];
-  }
-  if (l < 34) m.theta[l] = theta[l];
-  __syncthreads();
-}
-
-// Pair partner of internal species s (species sorted by id: nu_e, anti-nu_e
-// are partners, nu_x is its own partner).  Models without pair processes
-// have zero pair kernels, so the map is irrelevant for them.
-template <int NS>
-__device__ __forceinline__ constexpr int pair_partner(int s) {
-  return NS == 3 ? (s < 2 ? 1 - s : 2) : (NS == 2 ? 1 - s : 0);
-}
-
 template <int NS>
 struct WaveLds {
-  static constexpr int kStride = 33;  // padded row stride of the 32 x 32 build tile
   ModelLds m;
   double mst[NS][kLanes];   // owned moment of the old state (D* or I*)
   double base[NS][kLanes];  // D* + dtau chi^EmAb D_eq (number lanes) or I* (flux lanes)
@@ -349,19 +39,15 @@ struct WaveLds {
       double red[2 * NS * kLanes];  // reduction staging
       double redout[16];
     } it;                       // live during an inner loop
-    double tile[32 * kStride];  // kernel-row assembly, live while building
+    double tile[32 * kTileStride];  // kernel-row assembly, live while building
   } u;
-  // per-node factors of the current temperature (kernel build)
-  double P2[32], R2[32], G[32];
-  int n2[32];
+  SplitExp E;  // per-node factors of the current temperature (kernel build)
   // uniform per-point state
   double dref[NS];                      // ||D_s^[k,1]||_W^2 of the current inner loop
   double y[2];                          // matter iterate (Ye, e)
   double oq[2], of[2], odq[2], odf[2];  // outer Anderson history
   double T_last, r3, K, An, Ap;
 };
-
-__device__ __forceinline__ double ye43(double ye) { return ye * cbrt(ye); }
 
 template <int NS, int NQ, bool COUPLED>
 struct PointSolver {
@@ -390,76 +76,25 @@ struct PointSolver {
     });
   }
 
-  // Kernel rows at temperature T (Eqs. nesRatesNodal, pairRatesNodal with the
-  // kernels of Eqs. inOutInvarianceNES ... detailedBalancePair).  With
-  // b = exp(-(e_hi - e_lo) / (2T)) for e_hi >= e_lo and G_x = exp(-2 e_x / T):
-  //   Phi_in[hi][lo] = A e e' b^3,  Phi_in[lo][hi] = A e e' b,  Phi_out = Phi_in^T,
-  //   Phi_ann = A' e e' b^2,  Phi_pro = A' e e' G_hi  (both symmetric).
-  // b is assembled from per-node exponent splits x = e log2(e) / (2T) =
-  // n + f, P = 2^f, R = 2^-f:  b = ldexp(P_lo R_hi, n_lo - n_hi), so every
-  // factor stays <= 1 and nothing overflows at low temperature.  The 528
-  // unordered node pairs are spread over the 64 lanes by the model's pair
-  // schedule and written into a padded LDS tile, three times: Phi_in
-  // (number lanes load row q, flux lanes column q = row q of Phi_out),
-  // Phi_ann (number lanes load row q), Phi_pro (flux lanes load row q).
+  // Kernel rows at temperature T, assembled in the LDS tile three times:
+  // Phi_in (number lanes load row q, flux lanes column q = row q of
+  // Phi_out), Phi_ann (number lanes load row q), Phi_pro (flux lanes load
+  // row q).
   __device__ __forceinline__ static void build_rows(int h, int q, double invT, double An, double Ap, WaveLds<NS>& S,
                                                     double (&M1)[NQ], double (&M2)[NQ]) {
-    constexpr int ST = WaveLds<NS>::kStride;
-    const int lane = threadIdx.x;
-    const ModelLds& m = S.m;
-    if (lane < 32) {
-      const double e = m.eps[lane];
-      const double x = e * (0.5 * invT) * 1.4426950408889634;  // log2(e)
-      const double n = floor(x);
-      const double P = exp2(x - n);
-      S.P2[lane] = P;
-      S.R2[lane] = rcp_ge1(P);
-      S.n2[lane] = (int)n;
-      S.G[lane] = exp(-2.0 * e * invT);
-    }
+    constexpr int ST = kTileStride;
     double* T0 = S.u.tile;
-    __syncthreads();
-    // pair slot i of lane (h, q): nodes (q, q + d mod 32), d = h + 2 i; the
-    // d = 16 pairs are taken by q < 16 only, so every unordered pair
-    // (diagonal included) is written exactly once
-    constexpr int kSlots = 9;
-    // b = exp(-(eps_hi - eps_lo) / (2T)) of a node pair, from the split exponentials
-    auto half_boltz = [&](int lo, int hi) { return ldexp(S.P2[lo] * S.R2[hi], S.n2[lo] - S.n2[hi]); };
-    // pass 1: Phi_in
-#pragma unroll
-    for (int i = 0; i < kSlots; ++i) {
-      const int d = h + 2 * i;
-      const int j = (q + d) & 31;
-      const int lo = q < j ? q : j, hi = q < j ? j : q;
-      if (d < 16 || (d == 16 && q < 16)) {
-        const double b = half_boltz(lo, hi);
-        const double ee = An * (m.eps[lo] * m.eps[hi]);
-        T0[hi * ST + lo] = ee * (b * b * b);
-        T0[lo * ST + hi] = ee * b;
-      }
-    }
+    split_exp_prepare(S.m, invT, S.E);
+    fill_tile<kTilePhiIn>(S.m, S.E, An, h, q, T0);
     __syncthreads();
     {
-      // number lanes: row q; flux lanes: column q
       const int step = h ? ST : 1;
       const double* p = T0 + (h ? q : q * ST);
 #pragma unroll
       for (int j = 0; j < NQ; ++j) M1[j] = p[j * step];
     }
     __syncthreads();
-    // pass 2: Phi_ann
-#pragma unroll
-    for (int i = 0; i < kSlots; ++i) {
-      const int d = h + 2 * i;
-      const int j = (q + d) & 31;
-      const int lo = q < j ? q : j, hi = q < j ? j : q;
-      if (d < 16 || (d == 16 && q < 16)) {
-        const double b = half_boltz(lo, hi);
-        const double ann = Ap * (m.eps[lo] * m.eps[hi]) * (b * b);
-        T0[hi * ST + lo] = ann;
-        T0[lo * ST + hi] = ann;
-      }
-    }
+    fill_tile<kTilePhiAnn>(S.m, S.E, Ap, h, q, T0);
     __syncthreads();
     if (h == 0) {
       const double* p = T0 + q * ST;
@@ -467,18 +102,7 @@ struct PointSolver {
       for (int j = 0; j < NQ; ++j) M2[j] = p[j];
     }
     __syncthreads();
-    // pass 3: Phi_pro
-#pragma unroll
-    for (int i = 0; i < kSlots; ++i) {
-      const int d = h + 2 * i;
-      const int j = (q + d) & 31;
-      const int lo = q < j ? q : j, hi = q < j ? j : q;
-      if (d < 16 || (d == 16 && q < 16)) {
-        const double pro = Ap * (m.eps[lo] * m.eps[hi]) * S.G[hi];
-        T0[hi * ST + lo] = pro;
-        T0[lo * ST + hi] = pro;
-      }
-    }
+    fill_tile<kTilePhiPro>(S.m, S.E, Ap, h, q, T0);
     __syncthreads();
     if (h != 0) {
       const double* p = T0 + q * ST;

@@ -10,6 +10,7 @@ namespace nmc {
 
 constexpr int kMaxNq = 64;
 constexpr int kMaxNs = 3;
+constexpr int kReduceBlocks = 1024;  // first-stage blocks of the point reduction
 
 // Model table resident in device memory.  The kernels copy the per-node
 // tables into LDS once per work-group and read the uniform scalars through
@@ -76,7 +77,7 @@ hipError_t launch_reset_counter(int* counter, hipStream_t s);
 hipError_t launch_init_state(const DevModel* mdl, int ns, int nq, int64_t P, const double* T, const double* mu,
                              const double* rho11, const double* ye, const double* uD, const double* uI, double a,
                              double b, double c, double* D0, double* I0, double* e0, hipStream_t s);
-hipError_t launch_adjoint(const AdjArgs& a, int nq, int ns, hipStream_t s);
+hipError_t launch_adjoint(const AdjArgs& a, int nq, int ns, int num_cu, hipStream_t s);
 hipError_t launch_reduce_columns(const double* grad_pp, int64_t P, int ncol, double* partial, double* grad_theta,
                                  hipStream_t s);
 

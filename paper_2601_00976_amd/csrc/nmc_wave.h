@@ -1,0 +1,394 @@
+// Wave-level building blocks shared by the solve kernels (CDNA4, 64-lane
+// wavefronts): lane permutations, register reductions, the DPP contraction
+// blocks, and the LDS assembly of the energy-coupling kernel matrices.
+#pragma once
+
+#include <type_traits>
+#include <utility>
+
+#include "nmc_internal.h"
+
+namespace nmc {
+
+constexpr int kLanes = 64;
+
+template <int I, int N, class F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (I < N) {
+    f(std::integral_constant<int, I>{});
+    static_for<I + 1, N>(f);
+  }
+}
+
+// DPP lane permutation within 16-lane rows for controls that read a valid
+// lane for every lane (quad_perm, row mirrors), so no "old" value is needed
+template <int CTRL>
+__device__ __forceinline__ double dpp(double x) {
+  const long v = __builtin_amdgcn_mov_dpp(__builtin_bit_cast(long, x), CTRL, 0xF, 0xF, false);
+  return __builtin_bit_cast(double, v);
+}
+
+// broadcast lane I of every 16-lane row to the whole row (row_newbcast:I);
+// every lane is written, so no "old" operand is needed
+template <int I>
+__device__ __forceinline__ double row_bcast(double x) {
+  const long v = __builtin_amdgcn_mov_dpp(__builtin_bit_cast(long, x), 0x150 + I, 0xF, 0xF, false);
+  return __builtin_bit_cast(double, v);
+}
+
+__device__ __forceinline__ uint32_t lo32(double x) { return (uint32_t)__builtin_bit_cast(uint64_t, x); }
+__device__ __forceinline__ uint32_t hi32(double x) { return (uint32_t)(__builtin_bit_cast(uint64_t, x) >> 32); }
+__device__ __forceinline__ double mk64(uint32_t lo, uint32_t hi) {
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// v_permlane16_swap(v, v): first = rows (0,0,2,2) of v, second = rows (1,1,3,3)
+__device__ __forceinline__ void swap16(double v, double& first, double& second) {
+  auto a = __builtin_amdgcn_permlane16_swap(lo32(v), lo32(v), false, false);
+  auto b = __builtin_amdgcn_permlane16_swap(hi32(v), hi32(v), false, false);
+  first = mk64(a[0], b[0]);
+  second = mk64(a[1], b[1]);
+}
+
+// v_permlane32_swap(v, v): first = lanes 0..31 of v in both halves, second = lanes 32..63
+__device__ __forceinline__ void swap32(double v, double& first, double& second) {
+  auto a = __builtin_amdgcn_permlane32_swap(lo32(v), lo32(v), false, false);
+  auto b = __builtin_amdgcn_permlane32_swap(hi32(v), hi32(v), false, false);
+  first = mk64(a[0], b[0]);
+  second = mk64(a[1], b[1]);
+}
+
+// lower-half value + upper-half value, identical bits in every lane
+__device__ __forceinline__ double sum_halves(double v) {
+  double f, s;
+  swap32(v, f, s);
+  return f + s;
+}
+
+// Per-half sums of V lane values through LDS: s0[k] = sum over lanes 0..31,
+// s1[k] = sum over lanes 32..63.  Four lanes share each of the 2V sums; lane
+// r of a group adds the entries r, r + 4, ..., r + 28 of its half, starting
+// at a group-dependent rotation so that the 16 lanes of every LDS access
+// cycle hit 16 different banks.  Fixed summation order (deterministic).
+template <int V>
+__device__ __forceinline__ void half_sums(const double (&v)[V], double (&s0)[V], double (&s1)[V], double* red,
+                                          double* redout) {
+  static_assert(2 * V <= 16, "at most 16 sums");
+  const int l = threadIdx.x;
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < V; ++k) red[k * kLanes + l] = v[k];
+  __syncthreads();
+  const int sidx = l >> 2, r = l & 3;
+  double acc = 0.0;
+  if (sidx < 2 * V) {
+    const int hh = sidx / V, k = sidx - hh * V;
+    const double* b = red + k * kLanes + hh * 32;
+    const int rot = sidx & 3;
+    double part[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) part[i] = b[(r + 4 * ((i + rot) & 7)) & 31];
+    acc = ((part[0] + part[1]) + (part[2] + part[3])) + ((part[4] + part[5]) + (part[6] + part[7]));
+  }
+  acc += dpp<0xB1>(acc);  // quad_perm [1,0,3,2]
+  acc += dpp<0x4E>(acc);  // quad_perm [2,3,0,1]
+  if (r == 0 && sidx < 2 * V) redout[sidx] = acc;
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < V; ++k) {
+    s0[k] = redout[k];
+    s1[k] = redout[V + k];
+  }
+}
+
+// Register-only reductions (no LDS round trip).  Within a 16-lane row the
+// butterfly xor 1, xor 2 (quad_perm), half-row mirror and row mirror leaves
+// the row total in every lane, bitwise identical across the row.
+__device__ __forceinline__ double row_allsum(double v) {
+  v += dpp<0xB1>(v);   // quad_perm [1,0,3,2]
+  v += dpp<0x4E>(v);   // quad_perm [2,3,0,1]
+  v += dpp<0x141>(v);  // row_half_mirror
+  v += dpp<0x140>(v);  // row_mirror
+  return v;
+}
+
+// a from lanes 0..31 and b from lanes 32..63 halved into one register:
+// lanes 0..31 get a(l) + a(l + 32), lanes 32..63 get b(l - 32) + b(l)
+__device__ __forceinline__ double halve32(double a, double b) {
+  auto x = __builtin_amdgcn_permlane32_swap(lo32(a), lo32(b), false, false);
+  auto y = __builtin_amdgcn_permlane32_swap(hi32(a), hi32(b), false, false);
+  return mk64(x[0], y[0]) + mk64(x[1], y[1]);
+}
+
+// rows (0, 2) keep a summed with the partner row, rows (1, 3) keep b
+__device__ __forceinline__ double halve16(double a, double b) {
+  auto x = __builtin_amdgcn_permlane16_swap(lo32(a), lo32(b), false, false);
+  auto y = __builtin_amdgcn_permlane16_swap(hi32(a), hi32(b), false, false);
+  return mk64(x[0], y[0]) + mk64(x[1], y[1]);
+}
+
+// Sums of 4 values over all 64 lanes, returned in every lane.
+__device__ __forceinline__ void wave_sums4(const double (&v)[4], double (&out)[4]) {
+  // lanes 0..31: (v0, v1) over the wave halves; lanes 32..63: (v2, v3)
+  const double h01 = halve32(v[0], v[2]);
+  const double h23 = halve32(v[1], v[3]);
+  // row r now carries slot r summed over 4 lanes per column
+  const double r = row_allsum(halve16(h01, h23));
+  // rows (0,0,2,2) and (1,1,3,3), then both halves
+  double f, sc;
+  swap16(r, f, sc);
+  double f0, f1, s0, s1;
+  swap32(f, f0, f1);
+  swap32(sc, s0, s1);
+  out[0] = f0;
+  out[1] = s0;
+  out[2] = f1;
+  out[3] = s1;
+}
+
+// Per-half sums of 2 K values (K = 1..3): s0 over lanes 0..31, s1 over lanes
+// 32..63, returned in every lane.
+template <int K>
+__device__ __forceinline__ void half_sums_reg(const double (&v)[2 * K], double (&s0)[2 * K], double (&s1)[2 * K]) {
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    // rows (0, 2): slot k over the row pair; rows (1, 3): slot K + k
+    const double r = row_allsum(halve16(v[k], v[K + k]));
+    double f, sc;
+    swap16(r, f, sc);  // f: slot k of this half, sc: slot K + k
+    double a0, a1, b0, b1;
+    swap32(f, a0, a1);
+    swap32(sc, b0, b1);
+    s0[k] = a0;
+    s1[k] = a1;
+    s0[K + k] = b0;
+    s1[K + k] = b1;
+  }
+}
+
+__device__ __forceinline__ bool wave_any(bool b) { return __builtin_amdgcn_ballot_w64(b) != 0; }
+
+// Opaque copies: values derived from these are recomputed where they are
+// used instead of being hoisted out of the outer loop (hoisted invariants
+// end up spilled, which costs far more than recomputing them).
+__device__ __forceinline__ int opaque(int x) {
+  asm volatile("" : "+v"(x));
+  return x;
+}
+template <class T>
+__device__ __forceinline__ const T* opaque_ptr(const T* p) {
+  asm volatile("" : "+s"(p));
+  return p;
+}
+
+// Four columns of the contraction for every species and both matrices in one
+// asm block: acc1[t] += bcast(x[t], L0 + jj) * m1[jj], acc2[t] += bcast(x[t], L0 + jj) * m2[jj].
+// The leading s_nop 1 provides the two wait states a DPP source needs after
+// a VALU write, whatever the compiler schedules before the block.
+template <int NS>
+struct Fmac4;
+
+template <>
+struct Fmac4<1> {
+  template <int L0>
+  __device__ __forceinline__ static void run(double (&a1)[1], double (&a2)[1], const double (&x)[1], double m10,
+                                             double m11, double m12, double m13, double m20, double m21, double m22,
+                                             double m23) {
+    asm volatile(
+        "s_nop 1\n"
+        "v_fmac_f64_dpp %0, %2, %3 row_newbcast:%11 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %1, %2, %7 row_newbcast:%11 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %0, %2, %4 row_newbcast:%12 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %1, %2, %8 row_newbcast:%12 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %0, %2, %5 row_newbcast:%13 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %1, %2, %9 row_newbcast:%13 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %0, %2, %6 row_newbcast:%14 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %1, %2, %10 row_newbcast:%14 row_mask:0xf bank_mask:0xf\n"
+        : "+v"(a1[0]), "+v"(a2[0])
+        : "v"(x[0]), "v"(m10), "v"(m11), "v"(m12), "v"(m13), "v"(m20), "v"(m21), "v"(m22), "v"(m23), "i"(L0),
+          "i"(L0 + 1), "i"(L0 + 2), "i"(L0 + 3));
+  }
+};
+
+template <>
+struct Fmac4<2> {
+  template <int L0>
+  __device__ __forceinline__ static void run(double (&a1)[2], double (&a2)[2], const double (&x)[2], double m10,
+                                             double m11, double m12, double m13, double m20, double m21, double m22,
+                                             double m23) {
+    asm volatile(
+        "s_nop 1\n"
+        "v_fmac_f64_dpp %0, %4, %6 row_newbcast:%14 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %1, %5, %6 row_newbcast:%14 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %2, %4, %10 row_newbcast:%14 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %3, %5, %10 row_newbcast:%14 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %0, %4, %7 row_newbcast:%15 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %1, %5, %7 row_newbcast:%15 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %2, %4, %11 row_newbcast:%15 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %3, %5, %11 row_newbcast:%15 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %0, %4, %8 row_newbcast:%16 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %1, %5, %8 row_newbcast:%16 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %2, %4, %12 row_newbcast:%16 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %3, %5, %12 row_newbcast:%16 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %0, %4, %9 row_newbcast:%17 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %1, %5, %9 row_newbcast:%17 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %2, %4, %13 row_newbcast:%17 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %3, %5, %13 row_newbcast:%17 row_mask:0xf bank_mask:0xf\n"
+        : "+v"(a1[0]), "+v"(a1[1]), "+v"(a2[0]), "+v"(a2[1])
+        : "v"(x[0]), "v"(x[1]), "v"(m10), "v"(m11), "v"(m12), "v"(m13), "v"(m20), "v"(m21), "v"(m22), "v"(m23),
+          "i"(L0), "i"(L0 + 1), "i"(L0 + 2), "i"(L0 + 3));
+  }
+};
+
+template <>
+struct Fmac4<3> {
+  template <int L0>
+  __device__ __forceinline__ static void run(double (&a1)[3], double (&a2)[3], const double (&x)[3], double m10,
+                                             double m11, double m12, double m13, double m20, double m21, double m22,
+                                             double m23) {
+    asm volatile(
+        "s_nop 1\n"
+        "v_fmac_f64_dpp %0, %6, %9 row_newbcast:%17 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %1, %7, %9 row_newbcast:%17 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %2, %8, %9 row_newbcast:%17 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %3, %6, %13 row_newbcast:%17 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %4, %7, %13 row_newbcast:%17 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %5, %8, %13 row_newbcast:%17 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %0, %6, %10 row_newbcast:%18 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %1, %7, %10 row_newbcast:%18 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %2, %8, %10 row_newbcast:%18 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %3, %6, %14 row_newbcast:%18 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %4, %7, %14 row_newbcast:%18 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %5, %8, %14 row_newbcast:%18 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %0, %6, %11 row_newbcast:%19 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %1, %7, %11 row_newbcast:%19 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %2, %8, %11 row_newbcast:%19 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %3, %6, %15 row_newbcast:%19 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %4, %7, %15 row_newbcast:%19 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %5, %8, %15 row_newbcast:%19 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %0, %6, %12 row_newbcast:%20 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %1, %7, %12 row_newbcast:%20 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %2, %8, %12 row_newbcast:%20 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %3, %6, %16 row_newbcast:%20 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %4, %7, %16 row_newbcast:%20 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %5, %8, %16 row_newbcast:%20 row_mask:0xf bank_mask:0xf\n"
+        : "+v"(a1[0]), "+v"(a1[1]), "+v"(a1[2]), "+v"(a2[0]), "+v"(a2[1]), "+v"(a2[2])
+        : "v"(x[0]), "v"(x[1]), "v"(x[2]), "v"(m10), "v"(m11), "v"(m12), "v"(m13), "v"(m20), "v"(m21), "v"(m22),
+          "v"(m23), "i"(L0), "i"(L0 + 1), "i"(L0 + 2), "i"(L0 + 3));
+  }
+};
+
+// reciprocal of x >= 1 (finite): hardware estimate refined by two Newton steps
+__device__ __forceinline__ double rcp_ge1(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = __builtin_fma(-x, r, 1.0);
+  r = __builtin_fma(r, e, r);
+  e = __builtin_fma(-x, r, 1.0);
+  return __builtin_fma(r, e, r);
+}
+
+// Per-node model tables copied into LDS once per work-group (lane-indexed
+// reads of them are then LDS hits); the uniform scalars of the model stay in
+// the global table, where the scalar cache serves them.
+struct ModelLds {
+  double eps[32], w2[32], w3[32], shape[32];
+  double theta[34];  // per-node EmAb scales, a_nes, a_pair
+};
+
+__device__ __forceinline__ void load_model(const DevModel* __restrict__ md, const double* __restrict__ theta,
+                                           ModelLds& m) {
+  const int l = threadIdx.x;
+  if (l < 32) {
+    m.eps[l] = md->eps[l];
+    m.w2[l] = md->w2[l];
+    m.w3[l] = md->w3[l];
+    m.shape[l] = md->shape[l];
+  }
+  if (l < 34) m.theta[l] = theta[l];
+  __syncthreads();
+}
+
+// Pair partner of internal species s (species sorted by id: nu_e, anti-nu_e
+// are partners, nu_x is its own partner).  Models without pair processes
+// have zero pair kernels, so the map is irrelevant for them.
+template <int NS>
+__device__ __forceinline__ constexpr int pair_partner(int s) {
+  return NS == 3 ? (s < 2 ? 1 - s : 2) : (NS == 2 ? 1 - s : 0);
+}
+
+
+// Ye^(4/3) of the EOS
+__device__ __forceinline__ double ye43(double ye) { return ye * cbrt(ye); }
+
+// ---------------------------------------------------------------------------
+// Kernel matrices at temperature T (Eqs. nesRatesNodal, pairRatesNodal with
+// the kernels of Eqs. inOutInvarianceNES ... detailedBalancePair).  With
+// b = exp(-(e_hi - e_lo) / (2T)) for e_hi >= e_lo and G_x = exp(-2 e_x / T):
+//   Phi_in[hi][lo] = A e e' b^3,  Phi_in[lo][hi] = A e e' b,  Phi_out = Phi_in^T,
+//   Phi_ann = A' e e' b^2,  Phi_pro = A' e e' G_hi  (both symmetric).
+// b is assembled from per-node exponent splits x = e log2(e) / (2T) =
+// n + f, P = 2^f, R = 2^-f:  b = ldexp(P_lo R_hi, n_lo - n_hi), so every
+// factor stays <= 1 and nothing overflows at low temperature.
+constexpr int kTileStride = 33;  // padded row stride of a 32 x 32 LDS tile
+
+struct SplitExp {
+  double P2[32], R2[32], G[32];
+  int n2[32];
+};
+
+// lanes 0..31 fill the per-node factors of temperature 1 / invT; ends with a barrier
+__device__ __forceinline__ void split_exp_prepare(const ModelLds& m, double invT, SplitExp& E) {
+  const int lane = threadIdx.x;
+  if (lane < 32) {
+    const double e = m.eps[lane];
+    const double x = e * (0.5 * invT) * 1.4426950408889634;  // log2(e)
+    const double n = floor(x);
+    const double P = exp2(x - n);
+    E.P2[lane] = P;
+    E.R2[lane] = rcp_ge1(P);
+    E.n2[lane] = (int)n;
+    E.G[lane] = exp(-2.0 * e * invT);
+  }
+  __syncthreads();
+}
+
+enum TileKind { kTilePhiIn, kTilePhiAnn, kTilePhiPro };
+
+// Writes the full 32 x 32 matrix of the given kind with amplitude amp into
+// the tile (row-major, stride kTileStride).  Pair slot i of lane (h, q)
+// covers nodes (q, q + d mod 32), d = h + 2 i; the d = 16 pairs are taken by
+// q < 16 only, so each of the 528 unordered pairs (diagonal included) is
+// written exactly once.  h = lane / 32 and q = lane mod 32 are passed in
+// (callers launder them so that the index arithmetic is not hoisted out of
+// their loops).  No barrier: the caller synchronises.
+template <TileKind K>
+__device__ __forceinline__ void fill_tile(const ModelLds& m, const SplitExp& E, double amp, int h, int q,
+                                          double* T0) {
+  constexpr int ST = kTileStride;
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    const int d = h + 2 * i;
+    const int j = (q + d) & 31;
+    const int lo = q < j ? q : j, hi = q < j ? j : q;
+    if (d < 16 || (d == 16 && q < 16)) {
+      const double ee = amp * (m.eps[lo] * m.eps[hi]);
+      if constexpr (K == kTilePhiPro) {
+        const double v = ee * E.G[hi];
+        T0[hi * ST + lo] = v;
+        T0[lo * ST + hi] = v;
+      } else {
+        const double b = ldexp(E.P2[lo] * E.R2[hi], E.n2[lo] - E.n2[hi]);
+        if constexpr (K == kTilePhiIn) {
+          T0[hi * ST + lo] = ee * (b * b * b);
+          T0[lo * ST + hi] = ee * b;
+        } else {
+          const double v = ee * (b * b);
+          T0[hi * ST + lo] = v;
+          T0[lo * ST + hi] = v;
+        }
+      }
+    }
+  }
+}
+
+}  // namespace nmc

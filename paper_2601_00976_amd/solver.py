@@ -55,7 +55,7 @@ class Grid:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h is not None and N._lib is not None:
+        if h is not None and N is not None and N._lib is not None:
             N.lib().nmc_grid_destroy(h)
             self._h = None
 
@@ -83,7 +83,7 @@ class Model:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h is not None and N._lib is not None:
+        if h is not None and N is not None and N._lib is not None:
             N.lib().nmc_model_destroy(h)
             self._h = None
 
@@ -185,6 +185,67 @@ def solve(model: Model, params: Params, dtau: float, D0, I0, rho11, ye0, e0, the
                                     C.c_void_p(workspace.ptr), workspace.nbytes, C.byref(lc),
                                     _stream_handle(stream)))
     return out
+
+
+def adjoint(model: Model, dtau: float, rho11, theta, fwd, gbar, chi0=None, grad_theta=None, per_point=False,
+            workspace: Workspace | None = None, stream=None):
+    """Enqueue the implicit-function-theorem adjoint of a converged forward
+    solve (``fwd`` = its output dict) for the per-point loss
+    L_p = gbar[p, 0] (e*_p - e_p) + gbar[p, 1] (Ye_p - Ye*_p).
+
+    Adds dL/dtheta into ``grad_theta`` (allocated zero if None) and returns it,
+    with the (P, nq + 2) per-point terms when ``per_point``."""
+    P = rho11.shape[0]
+    nq = model.nq
+    _req(rho11, "rho11", (P,))
+    _req(theta, "theta", (nq + 2,))
+    _req(gbar, "gbar", (P, 2))
+    if chi0 is not None:
+        _req(chi0, "chi0", (P,))
+    bo = _batch_out(model, P, fwd)
+    bi = N.BatchIn(None, None, rho11.data_ptr(), None, None, None if chi0 is None else chi0.data_ptr(), None, None,
+                   theta.data_ptr())
+    if grad_theta is None:
+        grad_theta = torch.zeros(nq + 2, dtype=torch.float64, device=rho11.device)
+    _req(grad_theta, "grad_theta", (nq + 2,))
+    gpp = torch.empty(P, nq + 2, dtype=torch.float64, device=rho11.device) if per_point else None
+    if workspace is None:
+        workspace = Workspace(model, P, rho11.device)
+    N.check(N.lib().nmc_solve_batch_adjoint(model._h, P, float(dtau), C.byref(bi), C.byref(bo), gbar.data_ptr(),
+                                            grad_theta.data_ptr(), None if gpp is None else gpp.data_ptr(),
+                                            C.c_void_p(workspace.ptr), workspace.nbytes, _stream_handle(stream)))
+    return (grad_theta, gpp) if per_point else grad_theta
+
+
+class NMCSolve(torch.autograd.Function):
+    """Differentiable batched solve with respect to theta = (s_1..s_nq, a_nes, a_pair).
+
+    forward(theta, model, params, dtau, D0, I0, rho11, ye0, e0) returns
+    (D, I, Ye, e, L_E, L_Y) with L_E = e* - e and L_Y = Ye - Ye* per point.
+    backward folds the cotangents of Ye, e, L_E and L_Y into the per-point
+    loss weights of the adjoint; cotangents on D or I are not supported."""
+
+    @staticmethod
+    def forward(ctx, theta, model, params, dtau, D0, I0, rho11, ye0, e0):
+        out = solve(model, params, dtau, D0, I0, rho11, ye0, e0, theta)
+        ctx.model, ctx.dtau = model, dtau
+        ctx.out = out
+        ctx.save_for_backward(theta, rho11)
+        return out["D"], out["I"], out["ye"], out["e"], e0 - out["e"], out["ye"] - ye0
+
+    @staticmethod
+    def backward(ctx, gD, gI, gYe, ge, gLE, gLY):
+        for g, n in ((gD, "D"), (gI, "I")):
+            if g is not None and bool(torch.any(g != 0)):
+                raise NotImplementedError(f"NMCSolve.backward: cotangents on {n} are not supported")
+        theta, rho11 = ctx.saved_tensors
+        P = rho11.shape[0]
+        z = torch.zeros(P, dtype=torch.float64, device=rho11.device)
+        gE = (gLE if gLE is not None else z) - (ge if ge is not None else z)
+        gY = (gLY if gLY is not None else z) + (gYe if gYe is not None else z)
+        gbar = torch.stack([gE, gY], dim=1).contiguous()
+        g = adjoint(ctx.model, ctx.dtau, rho11, theta, ctx.out, gbar)
+        return g, None, None, None, None, None, None, None, None
 
 
 def init_state(model: Model, T, rho11, ye, uD, uI, a=1.0, b=0.1, c=0.1, mu=None, stream=None):
