@@ -75,6 +75,43 @@ def cpu_baseline(repeats: int, threads: int):
                        f"{solved} solves in {dt:.1f} s")
 
 
+def adjoint_ratio(model, params, theta, D0, I0, t, e0, ws, launch, reps=5):
+    """Adjoint versus forward cost on the first implicit step of the profile
+    (loss weights gbar = (1, 1) per point), both eager on the same stream and
+    timed with HIP events around each call."""
+    import torch
+    from paper_2601_00976_amd import solver as S
+    from paper_2601_00976_amd import workloads as W
+
+    P = D0.shape[0]
+    out = S.alloc_outputs(model, P, D0.device)
+    gbar = torch.ones(P, 2, dtype=torch.float64, device=D0.device)
+    grad = torch.zeros(model.nq + 2, dtype=torch.float64, device=D0.device)
+
+    def fwd():
+        S.solve(model, params, W.DTAU_KM, D0, I0, t["rho11"], t["ye"], e0, theta, out=out, workspace=ws,
+                launch=launch)
+
+    def adj():
+        S.adjoint(model, W.DTAU_KM, t["rho11"], theta, out, gbar, grad_theta=grad, workspace=ws)
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+        for a, b in ev:
+            a.record()
+            fn()
+            b.record()
+        torch.cuda.synchronize()
+        return sorted(a.elapsed_time(b) for a, b in ev)[reps // 2]
+
+    t_f = timed(fwd)
+    t_a = timed(adj)
+    return {"workload": "radial profile step 1, 2^16 points, gbar = (1, 1)", "forward_ms": t_f, "adjoint_ms": t_a,
+            "ratio": t_a / t_f}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -215,9 +252,7 @@ def main():
             "algorithmic_hbm_gbs": hbm_bytes_per_launch / kern_s_per_launch / 1e9,
         },
     }
-    adj = AT.adjoint_ratio(model, params, theta, D0, I0, t, e0, ws) if hasattr(AT, "adjoint_ratio") else None
-    if adj is not None:
-        line["adjoint_forward_ratio"] = adj
+    line["adjoint"] = adjoint_ratio(model, params, theta, D0, I0, t, e0, ws, launch)
     if not args.no_cpu:
         threads = int(os.environ.get("OMP_NUM_THREADS") or os.cpu_count() or 1)
         line["cpu_baseline"] = cpu_baseline(args.cpu_repeats, threads)

@@ -44,16 +44,17 @@ struct AdjLds {
   double z0[NS][NQ], z1[NS][NQ];  // Z = A^-T C^T
 };
 
-__device__ __forceinline__ double wave_max(double v) {
-  v = fmax(v, dpp<0xB1>(v));
-  v = fmax(v, dpp<0x4E>(v));
-  v = fmax(v, dpp<0x141>(v));
-  v = fmax(v, dpp<0x140>(v));
-  double f, s;
-  swap16(v, f, s);
-  v = fmax(f, s);
-  swap32(v, f, s);
-  return fmax(f, s);
+// maximum over the wave, in every lane
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
+  auto m = [](uint32_t a, uint32_t b) { return a > b ? a : b; };
+  v = m(v, (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xF, 0xF, false));   // quad_perm [1,0,3,2]
+  v = m(v, (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x4E, 0xF, 0xF, false));   // quad_perm [2,3,0,1]
+  v = m(v, (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x141, 0xF, 0xF, false));  // row_half_mirror
+  v = m(v, (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x140, 0xF, 0xF, false));  // row_mirror
+  auto a = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+  v = m(a[0], a[1]);
+  auto b = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+  return m(b[0], b[1]);
 }
 
 __device__ __forceinline__ double readlane_f64(double v, int lane) {
@@ -76,9 +77,13 @@ __device__ __forceinline__ bool solve_block_transposed(double (&R)[N], double c0
   bool ok = true;
   static_for<0, N>([&](auto kk) __attribute__((always_inline)) {
     constexpr int k = decltype(kk)::value;
-    const double cand = done ? -1.0 : fabs(R[k]);
-    const double mx = wave_max(cand);
-    uint64_t bal = __builtin_amdgcn_ballot_w64(!done && cand == mx);
+    // pivot: largest |R[k]| over the lanes not yet eliminated, compared on
+    // the high word of the absolute value (sign, exponent and 20 mantissa
+    // bits), i.e. threshold pivoting within a factor 1 + 2^-20 of the
+    // maximum; ties go to the lowest lane
+    const uint32_t key = done ? 0u : (hi32(R[k]) & 0x7fffffffu) + 1u;
+    const uint32_t mx = wave_max_u32(key);
+    uint64_t bal = __builtin_amdgcn_ballot_w64(!done && key == mx);
     if (bal == 0) {
       ok = false;
       bal = __builtin_amdgcn_ballot_w64(!done);
@@ -421,12 +426,24 @@ __global__ void reduce_stage1(const double* __restrict__ x, int64_t P, int ncol,
   partial[(int64_t)blockIdx.x * ncol + c] = s;
 }
 
-__global__ void reduce_stage2(const double* __restrict__ partial, int nblk, int ncol, double* __restrict__ out) {
-  const int c = threadIdx.x;
-  if (c >= ncol) return;
-  double s = 0.0;
-  for (int b = 0; b < nblk; ++b) s += partial[(int64_t)b * ncol + c];
-  out[c] += s;
+__global__ __launch_bounds__(256) void reduce_stage2(const double* __restrict__ partial, int nblk, int ncol,
+                                                     double* __restrict__ out) {
+  // per column: thread t sums partials t, t + 256, ... in order, then a
+  // fixed-shape tree over the 256 threads
+  __shared__ double red[256];
+  const int t = threadIdx.x;
+  for (int c = 0; c < ncol; ++c) {
+    double s = 0.0;
+    for (int b = t; b < nblk; b += 256) s += partial[(int64_t)b * ncol + c];
+    red[t] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+      if (t < w) red[t] += red[t + w];
+      __syncthreads();
+    }
+    if (t == 0) out[c] += red[0];
+    __syncthreads();
+  }
 }
 
 }  // namespace
