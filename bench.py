@@ -42,9 +42,9 @@ def flops_per_point(n_inner, n_outer, nq=NQ, ns=NS):
 
 
 def bytes_per_point(nq=NQ, ns=NS):
-    """Algorithmic HBM bytes of one point-solve: read D*, I* and 5 scalars,
-    write D, I, 3 scalars and 3 int32 counters."""
-    return 2 * ns * nq * 8 + 5 * 8 + 2 * ns * nq * 8 + 3 * 8 + 3 * 4
+    """Algorithmic HBM bytes of one point-solve: read D*, I* and 3 scalars
+    (rho11, Ye*, e*), write D, I, 3 scalars (Ye, e, T) and 3 int32 counters."""
+    return 2 * ns * nq * 8 + 3 * 8 + 2 * ns * nq * 8 + 3 * 8 + 3 * 4
 
 
 def cpu_baseline(repeats: int, threads: int):
@@ -117,7 +117,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--cpu-repeats", type=int, default=3, help="repeats of the 10-step chain in the oracle baseline")
+    ap.add_argument("--cpu-repeats", type=int, default=2, help="repeats of the 10-step chain in the oracle baseline")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--chunk", type=int, default=None)
     ap.add_argument("--blocks-per-cu", type=int, default=None)
