@@ -34,7 +34,7 @@ template <int NS>
 struct AdjLds {
   ModelLds m;
   SplitExp E;
-  double tile[32 * kTileStride];
+  double tin[32 * kTileStride], tann[32 * kTileStride], tpro[32 * kTileStride];  // unit-amplitude kernels
   double D[NS][NQ];
   double prow[64 + 2];  // pivot row of the current elimination step and its right-hand sides
   // per-row results, row = (species, node)
@@ -141,74 +141,40 @@ struct PointAdjoint {
   //   diagonal:            1 + dtau chi_(s, p)
   // with the kernels at the point's amplitudes; Phi_out[q][p] = Phi_in[p][q].
   template <int S0, int NB>
-  __device__ __forceinline__ static void block_rows(AdjLds<NS>& S, double dtau, double an, double ap,
+  __device__ __forceinline__ static void block_rows(AdjLds<NS>& S, double dtau, double a_nes, double a_pair,
                                                     double (&R)[32 * NB]) {
     constexpr int ST = kTileStride;
-    constexpr int N = 32 * NB;
     const int lane = opaque((int)threadIdx.x);  // laundered: lane-derived indices are not hoisted out of the point loop
     const int h = lane >> 5, p = lane & 31;
     const int si = NB == 2 ? h : 0;
     const int sp = S0 + si;  // species of this lane's column
-    const double dw = dtau * S.m.w2[p];
-#pragma unroll
-    for (int r = 0; r < N; ++r) R[r] = 0.0;
-    // NES: row species = column species
-    fill_tile<kTilePhiIn>(S.m, S.E, an, h, p, S.tile);
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-      const double tin = S.tile[q * ST + p], tout = S.tile[p * ST + q];
-      const double d = S.D[sp][q];
-      const double v = -dw * __builtin_fma(d, tout - tin, tin);
-      if constexpr (NB == 2) {
-        R[q] += si == 0 ? v : 0.0;
-        R[32 + q] += si == 1 ? v : 0.0;
-      } else {
-        R[q] += v;
-      }
-      if ((q & 3) == 3) asm volatile("" ::: "memory");
-    }
-    __syncthreads();
-    // pair: rows of the partner species (the block's other species, or the
-    // species itself for nu_x)
-    fill_tile<kTilePhiAnn>(S.m, S.E, ap, h, p, S.tile);
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-      const double t = dw * S.tile[q * ST + p];
-      if constexpr (NB == 2) {
-        R[q] += si == 1 ? t * S.D[S0][q] : 0.0;
-        R[32 + q] += si == 0 ? t * S.D[S0 + 1][q] : 0.0;
-      } else {
-        R[q] += t * S.D[S0][q];
-      }
-      if ((q & 3) == 3) asm volatile("" ::: "memory");
-    }
-    __syncthreads();
-    fill_tile<kTilePhiPro>(S.m, S.E, ap, h, p, S.tile);
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-      const double t = dw * S.tile[q * ST + p];
-      if constexpr (NB == 2) {
-        R[q] += si == 1 ? t * (1.0 - S.D[S0][q]) : 0.0;
-        R[32 + q] += si == 0 ? t * (1.0 - S.D[S0 + 1][q]) : 0.0;
-      } else {
-        R[q] += t * (1.0 - S.D[S0][q]);
-      }
-      if ((q & 3) == 3) asm volatile("" ::: "memory");
-    }
-    __syncthreads();
+    const double dwn = dtau * a_nes * S.m.w2[p], dwp = dtau * a_pair * S.m.w2[p];
     const double diag = 1.0 + dtau * S.chi[sp][p];
 #pragma unroll
-    for (int r = 0; r < N; ++r) R[r] += (r == lane) ? diag : 0.0;
+    for (int q = 0; q < NQ; ++q) {
+      const double tin = S.tin[q * ST + p], tout = S.tin[p * ST + q];
+      const double tann = S.tann[q * ST + p], tpro = S.tpro[q * ST + p];
+      // row (s, q), column (sp, p): NES if s = sp, pair if s is sp's partner
+      auto nes = [&](double d) { return -dwn * __builtin_fma(d, tout - tin, tin); };
+      auto pair = [&](double d) { return dwp * __builtin_fma(d, tann - tpro, tpro); };
+      const double dg = q == p ? diag : 0.0;
+      if constexpr (NB == 2) {
+        const double d0 = S.D[S0][q], d1 = S.D[S0 + 1][q];
+        R[q] = si == 0 ? nes(d0) + dg : pair(d0);
+        R[32 + q] = si == 1 ? nes(d1) + dg : pair(d1);
+      } else {
+        const double d = S.D[S0][q];
+        R[q] = nes(d) + pair(d) + dg;
+      }
+      if ((q & 3) == 3) asm volatile("" ::: "memory");
+    }
   }
 
   template <int S0, int NB>
-  __device__ __forceinline__ static bool block_solve(AdjLds<NS>& S, const DevModel* md, double dtau, double an,
-                                                     double ap, double K) {
+  __device__ __forceinline__ static bool block_solve(AdjLds<NS>& S, const DevModel* md, double dtau, double a_nes,
+                                                     double a_pair, double K) {
     double R[32 * NB];
-    block_rows<S0, NB>(S, dtau, an, ap, R);
+    block_rows<S0, NB>(S, dtau, a_nes, a_pair, R);
     const int lane = opaque((int)threadIdx.x);  // laundered: lane-derived indices are not hoisted out of the point loop
     const int h = lane >> 5, p = lane & 31;
     const int sp = S0 + (NB == 2 ? h : 0);
@@ -280,50 +246,28 @@ struct PointAdjoint {
     double en[NG], onn[NG], an[NG], ep[NG], dn[NG], dout[NG], dan[NG], dpr[NG];
 #pragma unroll
     for (int g = 0; g < NG; ++g) en[g] = onn[g] = an[g] = ep[g] = dn[g] = dout[g] = dan[g] = dpr[g] = 0.0;
-    fill_tile<kTilePhiIn>(S.m, S.E, rho, h, q, S.tile);
+    fill_tile<kTilePhiIn>(S.m, S.E, rho, h, q, S.tin);
+    fill_tile<kTilePhiAnn>(S.m, S.E, rho, h, q, S.tann);
+    fill_tile<kTilePhiPro>(S.m, S.E, rho, h, q, S.tpro);
     __syncthreads();
 #pragma unroll 2
     for (int p = 0; p < NQ; ++p) {
-      const double w = S.m.w2[p], dl = eq - S.m.eps[p], adl = fabs(dl);
-      const double tin = w * S.tile[q * ST + p], tout = w * S.tile[p * ST + q];
+      const double w = S.m.w2[p], epp = S.m.eps[p], dl = eq - epp, adl = fabs(dl);
+      const double tin = w * S.tin[q * ST + p], tout = w * S.tin[p * ST + q];
+      const double tann = w * S.tann[q * ST + p], tpro = w * S.tpro[q * ST + p];
 #pragma unroll
       for (int g = 0; g < NG; ++g) {
-        const double d = S.D[sg[g]][p];
+        const double d = S.D[sg[g]][p], db = S.D[sbg[g]][p];
         en[g] = __builtin_fma(tin, d, en[g]);
         dn[g] = __builtin_fma(tin * (adl + 0.5 * dl), d, dn[g]);
         onn[g] = __builtin_fma(tout, 1.0 - d, onn[g]);
         dout[g] = __builtin_fma(tout * (adl - 0.5 * dl), 1.0 - d, dout[g]);
+        an[g] = __builtin_fma(tann, db, an[g]);
+        dan[g] = __builtin_fma(tann * adl, db, dan[g]);
+        ep[g] = __builtin_fma(tpro, 1.0 - db, ep[g]);
+        dpr[g] = __builtin_fma(tpro * (adl + eq + epp), 1.0 - db, dpr[g]);
       }
     }
-    __syncthreads();
-    fill_tile<kTilePhiAnn>(S.m, S.E, rho, h, q, S.tile);
-    __syncthreads();
-#pragma unroll 2
-    for (int p = 0; p < NQ; ++p) {
-      const double w = S.m.w2[p], adl = fabs(eq - S.m.eps[p]);
-      const double t = w * S.tile[q * ST + p];
-#pragma unroll
-      for (int g = 0; g < NG; ++g) {
-        const double d = S.D[sbg[g]][p];
-        an[g] = __builtin_fma(t, d, an[g]);
-        dan[g] = __builtin_fma(t * adl, d, dan[g]);
-      }
-    }
-    __syncthreads();
-    fill_tile<kTilePhiPro>(S.m, S.E, rho, h, q, S.tile);
-    __syncthreads();
-#pragma unroll 2
-    for (int p = 0; p < NQ; ++p) {
-      const double w = S.m.w2[p], epp = S.m.eps[p], adl = fabs(eq - epp);
-      const double t = w * S.tile[q * ST + p];
-#pragma unroll
-      for (int g = 0; g < NG; ++g) {
-        const double d = 1.0 - S.D[sbg[g]][p];
-        ep[g] = __builtin_fma(t, d, ep[g]);
-        dpr[g] = __builtin_fma(t * (adl + eq + epp), d, dpr[g]);
-      }
-    }
-    __syncthreads();
     // ---- per-row Jacobian pieces ----------------------------------------
     {
       const double shape = chi0 * S.m.shape[q];
@@ -357,13 +301,13 @@ struct PointAdjoint {
     __syncthreads();
 
     // ---- Z = A^-T C^T, block by block ------------------------------------
-    const double amp_n = a_nes * rho, amp_p = a_pair * rho;
+    // (the tiles hold the kernels at unit amplitude a = 1, i.e. A = rho11)
     bool ok;
     if constexpr (NS == 1) {
-      ok = block_solve<0, 1>(S, md, dtau, amp_n, amp_p, K);
+      ok = block_solve<0, 1>(S, md, dtau, a_nes, a_pair, K);
     } else {
-      ok = block_solve<0, 2>(S, md, dtau, amp_n, amp_p, K);
-      if constexpr (NS == 3) ok = block_solve<2, 1>(S, md, dtau, amp_n, amp_p, K) && ok;
+      ok = block_solve<0, 2>(S, md, dtau, a_nes, a_pair, K);
+      if constexpr (NS == 3) ok = block_solve<2, 1>(S, md, dtau, a_nes, a_pair, K) && ok;
     }
 
     // ---- Schur complement on (Ye, e), multipliers and gradient ------------
