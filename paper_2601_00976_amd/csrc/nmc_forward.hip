@@ -598,6 +598,7 @@ hipError_t launch_forward(const FwdArgs& a, int nq, int ns, bool coupled, const 
       }
     }
   }
+  if (nq == 64) return launch_forward64(a, ns, coupled, L, num_cu, s);
   return hipErrorInvalidValue;
 }
 

@@ -1,0 +1,534 @@
+// Forward kernel of the implicit coupling solve for 64 energy nodes (CDNA4).
+//
+// Same algorithm as the 32-node kernel (Algorithm neutrinoMatterCoupling,
+// Sec. 3.5.3), different data placement.  The four 64 x 64 kernel matrices of
+// a point (128 KiB) fit neither in one wavefront's registers nor, at useful
+// occupancy, in LDS, so they are not stored at all.
+//
+// One 64-lane wavefront solves one point; lane q owns D_s[q] and I_s[q] of
+// every species.  In each inner iteration a lane regenerates row q of
+// Phi_in, Phi_out, Phi_ann and Phi_pro column by column from per-node
+// exponent splits broadcast from LDS and accumulates the four rate
+// contractions (Eqs. nesRatesNodal, pairRatesNodal) on the fly.  For column
+// j and row q, with (lo, hi) the lower / higher node of the pair:
+//   b = exp(-(e_hi - e_lo) / (2T)) = ldexp(P_lo R_hi, n_lo - n_hi),
+//   Phi_in[q][j] = A e_q e_j (j > q ? b : b^3),  Phi_out[q][j] = A e_q e_j (j > q ? b^3 : b),
+//   Phi_ann[q][j] = A' e_q e_j b^2,              Phi_pro[q][j] = A' e_q e_j G_hi,
+// with x = e log2(e) / (2T) = n + f, P = 2^f, R = 2^-f, G = exp(-2 e / T).
+// Anderson sums, norms and matter integrals are full-wave register
+// reductions.
+#include "nmc_wave.h"
+
+namespace nmc {
+namespace {
+
+constexpr int NQ64 = 64;
+
+template <int NS>
+struct Lds64 {
+  ModelLdsN<NQ64> m;
+  double hist[4][2 * NS][kLanes];  // Anderson history per owned moment: Q_prev, F_prev, dQ_old, dF_old
+  double colPR[kLanes][2];         // per node: P, R of the exponent split at the current T
+  double colGE[kLanes][2];         // per node: G = exp(-2 e / T), e
+  int coln[kLanes];                // per node: integer part n of the split
+  double X[NS][kLanes];            // W D of the current iterate
+  // uniform per-point state
+  double dref[NS];
+  double y[2], oq[2], of[2], odq[2], odf[2];
+  double T_last, r3, K, An, Ap;
+};
+
+// sums over the wave of V <= 12 lane values, in every lane
+template <int V>
+__device__ __forceinline__ void wave_sums(const double (&v)[V], double (&out)[V]) {
+  static_for<0, (V + 3) / 4>([&](auto cc) {
+    constexpr int c = decltype(cc)::value;
+    double in[4], o[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) in[i] = (4 * c + i < V) ? v[(4 * c + i < V) ? 4 * c + i : 0] : 0.0;
+    wave_sums4(in, o);
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      if (4 * c + i < V) out[4 * c + i] = o[i];
+  });
+}
+
+template <int NS, bool COUPLED>
+struct PointSolver64 {
+  static constexpr int NQ = NQ64;
+
+  // rates of the energy-coupling kernels for every species at the current
+  // iterate: etaN = Phi_in W D_s, outN = Phi_out W (1 - D_s),
+  // annP = Phi_ann W D_sbar, etaP = Phi_pro W (1 - D_sbar)
+  __device__ __forceinline__ static void rates(const Lds64<NS>& S, int q, double (&etaN)[NS], double (&outN)[NS],
+                                               double (&annP)[NS], double (&etaP)[NS]) {
+#pragma unroll
+    for (int t = 0; t < NS; ++t) etaN[t] = outN[t] = annP[t] = etaP[t] = 0.0;
+    const double Pq = S.colPR[q][0], Rq = S.colPR[q][1], Gq = S.colGE[q][0], eq = S.colGE[q][1];
+    const int nq = S.coln[q];
+    const double Aeq = S.An * eq, Apq = S.Ap * eq;
+#pragma unroll 4
+    for (int j = 0; j < NQ; ++j) {
+      const double Pj = S.colPR[j][0], Rj = S.colPR[j][1], Gj = S.colGE[j][0], ej = S.colGE[j][1];
+      const int nj = S.coln[j];
+      const double wj = S.m.w2[j];
+      const bool up = j > q;  // q is the lower node of the pair
+      const double b = ldexp(up ? Pq * Rj : Pj * Rq, up ? nq - nj : nj - nq);
+      const double b2 = b * b;
+      const double en = Aeq * ej, ep = Apq * ej;
+      const double u = en * b, v = en * (b2 * b);
+      const double fin = up ? u : v, fout = up ? v : u;
+      const double fann = ep * b2, fpro = ep * (up ? Gj : Gq);
+      double x[NS], y[NS];
+#pragma unroll
+      for (int t = 0; t < NS; ++t) {
+        x[t] = S.X[t][j];
+        y[t] = wj - x[t];
+      }
+#pragma unroll
+      for (int t = 0; t < NS; ++t) {
+        const int tb = pair_partner<NS>(t);
+        etaN[t] = __builtin_fma(fin, x[t], etaN[t]);
+        outN[t] = __builtin_fma(fout, y[t], outN[t]);
+        annP[t] = __builtin_fma(fann, x[tb], annP[t]);
+        etaP[t] = __builtin_fma(fpro, y[tb], etaP[t]);
+      }
+    }
+  }
+
+  __device__ static void solve(const FwdArgs& a, int64_t p, Lds64<NS>& S) {
+    const DevModel* __restrict__ md0 = a.mdl;
+    const DevModel* __restrict__ md = md0;
+    const ModelLdsN<NQ>& mt = S.m;
+    const int lane = threadIdx.x;
+    const int q0 = lane;
+    const double dtau = a.dtau;
+    const int64_t base = p * (int64_t)(NS * NQ);
+    const double rho = a.rho11[p];
+    const bool fixedT = a.prm.fixed_matter && a.T_fixed;
+
+    double Dst[NS], Ist[NS], D[NS], I[NS];
+#pragma unroll
+    for (int t = 0; t < NS; ++t) {
+      const int64_t o = base + md->ext[t] * NQ + lane;
+      Dst[t] = D[t] = a.D0[o];
+      Ist[t] = I[t] = a.I0[o];
+    }
+
+    if (rho < md->rho11_min) {
+      // coupling disabled at low density (Sec. 7.2): pass the state through
+#pragma unroll
+      for (int t = 0; t < NS; ++t) {
+        const int64_t o = base + md->ext[t] * NQ + lane;
+        a.D[o] = D[t];
+        a.I[o] = I[t];
+      }
+      if (lane == 0) {
+        const double ye_st = a.ye0[p], e_st = a.e0[p];
+        a.ye[p] = ye_st;
+        a.e[p] = e_st;
+        a.T[p] = fixedT ? a.T_fixed[p]
+                        : (e_st - md->eos_b * ye43(ye_st) * cbrt(rho)) / (md->eos_a * (1.0 + ye_st));
+        a.n_outer[p] = 0;
+        a.n_inner[p] = 0;
+        a.status[p] = NMC_STATUS_OK;
+      }
+      return;
+    }
+
+    S.r3 = cbrt(rho);
+    S.K = md->kcoup / rho;
+    S.An = (md->flags & NMC_NES) ? mt.theta[NQ] * rho : 0.0;
+    S.Ap = (md->flags & NMC_PAIR) ? mt.theta[NQ + 1] * rho : 0.0;
+    {
+      const double w2q = mt.w2[q0];
+      double v[NS], s[NS];
+#pragma unroll
+      for (int t = 0; t < NS; ++t) v[t] = w2q * D[t] * D[t];
+      wave_sums<NS>(v, s);
+#pragma unroll
+      for (int t = 0; t < NS; ++t) S.dref[t] = s[t];
+    }
+    S.y[0] = a.ye0[p];
+    S.y[1] = a.e0[p];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) S.oq[i] = S.of[i] = S.odq[i] = S.odf[i] = 0.0;
+    S.T_last = 0.0;
+
+    int status = NMC_STATUS_OK;
+    bool fatal = false, inner_failed = false, outer_conv = false;
+    int k, total_inner = 0;
+
+    for (k = 1; k <= a.prm.max_outer; ++k) {
+      // per-iteration opaque copies keep lane invariants from being hoisted
+      // out of this loop (and spilled)
+      const DevModel* __restrict__ md = opaque_ptr(md0);
+      const int q = opaque(q0);
+      // ---- ComputeOpacities(y^[k]) --------------------------------------
+      const double r3 = S.r3;
+      const double y0 = S.y[0], y1 = S.y[1];
+      const double T = fixedT ? a.T_fixed[p] : (y1 - md->eos_b * ye43(y0) * r3) / (md->eos_a * (1.0 + y0));
+      const double mu = (a.prm.fixed_matter && a.mu_fixed)
+                            ? a.mu_fixed[p]
+                            : md->mu_a * (y0 - md->mu_ye0) * r3 + md->mu_b * log(T / md->mu_t0);
+      if (!(T > 0.0) || !(y0 >= 0.0) || !isfinite(T) || !isfinite(mu)) {
+        status = NMC_STATUS_EOS_DOMAIN;
+        fatal = true;
+        break;
+      }
+      S.T_last = T;
+      const double invT = 1.0 / T;
+      // constant parts of the numerator and denominators of Q (Eqs.
+      // emissivityEmAbNodal, transportOpacityNodal, implicitMomentsNodal)
+      double baseD[NS], den0D[NS], den0I[NS];
+      const double epsq = mt.eps[q];
+      {
+        const double chi0 = a.chi0 ? a.chi0[p] : md->chi_ref * rho;
+        const double shape = chi0 * mt.shape[q];
+        const double sig = (md->flags & NMC_ISO) ? md->sigma_ratio * shape : 0.0;
+        const double emab_q = (md->flags & NMC_EMAB) ? mt.theta[q] * shape : 0.0;
+#pragma unroll
+        for (int t = 0; t < NS; ++t) {
+          const double chia = md->iemab[t] * emab_q;
+          const double x = (epsq - md->imusign[t] * mu) * invT;
+          const double ex = exp(-fabs(x));
+          const double r = rcp_ge1(1.0 + ex);
+          const double deq = x > 0.0 ? ex * r : r;
+          baseD[t] = Dst[t] + dtau * (chia * deq);
+          den0D[t] = 1.0 + dtau * chia;
+          den0I[t] = 1.0 + dtau * (chia + sig);
+        }
+      }
+      if constexpr (COUPLED) {
+        const double x = epsq * (0.5 * invT) * 1.4426950408889634;  // log2(e)
+        const double n = floor(x);
+        const double P = exp2(x - n);
+        S.colPR[q][0] = P;
+        S.colPR[q][1] = rcp_ge1(P);
+        S.colGE[q][0] = exp(-2.0 * epsq * invT);
+        S.colGE[q][1] = epsq;
+        S.coln[q] = (int)n;
+      }
+
+      // ---- inner loop over moments at fixed matter ------------------------
+      const double w2q = mt.w2[q];
+      double G11 = 0.0;
+      bool conv = false;
+      int l;
+      for (l = 1; l <= a.prm.max_inner; ++l) {
+        double etaN[NS], outN[NS], annP[NS], etaP[NS];
+        if constexpr (COUPLED) {
+#pragma unroll
+          for (int t = 0; t < NS; ++t) S.X[t][q] = w2q * D[t];
+          __syncthreads();
+          rates(S, q, etaN, outN, annP, etaP);
+          __syncthreads();
+        } else {
+#pragma unroll
+          for (int t = 0; t < NS; ++t) etaN[t] = outN[t] = annP[t] = etaP[t] = 0.0;
+        }
+        // Q and residual of both moments (owned entries x = (D_t, I_t))
+        double Qx[2 * NS], Fx[2 * NS];
+#pragma unroll
+        for (int t = 0; t < NS; ++t) {
+          const double eta = etaN[t] + etaP[t];
+          const double chi = (etaN[t] + outN[t]) + (etaP[t] + annP[t]);
+          Qx[t] = __builtin_fma(dtau, eta, baseD[t]) * rcp_ge1(__builtin_fma(dtau, chi, den0D[t]));
+          Qx[NS + t] = Ist[t] * rcp_ge1(__builtin_fma(dtau, chi, den0I[t]));
+          Fx[t] = Qx[t] - D[t];
+          Fx[NS + t] = Qx[NS + t] - I[t];
+        }
+        // Anderson step over min(l, M_inner) residuals (difference form)
+        const int mem = l < a.prm.m_inner ? l : a.prm.m_inner;
+        double Xn[2 * NS];
+        if (mem == 1) {
+#pragma unroll
+          for (int x = 0; x < 2 * NS; ++x) Xn[x] = Qx[x];
+        } else {
+          const double use1 = (mem == 3) ? 1.0 : 0.0;
+          double dQ2[2 * NS], dF2[2 * NS];
+          double v4[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+          for (int x = 0; x < 2 * NS; ++x) {
+            dQ2[x] = Qx[x] - S.hist[0][x][lane];
+            dF2[x] = Fx[x] - S.hist[1][x][lane];
+            const double dF1 = use1 * S.hist[3][x][lane];
+            v4[0] += dF1 * dF2[x];
+            v4[1] += dF2[x] * dF2[x];
+            v4[2] += dF1 * Fx[x];
+            v4[3] += dF2[x] * Fx[x];
+          }
+          double gs[4];
+          wave_sums4(v4, gs);
+          const double G12 = gs[0], G22 = gs[1], b1 = gs[2], b2 = gs[3];
+          double g1 = 0.0, g2 = 0.0;
+          bool two = (mem == 3);
+          if (two) {
+            const double tr = G11 + G22;
+            two = G11 > 1e-14 * tr;
+            if (two) {
+              const double r11 = 1.0 / G11;
+              const double l21 = G12 * r11;
+              const double p2 = G22 - G12 * l21;
+              two = p2 > 1e-14 * tr;
+              if (two) {
+                g2 = (b2 - l21 * b1) / p2;
+                g1 = (b1 - G12 * g2) * r11;
+              }
+            }
+          }
+          if (!two) {
+            g1 = 0.0;
+            g2 = (G22 > 1e-14 * G22) ? b2 / G22 : 0.0;
+          }
+#pragma unroll
+          for (int x = 0; x < 2 * NS; ++x) {
+            Xn[x] = Qx[x] - g2 * dQ2[x] - g1 * S.hist[2][x][lane];
+            S.hist[2][x][lane] = dQ2[x];
+            S.hist[3][x][lane] = dF2[x];
+          }
+          G11 = G22;
+        }
+#pragma unroll
+        for (int x = 0; x < 2 * NS; ++x) {
+          S.hist[0][x][lane] = Qx[x];
+          S.hist[1][x][lane] = Fx[x];
+        }
+        bool bad = false;
+#pragma unroll
+        for (int x = 0; x < 2 * NS; ++x) bad |= !isfinite(Xn[x]);
+        if (wave_any(bad)) {
+          status = NMC_STATUS_NONFINITE;
+          fatal = true;
+          break;
+        }
+        // Algorithm innerConverged, compared squared
+        {
+          double v[3 * NS], s[3 * NS];
+#pragma unroll
+          for (int t = 0; t < NS; ++t) {
+            const double dd = Xn[t] - D[t], di = Xn[NS + t] - I[t];
+            v[t] = w2q * dd * dd;
+            v[NS + t] = w2q * di * di;
+            v[2 * NS + t] = w2q * Xn[t] * Xn[t];
+          }
+          wave_sums<3 * NS>(v, s);
+          conv = true;
+#pragma unroll
+          for (int t = 0; t < NS; ++t) {
+            const double dm2 = s[t] > s[NS + t] ? s[t] : s[NS + t];
+            const double d0 = S.dref[t], dn2 = s[2 * NS + t];
+            const double dref2 = d0 > dn2 ? d0 : dn2;
+            if (!(dm2 <= a.tol_inner2 * dref2)) conv = false;
+          }
+          if (conv) {
+#pragma unroll
+            for (int t = 0; t < NS; ++t) S.dref[t] = s[2 * NS + t];
+          }
+        }
+#pragma unroll
+        for (int t = 0; t < NS; ++t) {
+          D[t] = Xn[t];
+          I[t] = Xn[NS + t];
+        }
+        if (conv) break;
+      }
+      total_inner += (l > a.prm.max_inner ? a.prm.max_inner : l);
+      if (fatal) break;
+      if (!conv) {
+        inner_failed = true;
+        double v[NS], s[NS];
+#pragma unroll
+        for (int t = 0; t < NS; ++t) v[t] = w2q * D[t] * D[t];
+        wave_sums<NS>(v, s);
+#pragma unroll
+        for (int t = 0; t < NS; ++t) S.dref[t] = s[t];
+      }
+      if (a.prm.fixed_matter) {
+        outer_conv = true;
+        break;
+      }
+
+      // ---- matter right-hand side (Eq. implicitFluidNodal at v = 0) -------
+      double yq0, yq1;
+      {
+        const double w3 = mt.w3[q];
+        double mv[2] = {0.0, 0.0}, s[2];
+#pragma unroll
+        for (int t = 0; t < NS; ++t) {
+          const double dd = D[t] - Dst[t];
+          mv[0] += md->ig[t] * w2q * dd;
+          mv[1] += md->imult[t] * w3 * dd;
+        }
+        wave_sums<2>(mv, s);
+        yq0 = a.ye0[p] - S.K * s[0];
+        yq1 = a.e0[p] - S.K * s[1];
+      }
+      const double f0 = yq0 - S.y[0], f1 = yq1 - S.y[1];
+      const int omem = k < a.prm.m_outer ? k : a.prm.m_outer;
+      double yn0, yn1;
+      if (omem == 1) {
+        yn0 = yq0;
+        yn1 = yq1;
+      } else {
+        const double dq20 = yq0 - S.oq[0], dq21 = yq1 - S.oq[1];
+        const double df20 = f0 - S.of[0], df21 = f1 - S.of[1];
+        const double odf0 = S.odf[0], odf1 = S.odf[1];
+        const double G22 = df20 * df20 + df21 * df21, b2 = df20 * f0 + df21 * f1;
+        double g1 = 0.0, g2 = 0.0;
+        bool two = (omem == 3);
+        if (two) {
+          const double G11o = odf0 * odf0 + odf1 * odf1;
+          const double G12 = odf0 * df20 + odf1 * df21, b1 = odf0 * f0 + odf1 * f1;
+          const double tr = G11o + G22;
+          two = G11o > 1e-14 * tr;
+          if (two) {
+            const double l21 = G12 / G11o;
+            const double p2 = G22 - G12 * l21;
+            two = p2 > 1e-14 * tr;
+            if (two) {
+              g2 = (b2 - l21 * b1) / p2;
+              g1 = (b1 - G12 * g2) / G11o;
+            }
+          }
+        }
+        if (!two) {
+          g1 = 0.0;
+          g2 = (G22 > 1e-14 * G22) ? b2 / G22 : 0.0;
+        }
+        yn0 = yq0 - g2 * dq20 - g1 * S.odq[0];
+        yn1 = yq1 - g2 * dq21 - g1 * S.odq[1];
+        S.odq[0] = dq20;
+        S.odq[1] = dq21;
+        S.odf[0] = df20;
+        S.odf[1] = df21;
+      }
+      S.oq[0] = yq0;
+      S.oq[1] = yq1;
+      S.of[0] = f0;
+      S.of[1] = f1;
+      if (!isfinite(yn0) || !isfinite(yn1)) {
+        status = NMC_STATUS_NONFINITE;
+        fatal = true;
+        break;
+      }
+      const bool oc = fabs(yn0 - S.y[0]) <= a.prm.tol_outer * fabs(a.ye0[p]) &&
+                      fabs(yn1 - S.y[1]) <= a.prm.tol_outer * fabs(a.e0[p]);
+      S.y[0] = yn0;
+      S.y[1] = yn1;
+      if (oc) {
+        outer_conv = true;
+        break;
+      }
+    }
+    if (k > a.prm.max_outer) k = a.prm.max_outer;
+    if (!fatal) {
+      if (!outer_conv) status = NMC_STATUS_MAX_OUTER;
+      else if (inner_failed) status = NMC_STATUS_MAX_INNER;
+    }
+
+    // ---- outputs --------------------------------------------------------
+    const double ye_st = a.ye0[p], e_st = a.e0[p];
+    double ye_out = ye_st, e_out = e_st, T_out = S.T_last;
+    if (!a.prm.fixed_matter) {
+      const double w2 = mt.w2[q0], w3 = mt.w3[q0];
+      double mv[2] = {0.0, 0.0}, s[2];
+#pragma unroll
+      for (int t = 0; t < NS; ++t) {
+        const double dd = D[t] - Dst[t];
+        mv[0] += md->ig[t] * w2 * dd;
+        mv[1] += md->imult[t] * w3 * dd;
+      }
+      wave_sums<2>(mv, s);
+      ye_out = ye_st - S.K * s[0];
+      e_out = e_st - S.K * s[1];
+      T_out = (e_out - md->eos_b * ye43(ye_out) * S.r3) / (md->eos_a * (1.0 + ye_out));
+    } else if (status == NMC_STATUS_EOS_DOMAIN) {
+      T_out = fixedT ? a.T_fixed[p] : (e_st - md->eos_b * ye43(ye_st) * S.r3) / (md->eos_a * (1.0 + ye_st));
+    }
+#pragma unroll
+    for (int t = 0; t < NS; ++t) {
+      const int64_t o = base + md->ext[t] * NQ + lane;
+      a.D[o] = D[t];
+      a.I[o] = I[t];
+    }
+    if (lane == 0) {
+      a.ye[p] = ye_out;
+      a.e[p] = e_out;
+      a.T[p] = T_out;
+      a.n_outer[p] = k;
+      a.n_inner[p] = total_inner;
+      a.status[p] = status;
+    }
+    __syncthreads();
+  }
+};
+
+template <int NS, bool COUPLED>
+__global__ __launch_bounds__(kLanes) void fwd64_kernel(FwdArgs a) {
+  __shared__ Lds64<NS> S;
+  load_model(a.mdl, a.theta, S.m);
+  if (a.queue) {
+    int nxt = 0;
+    if (threadIdx.x == 0) nxt = atomicAdd(a.queue, a.chunk);
+    for (;;) {
+      const int64_t b0 = __builtin_amdgcn_readfirstlane(nxt);
+      if (b0 >= a.P) break;
+      if (threadIdx.x == 0) nxt = atomicAdd(a.queue, a.chunk);
+      const int64_t end = b0 + a.chunk < a.P ? b0 + a.chunk : a.P;
+      for (int64_t p = b0; p < end; ++p) PointSolver64<NS, COUPLED>::solve(a, p, S);
+    }
+  } else {
+    const int64_t b0 = (int64_t)blockIdx.x * a.chunk;
+    const int64_t end = b0 + a.chunk < a.P ? b0 + a.chunk : a.P;
+    for (int64_t p = b0; p < end; ++p) PointSolver64<NS, COUPLED>::solve(a, p, S);
+  }
+}
+
+template <int NS, bool COUPLED>
+hipError_t launch64_t(const FwdArgs& a, const nmc_launch& L, int num_cu, hipStream_t s) {
+  auto kern = fwd64_kernel<NS, COUPLED>;
+  int64_t grid;
+  if (a.queue) {
+    int bpc = L.blocks_per_cu;
+    if (bpc <= 0) {
+      static int occ = 0;
+      if (occ <= 0) {
+        int o = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, kern, kLanes, 0) != hipSuccess || o <= 0) o = 8;
+        occ = o;
+      }
+      bpc = occ;
+    }
+    grid = (int64_t)bpc * num_cu;
+    const int64_t need = (a.P + a.chunk - 1) / a.chunk;
+    if (grid > need) grid = need;
+  } else {
+    grid = (a.P + a.chunk - 1) / a.chunk;
+  }
+  if (grid < 1) grid = 1;
+  hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(kLanes), 0, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_forward64(const FwdArgs& a, int ns, bool coupled, const nmc_launch& L, int num_cu,
+                            hipStream_t s) {
+  if (coupled) {
+    switch (ns) {
+      case 1: return launch64_t<1, true>(a, L, num_cu, s);
+      case 2: return launch64_t<2, true>(a, L, num_cu, s);
+      case 3: return launch64_t<3, true>(a, L, num_cu, s);
+    }
+  } else {
+    switch (ns) {
+      case 1: return launch64_t<1, false>(a, L, num_cu, s);
+      case 2: return launch64_t<2, false>(a, L, num_cu, s);
+      case 3: return launch64_t<3, false>(a, L, num_cu, s);
+    }
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace nmc

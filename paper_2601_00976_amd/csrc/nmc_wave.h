@@ -290,21 +290,24 @@ __device__ __forceinline__ double rcp_ge1(double x) {
 // Per-node model tables copied into LDS once per work-group (lane-indexed
 // reads of them are then LDS hits); the uniform scalars of the model stay in
 // the global table, where the scalar cache serves them.
-struct ModelLds {
-  double eps[32], w2[32], w3[32], shape[32];
-  double theta[34];  // per-node EmAb scales, a_nes, a_pair
+template <int NQ>
+struct ModelLdsN {
+  double eps[NQ], w2[NQ], w3[NQ], shape[NQ];
+  double theta[NQ + 2];  // per-node EmAb scales, a_nes, a_pair
 };
+using ModelLds = ModelLdsN<32>;
 
+template <int NQ>
 __device__ __forceinline__ void load_model(const DevModel* __restrict__ md, const double* __restrict__ theta,
-                                           ModelLds& m) {
+                                           ModelLdsN<NQ>& m) {
   const int l = threadIdx.x;
-  if (l < 32) {
+  if (l < NQ) {
     m.eps[l] = md->eps[l];
     m.w2[l] = md->w2[l];
     m.w3[l] = md->w3[l];
     m.shape[l] = md->shape[l];
   }
-  if (l < 34) m.theta[l] = theta[l];
+  for (int i = l; i < NQ + 2; i += kLanes) m.theta[i] = theta[i];
   __syncthreads();
 }
 
