@@ -26,14 +26,19 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-NQ, NS, N_ELEM = 32, 3, 16
-P_POINTS = 1 << 16
+NS = 3
 STEPS_PER_GRAPH = 10
+# name: (energy elements, points, workload id of the draws, traffic tag, kernel label)
+WORKLOADS = {
+    "profile32": (16, 1 << 16, 3, "fwd_kernel_nq32_ns3", "fwd_kernel<3,32> (persistent point solve)"),
+    "profile64": (32, 1 << 18, 4, "fwd64_kernel_nq64_ns3", "fwd64_kernel<3> (persistent point solve, 64 nodes)"),
+}
+NQ, P_POINTS = 32, 1 << 16  # headline workload
 PEAK_FP64_TFLOPS = 78.6   # MI355X FP64 vector, published
 PEAK_HBM_GBS = 8000.0
 
 
-def flops_per_point(n_inner, n_outer, nq=NQ, ns=NS):
+def flops_per_point(n_inner, n_outer, nq=32, ns=NS):
     """Algorithmic FLOPs of one point-solve (FMA = 2): per inner iteration the
     four energy-coupling mat-vecs of every species (8 ns nq^2) and pointwise
     plus Anderson work (40 ns nq); per outer iteration the kernel build and
@@ -41,7 +46,7 @@ def flops_per_point(n_inner, n_outer, nq=NQ, ns=NS):
     return n_inner * (8 * ns * nq * nq + 40 * ns * nq) + n_outer * (4 * nq * nq + 30 * ns * nq)
 
 
-def bytes_per_point(nq=NQ, ns=NS):
+def bytes_per_point(nq=32, ns=NS):
     """Algorithmic HBM bytes of one point-solve: read D*, I* and 3 scalars
     (rho11, Ye*, e*), write D, I, 3 scalars (Ye, e, T) and 3 int32 counters."""
     return 2 * ns * nq * 8 + 3 * 8 + 2 * ns * nq * 8 + 3 * 8 + 3 * 4
@@ -58,7 +63,7 @@ def cpu_baseline(repeats: int, threads: int):
 
     O.build(force=False)
     d = W.radial_profile(P=P_POINTS)
-    m = O.Model(n_elem=N_ELEM)
+    m = O.Model(n_elem=16)
     theta = m.default_theta(S.DEFAULT_A_NES, S.DEFAULT_A_PAIR)
     D0, I0, e0 = m.init_state(d.T, d.rho11, d.ye, d.uD, d.uI)
     solved = 0
@@ -121,6 +126,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--chunk", type=int, default=None)
     ap.add_argument("--blocks-per-cu", type=int, default=None)
+    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="profile32",
+                    help="profile32: the headline (2^16 points, 32 nodes); profile64: 2^18 points, 64 nodes")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the per-point solve needs no communication, and this "
@@ -138,10 +145,12 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
 
-    grid = S.Grid(N_ELEM)
+    n_elem, P_POINTS, wid, traffic_tag, kernel_label = WORKLOADS[args.workload]
+    nq = 2 * n_elem
+    grid = S.Grid(n_elem)
     model = S.Model(grid)
     params = S.Params()
-    draws = W.radial_profile(P=P_POINTS)
+    draws = W.radial_profile(P=P_POINTS, nq=nq, wid=wid)
     t = S.to_device(draws, dev)
     D0, I0, e0 = S.init_state(model, t["T"], t["rho11"], t["ye"], t["uD"], t["uI"])
     theta = model.default_theta()
@@ -206,16 +215,16 @@ def main():
     n_out = np.stack([o["n_outer"].cpu().numpy() for o in outs]).astype(np.float64)
     status = np.stack([o["status"].cpu().numpy() for o in outs])
     solved = int(np.sum(n_out > 0))
-    flops = float(np.sum(flops_per_point(n_in, n_out)))
+    flops = float(np.sum(flops_per_point(n_in, n_out, nq)))
     value = solved / (ms_per_step * 1e-3)
     kern_s_per_launch = kern_ms * 1e-3 / (n_timed * STEPS_PER_GRAPH)
     flops_per_launch = flops / STEPS_PER_GRAPH
     achieved = flops_per_launch / kern_s_per_launch / 1e12
-    hbm_bytes_per_launch = bytes_per_point() * P_POINTS
-    traffic = AT.stored_traffic("fwd_kernel_nq32_ns3")
+    hbm_bytes_per_launch = bytes_per_point(nq) * P_POINTS
+    traffic = AT.stored_traffic(traffic_tag)
 
     line = {
-        "metric": "implicit point-solves/sec at 32 energy nodes, 3 species (FP64)",
+        "metric": f"implicit point-solves/sec at {nq} energy nodes, 3 species (FP64)",
         "value": value,
         "unit": "point-solves/s",
         "n_gpus": 1,
@@ -228,9 +237,9 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {
-            "workload": "radial-profile, 2^16 points, 3 species, 32 energy nodes, full physics, "
-                        "10 chained implicit steps per captured graph",
-            "points": P_POINTS, "solved_point_steps_per_step": solved, "species": NS, "energy_nodes": NQ,
+            "workload": f"radial-profile, 2^{P_POINTS.bit_length() - 1} points, 3 species, {nq} energy nodes, "
+                        "full physics, 10 chained implicit steps per captured graph",
+            "points": P_POINTS, "solved_point_steps_per_step": solved, "species": NS, "energy_nodes": nq,
             "implicit_steps_per_step": STEPS_PER_GRAPH, "dtau_km": W.DTAU_KM, "tol": params.tol_inner,
             "anderson_memory": params.m_inner, "launch": {"chunk": launch.chunk,
                                                           "blocks_per_cu": launch.blocks_per_cu,
@@ -240,7 +249,7 @@ def main():
             "status_counts": np.bincount(status.ravel(), minlength=5).tolist(),
         },
         "roofline": {
-            "kernel": "fwd_kernel<3,32> (persistent point solve)",
+            "kernel": kernel_label,
             "bound": "alu",
             "achieved": achieved,
             "peak": PEAK_FP64_TFLOPS,
@@ -252,8 +261,9 @@ def main():
             "algorithmic_hbm_gbs": hbm_bytes_per_launch / kern_s_per_launch / 1e9,
         },
     }
-    line["adjoint"] = adjoint_ratio(model, params, theta, D0, I0, t, e0, ws, launch)
-    if not args.no_cpu:
+    if nq == 32:
+        line["adjoint"] = adjoint_ratio(model, params, theta, D0, I0, t, e0, ws, launch)
+    if not args.no_cpu and args.workload == "profile32":
         threads = int(os.environ.get("OMP_NUM_THREADS") or os.cpu_count() or 1)
         line["cpu_baseline"] = cpu_baseline(args.cpu_repeats, threads)
     print(json.dumps(line), flush=True)
