@@ -128,6 +128,8 @@ def main():
     ap.add_argument("--blocks-per-cu", type=int, default=None)
     ap.add_argument("--workload", choices=sorted(WORKLOADS), default="profile32",
                     help="profile32: the headline (2^16 points, 32 nodes); profile64: 2^18 points, 64 nodes")
+    ap.add_argument("--kernel-store", choices=("chip", "hbm"), default="chip",
+                    help="64 nodes only: kernel rows generated on chip (default) or precomputed per point in HBM")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the per-point solve needs no communication, and this "
@@ -159,13 +161,19 @@ def main():
         launch.chunk = args.chunk
     if args.blocks_per_cu is not None:
         launch.blocks_per_cu = args.blocks_per_cu
+    hbm_store = args.kernel_store == "hbm"
+    if hbm_store:
+        assert nq == 64, "--kernel-store hbm needs --workload profile64"
+        launch.kernel_store = 1
+        traffic_tag += "_hbm"
+        kernel_label = "fwd64_kernel<3> (kernels precomputed per point in HBM)"
 
     # working state (solved in place step after step) and per-step counters
     work = dict(D=D0.clone(), I=I0.clone(), ye=t["ye"].clone(), e=e0.clone())
     outs = [S.alloc_outputs(model, P_POINTS, dev) for _ in range(STEPS_PER_GRAPH)]
     for o in outs:
         o["D"], o["I"], o["ye"], o["e"] = work["D"], work["I"], work["ye"], work["e"]
-    ws = S.Workspace(model, P_POINTS, dev)
+    ws = S.Workspace(model, P_POINTS, dev, kernel_store=hbm_store)
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
           for _ in range(STEPS_PER_GRAPH)]
 
@@ -241,6 +249,7 @@ def main():
                         "full physics, 10 chained implicit steps per captured graph",
             "points": P_POINTS, "solved_point_steps_per_step": solved, "species": NS, "energy_nodes": nq,
             "implicit_steps_per_step": STEPS_PER_GRAPH, "dtau_km": W.DTAU_KM, "tol": params.tol_inner,
+            "kernel_store": args.kernel_store,
             "anderson_memory": params.m_inner, "launch": {"chunk": launch.chunk,
                                                           "blocks_per_cu": launch.blocks_per_cu,
                                                           "persistent": launch.persistent},

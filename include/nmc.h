@@ -153,7 +153,19 @@ typedef struct {
   int blocks_per_cu;   /* resident work-groups per compute unit for the persistent grid (0 = auto) */
   int chunk;           /* points taken per work-queue grab (>= 1) */
   int persistent;      /* 1: persistent grid with an atomic work queue; 0: one work-group per chunk */
+  int kernel_store;    /* NMC_KERNELS_ON_CHIP or NMC_KERNELS_HBM (see below) */
 } nmc_launch;
+
+/* Where the energy-coupling kernel matrices live during a solve.
+ * ON_CHIP: built on chip (registers / LDS) once per outer iteration (32
+ *   nodes) or regenerated in registers every inner iteration (64 nodes).
+ * HBM: 64-node solve only, for the roofline study of precomputed kernels:
+ *   Phi_in, Phi_out and Phi_ann of every point are written to the workspace
+ *   once per outer iteration and re-read by every inner iteration; the
+ *   workspace then needs nmc_kernel_store_bytes(m, P) more bytes after the
+ *   nmc_workspace_bytes(m, P) ones. */
+#define NMC_KERNELS_ON_CHIP 0
+#define NMC_KERNELS_HBM 1
 
 /* Defaults of the descriptors above (values in parentheses). */
 void nmc_model_desc_default(nmc_model_desc* desc);
@@ -175,6 +187,9 @@ int nmc_model_create(const nmc_grid* g, const nmc_model_desc* desc, nmc_model** 
 int nmc_model_destroy(nmc_model* m);
 /* Bytes of device workspace a solve call with P points needs. */
 size_t nmc_workspace_bytes(const nmc_model* m, int64_t P);
+/* Extra workspace bytes of a solve with kernel_store = NMC_KERNELS_HBM:
+ * 3 nq^2 doubles per point (0 if the model cannot use that mode). */
+size_t nmc_kernel_store_bytes(const nmc_model* m, int64_t P);
 
 /* Batched forward solve: Algorithm neutrinoMatterCoupling at every point.
  * Outputs may alias inputs (in-place step).  The output matter state is the

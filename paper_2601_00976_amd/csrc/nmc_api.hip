@@ -273,6 +273,12 @@ size_t nmc_workspace_bytes(const nmc_model* m, int64_t P) {
   return kCounterBytes + pp + part;
 }
 
+size_t nmc_kernel_store_bytes(const nmc_model* m, int64_t P) {
+  if (!m || P < 0 || m->host.nq != 64) return 0;
+  const size_t nq = (size_t)m->host.nq;
+  return ((size_t)P * 3 * nq * nq * sizeof(double) + 255) & ~(size_t)255;
+}
+
 static int check_params(const nmc_solver_params* p) {
   if (!p) return fail(NMC_E_INVALID_ARG, "null solver params");
   if (!(p->tol_inner > 0.0) || !(p->tol_outer > 0.0) || !isfinite(p->tol_inner) || !isfinite(p->tol_outer))
@@ -299,10 +305,21 @@ int nmc_solve_batch(const nmc_model* m, const nmc_solver_params* prm, int64_t P,
     return fail(NMC_E_INVALID_ARG, "solve_batch: null output array");
   if ((in->T_fixed || in->mu_fixed) && !prm->fixed_matter)
     return fail(NMC_E_INVALID_ARG, "solve_batch: T_fixed / mu_fixed need fixed_matter");
-  nmc_launch L = {0, 1, 1};
+  nmc_launch L = {0, 1, 1, NMC_KERNELS_ON_CHIP};
   if (launch) L = *launch;
   if (L.chunk < 1 || L.chunk > 4096 || L.blocks_per_cu < 0 || L.blocks_per_cu > 64)
     return fail(NMC_E_INVALID_ARG, "solve_batch: bad launch configuration");
+  if (L.kernel_store != NMC_KERNELS_ON_CHIP && L.kernel_store != NMC_KERNELS_HBM)
+    return fail(NMC_E_INVALID_ARG, "solve_batch: bad kernel_store %d", L.kernel_store);
+  double* kstore = nullptr;
+  if (L.kernel_store == NMC_KERNELS_HBM) {
+    if (m->host.nq != 64 || !(m->host.flags & (NMC_NES | NMC_PAIR)))
+      return fail(NMC_E_UNSUPPORTED, "solve_batch: kernels in HBM need 64 nodes and NES or pair physics");
+    const size_t need = nmc_workspace_bytes(m, P) + nmc_kernel_store_bytes(m, P);
+    if (!ws || !aligned256(ws) || ws_bytes < need)
+      return fail(NMC_E_WORKSPACE, "solve_batch: kernels in HBM need %zu workspace bytes", need);
+    kstore = (double*)((char*)ws + nmc_workspace_bytes(m, P));
+  }
   if (L.persistent) {
     if (!ws || !aligned256(ws) || ws_bytes < kCounterBytes)
       return fail(NMC_E_WORKSPACE, "solve_batch: persistent launch needs a 256-byte aligned workspace");
@@ -338,6 +355,7 @@ int nmc_solve_batch(const nmc_model* m, const nmc_solver_params* prm, int64_t P,
   a.n_inner = out->n_inner;
   a.status = out->status;
   a.chunk = L.chunk;
+  a.kstore = kstore;
   hipStream_t s = (hipStream_t)stream;
   if (L.persistent) {
     a.queue = (int*)ws;

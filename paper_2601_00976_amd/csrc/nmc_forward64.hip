@@ -17,6 +17,14 @@
 // with x = e log2(e) / (2T) = n + f, P = 2^f, R = 2^-f, G = exp(-2 e / T).
 // Anderson sums, norms and matter integrals are full-wave register
 // reductions.
+//
+// The PRE variant (kernel_store = HBM; the roofline study of precomputed
+// kernels) writes Phi_in, Phi_out and Phi_ann of the point to the workspace
+// once per outer iteration, laid out [matrix][column j][row q] so that every
+// access is a coalesced 512-byte wave load or store, and reads them back in
+// every inner iteration (Phi_pro = A' e_q e_j G_hi stays a product of two
+// stored per-node factors).  Each lane reads only what it wrote, so no
+// barrier is needed between the two.
 #include "nmc_wave.h"
 
 namespace nmc {
@@ -53,46 +61,95 @@ __device__ __forceinline__ void wave_sums(const double (&v)[V], double (&out)[V]
   });
 }
 
-template <int NS, bool COUPLED>
+template <int NS, bool COUPLED, bool PRE>
 struct PointSolver64 {
   static constexpr int NQ = NQ64;
+
+  // entries of row q, column j of the four kernels (up to the pair factor
+  // Phi_pro, which is returned too)
+  struct Row {
+    double Pq, Rq, Gq, Aeq, Apq;
+    int nq;
+  };
+  __device__ __forceinline__ static Row row_consts(const Lds64<NS>& S, int q) {
+    Row r;
+    r.Pq = S.colPR[q][0];
+    r.Rq = S.colPR[q][1];
+    r.Gq = S.colGE[q][0];
+    const double eq = S.colGE[q][1];
+    r.nq = S.coln[q];
+    r.Aeq = S.An * eq;
+    r.Apq = S.Ap * eq;
+    return r;
+  }
+  __device__ __forceinline__ static void entries(const Lds64<NS>& S, const Row& r, int q, int j, double& fin,
+                                                 double& fout, double& fann, double& fpro) {
+    const double Pj = S.colPR[j][0], Rj = S.colPR[j][1], Gj = S.colGE[j][0], ej = S.colGE[j][1];
+    const int nj = S.coln[j];
+    const bool up = j > q;  // q is the lower node of the pair
+    const double b = ldexp(up ? r.Pq * Rj : Pj * r.Rq, up ? r.nq - nj : nj - r.nq);
+    const double b2 = b * b;
+    const double en = r.Aeq * ej, ep = r.Apq * ej;
+    const double u = en * b, v = en * (b2 * b);
+    fin = up ? u : v;
+    fout = up ? v : u;
+    fann = ep * b2;
+    fpro = ep * (up ? Gj : r.Gq);
+  }
+  __device__ __forceinline__ static void accumulate(const Lds64<NS>& S, int j, double fin, double fout, double fann,
+                                                    double fpro, double (&etaN)[NS], double (&outN)[NS],
+                                                    double (&annP)[NS], double (&etaP)[NS]) {
+    const double wj = S.m.w2[j];
+    double x[NS], y[NS];
+#pragma unroll
+    for (int t = 0; t < NS; ++t) {
+      x[t] = S.X[t][j];
+      y[t] = wj - x[t];
+    }
+#pragma unroll
+    for (int t = 0; t < NS; ++t) {
+      const int tb = pair_partner<NS>(t);
+      etaN[t] = __builtin_fma(fin, x[t], etaN[t]);
+      outN[t] = __builtin_fma(fout, y[t], outN[t]);
+      annP[t] = __builtin_fma(fann, x[tb], annP[t]);
+      etaP[t] = __builtin_fma(fpro, y[tb], etaP[t]);
+    }
+  }
 
   // rates of the energy-coupling kernels for every species at the current
   // iterate: etaN = Phi_in W D_s, outN = Phi_out W (1 - D_s),
   // annP = Phi_ann W D_sbar, etaP = Phi_pro W (1 - D_sbar)
-  __device__ __forceinline__ static void rates(const Lds64<NS>& S, int q, double (&etaN)[NS], double (&outN)[NS],
-                                               double (&annP)[NS], double (&etaP)[NS]) {
+  __device__ __forceinline__ static void rates(const Lds64<NS>& S, int q, const double* __restrict__ kst,
+                                               double (&etaN)[NS], double (&outN)[NS], double (&annP)[NS],
+                                               double (&etaP)[NS]) {
 #pragma unroll
     for (int t = 0; t < NS; ++t) etaN[t] = outN[t] = annP[t] = etaP[t] = 0.0;
-    const double Pq = S.colPR[q][0], Rq = S.colPR[q][1], Gq = S.colGE[q][0], eq = S.colGE[q][1];
-    const int nq = S.coln[q];
-    const double Aeq = S.An * eq, Apq = S.Ap * eq;
+    const Row r = row_consts(S, q);
 #pragma unroll 4
     for (int j = 0; j < NQ; ++j) {
-      const double Pj = S.colPR[j][0], Rj = S.colPR[j][1], Gj = S.colGE[j][0], ej = S.colGE[j][1];
-      const int nj = S.coln[j];
-      const double wj = S.m.w2[j];
-      const bool up = j > q;  // q is the lower node of the pair
-      const double b = ldexp(up ? Pq * Rj : Pj * Rq, up ? nq - nj : nj - nq);
-      const double b2 = b * b;
-      const double en = Aeq * ej, ep = Apq * ej;
-      const double u = en * b, v = en * (b2 * b);
-      const double fin = up ? u : v, fout = up ? v : u;
-      const double fann = ep * b2, fpro = ep * (up ? Gj : Gq);
-      double x[NS], y[NS];
-#pragma unroll
-      for (int t = 0; t < NS; ++t) {
-        x[t] = S.X[t][j];
-        y[t] = wj - x[t];
+      double fin, fout, fann, fpro;
+      if constexpr (PRE) {
+        fin = kst[j * NQ + q];
+        fout = kst[(NQ + j) * NQ + q];
+        fann = kst[(2 * NQ + j) * NQ + q];
+        fpro = r.Apq * S.colGE[j][1] * (j > q ? S.colGE[j][0] : r.Gq);
+      } else {
+        entries(S, r, q, j, fin, fout, fann, fpro);
       }
-#pragma unroll
-      for (int t = 0; t < NS; ++t) {
-        const int tb = pair_partner<NS>(t);
-        etaN[t] = __builtin_fma(fin, x[t], etaN[t]);
-        outN[t] = __builtin_fma(fout, y[t], outN[t]);
-        annP[t] = __builtin_fma(fann, x[tb], annP[t]);
-        etaP[t] = __builtin_fma(fpro, y[tb], etaP[t]);
-      }
+      accumulate(S, j, fin, fout, fann, fpro, etaN, outN, annP, etaP);
+    }
+  }
+
+  // PRE: Phi_in, Phi_out, Phi_ann row q of the current temperature to HBM
+  __device__ __forceinline__ static void store_rows(const Lds64<NS>& S, int q, double* __restrict__ kst) {
+    const Row r = row_consts(S, q);
+#pragma unroll 4
+    for (int j = 0; j < NQ; ++j) {
+      double fin, fout, fann, fpro;
+      entries(S, r, q, j, fin, fout, fann, fpro);
+      kst[j * NQ + q] = fin;
+      kst[(NQ + j) * NQ + q] = fout;
+      kst[(2 * NQ + j) * NQ + q] = fann;
     }
   }
 
@@ -106,6 +163,7 @@ struct PointSolver64 {
     const int64_t base = p * (int64_t)(NS * NQ);
     const double rho = a.rho11[p];
     const bool fixedT = a.prm.fixed_matter && a.T_fixed;
+    double* __restrict__ kst = PRE ? a.kstore + p * (int64_t)(3 * NQ * NQ) : nullptr;
 
     double Dst[NS], Ist[NS], D[NS], I[NS];
 #pragma unroll
@@ -208,6 +266,10 @@ struct PointSolver64 {
         S.colGE[q][0] = exp(-2.0 * epsq * invT);
         S.colGE[q][1] = epsq;
         S.coln[q] = (int)n;
+        if constexpr (PRE) {
+          __syncthreads();
+          store_rows(S, q, kst);
+        }
       }
 
       // ---- inner loop over moments at fixed matter ------------------------
@@ -221,7 +283,7 @@ struct PointSolver64 {
 #pragma unroll
           for (int t = 0; t < NS; ++t) S.X[t][q] = w2q * D[t];
           __syncthreads();
-          rates(S, q, etaN, outN, annP, etaP);
+          rates(S, q, kst, etaN, outN, annP, etaP);
           __syncthreads();
         } else {
 #pragma unroll
@@ -464,7 +526,7 @@ struct PointSolver64 {
   }
 };
 
-template <int NS, bool COUPLED>
+template <int NS, bool COUPLED, bool PRE>
 __global__ __launch_bounds__(kLanes) void fwd64_kernel(FwdArgs a) {
   __shared__ Lds64<NS> S;
   load_model(a.mdl, a.theta, S.m);
@@ -476,18 +538,18 @@ __global__ __launch_bounds__(kLanes) void fwd64_kernel(FwdArgs a) {
       if (b0 >= a.P) break;
       if (threadIdx.x == 0) nxt = atomicAdd(a.queue, a.chunk);
       const int64_t end = b0 + a.chunk < a.P ? b0 + a.chunk : a.P;
-      for (int64_t p = b0; p < end; ++p) PointSolver64<NS, COUPLED>::solve(a, p, S);
+      for (int64_t p = b0; p < end; ++p) PointSolver64<NS, COUPLED, PRE>::solve(a, p, S);
     }
   } else {
     const int64_t b0 = (int64_t)blockIdx.x * a.chunk;
     const int64_t end = b0 + a.chunk < a.P ? b0 + a.chunk : a.P;
-    for (int64_t p = b0; p < end; ++p) PointSolver64<NS, COUPLED>::solve(a, p, S);
+    for (int64_t p = b0; p < end; ++p) PointSolver64<NS, COUPLED, PRE>::solve(a, p, S);
   }
 }
 
-template <int NS, bool COUPLED>
+template <int NS, bool COUPLED, bool PRE>
 hipError_t launch64_t(const FwdArgs& a, const nmc_launch& L, int num_cu, hipStream_t s) {
-  auto kern = fwd64_kernel<NS, COUPLED>;
+  auto kern = fwd64_kernel<NS, COUPLED, PRE>;
   int64_t grid;
   if (a.queue) {
     int bpc = L.blocks_per_cu;
@@ -515,17 +577,24 @@ hipError_t launch64_t(const FwdArgs& a, const nmc_launch& L, int num_cu, hipStre
 
 hipError_t launch_forward64(const FwdArgs& a, int ns, bool coupled, const nmc_launch& L, int num_cu,
                             hipStream_t s) {
-  if (coupled) {
+  if (a.kstore) {
+    if (!coupled) return hipErrorInvalidValue;
     switch (ns) {
-      case 1: return launch64_t<1, true>(a, L, num_cu, s);
-      case 2: return launch64_t<2, true>(a, L, num_cu, s);
-      case 3: return launch64_t<3, true>(a, L, num_cu, s);
+      case 1: return launch64_t<1, true, true>(a, L, num_cu, s);
+      case 2: return launch64_t<2, true, true>(a, L, num_cu, s);
+      case 3: return launch64_t<3, true, true>(a, L, num_cu, s);
+    }
+  } else if (coupled) {
+    switch (ns) {
+      case 1: return launch64_t<1, true, false>(a, L, num_cu, s);
+      case 2: return launch64_t<2, true, false>(a, L, num_cu, s);
+      case 3: return launch64_t<3, true, false>(a, L, num_cu, s);
     }
   } else {
     switch (ns) {
-      case 1: return launch64_t<1, false>(a, L, num_cu, s);
-      case 2: return launch64_t<2, false>(a, L, num_cu, s);
-      case 3: return launch64_t<3, false>(a, L, num_cu, s);
+      case 1: return launch64_t<1, false, false>(a, L, num_cu, s);
+      case 2: return launch64_t<2, false, false>(a, L, num_cu, s);
+      case 3: return launch64_t<3, false, false>(a, L, num_cu, s);
     }
   }
   return hipErrorInvalidValue;

@@ -55,6 +55,7 @@ struct FwdArgs {
   const double *D0, *I0, *rho11, *ye0, *e0, *chi0, *T_fixed, *mu_fixed, *theta;
   double *D, *I, *ye, *e, *T;
   int32_t *n_outer, *n_inner, *status;
+  double* kstore;  // per-point kernel matrices (kernel_store = HBM) or nullptr
   int* queue;  // work-queue counter (persistent mode) or nullptr
   int chunk;   // points per grab
 };

@@ -22,11 +22,12 @@ STATUS_OK, STATUS_MAX_OUTER, STATUS_MAX_INNER, STATUS_NONFINITE, STATUS_EOS_DOMA
 NU_E, NU_E_BAR, NU_X = 0, 1, 2
 EMAB, ISO, NES, PAIR = 1, 2, 4, 8
 ALL_PHYSICS = 15
+KERNELS_ON_CHIP, KERNELS_HBM = 0, 1
 SPACING_LOG, SPACING_ZOOM = 0, 1
 
 EXPORTED = (
     "nmc_model_desc_default", "nmc_solver_params_default", "nmc_grid_create", "nmc_grid_query",
-    "nmc_grid_destroy", "nmc_model_create", "nmc_model_destroy", "nmc_workspace_bytes",
+    "nmc_grid_destroy", "nmc_model_create", "nmc_model_destroy", "nmc_workspace_bytes", "nmc_kernel_store_bytes",
     "nmc_solve_batch", "nmc_solve_batch_adjoint", "nmc_init_state", "nmc_error_string",
     "nmc_last_error",
 )
@@ -66,7 +67,7 @@ class BatchOut(C.Structure):
 
 
 class Launch(C.Structure):
-    _fields_ = [("blocks_per_cu", C.c_int), ("chunk", C.c_int), ("persistent", C.c_int)]
+    _fields_ = [("blocks_per_cu", C.c_int), ("chunk", C.c_int), ("persistent", C.c_int), ("kernel_store", C.c_int)]
 
 
 _lib = None
@@ -91,6 +92,8 @@ def lib():
         L.nmc_model_destroy.argtypes = [vp]
         L.nmc_workspace_bytes.argtypes = [vp, C.c_int64]
         L.nmc_workspace_bytes.restype = C.c_size_t
+        L.nmc_kernel_store_bytes.argtypes = [vp, C.c_int64]
+        L.nmc_kernel_store_bytes.restype = C.c_size_t
         L.nmc_solve_batch.argtypes = [vp, C.POINTER(SolverParams), C.c_int64, C.c_double, C.POINTER(BatchIn),
                                       C.POINTER(BatchOut), vp, C.c_size_t, C.POINTER(Launch), vp]
         L.nmc_solve_batch_adjoint.argtypes = [vp, C.c_int64, C.c_double, C.POINTER(BatchIn), C.POINTER(BatchOut),

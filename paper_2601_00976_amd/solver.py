@@ -90,6 +90,10 @@ class Model:
     def workspace_bytes(self, P: int) -> int:
         return int(N.lib().nmc_workspace_bytes(self._h, P))
 
+    def kernel_store_bytes(self, P: int) -> int:
+        """Extra workspace bytes of a solve with the kernels precomputed in HBM."""
+        return int(N.lib().nmc_kernel_store_bytes(self._h, P))
+
     def default_theta(self, a_nes: float = DEFAULT_A_NES, a_pair: float = DEFAULT_A_PAIR, device="cuda"):
         th = torch.ones(self.nq + 2, dtype=torch.float64, device=device)
         th[self.nq] = a_nes
@@ -117,16 +121,17 @@ class LaunchConfig:
     blocks_per_cu: int = 0
     chunk: int = 4
     persistent: bool = True
+    kernel_store: int = 0  # N.KERNELS_ON_CHIP or N.KERNELS_HBM (64-node roofline study)
 
     def c(self):
-        return N.Launch(self.blocks_per_cu, self.chunk, int(self.persistent))
+        return N.Launch(self.blocks_per_cu, self.chunk, int(self.persistent), int(self.kernel_store))
 
 
 class Workspace:
     """Device workspace for solve calls (allocated once, reused)."""
 
-    def __init__(self, model: Model, P: int, device="cuda"):
-        nb = max(model.workspace_bytes(P), 256)
+    def __init__(self, model: Model, P: int, device="cuda", kernel_store: bool = False):
+        nb = max(model.workspace_bytes(P) + (model.kernel_store_bytes(P) if kernel_store else 0), 256)
         self.buf = torch.empty(nb + 256, dtype=torch.uint8, device=device)
         off = (-self.buf.data_ptr()) % 256
         self.ptr = self.buf.data_ptr() + off

@@ -23,7 +23,13 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 COPY_BYTES = 1 << 28  # 256 MiB calibration copy
-KERNELS = {"fwd_kernel<3, 32, true>": "fwd_kernel_nq32_ns3", "adj_kernel<3>": "adj_kernel_nq32_ns3"}
+KERNELS = {
+    "fwd_kernel<3, 32, true>": ("fwd_kernel_nq32_ns3", "radial profile, 2^16 points, 32 nodes, step 1"),
+    "adj_kernel<3>": ("adj_kernel_nq32_ns3", "radial profile, 2^16 points, 32 nodes, step 1"),
+    "fwd64_kernel<3, true, false>": ("fwd64_kernel_nq64_ns3", "radial profile, 2^18 points, 64 nodes, step 1"),
+    "fwd64_kernel<3, true, true>": ("fwd64_kernel_nq64_ns3_hbm",
+                                    "radial profile, 2^18 points, 64 nodes, step 1, kernels in HBM"),
+}
 
 
 def run():
@@ -49,6 +55,19 @@ def run():
         S.solve(model, S.Params(), W.DTAU_KM, D0, I0, t["rho11"], t["ye"], e0, theta, out=out, workspace=ws)
     gbar = torch.ones(1 << 16, 2, dtype=torch.float64, device=dev)
     S.adjoint(model, W.DTAU_KM, t["rho11"], theta, out, gbar, workspace=ws)
+    torch.cuda.synchronize()
+    del ws, out, gbar, D0, I0, e0, t
+    # 64 nodes, 2^18 points: kernels on chip, then precomputed in HBM
+    P64 = 1 << 18
+    m64 = S.Model(S.Grid(32))
+    t = S.to_device(W.radial_profile(P=P64, nq=64, wid=4), dev)
+    D0, I0, e0 = S.init_state(m64, t["T"], t["rho11"], t["ye"], t["uD"], t["uI"])
+    th64 = m64.default_theta()
+    out = S.alloc_outputs(m64, P64, dev)
+    ws = S.Workspace(m64, P64, dev, kernel_store=True)
+    for store in (0, 1):
+        S.solve(m64, S.Params(), W.DTAU_KM, D0, I0, t["rho11"], t["ye"], e0, th64, out=out, workspace=ws,
+                launch=S.LaunchConfig(kernel_store=store))
     torch.cuda.synchronize()
     print("traffic run done", flush=True)
 
@@ -86,7 +105,7 @@ def summarize(fetch_db, write_db):
     kib = COPY_BYTES / 1024.0
     sf, sw = kib / cf, kib / cw
     h = kernel_source_hash()
-    for key, tag in KERNELS.items():
+    for key, (tag, what) in KERNELS.items():
         vf, nf = _match(f, key)
         vw, nw = _match(w, key)
         if vf is None or vw is None:
@@ -94,7 +113,7 @@ def summarize(fetch_db, write_db):
         total = (vf * sf + vw * sw) * 1024.0
         path = os.path.join(ROOT, "profiles", f"traffic_{tag}.txt")
         with open(path, "w") as o:
-            o.write(f"# HBM traffic of {key} (radial profile, 2^16 points, step 1)\n")
+            o.write(f"# HBM traffic of {key} ({what})\n")
             o.write("# commands (GPU box, from the repository root):\n")
             o.write("#   cd /tmp && export TMPDIR=/tmp\n")
             o.write("#   rocprofv3 --pmc FETCH_SIZE -d <dir>/fetch -o run -- python3 <repo>/paper_2601_00976_amd/traffic.py run\n")

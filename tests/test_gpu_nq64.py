@@ -83,3 +83,21 @@ def test_nq64_ragged_launches_bitwise(launch):
     _, b = PT.run_gpu(d, ALL3, O.ALL_PHYSICS, W.DTAU_KM, S.Params(), theta, n_elem=NE, launch=launch)
     for k in ("D", "I", "ye", "e", "T", "n_outer", "n_inner", "status"):
         assert np.array_equal(a[k], b[k]), k
+
+
+def test_nq64_kernels_in_hbm_bitwise():
+    import torch
+    _say("64 nodes, kernels precomputed in HBM vs on chip, P=200: bitwise equal")
+    d = _profile(200, seed=4)
+    theta_np = _theta()
+    m = S.Model(S.Grid(NE))
+    t = S.to_device(d)
+    D0, I0, e0 = S.init_state(m, t["T"], t["rho11"], t["ye"], t["uD"], t["uI"])
+    theta = torch.as_tensor(theta_np, device="cuda")
+    a = S.solve(m, S.Params(), W.DTAU_KM, D0, I0, t["rho11"], t["ye"], e0, theta)
+    ws = S.Workspace(m, len(d.rho11), kernel_store=True)
+    b = S.solve(m, S.Params(), W.DTAU_KM, D0, I0, t["rho11"], t["ye"], e0, theta, workspace=ws,
+                launch=S.LaunchConfig(kernel_store=1))
+    torch.cuda.synchronize()
+    for k in a:
+        assert torch.equal(a[k], b[k]), k
