@@ -128,8 +128,9 @@ def main():
     ap.add_argument("--blocks-per-cu", type=int, default=None)
     ap.add_argument("--workload", choices=sorted(WORKLOADS), default="profile32",
                     help="profile32: the headline (2^16 points, 32 nodes); profile64: 2^18 points, 64 nodes")
-    ap.add_argument("--kernel-store", choices=("chip", "hbm"), default="chip",
-                    help="64 nodes only: kernel rows generated on chip (default) or precomputed per point in HBM")
+    ap.add_argument("--kernel-store", choices=("chip", "regen", "registers", "hbm"), default="chip",
+                    help="chip: library default (regen); regen: kernel entries regenerated every inner iteration; "
+                         "registers (32 nodes): rows held in VGPRs; hbm (64 nodes): kernels precomputed in HBM")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the per-point solve needs no communication, and this "
@@ -162,6 +163,13 @@ def main():
     if args.blocks_per_cu is not None:
         launch.blocks_per_cu = args.blocks_per_cu
     hbm_store = args.kernel_store == "hbm"
+    if args.kernel_store == "regen":
+        launch.kernel_store = 2
+    if args.kernel_store == "registers":
+        assert nq == 32, "--kernel-store registers needs --workload profile32"
+        launch.kernel_store = 3
+        traffic_tag += "_registers"
+        kernel_label = "fwd_kernel<3,32> (kernel rows held in VGPRs, DPP contraction)"
     if hbm_store:
         assert nq == 64, "--kernel-store hbm needs --workload profile64"
         launch.kernel_store = 1

@@ -157,8 +157,7 @@ typedef struct {
 } nmc_launch;
 
 /* Where the energy-coupling kernel matrices live during a solve.
- * ON_CHIP: built on chip (registers / LDS) once per outer iteration (32
- *   nodes) or regenerated in registers every inner iteration (64 nodes).
+ * ON_CHIP: the library's default, currently REGEN for 32 and 64 nodes.
  * HBM: 64-node solve only, for the roofline study of precomputed kernels:
  *   Phi_in, Phi_out and Phi_ann of every point are written to the workspace
  *   once per outer iteration and re-read by every inner iteration; the
@@ -166,6 +165,14 @@ typedef struct {
  *   nmc_workspace_bytes(m, P) ones. */
 #define NMC_KERNELS_ON_CHIP 0
 #define NMC_KERNELS_HBM 1
+/* REGEN: kernel entries regenerated from per-node factors in every inner
+ * iteration, nothing stored (the 64-node solve always works this way; for 32
+ * nodes it is an alternative to the register-resident rows). */
+#define NMC_KERNELS_REGEN 2
+/* REGISTERS: 32 nodes only: the kernel rows are assembled once per outer
+ * iteration (LDS tile) and held in VGPRs; the inner iterations contract them
+ * with DPP row broadcasts. */
+#define NMC_KERNELS_REGISTERS 3
 
 /* Defaults of the descriptors above (values in parentheses). */
 void nmc_model_desc_default(nmc_model_desc* desc);

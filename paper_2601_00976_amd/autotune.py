@@ -2,7 +2,8 @@
 
 The knobs are the points taken per work-queue grab (`chunk`), the resident
 work-groups per compute unit of the persistent grid (`blocks_per_cu`, 0 =
-occupancy limit) and persistent versus one-work-group-per-chunk launches.
+occupancy limit), persistent versus one-work-group-per-chunk launches, and
+(32 nodes) regenerated versus register-resident kernel rows.
 `tune()` times candidate shapes on a real batch and stores the winner in a
 JSON cache next to this file, keyed by (energy nodes, species, device name);
 `best_launch()` reads the cache and falls back to the persistent default.
@@ -42,11 +43,13 @@ def best_launch(model, P: int) -> S.LaunchConfig:
     return S.LaunchConfig(blocks_per_cu=0, chunk=4, persistent=True)
 
 
-def candidates():
-    for persistent in (True, False):
-        for chunk in (1, 2, 4, 8):
-            for bpc in ((0, 4, 6) if persistent else (0,)):
-                yield S.LaunchConfig(blocks_per_cu=bpc, chunk=chunk, persistent=persistent)
+def candidates(model=None):
+    stores = (0, 3) if model is None or model.nq == 32 else (0,)
+    for store in stores:
+        for persistent in (True, False):
+            for chunk in (1, 2, 4, 8):
+                for bpc in ((0, 4, 6) if persistent else (0,)):
+                    yield S.LaunchConfig(blocks_per_cu=bpc, chunk=chunk, persistent=persistent, kernel_store=store)
 
 
 def tune(model, params, dtau, D0, I0, rho11, ye0, e0, theta, repeats: int = 3, write: bool = True):
@@ -57,7 +60,7 @@ def tune(model, params, dtau, D0, I0, rho11, ye0, e0, theta, repeats: int = 3, w
     ws = S.Workspace(model, P, D0.device)
     out = S.alloc_outputs(model, P, D0.device)
     results = []
-    for L in candidates():
+    for L in candidates(model):
         S.solve(model, params, dtau, D0, I0, rho11, ye0, e0, theta, out=out, workspace=ws, launch=L)
         torch.cuda.synchronize()
         a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -72,7 +75,7 @@ def tune(model, params, dtau, D0, I0, rho11, ye0, e0, theta, repeats: int = 3, w
     if write:
         cache = _load()
         cache[_key(model)] = {"launch": {"blocks_per_cu": best.blocks_per_cu, "chunk": best.chunk,
-                                         "persistent": bool(best.persistent)},
+                                         "persistent": bool(best.persistent), "kernel_store": best.kernel_store},
                               "ms": results[0][0], "P": P}
         with open(CACHE, "w") as f:
             json.dump(cache, f, indent=1, sort_keys=True)

@@ -27,21 +27,23 @@ namespace {
 // Per-wave LDS scratch of the point solver: per-lane arrays, reduction
 // staging, and the uniform per-point state of the outer (matter) loop, kept
 // here so that it does not occupy VGPRs across the inner loop.
-template <int NS>
+template <int NS, int KM>
 struct WaveLds {
   ModelLds m;
-  double mst[NS][kLanes];   // owned moment of the old state (D* or I*)
+  double mst[KM == 0 ? NS : 1][kLanes];  // owned moment of the old state (D* or I*); in VGPRs when KM = 1
   double base[NS][kLanes];  // D* + dtau chi^EmAb D_eq (number lanes) or I* (flux lanes)
   double den0[NS][kLanes];  // 1 + dtau chi^EmAb (number lanes) or 1 + dtau (chi^EmAb + sigma^Iso)
   union {
     struct {
-      double hist[4][NS][kLanes];   // Anderson history: Q_prev, F_prev, dQ_old, dF_old
-      double red[2 * NS * kLanes];  // reduction staging
-      double redout[16];
-    } it;                       // live during an inner loop
-    double tile[32 * kTileStride];  // kernel-row assembly, live while building
+      double hist[4][NS][kLanes];                     // Anderson history: Q_prev, F_prev, dQ_old, dF_old
+      double red[KM == 0 ? 2 * NS * kLanes : 1];      // reduction staging (KM = 0)
+      double redout[KM == 0 ? 16 : 1];
+    } it;                                             // live during an inner loop
+    double tile[KM == 0 ? 32 * kTileStride : 1];      // kernel-row assembly (KM = 0), live while building
   } u;
-  SplitExp E;  // per-node factors of the current temperature (kernel build)
+  SplitExp E;                  // per-node factors of the current temperature
+  double X[KM == 1 ? NS : 1][32];  // W D of the current iterate (KM = 1)
+  double Y[KM == 1 ? NS : 1][32];  // W (1 - D) of the current iterate (KM = 1)
   // uniform per-point state
   double dref[NS];                      // ||D_s^[k,1]||_W^2 of the current inner loop
   double y[2];                          // matter iterate (Ye, e)
@@ -49,9 +51,59 @@ struct WaveLds {
   double T_last, r3, K, An, Ap;
 };
 
-template <int NS, int NQ, bool COUPLED>
+// KM = 0: kernel rows built once per outer iteration and held in VGPRs,
+// contracted with DPP broadcasts.  KM = 1: kernel entries regenerated in
+// every inner iteration from the per-node exponent splits, the two lane
+// halves taking columns 0..15 and 16..31 of the same rows.
+template <int NS, int NQ, bool COUPLED, int KM>
 struct PointSolver {
   static_assert(NQ == 32, "lane layout is for 32 energy nodes");
+
+  // KM = 1: rates of row q over columns j0 .. j0 + 15 (partial sums):
+  // eta = Phi_in W D_s + Phi_pro W (1 - D_sbar),
+  // chi = eta + Phi_out W (1 - D_s) + Phi_ann W D_sbar
+  __device__ __forceinline__ static void regen_rates(const WaveLds<NS, KM>& S, int q, int j0, double (&eta)[NS],
+                                                     double (&chi)[NS]) {
+    const SplitExp& E = S.E;
+    const double Pq = E.P2[q], Rq = E.R2[q], Gq = E.G[q], eq = S.m.eps[q];
+    const int nq = E.n2[q];
+    const double Aeq = S.An * eq, Apq = S.Ap * eq;
+    double etaN[NS], outN[NS], annP[NS], etaP[NS];
+#pragma unroll
+    for (int t = 0; t < NS; ++t) etaN[t] = outN[t] = annP[t] = etaP[t] = 0.0;
+#pragma unroll 4
+    for (int jj = 0; jj < 16; ++jj) {
+      const int j = j0 + jj;
+      const double Pj = E.P2[j], Rj = E.R2[j], Gj = E.G[j], ej = S.m.eps[j];
+      const int nj = E.n2[j];
+      const bool up = j > q;  // q is the lower node of the pair
+      const double b = ldexp(up ? Pq * Rj : Pj * Rq, up ? nq - nj : nj - nq);
+      const double b2 = b * b;
+      const double en = Aeq * ej, ep = Apq * ej;
+      const double u = en * b, v = en * (b2 * b);
+      const double fin = up ? u : v, fout = up ? v : u;
+      const double fann = ep * b2, fpro = ep * (up ? Gj : Gq);
+      double x[NS], y[NS];
+#pragma unroll
+      for (int t = 0; t < NS; ++t) {
+        x[t] = S.X[t][j];
+        y[t] = S.Y[t][j];
+      }
+#pragma unroll
+      for (int t = 0; t < NS; ++t) {
+        const int tb = pair_partner<NS>(t);
+        etaN[t] = __builtin_fma(fin, x[t], etaN[t]);
+        outN[t] = __builtin_fma(fout, y[t], outN[t]);
+        annP[t] = __builtin_fma(fann, x[tb], annP[t]);
+        etaP[t] = __builtin_fma(fpro, y[tb], etaP[t]);
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < NS; ++t) {
+      eta[t] = etaN[t] + etaP[t];
+      chi[t] = (etaN[t] + outN[t]) + (etaP[t] + annP[t]);
+    }
+  }
 
   // Energy-coupling contraction: a1[t] = sum_j M1[j] X_t[j], a2[t] = sum_j M2[j] X_t[j]
   // where X_t = W D_t on number lanes and W (1 - D_t) on flux lanes.  Column
@@ -76,11 +128,32 @@ struct PointSolver {
     });
   }
 
+  // per-half sums (lanes 0..31, lanes 32..63) of V lane values, every lane
+  // gets both: through LDS (KM = 0) or register permutations (KM = 1)
+  template <int V>
+  __device__ __forceinline__ static void hsum(const double (&v)[V], double (&s0)[V], double (&s1)[V],
+                                              WaveLds<NS, KM>& S) {
+    if constexpr (KM == 0) {
+      half_sums<V>(v, s0, s1, S.u.it.red, S.u.it.redout);
+    } else {
+      constexpr int K = (V + 1) / 2;
+      double w[2 * K], a0[2 * K], a1[2 * K];
+#pragma unroll
+      for (int i = 0; i < 2 * K; ++i) w[i] = i < V ? v[i < V ? i : 0] : 0.0;
+      half_sums_reg<K>(w, a0, a1);
+#pragma unroll
+      for (int i = 0; i < V; ++i) {
+        s0[i] = a0[i];
+        s1[i] = a1[i];
+      }
+    }
+  }
+
   // Kernel rows at temperature T, assembled in the LDS tile three times:
   // Phi_in (number lanes load row q, flux lanes column q = row q of
   // Phi_out), Phi_ann (number lanes load row q), Phi_pro (flux lanes load
   // row q).
-  __device__ __forceinline__ static void build_rows(int h, int q, double invT, double An, double Ap, WaveLds<NS>& S,
+  __device__ __forceinline__ static void build_rows(int h, int q, double invT, double An, double Ap, WaveLds<NS, KM>& S,
                                                     double (&M1)[NQ], double (&M2)[NQ]) {
     constexpr int ST = kTileStride;
     double* T0 = S.u.tile;
@@ -112,7 +185,7 @@ struct PointSolver {
     __syncthreads();
   }
 
-  __device__ static void solve(const FwdArgs& a, int64_t p, WaveLds<NS>& S) {
+  __device__ static void solve(const FwdArgs& a, int64_t p, WaveLds<NS, KM>& S) {
     const DevModel* __restrict__ md0 = a.mdl;
     const DevModel* __restrict__ md = md0;
     const ModelLds& mt = S.m;
@@ -154,8 +227,16 @@ struct PointSolver {
       }
       return;
     }
+    double MstR[KM == 1 ? NS : 1];
 #pragma unroll
-    for (int t = 0; t < NS; ++t) S.mst[t][lane] = M[t];
+    for (int t = 0; t < NS; ++t) {
+      if constexpr (KM == 0) S.mst[t][lane] = M[t];
+      else MstR[t] = M[t];
+    }
+    auto mst = [&](int t) -> double {
+      if constexpr (KM == 0) return S.mst[t][lane];
+      else return MstR[t];
+    };
 
     // point constants: rho^(1/3), coupling K, kernel amplitudes
     S.r3 = cbrt(rho);
@@ -169,7 +250,7 @@ struct PointSolver {
       double v[NS], s0[NS], s1[NS];
 #pragma unroll
       for (int t = 0; t < NS; ++t) v[t] = h ? 0.0 : w2q * Dcur[t] * Dcur[t];
-      half_sums<NS>(v, s0, s1, S.u.it.red, S.u.it.redout);
+      hsum<NS>(v, s0, s1, S);
 #pragma unroll
       for (int t = 0; t < NS; ++t) S.dref[t] = s0[t];
     }
@@ -183,7 +264,7 @@ struct PointSolver {
     bool fatal = false, inner_failed = false, outer_conv = false;
     int k, total_inner = 0;
 
-    double M1[NQ], M2[NQ];
+    double M1[KM == 0 ? NQ : 1], M2[KM == 0 ? NQ : 1];
     for (k = 1; k <= a.prm.max_outer; ++k) {
       // per-iteration opaque copies keep lane invariants from being hoisted
       // out of this loop (and spilled)
@@ -223,14 +304,17 @@ struct PointSolver {
           const double ex = exp(-fabs(x));
           const double r = rcp_ge1(1.0 + ex);
           const double deq = x > 0.0 ? ex * r : r;
-          S.base[t][lane] = h ? S.mst[t][lane] : S.mst[t][lane] + dtau * (chia * deq);
+          S.base[t][lane] = h ? mst(t) : mst(t) + dtau * (chia * deq);
           S.den0[t][lane] = 1.0 + dtau * (h ? chia + sig : chia);
         }
       }
 
       // kernel rows in registers: number lanes Phi_in[q][:], Phi_ann[q][:];
       // flux lanes Phi_out[q][:], Phi_pro[q][:]
-      if constexpr (COUPLED) build_rows(h, q, invT, S.An, S.Ap, S, M1, M2);
+      if constexpr (COUPLED) {
+        if constexpr (KM == 0) build_rows(h, q, invT, S.An, S.Ap, S, M1, M2);
+        else split_exp_prepare(S.m, invT, S.E);
+      }
 
       // ---- inner loop over moments at fixed matter (M^[k,1] = M^[k-1,*]) --
       const double w2q = mt.w2[q];
@@ -242,7 +326,24 @@ struct PointSolver {
       for (l = 1; l <= a.prm.max_inner; ++l) {
         // ComputeRates(M^[k,l])
         double eta_c[NS], chi_c[NS];
-        if constexpr (COUPLED) {
+        if constexpr (COUPLED && KM == 1) {
+          if (h == 0) {
+#pragma unroll
+            for (int t = 0; t < NS; ++t) {
+              S.X[t][q] = w2q * Dcur[t];
+              S.Y[t][q] = __builtin_fma(-w2q, Dcur[t], w2q);
+            }
+          }
+          __syncthreads();
+          double e_p[NS], c_p[NS];
+          regen_rates(S, q, 16 * h, e_p, c_p);
+          __syncthreads();
+#pragma unroll
+          for (int t = 0; t < NS; ++t) {
+            eta_c[t] = sum_halves(e_p[t]);
+            chi_c[t] = sum_halves(c_p[t]);
+          }
+        } else if constexpr (COUPLED) {
           double XR[NS][2];
 #pragma unroll
           for (int t = 0; t < NS; ++t) swap16(__builtin_fma(xa, Dcur[t], xb), XR[t][0], XR[t][1]);
@@ -389,7 +490,7 @@ struct PointSolver {
         double v[NS], s0[NS], s1[NS];
 #pragma unroll
         for (int t = 0; t < NS; ++t) v[t] = h ? 0.0 : w2q * M[t] * M[t];
-        half_sums<NS>(v, s0, s1, S.u.it.red, S.u.it.redout);
+        hsum<NS>(v, s0, s1, S);
 #pragma unroll
         for (int t = 0; t < NS; ++t) S.dref[t] = s0[t];
       }
@@ -406,12 +507,12 @@ struct PointSolver {
         if (h == 0) {
 #pragma unroll
           for (int t = 0; t < NS; ++t) {
-            const double dd = M[t] - S.mst[t][lane];
+            const double dd = M[t] - mst(t);
             mv[0] += md->ig[t] * w2q * dd;
             mv[1] += md->imult[t] * w3 * dd;
           }
         }
-        half_sums<2>(mv, s0, s1, S.u.it.red, S.u.it.redout);
+        hsum<2>(mv, s0, s1, S);
         yq0 = a.ye0[p] - S.K * s0[0];
         yq1 = a.e0[p] - S.K * s0[1];
       }
@@ -492,12 +593,12 @@ struct PointSolver {
       if (h == 0) {
 #pragma unroll
         for (int t = 0; t < NS; ++t) {
-          const double dd = M[t] - S.mst[t][lane];
+          const double dd = M[t] - mst(t);
           mv[0] += md->ig[t] * w2 * dd;
           mv[1] += md->imult[t] * w3 * dd;
         }
       }
-      half_sums<2>(mv, s0, s1, S.u.it.red, S.u.it.redout);
+      hsum<2>(mv, s0, s1, S);
       ye_out = ye_st - S.K * s0[0];
       e_out = e_st - S.K * s0[1];
       T_out = (e_out - md->eos_b * ye43(ye_out) * S.r3) / (md->eos_a * (1.0 + ye_out));
@@ -520,9 +621,9 @@ struct PointSolver {
   }
 };
 
-template <int NS, int NQ, bool COUPLED>
-__global__ __launch_bounds__(kLanes, 2) void fwd_kernel(FwdArgs a) {
-  __shared__ WaveLds<NS> S;
+template <int NS, int NQ, bool COUPLED, int KM>
+__global__ __launch_bounds__(kLanes, KM == 0 ? 2 : 3) void fwd_kernel(FwdArgs a) {
+  __shared__ WaveLds<NS, KM> S;
   load_model(a.mdl, a.theta, S.m);
   if (a.queue) {
     // persistent grid: pop chunks of points from the work queue until
@@ -534,12 +635,12 @@ __global__ __launch_bounds__(kLanes, 2) void fwd_kernel(FwdArgs a) {
       if (b0 >= a.P) break;
       if (threadIdx.x == 0) nxt = atomicAdd(a.queue, a.chunk);
       const int64_t end = b0 + a.chunk < a.P ? b0 + a.chunk : a.P;
-      for (int64_t p = b0; p < end; ++p) PointSolver<NS, NQ, COUPLED>::solve(a, p, S);
+      for (int64_t p = b0; p < end; ++p) PointSolver<NS, NQ, COUPLED, KM>::solve(a, p, S);
     }
   } else {
     const int64_t b0 = (int64_t)blockIdx.x * a.chunk;
     const int64_t end = b0 + a.chunk < a.P ? b0 + a.chunk : a.P;
-    for (int64_t p = b0; p < end; ++p) PointSolver<NS, NQ, COUPLED>::solve(a, p, S);
+    for (int64_t p = b0; p < end; ++p) PointSolver<NS, NQ, COUPLED, KM>::solve(a, p, S);
   }
 }
 
@@ -547,9 +648,9 @@ __global__ void reset_counter_kernel(int* c) {
   if (threadIdx.x == 0) *c = 0;
 }
 
-template <int NS, int NQ, bool COUPLED>
+template <int NS, int NQ, bool COUPLED, int KM>
 hipError_t launch_fwd_t(const FwdArgs& a, const nmc_launch& L, int num_cu, hipStream_t s) {
-  auto kern = fwd_kernel<NS, NQ, COUPLED>;
+  auto kern = fwd_kernel<NS, NQ, COUPLED, KM>;
   int64_t grid;
   if (a.queue) {
     int bpc = L.blocks_per_cu;
@@ -584,17 +685,23 @@ hipError_t launch_reset_counter(int* counter, hipStream_t s) {
 hipError_t launch_forward(const FwdArgs& a, int nq, int ns, bool coupled, const nmc_launch& L, int num_cu,
                           hipStream_t s) {
   if (nq == 32) {
-    if (coupled) {
+    if (coupled && L.kernel_store != NMC_KERNELS_REGISTERS) {
       switch (ns) {
-        case 1: return launch_fwd_t<1, 32, true>(a, L, num_cu, s);
-        case 2: return launch_fwd_t<2, 32, true>(a, L, num_cu, s);
-        case 3: return launch_fwd_t<3, 32, true>(a, L, num_cu, s);
+        case 1: return launch_fwd_t<1, 32, true, 1>(a, L, num_cu, s);
+        case 2: return launch_fwd_t<2, 32, true, 1>(a, L, num_cu, s);
+        case 3: return launch_fwd_t<3, 32, true, 1>(a, L, num_cu, s);
+      }
+    } else if (coupled) {
+      switch (ns) {
+        case 1: return launch_fwd_t<1, 32, true, 0>(a, L, num_cu, s);
+        case 2: return launch_fwd_t<2, 32, true, 0>(a, L, num_cu, s);
+        case 3: return launch_fwd_t<3, 32, true, 0>(a, L, num_cu, s);
       }
     } else {
       switch (ns) {
-        case 1: return launch_fwd_t<1, 32, false>(a, L, num_cu, s);
-        case 2: return launch_fwd_t<2, 32, false>(a, L, num_cu, s);
-        case 3: return launch_fwd_t<3, 32, false>(a, L, num_cu, s);
+        case 1: return launch_fwd_t<1, 32, false, 0>(a, L, num_cu, s);
+        case 2: return launch_fwd_t<2, 32, false, 0>(a, L, num_cu, s);
+        case 3: return launch_fwd_t<3, 32, false, 0>(a, L, num_cu, s);
       }
     }
   }

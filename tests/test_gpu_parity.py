@@ -172,3 +172,22 @@ def test_empty_and_single():
     mo, ref = PT.run_oracle(d, ALL3, O.ALL_PHYSICS, W.DTAU_KM, O.Params(), theta)
     _, got = PT.run_gpu(d, ALL3, O.ALL_PHYSICS, W.DTAU_KM, S.Params(), theta)
     _compare(ref, got, mo.w2, model=mo, rho11=d.rho11)
+
+
+def test_regenerated_kernels_profile_and_box():
+    _say("32 nodes, kernel entries regenerated per inner iteration: profile sample P=512 and box P=256")
+    L = S.LaunchConfig(kernel_store=2)
+    d = W.radial_profile(P=1 << 16).take(np.arange(0, 1 << 16, 128))
+    theta = _theta(32)
+    m, ref = PT.run_oracle(d, ALL3, O.ALL_PHYSICS, W.DTAU_KM, O.Params(), theta)
+    _, got = PT.run_gpu(d, ALL3, O.ALL_PHYSICS, W.DTAU_KM, S.Params(), theta, launch=L)
+    _compare(ref, got, m.w2, model=m, rho11=d.rho11)
+    d = _box_sample(256, seed=3)
+    m, ref = PT.run_oracle(d, ALL3, O.ALL_PHYSICS, W.DTAU_KM, O.Params(), theta)
+    _, got = PT.run_gpu(d, ALL3, O.ALL_PHYSICS, W.DTAU_KM, S.Params(), theta, launch=L)
+    _compare(ref, got, m.w2, model=m, rho11=d.rho11)
+    for sp in ((O.NU_E, O.NU_E_BAR), (O.NU_X,)):
+        dd = W.radial_profile(P=1 << 16, ns=len(sp)).take(np.arange(0, 1 << 16, 512))
+        m, ref = PT.run_oracle(dd, sp, O.ALL_PHYSICS, W.DTAU_KM, O.Params(), theta)
+        _, got = PT.run_gpu(dd, sp, O.ALL_PHYSICS, W.DTAU_KM, S.Params(), theta, launch=L)
+        _compare(ref, got, m.w2, model=m, rho11=dd.rho11, species=sp)
