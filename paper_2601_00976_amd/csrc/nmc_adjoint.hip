@@ -20,8 +20,8 @@
 // holds row r of A^T (column r of A) and the two right-hand sides.  Gaussian
 // elimination picks the pivot row by a wave-wide argmax over the lanes not yet
 // eliminated (partial pivoting without moving rows), broadcasts it through
-// LDS, and every other lane updates its row; back substitution runs over the
-// recorded pivot order.  Per-point terms go to a (P, nq + 2) array and are
+// scalar registers (v_readlane), and every other lane updates its row; back
+// substitution runs over the recorded pivot order.  Per-point terms go to a (P, nq + 2) array and are
 // summed over points by a fixed-order two-stage reduction.
 #include "nmc_wave.h"
 
@@ -36,7 +36,6 @@ struct AdjLds {
   SplitExp E;
   double tin[32 * kTileStride], tann[32 * kTileStride], tpro[32 * kTileStride];  // unit-amplitude kernels
   double D[NS][NQ];
-  double prow[64 + 2];  // pivot row of the current elimination step and its right-hand sides
   // per-row results, row = (species, node)
   double chi[NS][NQ];         // total opacity chi of the row
   double b0[NS][NQ], b1[NS][NQ];  // dR_D / dYe, dR_D / de
@@ -57,6 +56,15 @@ __device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
   return m(b[0], b[1]);
 }
 
+// reciprocal: hardware estimate refined by two Newton steps (x finite, nonzero)
+__device__ __forceinline__ double rcp_nr(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = __builtin_fma(-x, r, 1.0);
+  r = __builtin_fma(r, e, r);
+  e = __builtin_fma(-x, r, 1.0);
+  return __builtin_fma(r, e, r);
+}
+
 __device__ __forceinline__ double readlane_f64(double v, int lane) {
   const uint32_t lo = __builtin_amdgcn_readlane((int)lo32(v), lane);
   const uint32_t hi = __builtin_amdgcn_readlane((int)hi32(v), lane);
@@ -67,9 +75,11 @@ __device__ __forceinline__ double readlane_f64(double v, int lane) {
 // lane r enters with R = row r of A^T and c = (c0, c1) its right-hand sides
 // and leaves with (z0, z1) = entry r of the two solutions.  Returns false if
 // a pivot was zero or non-finite (the results are then not finite either).
+// The pivot row is broadcast with v_readlane into scalar registers, which the
+// update FMAs of the other lanes read directly (no LDS round trip).
 template <int N>
-__device__ __forceinline__ bool solve_block_transposed(double (&R)[N], double c0, double c1, double* prow,
-                                                       double& z0, double& z1) {
+__device__ __forceinline__ bool solve_block_transposed(double (&R)[N], double c0, double c1, double& z0,
+                                                       double& z1) {
   const int lane = opaque((int)threadIdx.x);
   const bool active = lane < N;
   bool done = !active;
@@ -89,36 +99,30 @@ __device__ __forceinline__ bool solve_block_transposed(double (&R)[N], double c0
       bal = __builtin_amdgcn_ballot_w64(!done);
     }
     const int pl = (int)__builtin_ctzll(bal);
+    const double piv = readlane_f64(R[k], pl);
+    ok = ok && piv != 0.0 && isfinite(piv);
     if (lane == pl) {
-#pragma unroll
-      for (int j = k; j < N; ++j) prow[j] = R[j];
-      prow[N] = c0;
-      prow[N + 1] = c1;
       mystep = k;
       done = true;
     }
-    __syncthreads();
-    const double piv = prow[k];
-    ok = ok && piv != 0.0 && isfinite(piv);
     if (!done) {
-      const double l = R[k] / piv;
+      const double l = R[k] * rcp_nr(piv);
 #pragma unroll
       for (int j = k + 1; j < N; ++j) {
-        R[j] = __builtin_fma(-l, prow[j], R[j]);
-        // keep at most a few pivot-row loads in flight (register pressure)
-        if ((j & 7) == 7) asm volatile("" ::: "memory");
+        R[j] = __builtin_fma(-l, readlane_f64(R[j], pl), R[j]);
+        // bound the scalar registers in flight: no scheduling across this point
+        if ((j & 3) == 3) __builtin_amdgcn_sched_barrier(0);
       }
-      c0 = __builtin_fma(-l, prow[N], c0);
-      c1 = __builtin_fma(-l, prow[N + 1], c1);
+      c0 = __builtin_fma(-l, readlane_f64(c0, pl), c0);
+      c1 = __builtin_fma(-l, readlane_f64(c1, pl), c1);
     }
-    __syncthreads();
   });
   z0 = z1 = 0.0;
   static_for<0, N>([&](auto kk) __attribute__((always_inline)) {
     constexpr int k = N - 1 - decltype(kk)::value;
     const uint64_t bal = __builtin_amdgcn_ballot_w64(mystep == k);
     const int pl = bal ? (int)__builtin_ctzll(bal) : 0;
-    const double r = 1.0 / R[k];
+    const double r = rcp_nr(R[k]);
     const double zk0 = readlane_f64(c0 * r, pl), zk1 = readlane_f64(c1 * r, pl);
     if (lane == k) {
       z0 = zk0;
@@ -182,7 +186,7 @@ struct PointAdjoint {
     const double c0 = K * md->ig[sp] * S.m.w2[p];
     const double c1 = K * md->imult[sp] * S.m.w3[p];
     double z0, z1;
-    const bool ok = solve_block_transposed<32 * NB>(R, c0, c1, S.prow, z0, z1);
+    const bool ok = solve_block_transposed<32 * NB>(R, c0, c1, z0, z1);
     if (lane < 32 * NB) {
       S.z0[sp][p] = z0;
       S.z1[sp][p] = z1;

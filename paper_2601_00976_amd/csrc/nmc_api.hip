@@ -46,7 +46,7 @@ int hip_fail(hipError_t e, const char* what) {
 
 bool aligned256(const void* p) { return ((uintptr_t)p & 255u) == 0; }
 
-constexpr size_t kCounterBytes = 256;
+constexpr size_t kCounterBytes = 2048;  // work-queue counters: 8 lines of 256 bytes
 
 int partner_id(int id) { return id == NMC_NU_E ? NMC_NU_E_BAR : (id == NMC_NU_E_BAR ? NMC_NU_E : NMC_NU_X); }
 
@@ -266,7 +266,7 @@ int nmc_model_destroy(nmc_model* m) {
 
 size_t nmc_workspace_bytes(const nmc_model* m, int64_t P) {
   if (!m || P < 0) return 0;
-  // queue counter + per-point adjoint terms and a column-partial buffer
+  // queue counters + per-point adjoint terms and a column-partial buffer
   const size_t nt = (size_t)m->host.nq + 2;
   const size_t pp = ((size_t)P * nt * sizeof(double) + 255) & ~(size_t)255;
   const size_t part = ((size_t)nmc::kReduceBlocks * nt * sizeof(double) + 255) & ~(size_t)255;

@@ -626,14 +626,9 @@ __global__ __launch_bounds__(kLanes, KM == 0 ? 2 : 3) void fwd_kernel(FwdArgs a)
   __shared__ WaveLds<NS, KM> S;
   load_model(a.mdl, a.theta, S.m);
   if (a.queue) {
-    // persistent grid: pop chunks of points from the work queue until
-    // drained; the next grab is issued before the current chunk is solved
-    int nxt = 0;
-    if (threadIdx.x == 0) nxt = atomicAdd(a.queue, a.chunk);
-    for (;;) {
-      const int64_t b0 = __builtin_amdgcn_readfirstlane(nxt);
-      if (b0 >= a.P) break;
-      if (threadIdx.x == 0) nxt = atomicAdd(a.queue, a.chunk);
+    WorkQueue wq(a.queue, a.P, a.chunk);
+    for (int64_t g; (g = wq.next()) >= 0;) {
+      const int64_t b0 = g * a.chunk;
       const int64_t end = b0 + a.chunk < a.P ? b0 + a.chunk : a.P;
       for (int64_t p = b0; p < end; ++p) PointSolver<NS, NQ, COUPLED, KM>::solve(a, p, S);
     }
@@ -645,7 +640,7 @@ __global__ __launch_bounds__(kLanes, KM == 0 ? 2 : 3) void fwd_kernel(FwdArgs a)
 }
 
 __global__ void reset_counter_kernel(int* c) {
-  if (threadIdx.x == 0) *c = 0;
+  if (threadIdx.x < kQueues) c[threadIdx.x * kQueueStride] = 0;
 }
 
 template <int NS, int NQ, bool COUPLED, int KM>
@@ -660,7 +655,9 @@ hipError_t launch_fwd_t(const FwdArgs& a, const nmc_launch& L, int num_cu, hipSt
       if (occ <= 0) {
         int o = 0;
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, kern, kLanes, 0) != hipSuccess || o <= 0) o = 8;
-        occ = o;
+        // the query under-reports resident one-wave work-groups; a surplus is
+        // harmless (late work-groups find the queue drained and exit)
+        occ = o < 16 ? 16 : o;
       }
       bpc = occ;
     }

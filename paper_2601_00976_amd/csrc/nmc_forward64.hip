@@ -531,12 +531,9 @@ __global__ __launch_bounds__(kLanes) void fwd64_kernel(FwdArgs a) {
   __shared__ Lds64<NS> S;
   load_model(a.mdl, a.theta, S.m);
   if (a.queue) {
-    int nxt = 0;
-    if (threadIdx.x == 0) nxt = atomicAdd(a.queue, a.chunk);
-    for (;;) {
-      const int64_t b0 = __builtin_amdgcn_readfirstlane(nxt);
-      if (b0 >= a.P) break;
-      if (threadIdx.x == 0) nxt = atomicAdd(a.queue, a.chunk);
+    WorkQueue wq(a.queue, a.P, a.chunk);
+    for (int64_t g; (g = wq.next()) >= 0;) {
+      const int64_t b0 = g * a.chunk;
       const int64_t end = b0 + a.chunk < a.P ? b0 + a.chunk : a.P;
       for (int64_t p = b0; p < end; ++p) PointSolver64<NS, COUPLED, PRE>::solve(a, p, S);
     }
@@ -558,7 +555,9 @@ hipError_t launch64_t(const FwdArgs& a, const nmc_launch& L, int num_cu, hipStre
       if (occ <= 0) {
         int o = 0;
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, kern, kLanes, 0) != hipSuccess || o <= 0) o = 8;
-        occ = o;
+        // the query under-reports resident one-wave work-groups; a surplus is
+        // harmless (late work-groups find the queue drained and exit)
+        occ = o < 16 ? 16 : o;
       }
       bpc = occ;
     }

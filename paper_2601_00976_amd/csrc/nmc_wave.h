@@ -311,6 +311,37 @@ __device__ __forceinline__ void load_model(const DevModel* __restrict__ md, cons
   __syncthreads();
 }
 
+// Work queue of the persistent kernels: up to kQueues counters, each on its
+// own 256-byte line, one per class of work-group ids (id mod nq: one per XCD
+// when work-groups are dealt round-robin to the 8 XCDs).  Counter c hands out
+// chunk indices c, c + nq, c + 2 nq, ..., so every queue sees the same mix of
+// cheap and expensive points.  Every work-group loops until its queue is
+// exhausted, so the grid drains before the kernel ends.
+constexpr int kQueues = 8;
+constexpr int kQueueStride = 64;  // ints
+
+struct WorkQueue {
+  int* ctr;
+  int64_t nchunks;
+  int nq, c, nxt;
+  __device__ __forceinline__ WorkQueue(int* queue, int64_t P, int chunk) {
+    nq = gridDim.x < kQueues ? (int)gridDim.x : kQueues;
+    c = blockIdx.x % nq;
+    ctr = queue + c * kQueueStride;
+    nchunks = (P + chunk - 1) / chunk;
+    nxt = 0;
+    if (threadIdx.x == 0) nxt = atomicAdd(ctr, 1);
+  }
+  // next chunk index of this work-group (uniform), or -1 once drained; the
+  // following grab is issued before the chunk is solved
+  __device__ __forceinline__ int64_t next() {
+    const int64_t g = (int64_t)__builtin_amdgcn_readfirstlane(nxt) * nq + c;
+    if (g >= nchunks) return -1;
+    if (threadIdx.x == 0) nxt = atomicAdd(ctr, 1);
+    return g;
+  }
+};
+
 // Pair partner of internal species s (species sorted by id: nu_e, anti-nu_e
 // are partners, nu_x is its own partner).  Models without pair processes
 // have zero pair kernels, so the map is irrelevant for them.

@@ -174,9 +174,10 @@ def test_empty_and_single():
     _compare(ref, got, mo.w2, model=mo, rho11=d.rho11)
 
 
-def test_regenerated_kernels_profile_and_box():
-    _say("32 nodes, kernel entries regenerated per inner iteration: profile sample P=512 and box P=256")
-    L = S.LaunchConfig(kernel_store=2)
+@pytest.mark.parametrize("store", [2, 3])
+def test_kernel_modes_profile_and_box(store):
+    _say(f"32 nodes, kernel_store={store} (2: regenerated, 3: register rows): profile P=512, box P=256")
+    L = S.LaunchConfig(kernel_store=store)
     d = W.radial_profile(P=1 << 16).take(np.arange(0, 1 << 16, 128))
     theta = _theta(32)
     m, ref = PT.run_oracle(d, ALL3, O.ALL_PHYSICS, W.DTAU_KM, O.Params(), theta)
