@@ -122,7 +122,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--cpu-repeats", type=int, default=2, help="repeats of the 10-step chain in the oracle baseline")
+    ap.add_argument("--cpu-repeats", type=int, default=4, help="repeats of the 10-step chain in the oracle baseline")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--chunk", type=int, default=None)
     ap.add_argument("--blocks-per-cu", type=int, default=None)
