@@ -157,7 +157,10 @@ typedef struct {
 } nmc_launch;
 
 /* Where the energy-coupling kernel matrices live during a solve.
- * ON_CHIP: the library's default, currently REGEN for 32 and 64 nodes.
+ * ON_CHIP: the library's default.  32 nodes: the kernel entries are
+ *   regenerated in every inner iteration from per-node factors and the
+ *   lane's pair factors exp(-|e - e'| / (2T)) computed once per outer
+ *   iteration (kept in VGPRs); 64 nodes: as REGEN.
  * HBM: 64-node solve only, for the roofline study of precomputed kernels:
  *   Phi_in, Phi_out and Phi_ann of every point are written to the workspace
  *   once per outer iteration and re-read by every inner iteration; the

@@ -3,7 +3,8 @@
 The knobs are the points taken per work-queue grab (`chunk`), the resident
 work-groups per compute unit of the persistent grid (`blocks_per_cu`, 0 =
 occupancy limit), persistent versus one-work-group-per-chunk launches, and
-(32 nodes) regenerated versus register-resident kernel rows.
+(32 nodes) the kernel-row mode: regenerated with cached pair factors (the
+default), fully regenerated, or register-resident.
 `tune()` times candidate shapes on a real batch and stores the winner in a
 JSON cache next to this file, keyed by (energy nodes, species, device name);
 `best_launch()` reads the cache and falls back to the persistent default.
@@ -48,7 +49,7 @@ def candidates(model=None, persistent_only=True):
     work-queue kernel, so by default only persistent shapes are tuned (one
     work-group per chunk, the hardware dispatcher acting as the queue, is
     available through LaunchConfig(persistent=False))."""
-    stores = (0, 3) if model is None or model.nq == 32 else (0,)
+    stores = (0, 2, 3) if model is None or model.nq == 32 else (0,)
     for store in stores:
         for persistent in ((True,) if persistent_only else (True, False)):
             for chunk in (1, 2, 4, 8):

@@ -30,7 +30,7 @@ namespace {
 template <int NS, int KM>
 struct WaveLds {
   ModelLds m;
-  double mst[KM == 0 ? NS : 1][kLanes];  // owned moment of the old state (D* or I*); in VGPRs when KM = 1
+  double mst[KM == 0 ? NS : 1][kLanes];  // owned moment of the old state (D* or I*); in VGPRs when KM >= 1
   double base[NS][kLanes];  // D* + dtau chi^EmAb D_eq (number lanes) or I* (flux lanes)
   double den0[NS][kLanes];  // 1 + dtau chi^EmAb (number lanes) or 1 + dtau (chi^EmAb + sigma^Iso)
   union {
@@ -42,8 +42,8 @@ struct WaveLds {
     double tile[KM == 0 ? 32 * kTileStride : 1];      // kernel-row assembly (KM = 0), live while building
   } u;
   SplitExp E;                  // per-node factors of the current temperature
-  double X[KM == 1 ? NS : 1][32];  // W D of the current iterate (KM = 1)
-  double Y[KM == 1 ? NS : 1][32];  // W (1 - D) of the current iterate (KM = 1)
+  double X[KM >= 1 ? NS : 1][32];  // W D of the current iterate (KM >= 1)
+  double Y[KM >= 1 ? NS : 1][32];  // W (1 - D) of the current iterate (KM >= 1)
   // uniform per-point state
   double dref[NS];                      // ||D_s^[k,1]||_W^2 of the current inner loop
   double y[2];                          // matter iterate (Ye, e)
@@ -54,7 +54,9 @@ struct WaveLds {
 // KM = 0: kernel rows built once per outer iteration and held in VGPRs,
 // contracted with DPP broadcasts.  KM = 1: kernel entries regenerated in
 // every inner iteration from the per-node exponent splits, the two lane
-// halves taking columns 0..15 and 16..31 of the same rows.
+// halves taking columns 0..15 and 16..31 of the same rows.  KM = 2: as KM = 1,
+// with the lane's 16 factors b computed once per outer iteration and kept in
+// VGPRs (the default).
 template <int NS, int NQ, bool COUPLED, int KM>
 struct PointSolver {
   static_assert(NQ == 32, "lane layout is for 32 energy nodes");
@@ -62,7 +64,8 @@ struct PointSolver {
   // KM = 1: rates of row q over columns j0 .. j0 + 15 (partial sums):
   // eta = Phi_in W D_s + Phi_pro W (1 - D_sbar),
   // chi = eta + Phi_out W (1 - D_s) + Phi_ann W D_sbar
-  __device__ __forceinline__ static void regen_rates(const WaveLds<NS, KM>& S, int q, int j0, double (&eta)[NS],
+  __device__ __forceinline__ static void regen_rates(const WaveLds<NS, KM>& S, int q, int j0,
+                                                     const double (&Bq)[KM == 2 ? 16 : 1], double (&eta)[NS],
                                                      double (&chi)[NS]) {
     const SplitExp& E = S.E;
     const double Pq = E.P2[q], Rq = E.R2[q], Gq = E.G[q], eq = S.m.eps[q];
@@ -71,13 +74,19 @@ struct PointSolver {
     double etaN[NS], outN[NS], annP[NS], etaP[NS];
 #pragma unroll
     for (int t = 0; t < NS; ++t) etaN[t] = outN[t] = annP[t] = etaP[t] = 0.0;
-#pragma unroll 4
+#pragma unroll(KM == 2 ? 16 : 4)
     for (int jj = 0; jj < 16; ++jj) {
       const int j = j0 + jj;
-      const double Pj = E.P2[j], Rj = E.R2[j], Gj = E.G[j], ej = S.m.eps[j];
-      const int nj = E.n2[j];
+      const double Gj = E.G[j], ej = S.m.eps[j];
       const bool up = j > q;  // q is the lower node of the pair
-      const double b = ldexp(up ? Pq * Rj : Pj * Rq, up ? nq - nj : nj - nq);
+      double b;
+      if constexpr (KM == 2) {
+        b = Bq[jj];
+      } else {
+        const double Pj = E.P2[j], Rj = E.R2[j];
+        const int nj = E.n2[j];
+        b = ldexp(up ? Pq * Rj : Pj * Rq, up ? nq - nj : nj - nq);
+      }
       const double b2 = b * b;
       const double en = Aeq * ej, ep = Apq * ej;
       const double u = en * b, v = en * (b2 * b);
@@ -227,7 +236,7 @@ struct PointSolver {
       }
       return;
     }
-    double MstR[KM == 1 ? NS : 1];
+    double MstR[KM >= 1 ? NS : 1];
 #pragma unroll
     for (int t = 0; t < NS; ++t) {
       if constexpr (KM == 0) S.mst[t][lane] = M[t];
@@ -311,9 +320,21 @@ struct PointSolver {
 
       // kernel rows in registers: number lanes Phi_in[q][:], Phi_ann[q][:];
       // flux lanes Phi_out[q][:], Phi_pro[q][:]
+      double Bq[KM == 2 ? 16 : 1];
       if constexpr (COUPLED) {
         if constexpr (KM == 0) build_rows(h, q, invT, S.An, S.Ap, S, M1, M2);
         else split_exp_prepare(S.m, invT, S.E);
+        if constexpr (KM == 2) {
+          // b of this lane's 16 columns, kept in VGPRs for the inner loop
+          const double Pq = S.E.P2[q], Rq = S.E.R2[q];
+          const int nq = S.E.n2[q];
+#pragma unroll
+          for (int jj = 0; jj < 16; ++jj) {
+            const int j = 16 * h + jj;
+            const bool up = j > q;
+            Bq[jj] = ldexp(up ? Pq * S.E.R2[j] : S.E.P2[j] * Rq, up ? nq - S.E.n2[j] : S.E.n2[j] - nq);
+          }
+        }
       }
 
       // ---- inner loop over moments at fixed matter (M^[k,1] = M^[k-1,*]) --
@@ -326,7 +347,7 @@ struct PointSolver {
       for (l = 1; l <= a.prm.max_inner; ++l) {
         // ComputeRates(M^[k,l])
         double eta_c[NS], chi_c[NS];
-        if constexpr (COUPLED && KM == 1) {
+        if constexpr (COUPLED && KM >= 1) {
           if (h == 0) {
 #pragma unroll
             for (int t = 0; t < NS; ++t) {
@@ -336,7 +357,7 @@ struct PointSolver {
           }
           __syncthreads();
           double e_p[NS], c_p[NS];
-          regen_rates(S, q, 16 * h, e_p, c_p);
+          regen_rates(S, q, 16 * h, Bq, e_p, c_p);
           __syncthreads();
 #pragma unroll
           for (int t = 0; t < NS; ++t) {
@@ -622,7 +643,7 @@ struct PointSolver {
 };
 
 template <int NS, int NQ, bool COUPLED, int KM>
-__global__ __launch_bounds__(kLanes, KM == 0 ? 2 : 3) void fwd_kernel(FwdArgs a) {
+__global__ __launch_bounds__(kLanes, KM == 1 ? 3 : 2) void fwd_kernel(FwdArgs a) {
   __shared__ WaveLds<NS, KM> S;
   load_model(a.mdl, a.theta, S.m);
   if (a.queue) {
@@ -682,11 +703,17 @@ hipError_t launch_reset_counter(int* counter, hipStream_t s) {
 hipError_t launch_forward(const FwdArgs& a, int nq, int ns, bool coupled, const nmc_launch& L, int num_cu,
                           hipStream_t s) {
   if (nq == 32) {
-    if (coupled && L.kernel_store != NMC_KERNELS_REGISTERS) {
+    if (coupled && L.kernel_store == NMC_KERNELS_REGEN) {
       switch (ns) {
         case 1: return launch_fwd_t<1, 32, true, 1>(a, L, num_cu, s);
         case 2: return launch_fwd_t<2, 32, true, 1>(a, L, num_cu, s);
         case 3: return launch_fwd_t<3, 32, true, 1>(a, L, num_cu, s);
+      }
+    } else if (coupled && L.kernel_store != NMC_KERNELS_REGISTERS) {
+      switch (ns) {
+        case 1: return launch_fwd_t<1, 32, true, 2>(a, L, num_cu, s);
+        case 2: return launch_fwd_t<2, 32, true, 2>(a, L, num_cu, s);
+        case 3: return launch_fwd_t<3, 32, true, 2>(a, L, num_cu, s);
       }
     } else if (coupled) {
       switch (ns) {
