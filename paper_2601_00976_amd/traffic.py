@@ -24,7 +24,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 COPY_BYTES = 1 << 28  # 256 MiB calibration copy
 KERNELS = {
-    "fwd_kernel<3, 32, true>": ("fwd_kernel_nq32_ns3", "radial profile, 2^16 points, 32 nodes, step 1"),
+    "fwd_kernel<3, 32, true, 2>": ("fwd_kernel_nq32_ns3", "radial profile, 2^16 points, 32 nodes, step 1"),
     "adj_kernel<3>": ("adj_kernel_nq32_ns3", "radial profile, 2^16 points, 32 nodes, step 1"),
     "fwd64_kernel<3, true, false>": ("fwd64_kernel_nq64_ns3", "radial profile, 2^18 points, 64 nodes, step 1"),
     "fwd64_kernel<3, true, true>": ("fwd64_kernel_nq64_ns3_hbm",
