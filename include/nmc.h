@@ -206,7 +206,9 @@ size_t nmc_kernel_store_bytes(const nmc_model* m, int64_t P);
  * matter right-hand side evaluated at the final moments, so lepton number and
  * energy balance hold to rounding.  `ws` is device workspace of at least
  * nmc_workspace_bytes(m, P) bytes, 256-byte aligned, not shared with a
- * concurrently running call.  `launch` may be NULL (autotuned defaults). */
+ * concurrently running call.  `launch` may be NULL: persistent grid, one
+ * point per grab, kernels on chip (the Python layer passes the autotuned
+ * shape).  Returns NMC_E_UNSUPPORTED for grids other than 32 or 64 nodes. */
 int nmc_solve_batch(const nmc_model* m, const nmc_solver_params* prm, int64_t P, double dtau,
                     const nmc_batch_in* in, const nmc_batch_out* out, void* ws, size_t ws_bytes,
                     const nmc_launch* launch, void* stream);
@@ -217,7 +219,12 @@ int nmc_solve_batch(const nmc_model* m, const nmc_solver_params* prm, int64_t P,
  * dL/dtheta = sum_p -lambda_p^T dR_p/dtheta to grad_theta (nq + 2), where
  * R_x^T lambda_p = dL_p/dx at x = (D, Ye, e); grad_pp (P, nq + 2) receives the
  * per-point terms if not NULL.  Points with nonzero status or skipped points
- * contribute zero.  The summation over points is deterministic. */
+ * contribute zero.  The summation over points is deterministic.
+ * Reads in->rho11, in->theta, in->chi0 (may be NULL) and fwd->{D, ye, e,
+ * status, n_outer}; gbar is (P, 2) on the device.  `ws` as for the forward
+ * call (nmc_workspace_bytes(m, P), 256-byte aligned).  32-node grids only
+ * (NMC_E_UNSUPPORTED otherwise).  A singular Jacobian (a zero or non-finite
+ * pivot) makes that point's terms NaN. */
 int nmc_solve_batch_adjoint(const nmc_model* m, int64_t P, double dtau, const nmc_batch_in* in,
                             const nmc_batch_out* fwd, const double* gbar, double* grad_theta,
                             double* grad_pp, void* ws, size_t ws_bytes, void* stream);

@@ -1,24 +1,26 @@
-// Forward kernel of the implicit neutrino-matter coupling solve on CDNA4.
+// Forward kernel of the implicit neutrino-matter coupling solve on CDNA4,
+// 32 energy nodes.
 //
 // One 64-lane wavefront solves one spatial point at a time (Algorithm
 // neutrinoMatterCoupling, Sec. 3.5.3); spatial points are independent because
 // the nodal DG collocation decouples them (Sec. 3.1.2).
 //
-// Lane layout for 32 energy nodes: lane = 32 h + q.
-//   h = 0 ("number lanes"): own the number moments D_s[q] of every species and
-//          hold row q of Phi_in and Phi_ann in VGPRs;
-//   h = 1 ("flux lanes"):   own the flux moments I_s[q] and hold row q of
-//          Phi_out and Phi_pro.
-// The energy-coupling rates (Eqs. nesRatesNodal, pairRatesNodal) are two
-// stacked (64 x 32) x (32 x ns) products per inner iteration:
-//   [Phi_in ; Phi_out] rows x (W D | W (1 - D))  and  [Phi_ann ; Phi_pro] x (same).
-// The moment vectors W D (number lanes' rows) and W (1 - D) (flux lanes' rows)
-// are kept replicated per 16-lane DPP row and broadcast into the FMAs with
-// DPP row_newbcast, so the kernel rows never leave the register file and no
-// LDS traffic is spent on the contraction.  Half-wave partial rates are
-// combined with v_permlane32_swap; moment vectors are redistributed with
-// v_permlane16_swap.  Weighted norms and Anderson inner products are reduced
-// through LDS.
+// Lane layout: lane = 32 h + q.
+//   h = 0 ("number lanes"): own the number moments D_s[q] of every species;
+//   h = 1 ("flux lanes"):   own the flux moments I_s[q].
+// Both halves of row q cooperate on the energy-coupling rates of node q
+// (Eqs. nesRatesNodal, pairRatesNodal), in one of three modes (KM):
+//   KM = 2 (default) / 1: the two halves take columns 0..15 / 16..31 of the
+//     four kernel matrices, regenerate the entries from per-node exponent
+//     splits (KM = 2 keeps the lane's pair factors b in VGPRs across the inner
+//     loop) and contract them against W D and W (1 - D) broadcast from LDS;
+//     the half sums combine with v_permlane32_swap.
+//   KM = 0: number lanes hold rows q of Phi_in and Phi_ann, flux lanes rows q
+//     of Phi_out and Phi_pro in VGPRs (assembled once per outer iteration in
+//     an LDS tile); the moment vectors are replicated per 16-lane DPP row with
+//     v_permlane16_swap and broadcast into v_fmac_f64_dpp row_newbcast FMAs.
+// Anderson inner products and weighted norms are register reductions; the
+// Anderson history and the per-point uniform state live in LDS.
 #include "nmc_wave.h"
 
 namespace nmc {
