@@ -101,13 +101,21 @@ def tune(model, params, dtau, D0, I0, rho11, ye0, e0, theta, repeats: int = 5, w
     return results
 
 
+def _code_only(text: str) -> str:
+    """C/C++ source without comments and with whitespace collapsed."""
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return " ".join(text.split())
+
+
 def kernel_source_hash() -> str:
-    """Hash of the HIP sources, used to tell whether stored counter
-    measurements still describe the current kernels."""
+    """Hash of the HIP sources (code only: comments and layout do not count),
+    used to tell whether stored counter measurements still describe the
+    current kernels."""
     h = hashlib.sha256()
     for p in sorted(glob.glob(os.path.join(HERE, "csrc", "*"))):
-        with open(p, "rb") as f:
-            h.update(f.read())
+        with open(p, encoding="utf-8") as f:
+            h.update(_code_only(f.read()).encode())
     return h.hexdigest()[:16]
 
 

@@ -114,7 +114,8 @@ def summarize(fetch_db, write_db):
         path = os.path.join(ROOT, "profiles", f"traffic_{tag}.txt")
         with open(path, "w") as o:
             o.write(f"# HBM traffic of {key} ({what})\n")
-            o.write("# commands (GPU box, from the repository root):\n")
+            o.write("# commands (GPU box, from the repository root; source_hash = code-only hash of csrc/, "
+                    "see autotune.kernel_source_hash):\n")
             o.write("#   cd /tmp && export TMPDIR=/tmp\n")
             o.write("#   rocprofv3 --pmc FETCH_SIZE -d <dir>/fetch -o run -- python3 <repo>/paper_2601_00976_amd/traffic.py run\n")
             o.write("#   rocprofv3 --pmc WRITE_SIZE -d <dir>/write -o run -- python3 <repo>/paper_2601_00976_amd/traffic.py run\n")
