@@ -13,8 +13,9 @@
 //   KM = 2 (default) / 1: the two halves take columns 0..15 / 16..31 of the
 //     four kernel matrices, regenerate the entries from per-node exponent
 //     splits (KM = 2 keeps the lane's pair factors b in VGPRs across the inner
-//     loop) and contract them against W D and W (1 - D) broadcast from LDS;
-//     the half sums combine with v_permlane32_swap.
+//     loop) without their common factor A e_q e_j, contract them against
+//     W e D and W e (1 - D) broadcast from LDS and scale the row sums by
+//     A e_q; the half sums combine with v_permlane32_swap.
 //   KM = 0: number lanes hold rows q of Phi_in and Phi_ann, flux lanes rows q
 //     of Phi_out and Phi_pro in VGPRs (assembled once per outer iteration in
 //     an LDS tile); the moment vectors are replicated per 16-lane DPP row with
@@ -44,8 +45,8 @@ struct WaveLds {
     double tile[KM == 0 ? 32 * kTileStride : 1];      // kernel-row assembly (KM = 0), live while building
   } u;
   SplitExp E;                  // per-node factors of the current temperature
-  double X[KM >= 1 ? NS : 1][32];  // W D of the current iterate (KM >= 1)
-  double Y[KM >= 1 ? NS : 1][32];  // W (1 - D) of the current iterate (KM >= 1)
+  double X[KM >= 1 ? NS : 1][32];  // W e D of the current iterate (KM >= 1)
+  double Y[KM >= 1 ? NS : 1][32];  // W e (1 - D) of the current iterate (KM >= 1)
   // uniform per-point state
   double dref[NS];                      // ||D_s^[k,1]||_W^2 of the current inner loop
   double y[2];                          // matter iterate (Ye, e)
@@ -70,8 +71,7 @@ struct PointSolver {
                                                      const double (&Bq)[KM == 2 ? 16 : 1], double (&eta)[NS],
                                                      double (&chi)[NS]) {
     const SplitExp& E = S.E;
-    const double Pq = E.P2[q], Rq = E.R2[q], Gq = E.G[q], eq = S.m.eps[q];
-    const int nq = E.n2[q];
+    const double Gq = E.G[q], eq = S.m.eps[q];
     const double Aeq = S.An * eq, Apq = S.Ap * eq;
     double etaN[NS], outN[NS], annP[NS], etaP[NS];
 #pragma unroll
@@ -79,21 +79,21 @@ struct PointSolver {
 #pragma unroll(KM == 2 ? 16 : 4)
     for (int jj = 0; jj < 16; ++jj) {
       const int j = j0 + jj;
-      const double Gj = E.G[j], ej = S.m.eps[j];
+      const double Gj = E.G[j];
       const bool up = j > q;  // q is the lower node of the pair
       double b;
       if constexpr (KM == 2) {
         b = Bq[jj];
       } else {
-        const double Pj = E.P2[j], Rj = E.R2[j];
-        const int nj = E.n2[j];
+        const double Pq = E.P2[q], Rq = E.R2[q], Pj = E.P2[j], Rj = E.R2[j];
+        const int nq = E.n2[q], nj = E.n2[j];
         b = ldexp(up ? Pq * Rj : Pj * Rq, up ? nq - nj : nj - nq);
       }
-      const double b2 = b * b;
-      const double en = Aeq * ej, ep = Apq * ej;
-      const double u = en * b, v = en * (b2 * b);
-      const double fin = up ? u : v, fout = up ? v : u;
-      const double fann = ep * b2, fpro = ep * (up ? Gj : Gq);
+      // kernel entries without the factor A e_q e_j: e_j rides on the
+      // broadcast vectors X, Y and A e_q is applied to the row sums
+      const double b2 = b * b, b3 = b2 * b;
+      const double fin = up ? b : b3, fout = up ? b3 : b;
+      const double fann = b2, fpro = up ? Gj : Gq;
       double x[NS], y[NS];
 #pragma unroll
       for (int t = 0; t < NS; ++t) {
@@ -111,10 +111,11 @@ struct PointSolver {
     }
 #pragma unroll
     for (int t = 0; t < NS; ++t) {
-      eta[t] = etaN[t] + etaP[t];
-      chi[t] = (etaN[t] + outN[t]) + (etaP[t] + annP[t]);
+      eta[t] = __builtin_fma(Aeq, etaN[t], Apq * etaP[t]);
+      chi[t] = __builtin_fma(Aeq, etaN[t] + outN[t], Apq * (etaP[t] + annP[t]));
     }
   }
+
 
   // Energy-coupling contraction: a1[t] = sum_j M1[j] X_t[j], a2[t] = sum_j M2[j] X_t[j]
   // where X_t = W D_t on number lanes and W (1 - D_t) on flux lanes.  Column
@@ -340,7 +341,7 @@ struct PointSolver {
       }
 
       // ---- inner loop over moments at fixed matter (M^[k,1] = M^[k-1,*]) --
-      const double w2q = mt.w2[q];
+      const double w2q = mt.w2[q], w2eq = w2q * mt.eps[q];
       const double xa = h ? -w2q : w2q, xb = h ? w2q : 0.0;  // X = xa D + xb
       const double dth = h ? 0.0 : dtau;
       double G11 = 0.0;
@@ -353,8 +354,8 @@ struct PointSolver {
           if (h == 0) {
 #pragma unroll
             for (int t = 0; t < NS; ++t) {
-              S.X[t][q] = w2q * Dcur[t];
-              S.Y[t][q] = __builtin_fma(-w2q, Dcur[t], w2q);
+              S.X[t][q] = w2eq * Dcur[t];
+              S.Y[t][q] = __builtin_fma(-w2eq, Dcur[t], w2eq);
             }
           }
           __syncthreads();

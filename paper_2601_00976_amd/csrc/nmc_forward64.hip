@@ -15,16 +15,19 @@
 //   Phi_in[q][j] = A e_q e_j (j > q ? b : b^3),  Phi_out[q][j] = A e_q e_j (j > q ? b^3 : b),
 //   Phi_ann[q][j] = A' e_q e_j b^2,              Phi_pro[q][j] = A' e_q e_j G_hi,
 // with x = e log2(e) / (2T) = n + f, P = 2^f, R = 2^-f, G = exp(-2 e / T).
-// Anderson sums, norms and matter integrals are full-wave register
-// reductions.
+// The lanes form the entries without their common factor A e_q e_j (A' e_q
+// e_j for pair), contract them against W e D and W e (1 - D) and scale the
+// row sums by A e_q (A' e_q).  Anderson sums, norms and matter integrals are
+// full-wave register reductions.
 //
 // The PRE variant (kernel_store = HBM; the roofline study of precomputed
-// kernels) writes Phi_in, Phi_out and Phi_ann of the point to the workspace
-// once per outer iteration, laid out [matrix][column j][row q] so that every
-// access is a coalesced 512-byte wave load or store, and reads them back in
-// every inner iteration (Phi_pro = A' e_q e_j G_hi stays a product of two
-// stored per-node factors).  Each lane reads only what it wrote, so no
-// barrier is needed between the two.
+// kernels) writes the scaled Phi_in, Phi_out and Phi_ann of the point to the
+// workspace once per outer iteration, laid out [matrix][column j][row q] so
+// that every access is a coalesced 512-byte wave load or store, and reads
+// them back in every inner iteration (the scaled Phi_pro is G_hi, a stored
+// per-node factor).  Each lane reads only what it wrote, so no barrier is
+// needed between the two.  Both variants perform the same floating-point
+// operations on the same values, so their results agree bit for bit.
 #include "nmc_wave.h"
 
 namespace nmc {
@@ -37,9 +40,9 @@ struct Lds64 {
   ModelLdsN<NQ64> m;
   double hist[4][2 * NS][kLanes];  // Anderson history per owned moment: Q_prev, F_prev, dQ_old, dF_old
   double colPR[kLanes][2];         // per node: P, R of the exponent split at the current T
-  double colGE[kLanes][2];         // per node: G = exp(-2 e / T), e
+  double colGE[kLanes][2];         // per node: G = exp(-2 e / T), W e
   int coln[kLanes];                // per node: integer part n of the split
-  double X[NS][kLanes];            // W D of the current iterate
+  double X[NS][kLanes];            // W e D of the current iterate
   // uniform per-point state
   double dref[NS];
   double y[2], oq[2], of[2], odq[2], odf[2];
@@ -65,8 +68,9 @@ template <int NS, bool COUPLED, bool PRE>
 struct PointSolver64 {
   static constexpr int NQ = NQ64;
 
-  // entries of row q, column j of the four kernels (up to the pair factor
-  // Phi_pro, which is returned too)
+  // entries of row q, column j of the four kernels without their common
+  // factor A e_q e_j (A' e_q e_j for pair): e_j rides on the contracted
+  // vectors and A e_q scales the row sums
   struct Row {
     double Pq, Rq, Gq, Aeq, Apq;
     int nq;
@@ -76,7 +80,7 @@ struct PointSolver64 {
     r.Pq = S.colPR[q][0];
     r.Rq = S.colPR[q][1];
     r.Gq = S.colGE[q][0];
-    const double eq = S.colGE[q][1];
+    const double eq = S.m.eps[q];
     r.nq = S.coln[q];
     r.Aeq = S.An * eq;
     r.Apq = S.Ap * eq;
@@ -84,22 +88,20 @@ struct PointSolver64 {
   }
   __device__ __forceinline__ static void entries(const Lds64<NS>& S, const Row& r, int q, int j, double& fin,
                                                  double& fout, double& fann, double& fpro) {
-    const double Pj = S.colPR[j][0], Rj = S.colPR[j][1], Gj = S.colGE[j][0], ej = S.colGE[j][1];
+    const double Pj = S.colPR[j][0], Rj = S.colPR[j][1], Gj = S.colGE[j][0];
     const int nj = S.coln[j];
     const bool up = j > q;  // q is the lower node of the pair
     const double b = ldexp(up ? r.Pq * Rj : Pj * r.Rq, up ? r.nq - nj : nj - r.nq);
-    const double b2 = b * b;
-    const double en = r.Aeq * ej, ep = r.Apq * ej;
-    const double u = en * b, v = en * (b2 * b);
-    fin = up ? u : v;
-    fout = up ? v : u;
-    fann = ep * b2;
-    fpro = ep * (up ? Gj : r.Gq);
+    const double b2 = b * b, b3 = b2 * b;
+    fin = up ? b : b3;
+    fout = up ? b3 : b;
+    fann = b2;
+    fpro = up ? Gj : r.Gq;
   }
   __device__ __forceinline__ static void accumulate(const Lds64<NS>& S, int j, double fin, double fout, double fann,
                                                     double fpro, double (&etaN)[NS], double (&outN)[NS],
                                                     double (&annP)[NS], double (&etaP)[NS]) {
-    const double wj = S.m.w2[j];
+    const double wj = S.colGE[j][1];
     double x[NS], y[NS];
 #pragma unroll
     for (int t = 0; t < NS; ++t) {
@@ -118,7 +120,7 @@ struct PointSolver64 {
 
   // rates of the energy-coupling kernels for every species at the current
   // iterate: etaN = Phi_in W D_s, outN = Phi_out W (1 - D_s),
-  // annP = Phi_ann W D_sbar, etaP = Phi_pro W (1 - D_sbar)
+  // annP = Phi_ann W D_sbar, etaP = Phi_pro W (1 - D_sbar); X holds W e D
   __device__ __forceinline__ static void rates(const Lds64<NS>& S, int q, const double* __restrict__ kst,
                                                double (&etaN)[NS], double (&outN)[NS], double (&annP)[NS],
                                                double (&etaP)[NS]) {
@@ -132,11 +134,18 @@ struct PointSolver64 {
         fin = kst[j * NQ + q];
         fout = kst[(NQ + j) * NQ + q];
         fann = kst[(2 * NQ + j) * NQ + q];
-        fpro = r.Apq * S.colGE[j][1] * (j > q ? S.colGE[j][0] : r.Gq);
+        fpro = j > q ? S.colGE[j][0] : r.Gq;
       } else {
         entries(S, r, q, j, fin, fout, fann, fpro);
       }
       accumulate(S, j, fin, fout, fann, fpro, etaN, outN, annP, etaP);
+    }
+#pragma unroll
+    for (int t = 0; t < NS; ++t) {
+      etaN[t] *= r.Aeq;
+      outN[t] *= r.Aeq;
+      annP[t] *= r.Apq;
+      etaP[t] *= r.Apq;
     }
   }
 
@@ -264,7 +273,7 @@ struct PointSolver64 {
         S.colPR[q][0] = P;
         S.colPR[q][1] = rcp_ge1(P);
         S.colGE[q][0] = exp(-2.0 * epsq * invT);
-        S.colGE[q][1] = epsq;
+        S.colGE[q][1] = mt.w2[q] * epsq;
         S.coln[q] = (int)n;
         if constexpr (PRE) {
           __syncthreads();
@@ -273,7 +282,7 @@ struct PointSolver64 {
       }
 
       // ---- inner loop over moments at fixed matter ------------------------
-      const double w2q = mt.w2[q];
+      const double w2q = mt.w2[q], w2eq = w2q * mt.eps[q];
       double G11 = 0.0;
       bool conv = false;
       int l;
@@ -281,7 +290,7 @@ struct PointSolver64 {
         double etaN[NS], outN[NS], annP[NS], etaP[NS];
         if constexpr (COUPLED) {
 #pragma unroll
-          for (int t = 0; t < NS; ++t) S.X[t][q] = w2q * D[t];
+          for (int t = 0; t < NS; ++t) S.X[t][q] = w2eq * D[t];
           __syncthreads();
           rates(S, q, kst, etaN, outN, annP, etaP);
           __syncthreads();
