@@ -45,8 +45,8 @@ struct WaveLds {
     double tile[KM == 0 ? 32 * kTileStride : 1];      // kernel-row assembly (KM = 0), live while building
   } u;
   SplitExp E;                  // per-node factors of the current temperature
-  double X[KM >= 1 ? NS : 1][32];  // W e D of the current iterate (KM >= 1)
-  double Y[KM >= 1 ? NS : 1][32];  // W e (1 - D) of the current iterate (KM >= 1)
+  alignas(16) double X[KM >= 1 ? NS : 1][32];  // W e D of the current iterate (KM >= 1)
+  alignas(16) double Y[KM >= 1 ? NS : 1][32];  // W e (1 - D) of the current iterate (KM >= 1)
   // uniform per-point state
   double dref[NS];                      // ||D_s^[k,1]||_W^2 of the current inner loop
   double y[2];                          // matter iterate (Ye, e)
@@ -76,37 +76,50 @@ struct PointSolver {
     double etaN[NS], outN[NS], annP[NS], etaP[NS];
 #pragma unroll
     for (int t = 0; t < NS; ++t) etaN[t] = outN[t] = annP[t] = etaP[t] = 0.0;
-#pragma unroll(KM == 2 ? 16 : 4)
-    for (int jj = 0; jj < 16; ++jj) {
-      const int j = j0 + jj;
-      const double Gj = E.G[j];
-      const bool up = j > q;  // q is the lower node of the pair
-      double b;
-      if constexpr (KM == 2) {
-        b = Bq[jj];
-      } else {
-        const double Pq = E.P2[q], Rq = E.R2[q], Pj = E.P2[j], Rj = E.R2[j];
-        const int nq = E.n2[q], nj = E.n2[j];
-        b = ldexp(up ? Pq * Rj : Pj * Rq, up ? nq - nj : nj - nq);
-      }
-      // kernel entries without the factor A e_q e_j: e_j rides on the
-      // broadcast vectors X, Y and A e_q is applied to the row sums
-      const double b2 = b * b, b3 = b2 * b;
-      const double fin = up ? b : b3, fout = up ? b3 : b;
-      const double fann = b2, fpro = up ? Gj : Gq;
-      double x[NS], y[NS];
+    // columns are read in 16-byte pairs (one ds_read_b128 per array and
+    // pair, addressed from a single per-half base)
+    const double2* __restrict__ G2 = reinterpret_cast<const double2*>(&E.G[j0]);
+#pragma unroll(KM == 2 ? 8 : 2)
+    for (int jp = 0; jp < 8; ++jp) {
+      const double2 g2 = G2[jp];
+      double2 x2[NS], y2[NS];
 #pragma unroll
       for (int t = 0; t < NS; ++t) {
-        x[t] = S.X[t][j];
-        y[t] = S.Y[t][j];
+        x2[t] = reinterpret_cast<const double2*>(&S.X[t][j0])[jp];
+        y2[t] = reinterpret_cast<const double2*>(&S.Y[t][j0])[jp];
       }
 #pragma unroll
-      for (int t = 0; t < NS; ++t) {
-        const int tb = pair_partner<NS>(t);
-        etaN[t] = __builtin_fma(fin, x[t], etaN[t]);
-        outN[t] = __builtin_fma(fout, y[t], outN[t]);
-        annP[t] = __builtin_fma(fann, x[tb], annP[t]);
-        etaP[t] = __builtin_fma(fpro, y[tb], etaP[t]);
+      for (int e = 0; e < 2; ++e) {
+        const int jj = 2 * jp + e, j = j0 + jj;
+        const double Gj = e ? g2.y : g2.x;
+        const bool up = j > q;  // q is the lower node of the pair
+        double b;
+        if constexpr (KM == 2) {
+          b = Bq[jj];
+        } else {
+          const double Pq = E.P2[q], Rq = E.R2[q], Pj = E.P2[j], Rj = E.R2[j];
+          const int nq = E.n2[q], nj = E.n2[j];
+          b = ldexp(up ? Pq * Rj : Pj * Rq, up ? nq - nj : nj - nq);
+        }
+        // kernel entries without the factor A e_q e_j: e_j rides on the
+        // broadcast vectors X, Y and A e_q is applied to the row sums
+        const double b2 = b * b, b3 = b2 * b;
+        const double fin = up ? b : b3, fout = up ? b3 : b;
+        const double fann = b2, fpro = up ? Gj : Gq;
+        double x[NS], y[NS];
+#pragma unroll
+        for (int t = 0; t < NS; ++t) {
+          x[t] = e ? x2[t].y : x2[t].x;
+          y[t] = e ? y2[t].y : y2[t].x;
+        }
+#pragma unroll
+        for (int t = 0; t < NS; ++t) {
+          const int tb = pair_partner<NS>(t);
+          etaN[t] = __builtin_fma(fin, x[t], etaN[t]);
+          outN[t] = __builtin_fma(fout, y[t], outN[t]);
+          annP[t] = __builtin_fma(fann, x[tb], annP[t]);
+          etaP[t] = __builtin_fma(fpro, y[tb], etaP[t]);
+        }
       }
     }
 #pragma unroll

@@ -365,7 +365,7 @@ __device__ __forceinline__ double ye43(double ye) { return ye * cbrt(ye); }
 // factor stays <= 1 and nothing overflows at low temperature.
 constexpr int kTileStride = 33;  // padded row stride of a 32 x 32 LDS tile
 
-struct SplitExp {
+struct alignas(16) SplitExp {
   double P2[32], R2[32], G[32];
   int n2[32];
 };
