@@ -18,11 +18,11 @@
 // in id order the blocks are (nu_e, anti-nu_e) of size 64 and nu_x of size
 // 32.  Each block is factorised in registers, one wavefront per point: lane r
 // holds row r of A^T (column r of A) and the two right-hand sides.  Gaussian
-// elimination picks the pivot row by a wave-wide argmax over the lanes not yet
-// eliminated (partial pivoting without moving rows), broadcasts it through
-// scalar registers (v_readlane), and every other lane updates its row; back
-// substitution runs over the recorded pivot order.  Per-point terms go to a (P, nq + 2) array and are
-// summed over points by a fixed-order two-stage reduction.
+// elimination runs without row exchanges (the W-scaled columns of A are
+// strictly diagonally dominant), broadcasting the pivot row of each step
+// through LDS; back substitution follows.  Per-point terms go to a
+// (P, nq + 2) array and are summed over points by a fixed-order two-stage
+// reduction.
 #include "nmc_wave.h"
 
 namespace nmc {
@@ -34,27 +34,15 @@ template <int NS>
 struct AdjLds {
   ModelLds m;
   SplitExp E;
-  double tin[32 * kTileStride], tann[32 * kTileStride], tpro[32 * kTileStride];  // unit-amplitude kernels
+  double tb[32 * kTileStride];  // pair factors b = exp(-|e_q - e_p| / (2T)) of the kernels
   double D[NS][NQ];
   // per-row results, row = (species, node)
   double chi[NS][NQ];         // total opacity chi of the row
   double b0[NS][NQ], b1[NS][NQ];  // dR_D / dYe, dR_D / de
   double da[NS][NQ], dp[NS][NQ], ds[NS][NQ];  // dR_D / d a_nes, / d a_pair, / d s_q
   double z0[NS][NQ], z1[NS][NQ];  // Z = A^-T C^T
+  alignas(16) double prow[2 * NQ + 2];  // pivot-row broadcast of the block factorisation
 };
-
-// maximum over the wave, in every lane
-__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
-  auto m = [](uint32_t a, uint32_t b) { return a > b ? a : b; };
-  v = m(v, (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xF, 0xF, false));   // quad_perm [1,0,3,2]
-  v = m(v, (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x4E, 0xF, 0xF, false));   // quad_perm [2,3,0,1]
-  v = m(v, (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x141, 0xF, 0xF, false));  // row_half_mirror
-  v = m(v, (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x140, 0xF, 0xF, false));  // row_mirror
-  auto a = __builtin_amdgcn_permlane16_swap(v, v, false, false);
-  v = m(a[0], a[1]);
-  auto b = __builtin_amdgcn_permlane32_swap(v, v, false, false);
-  return m(b[0], b[1]);
-}
 
 // reciprocal: hardware estimate refined by two Newton steps (x finite, nonzero)
 __device__ __forceinline__ double rcp_nr(double x) {
@@ -74,66 +62,88 @@ __device__ __forceinline__ double readlane_f64(double v, int lane) {
 // Solves A^T z = c for one diagonal block of size N (lanes 0..N-1 active):
 // lane r enters with R = row r of A^T and c = (c0, c1) its right-hand sides
 // and leaves with (z0, z1) = entry r of the two solutions.  Returns false if
-// a pivot was zero or non-finite (the results are then not finite either).
-// The pivot row is broadcast with v_readlane into scalar registers, which the
-// update FMAs of the other lanes read directly (no LDS round trip).
+// a pivot was zero or non-finite, detected as a non-finite solution entry
+// (such a pivot turns the multipliers or a quotient of the back
+// substitution into inf or NaN, which propagate into z).
+//
+// Gaussian elimination without row exchanges: with D in [0, 1] and
+// non-negative kernels, diag(W) A is strictly diagonally dominant by
+// columns (the off-diagonal column sums of the W-scaled NES and pair terms
+// equal the kernel part of the diagonal opacity, leaving a margin
+// W_p (1 + dtau chi^EmAb_p)), and elimination without pivoting is stable for
+// such matrices.  Step k broadcasts row k of A^T (held by lane k) through
+// the LDS row buffer prow: lane k writes its entries k+1..N-1 and its two
+// right-hand sides, every lane reads them back as 16-byte broadcasts.  A
+// single wavefront runs the work-group, so its LDS accesses complete in
+// program order and no barrier is needed.
+// ds_write2_b64 of (a, b) to LDS bytes base + 8 J and base + 8 (J + 1)
+template <int J>
+__device__ __forceinline__ void lds_write2_f64(uint32_t base, double a, double b) {
+  static_assert(J + 1 <= 255, "ds_write2_b64 offsets are 8-bit");
+  asm volatile("ds_write2_b64 %0, %1, %2 offset0:%3 offset1:%4" : : "v"(base), "v"(a), "v"(b), "i"(J), "i"(J + 1)
+               : "memory");
+}
+
 template <int N>
 __device__ __forceinline__ bool solve_block_transposed(double (&R)[N], double c0, double c1, double& z0,
-                                                       double& z1) {
+                                                       double& z1, double* prow_generic) {
+  typedef double f64x2 __attribute__((ext_vector_type(2)));
+  typedef __attribute__((address_space(3))) double lds_f64;
+  typedef __attribute__((address_space(3))) f64x2 lds_f64x2;
   const int lane = opaque((int)threadIdx.x);
-  const bool active = lane < N;
-  bool done = !active;
-  int mystep = -1;
-  bool ok = true;
   static_for<0, N>([&](auto kk) __attribute__((always_inline)) {
     constexpr int k = decltype(kk)::value;
-    // pivot: largest |R[k]| over the lanes not yet eliminated, compared on
-    // the high word of the absolute value (sign, exponent and 20 mantissa
-    // bits), i.e. threshold pivoting within a factor 1 + 2^-20 of the
-    // maximum; ties go to the lowest lane
-    const uint32_t key = done ? 0u : (hi32(R[k]) & 0x7fffffffu) + 1u;
-    const uint32_t mx = wave_max_u32(key);
-    uint64_t bal = __builtin_amdgcn_ballot_w64(!done && key == mx);
-    if (bal == 0) {
-      ok = false;
-      bal = __builtin_amdgcn_ballot_w64(!done);
+    lds_f64* prow = (lds_f64*)prow_generic;
+    lds_f64x2* prow2 = (lds_f64x2*)prow;
+    const double piv = readlane_f64(R[k], k);
+    // entries k+1..N-1 and the right-hand sides at N, N+1; 16-byte pairs
+    // start at the first even index
+    constexpr int j2 = (k + 2) & ~1;
+    if (lane == k) {
+      // ds_write2_b64 from one base register with 8-byte-unit offsets (the
+      // writes and the reads below are LDS operations of one wavefront and
+      // complete in program order)
+      const uint32_t base = (uint32_t)(uintptr_t)prow;
+      if constexpr ((k & 1) == 0) prow[k + 1] = R[k + 1];
+      static_for<0, (N - j2) / 2>([&](auto ii) __attribute__((always_inline)) {
+        constexpr int j = j2 + 2 * decltype(ii)::value;
+        lds_write2_f64<j>(base, R[j], R[j + 1]);
+      });
+      prow[N] = c0;
+      prow[N + 1] = c1;
     }
-    const int pl = (int)__builtin_ctzll(bal);
-    const double piv = readlane_f64(R[k], pl);
-    ok = ok && piv != 0.0 && isfinite(piv);
-    if (lane == pl) {
-      mystep = k;
-      done = true;
-    }
-    if (!done) {
+    if (lane > k) {
       const double l = R[k] * rcp_nr(piv);
+      if constexpr ((k & 1) == 0) R[k + 1] = __builtin_fma(-l, prow[k + 1], R[k + 1]);
 #pragma unroll
-      for (int j = k + 1; j < N; ++j) {
-        R[j] = __builtin_fma(-l, readlane_f64(R[j], pl), R[j]);
-        // bound the scalar registers in flight: no scheduling across this point
-        if ((j & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+      for (int j = j2; j < N; j += 2) {
+        const f64x2 v = prow2[j / 2];
+        R[j] = __builtin_fma(-l, v.x, R[j]);
+        R[j + 1] = __builtin_fma(-l, v.y, R[j + 1]);
       }
-      c0 = __builtin_fma(-l, readlane_f64(c0, pl), c0);
-      c1 = __builtin_fma(-l, readlane_f64(c1, pl), c1);
+      const f64x2 cv = prow2[N / 2];
+      c0 = __builtin_fma(-l, cv.x, c0);
+      c1 = __builtin_fma(-l, cv.y, c1);
     }
   });
+  // back substitution, column by column: z_k from lane k, then every row
+  // above it removes its term
   z0 = z1 = 0.0;
   static_for<0, N>([&](auto kk) __attribute__((always_inline)) {
     constexpr int k = N - 1 - decltype(kk)::value;
-    const uint64_t bal = __builtin_amdgcn_ballot_w64(mystep == k);
-    const int pl = bal ? (int)__builtin_ctzll(bal) : 0;
-    const double r = rcp_nr(R[k]);
-    const double zk0 = readlane_f64(c0 * r, pl), zk1 = readlane_f64(c1 * r, pl);
+    const double r = rcp_nr(readlane_f64(R[k], k));
+    const double zk0 = readlane_f64(c0, k) * r, zk1 = readlane_f64(c1, k) * r;
     if (lane == k) {
       z0 = zk0;
       z1 = zk1;
     }
-    if (mystep >= 0 && mystep < k) {
+    if (lane < k) {
       c0 = __builtin_fma(-R[k], zk0, c0);
       c1 = __builtin_fma(-R[k], zk1, c1);
     }
   });
-  return ok;
+  // a zero or non-finite pivot makes some entry of the solution non-finite
+  return __builtin_amdgcn_ballot_w64(lane < N && !(isfinite(z0) && isfinite(z1))) == 0;
 }
 
 template <int NS>
@@ -144,30 +154,47 @@ struct PointAdjoint {
   //   partner species:     +dtau W_p [D_q Phi_ann[q][p] + (1 - D_q) Phi_pro[q][p]]
   //   diagonal:            1 + dtau chi_(s, p)
   // with the kernels at the point's amplitudes; Phi_out[q][p] = Phi_in[p][q].
+  // The kernels are formed from the pair factors b: with c = rho e_q e_p,
+  // Phi_in[q][p] = c (p > q ? b : b^3), Phi_out[q][p] = c (q > p ? b : b^3),
+  // Phi_ann = c b^2, Phi_pro = c G_max(q, p).
   template <int S0, int NB>
-  __device__ __forceinline__ static void block_rows(AdjLds<NS>& S, double dtau, double a_nes, double a_pair,
-                                                    double (&R)[32 * NB]) {
+  __device__ __forceinline__ static void block_rows(AdjLds<NS>& S, double dtau, double rho, double a_nes,
+                                                    double a_pair, double (&R)[32 * NB]) {
     constexpr int ST = kTileStride;
     const int lane = opaque((int)threadIdx.x);  // laundered: lane-derived indices are not hoisted out of the point loop
     const int h = lane >> 5, p = lane & 31;
     const int si = NB == 2 ? h : 0;
     const int sp = S0 + si;  // species of this lane's column
-    const double dwn = dtau * a_nes * S.m.w2[p], dwp = dtau * a_pair * S.m.w2[p];
+    const double rwe = rho * S.m.w2[p] * S.m.eps[p];
+    const double dwn = dtau * a_nes * rwe, dwp = dtau * a_pair * rwe;
     const double diag = 1.0 + dtau * S.chi[sp][p];
+    const double Gp = S.E.G[p];
+    // the moments are re-read here (an opaque zero offset keeps the compiler
+    // from carrying the values loaded for the contractions through the
+    // factorisation of the previous block in registers)
+    int z = 0;
+    asm volatile("" : "+s"(z));
+    const double* __restrict__ Db = &S.D[S0][z];
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
-      const double tin = S.tin[q * ST + p], tout = S.tin[p * ST + q];
-      const double tann = S.tann[q * ST + p], tpro = S.tpro[q * ST + p];
+      const double eq = S.m.eps[q], Gq = S.E.G[q];
+      const double b = S.tb[q * ST + p], b2 = b * b, b3 = b2 * b;
+      const double fin = p > q ? b : b3, fout = q > p ? b : b3;
+      const double fpro = q > p ? Gq : Gp;
+      const double nq = -dwn * eq, pq = dwp * eq;
       // row (s, q), column (sp, p): NES if s = sp, pair if s is sp's partner
-      auto nes = [&](double d) { return -dwn * __builtin_fma(d, tout - tin, tin); };
-      auto pair = [&](double d) { return dwp * __builtin_fma(d, tann - tpro, tpro); };
+      auto nes = [&](double d) { return nq * __builtin_fma(d, fout - fin, fin); };
+      auto pair = [&](double d) { return pq * __builtin_fma(d, b2 - fpro, fpro); };
       const double dg = q == p ? diag : 0.0;
       if constexpr (NB == 2) {
-        const double d0 = S.D[S0][q], d1 = S.D[S0 + 1][q];
-        R[q] = si == 0 ? nes(d0) + dg : pair(d0);
-        R[32 + q] = si == 1 ? nes(d1) + dg : pair(d1);
+        // d is the moment of the row's species: the lane's own species for
+        // its NES row, the partner's for its pair row
+        const double d0 = Db[q], d1 = Db[NQ + q];
+        const double vn = nes(si == 0 ? d0 : d1) + dg, vp = pair(si == 0 ? d1 : d0);
+        R[q] = si == 0 ? vn : vp;
+        R[32 + q] = si == 0 ? vp : vn;
       } else {
-        const double d = S.D[S0][q];
+        const double d = Db[q];
         R[q] = nes(d) + pair(d) + dg;
       }
       if ((q & 3) == 3) asm volatile("" ::: "memory");
@@ -175,10 +202,10 @@ struct PointAdjoint {
   }
 
   template <int S0, int NB>
-  __device__ __forceinline__ static bool block_solve(AdjLds<NS>& S, const DevModel* md, double dtau, double a_nes,
-                                                     double a_pair, double K) {
+  __device__ __forceinline__ static bool block_solve(AdjLds<NS>& S, const DevModel* md, double dtau, double rho,
+                                                     double a_nes, double a_pair, double K) {
     double R[32 * NB];
-    block_rows<S0, NB>(S, dtau, a_nes, a_pair, R);
+    block_rows<S0, NB>(S, dtau, rho, a_nes, a_pair, R);
     const int lane = opaque((int)threadIdx.x);  // laundered: lane-derived indices are not hoisted out of the point loop
     const int h = lane >> 5, p = lane & 31;
     const int sp = S0 + (NB == 2 ? h : 0);
@@ -186,7 +213,7 @@ struct PointAdjoint {
     const double c0 = K * md->ig[sp] * S.m.w2[p];
     const double c1 = K * md->imult[sp] * S.m.w3[p];
     double z0, z1;
-    const bool ok = solve_block_transposed<32 * NB>(R, c0, c1, z0, z1);
+    const bool ok = solve_block_transposed<32 * NB>(R, c0, c1, z0, z1, S.prow);
     if (lane < 32 * NB) {
       S.z0[sp][p] = z0;
       S.z1[sp][p] = z1;
@@ -250,15 +277,17 @@ struct PointAdjoint {
     double en[NG], onn[NG], an[NG], ep[NG], dn[NG], dout[NG], dan[NG], dpr[NG];
 #pragma unroll
     for (int g = 0; g < NG; ++g) en[g] = onn[g] = an[g] = ep[g] = dn[g] = dout[g] = dan[g] = dpr[g] = 0.0;
-    fill_tile<kTilePhiIn>(S.m, S.E, rho, h, q, S.tin);
-    fill_tile<kTilePhiAnn>(S.m, S.E, rho, h, q, S.tann);
-    fill_tile<kTilePhiPro>(S.m, S.E, rho, h, q, S.tpro);
+    fill_tile<kTilePairFactor>(S.m, S.E, 1.0, h, q, S.tb);
     __syncthreads();
+    // the kernels without their common factor rho e_q (applied to the sums)
+    const double Gq = S.E.G[q];
 #pragma unroll 2
     for (int p = 0; p < NQ; ++p) {
-      const double w = S.m.w2[p], epp = S.m.eps[p], dl = eq - epp, adl = fabs(dl);
-      const double tin = w * S.tin[q * ST + p], tout = w * S.tin[p * ST + q];
-      const double tann = w * S.tann[q * ST + p], tpro = w * S.tpro[q * ST + p];
+      const double epp = S.m.eps[p], we = S.m.w2[p] * epp, dl = eq - epp, adl = fabs(dl);
+      const double b = S.tb[q * ST + p], b2 = b * b, b3 = b2 * b;
+      const bool up = p > q;
+      const double tin = we * (up ? b : b3), tout = we * (up ? b3 : b);
+      const double tann = we * b2, tpro = we * (up ? S.E.G[p] : Gq);
 #pragma unroll
       for (int g = 0; g < NG; ++g) {
         const double d = S.D[sg[g]][p], db = S.D[sbg[g]][p];
@@ -270,6 +299,20 @@ struct PointAdjoint {
         dan[g] = __builtin_fma(tann * adl, db, dan[g]);
         ep[g] = __builtin_fma(tpro, 1.0 - db, ep[g]);
         dpr[g] = __builtin_fma(tpro * (adl + eq + epp), 1.0 - db, dpr[g]);
+      }
+    }
+    {
+      const double sc = rho * eq;
+#pragma unroll
+      for (int g = 0; g < NG; ++g) {
+        en[g] *= sc;
+        dn[g] *= sc;
+        onn[g] *= sc;
+        dout[g] *= sc;
+        an[g] *= sc;
+        dan[g] *= sc;
+        ep[g] *= sc;
+        dpr[g] *= sc;
       }
     }
     // ---- per-row Jacobian pieces ----------------------------------------
@@ -305,13 +348,13 @@ struct PointAdjoint {
     __syncthreads();
 
     // ---- Z = A^-T C^T, block by block ------------------------------------
-    // (the tiles hold the kernels at unit amplitude a = 1, i.e. A = rho11)
+    // (kernels at unit amplitude a = 1, i.e. A = rho11, scaled by a_nes, a_pair)
     bool ok;
     if constexpr (NS == 1) {
-      ok = block_solve<0, 1>(S, md, dtau, a_nes, a_pair, K);
+      ok = block_solve<0, 1>(S, md, dtau, rho, a_nes, a_pair, K);
     } else {
-      ok = block_solve<0, 2>(S, md, dtau, a_nes, a_pair, K);
-      if constexpr (NS == 3) ok = block_solve<2, 1>(S, md, dtau, a_nes, a_pair, K) && ok;
+      ok = block_solve<0, 2>(S, md, dtau, rho, a_nes, a_pair, K);
+      if constexpr (NS == 3) ok = block_solve<2, 1>(S, md, dtau, rho, a_nes, a_pair, K) && ok;
     }
 
     // ---- Schur complement on (Ye, e), multipliers and gradient ------------

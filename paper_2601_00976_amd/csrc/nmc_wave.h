@@ -386,10 +386,12 @@ __device__ __forceinline__ void split_exp_prepare(const ModelLds& m, double invT
   __syncthreads();
 }
 
-enum TileKind { kTilePhiIn, kTilePhiAnn, kTilePhiPro };
+enum TileKind { kTilePhiIn, kTilePhiAnn, kTilePhiPro, kTilePairFactor };
 
 // Writes the full 32 x 32 matrix of the given kind with amplitude amp into
-// the tile (row-major, stride kTileStride).  Pair slot i of lane (h, q)
+// the tile (row-major, stride kTileStride); kTilePairFactor is the symmetric
+// b = exp(-|e_q - e_j| / (2T)) itself (amp unused, exactly 1 on the
+// diagonal).  Pair slot i of lane (h, q)
 // covers nodes (q, q + d mod 32), d = h + 2 i; the d = 16 pairs are taken by
 // q < 16 only, so each of the 528 unordered pairs (diagonal included) is
 // written exactly once.  h = lane / 32 and q = lane mod 32 are passed in
@@ -406,7 +408,11 @@ __device__ __forceinline__ void fill_tile(const ModelLds& m, const SplitExp& E, 
     const int lo = q < j ? q : j, hi = q < j ? j : q;
     if (d < 16 || (d == 16 && q < 16)) {
       const double ee = amp * (m.eps[lo] * m.eps[hi]);
-      if constexpr (K == kTilePhiPro) {
+      if constexpr (K == kTilePairFactor) {
+        const double b = lo == hi ? 1.0 : ldexp(E.P2[lo] * E.R2[hi], E.n2[lo] - E.n2[hi]);
+        T0[hi * ST + lo] = b;
+        T0[lo * ST + hi] = b;
+      } else if constexpr (K == kTilePhiPro) {
         const double v = ee * E.G[hi];
         T0[hi * ST + lo] = v;
         T0[lo * ST + hi] = v;
