@@ -44,15 +44,6 @@ struct AdjLds {
   alignas(16) double prow[2 * NQ + 2];  // pivot-row broadcast of the block factorisation
 };
 
-// reciprocal: hardware estimate refined by two Newton steps (x finite, nonzero)
-__device__ __forceinline__ double rcp_nr(double x) {
-  double r = __builtin_amdgcn_rcp(x);
-  double e = __builtin_fma(-x, r, 1.0);
-  r = __builtin_fma(r, e, r);
-  e = __builtin_fma(-x, r, 1.0);
-  return __builtin_fma(r, e, r);
-}
-
 __device__ __forceinline__ double readlane_f64(double v, int lane) {
   const uint32_t lo = __builtin_amdgcn_readlane((int)lo32(v), lane);
   const uint32_t hi = __builtin_amdgcn_readlane((int)hi32(v), lane);

@@ -52,6 +52,8 @@ struct WaveLds {
   double y[2];                          // matter iterate (Ye, e)
   double oq[2], of[2], odq[2], odf[2];  // outer Anderson history
   double T_last, r3, K, An, Ap;
+  // per-point inputs read in every outer iteration, staged once per point
+  double ye_st, e_st, chi0, T_fix, mu_fix;
 };
 
 // KM = 0: kernel rows built once per outer iteration and held in VGPRs,
@@ -210,9 +212,10 @@ struct PointSolver {
     __syncthreads();
   }
 
-  __device__ static void solve(const FwdArgs& a, int64_t p, WaveLds<NS, KM>& S) {
-    const DevModel* __restrict__ md0 = a.mdl;
-    const DevModel* __restrict__ md = md0;
+  // settle() is called once the point's inputs are loaded (work-queue hook)
+  template <class Settle>
+  __device__ static void solve(const FwdArgs& a, int64_t p, WaveLds<NS, KM>& S, Settle&& settle) {
+    const_ptr<DevModel> md = scalar_ptr(a.mdl);
     const ModelLds& mt = S.m;
     const int lane = threadIdx.x;
     const int h0 = lane >> 5;  // 0: number lanes, 1: flux lanes
@@ -226,13 +229,19 @@ struct PointSolver {
 
     // the moment a lane owns: D* on number lanes, I* on flux lanes; D* on
     // every lane (flux lanes form W (1 - D) from it)
+    // (both loads in every lane: the two lanes of node q read the same
+    // elements, so the wave still fetches each line once, and no load waits
+    // behind a branch)
     double M[NS], Dcur[NS];
 #pragma unroll
     for (int t = 0; t < NS; ++t) {
-      Dcur[t] = a.D0[base + md->ext[t] * NQ + q];
-      M[t] = h ? a.I0[base + md->ext[t] * NQ + q] : Dcur[t];
+      const int64_t o = base + md->ext[t] * NQ + q;
+      const double dv = a.D0[o], iv = a.I0[o];
+      Dcur[t] = dv;
+      M[t] = h ? iv : dv;
     }
 
+    settle();
     if (rho < md->rho11_min) {
       // coupling disabled at low density (Sec. 7.2): pass the state through
 #pragma unroll
@@ -279,8 +288,11 @@ struct PointSolver {
 #pragma unroll
       for (int t = 0; t < NS; ++t) S.dref[t] = s0[t];
     }
-    S.y[0] = a.ye0[p];
-    S.y[1] = a.e0[p];
+    S.ye_st = S.y[0] = a.ye0[p];
+    S.e_st = S.y[1] = a.e0[p];
+    S.chi0 = a.chi0 ? a.chi0[p] : md->chi_ref * rho;
+    if (fixedT) S.T_fix = a.T_fixed[p];
+    if (a.prm.fixed_matter && a.mu_fixed) S.mu_fix = a.mu_fixed[p];
 #pragma unroll
     for (int i = 0; i < 2; ++i) S.oq[i] = S.of[i] = S.odq[i] = S.odf[i] = 0.0;
     S.T_last = 0.0;
@@ -293,14 +305,14 @@ struct PointSolver {
     for (k = 1; k <= a.prm.max_outer; ++k) {
       // per-iteration opaque copies keep lane invariants from being hoisted
       // out of this loop (and spilled)
-      const DevModel* __restrict__ md = opaque_ptr(md0);
+      const_ptr<DevModel> md = scalar_ptr(a.mdl);
       const int q = opaque(q0), h = opaque(h0);
       // ---- ComputeOpacities(y^[k]) --------------------------------------
       const double r3 = S.r3;
       const double y0 = S.y[0], y1 = S.y[1];
-      const double T = fixedT ? a.T_fixed[p] : (y1 - md->eos_b * ye43(y0) * r3) / (md->eos_a * (1.0 + y0));
+      const double T = fixedT ? S.T_fix : (y1 - md->eos_b * ye43(y0) * r3) / (md->eos_a * (1.0 + y0));
       const double mu = (a.prm.fixed_matter && a.mu_fixed)
-                            ? a.mu_fixed[p]
+                            ? S.mu_fix
                             : md->mu_a * (y0 - md->mu_ye0) * r3 + md->mu_b * log(T / md->mu_t0);
       if (!(T > 0.0) || !(y0 >= 0.0) || !isfinite(T) || !isfinite(mu)) {
         status = NMC_STATUS_EOS_DOMAIN;
@@ -317,7 +329,7 @@ struct PointSolver {
       // sigma_ratio chi0 shape_q.  Stored as the constant parts of the
       // numerator and denominator of Q.
       {
-        const double chi0 = a.chi0 ? a.chi0[p] : md->chi_ref * rho;
+        const double chi0 = S.chi0;
         const double shape = chi0 * mt.shape[q];
         const double sig = (md->flags & NMC_ISO) ? md->sigma_ratio * shape : 0.0;
         const double emab_q = (md->flags & NMC_EMAB) ? mt.theta[q] * shape : 0.0;
@@ -327,7 +339,7 @@ struct PointSolver {
           const double chia = md->iemab[t] * emab_q;
           const double x = (epsq - md->imusign[t] * mu) * invT;
           const double ex = exp(-fabs(x));
-          const double r = rcp_ge1(1.0 + ex);
+          const double r = rcp_nr(1.0 + ex);
           const double deq = x > 0.0 ? ex * r : r;
           S.base[t][lane] = h ? mst(t) : mst(t) + dtau * (chia * deq);
           S.den0[t][lane] = 1.0 + dtau * (h ? chia + sig : chia);
@@ -407,7 +419,7 @@ struct PointSolver {
         for (int t = 0; t < NS; ++t) {
           const double num = __builtin_fma(dth, eta_c[t], S.base[t][lane]);
           const double den = __builtin_fma(dtau, chi_c[t], S.den0[t][lane]);
-          Q[t] = num * rcp_ge1(den);
+          Q[t] = num * rcp_nr(den);
           F[t] = Q[t] - M[t];
         }
 
@@ -436,29 +448,8 @@ struct PointSolver {
           wave_sums4(v4, gs);
           const double G12 = gs[0], G22 = gs[1];
           const double b1 = gs[2], b2 = gs[3];
-          // normal equations by LDL^T (the Cholesky pivots G11 and
-          // G22 - G12^2 / G11, without square roots); a pivot <= 1e-14 trace
-          // drops the oldest column, none left gives Picard
-          double g1 = 0.0, g2 = 0.0;
-          bool two = (mem == 3);
-          if (two) {
-            const double tr = G11 + G22;
-            two = G11 > 1e-14 * tr;
-            if (two) {
-              const double r11 = 1.0 / G11;
-              const double l21 = G12 * r11;
-              const double p2 = G22 - G12 * l21;
-              two = p2 > 1e-14 * tr;
-              if (two) {
-                g2 = (b2 - l21 * b1) / p2;
-                g1 = (b1 - G12 * g2) * r11;
-              }
-            }
-          }
-          if (!two) {
-            g1 = 0.0;
-            g2 = (G22 > 1e-14 * G22) ? b2 / G22 : 0.0;
-          }
+          double g1, g2;
+          anderson2(mem == 3, G11, G12, G22, b1, b2, g1, g2);
 #pragma unroll
           for (int t = 0; t < NS; ++t) {
             Mnew[t] = Q[t] - g2 * dQ2[t] - g1 * S.u.it.hist[2][t][lane];
@@ -550,8 +541,8 @@ struct PointSolver {
           }
         }
         hsum<2>(mv, s0, s1, S);
-        yq0 = a.ye0[p] - S.K * s0[0];
-        yq1 = a.e0[p] - S.K * s0[1];
+        yq0 = S.ye_st - S.K * s0[0];
+        yq1 = S.e_st - S.K * s0[1];
       }
       const double f0 = yq0 - S.y[0], f1 = yq1 - S.y[1];
 
@@ -566,27 +557,10 @@ struct PointSolver {
         const double df20 = f0 - S.of[0], df21 = f1 - S.of[1];
         const double odf0 = S.odf[0], odf1 = S.odf[1];
         const double G22 = df20 * df20 + df21 * df21, b2 = df20 * f0 + df21 * f1;
-        double g1 = 0.0, g2 = 0.0;
-        bool two = (omem == 3);
-        if (two) {
-          const double G11o = odf0 * odf0 + odf1 * odf1;
-          const double G12 = odf0 * df20 + odf1 * df21, b1 = odf0 * f0 + odf1 * f1;
-          const double tr = G11o + G22;
-          two = G11o > 1e-14 * tr;
-          if (two) {
-            const double l21 = G12 / G11o;
-            const double p2 = G22 - G12 * l21;
-            two = p2 > 1e-14 * tr;
-            if (two) {
-              g2 = (b2 - l21 * b1) / p2;
-              g1 = (b1 - G12 * g2) / G11o;
-            }
-          }
-        }
-        if (!two) {
-          g1 = 0.0;
-          g2 = (G22 > 1e-14 * G22) ? b2 / G22 : 0.0;
-        }
+        const double G11o = odf0 * odf0 + odf1 * odf1;
+        const double G12 = odf0 * df20 + odf1 * df21, b1 = odf0 * f0 + odf1 * f1;
+        double g1, g2;
+        anderson2(omem == 3, G11o, G12, G22, b1, b2, g1, g2);
         yn0 = yq0 - g2 * dq20 - g1 * S.odq[0];
         yn1 = yq1 - g2 * dq21 - g1 * S.odq[1];
         S.odq[0] = dq20;
@@ -604,8 +578,8 @@ struct PointSolver {
         break;
       }
       // Algorithm outerConverged: componentwise against y*
-      const bool oc = fabs(yn0 - S.y[0]) <= a.prm.tol_outer * fabs(a.ye0[p]) &&
-                      fabs(yn1 - S.y[1]) <= a.prm.tol_outer * fabs(a.e0[p]);
+      const bool oc = fabs(yn0 - S.y[0]) <= a.prm.tol_outer * fabs(S.ye_st) &&
+                      fabs(yn1 - S.y[1]) <= a.prm.tol_outer * fabs(S.e_st);
       S.y[0] = yn0;
       S.y[1] = yn1;
       if (oc) {
@@ -620,7 +594,7 @@ struct PointSolver {
     }
 
     // ---- outputs --------------------------------------------------------
-    const double ye_st = a.ye0[p], e_st = a.e0[p];
+    const double ye_st = S.ye_st, e_st = S.e_st;
     double ye_out = ye_st, e_out = e_st, T_out = S.T_last;
     if (!a.prm.fixed_matter) {
       // final matter state from the final moments (exact lepton-number and
@@ -640,7 +614,7 @@ struct PointSolver {
       e_out = e_st - S.K * s0[1];
       T_out = (e_out - md->eos_b * ye43(ye_out) * S.r3) / (md->eos_a * (1.0 + ye_out));
     } else if (status == NMC_STATUS_EOS_DOMAIN) {
-      T_out = fixedT ? a.T_fixed[p] : (e_st - md->eos_b * ye43(ye_st) * S.r3) / (md->eos_a * (1.0 + ye_st));
+      T_out = fixedT ? S.T_fix : (e_st - md->eos_b * ye43(ye_st) * S.r3) / (md->eos_a * (1.0 + ye_st));
     }
 #pragma unroll
     for (int t = 0; t < NS; ++t) {
@@ -667,12 +641,12 @@ __global__ __launch_bounds__(kLanes, KM == 1 ? 3 : 2) void fwd_kernel(FwdArgs a)
     for (int64_t g; (g = wq.next()) >= 0;) {
       const int64_t b0 = g * a.chunk;
       const int64_t end = b0 + a.chunk < a.P ? b0 + a.chunk : a.P;
-      for (int64_t p = b0; p < end; ++p) PointSolver<NS, NQ, COUPLED, KM>::solve(a, p, S);
+      for (int64_t p = b0; p < end; ++p) PointSolver<NS, NQ, COUPLED, KM>::solve(a, p, S, [&] { wq.settle(); });
     }
   } else {
     const int64_t b0 = (int64_t)blockIdx.x * a.chunk;
     const int64_t end = b0 + a.chunk < a.P ? b0 + a.chunk : a.P;
-    for (int64_t p = b0; p < end; ++p) PointSolver<NS, NQ, COUPLED, KM>::solve(a, p, S);
+    for (int64_t p = b0; p < end; ++p) PointSolver<NS, NQ, COUPLED, KM>::solve(a, p, S, [] {});
   }
 }
 

@@ -47,6 +47,8 @@ struct Lds64 {
   double dref[NS];
   double y[2], oq[2], of[2], odq[2], odf[2];
   double T_last, r3, K, An, Ap;
+  // per-point inputs read in every outer iteration, staged once per point
+  double ye_st, e_st, chi0, T_fix, mu_fix;
 };
 
 // sums over the wave of V <= 12 lane values, in every lane
@@ -162,9 +164,10 @@ struct PointSolver64 {
     }
   }
 
-  __device__ static void solve(const FwdArgs& a, int64_t p, Lds64<NS>& S) {
-    const DevModel* __restrict__ md0 = a.mdl;
-    const DevModel* __restrict__ md = md0;
+  // settle() is called once the point's inputs are loaded (work-queue hook)
+  template <class Settle>
+  __device__ static void solve(const FwdArgs& a, int64_t p, Lds64<NS>& S, Settle&& settle) {
+    const_ptr<DevModel> md = scalar_ptr(a.mdl);
     const ModelLdsN<NQ>& mt = S.m;
     const int lane = threadIdx.x;
     const int q0 = lane;
@@ -182,6 +185,7 @@ struct PointSolver64 {
       Ist[t] = I[t] = a.I0[o];
     }
 
+    settle();
     if (rho < md->rho11_min) {
       // coupling disabled at low density (Sec. 7.2): pass the state through
 #pragma unroll
@@ -216,8 +220,11 @@ struct PointSolver64 {
 #pragma unroll
       for (int t = 0; t < NS; ++t) S.dref[t] = s[t];
     }
-    S.y[0] = a.ye0[p];
-    S.y[1] = a.e0[p];
+    S.ye_st = S.y[0] = a.ye0[p];
+    S.e_st = S.y[1] = a.e0[p];
+    S.chi0 = a.chi0 ? a.chi0[p] : md->chi_ref * rho;
+    if (fixedT) S.T_fix = a.T_fixed[p];
+    if (a.prm.fixed_matter && a.mu_fixed) S.mu_fix = a.mu_fixed[p];
 #pragma unroll
     for (int i = 0; i < 2; ++i) S.oq[i] = S.of[i] = S.odq[i] = S.odf[i] = 0.0;
     S.T_last = 0.0;
@@ -229,14 +236,14 @@ struct PointSolver64 {
     for (k = 1; k <= a.prm.max_outer; ++k) {
       // per-iteration opaque copies keep lane invariants from being hoisted
       // out of this loop (and spilled)
-      const DevModel* __restrict__ md = opaque_ptr(md0);
+      const_ptr<DevModel> md = scalar_ptr(a.mdl);
       const int q = opaque(q0);
       // ---- ComputeOpacities(y^[k]) --------------------------------------
       const double r3 = S.r3;
       const double y0 = S.y[0], y1 = S.y[1];
-      const double T = fixedT ? a.T_fixed[p] : (y1 - md->eos_b * ye43(y0) * r3) / (md->eos_a * (1.0 + y0));
+      const double T = fixedT ? S.T_fix : (y1 - md->eos_b * ye43(y0) * r3) / (md->eos_a * (1.0 + y0));
       const double mu = (a.prm.fixed_matter && a.mu_fixed)
-                            ? a.mu_fixed[p]
+                            ? S.mu_fix
                             : md->mu_a * (y0 - md->mu_ye0) * r3 + md->mu_b * log(T / md->mu_t0);
       if (!(T > 0.0) || !(y0 >= 0.0) || !isfinite(T) || !isfinite(mu)) {
         status = NMC_STATUS_EOS_DOMAIN;
@@ -250,7 +257,7 @@ struct PointSolver64 {
       double baseD[NS], den0D[NS], den0I[NS];
       const double epsq = mt.eps[q];
       {
-        const double chi0 = a.chi0 ? a.chi0[p] : md->chi_ref * rho;
+        const double chi0 = S.chi0;
         const double shape = chi0 * mt.shape[q];
         const double sig = (md->flags & NMC_ISO) ? md->sigma_ratio * shape : 0.0;
         const double emab_q = (md->flags & NMC_EMAB) ? mt.theta[q] * shape : 0.0;
@@ -259,7 +266,7 @@ struct PointSolver64 {
           const double chia = md->iemab[t] * emab_q;
           const double x = (epsq - md->imusign[t] * mu) * invT;
           const double ex = exp(-fabs(x));
-          const double r = rcp_ge1(1.0 + ex);
+          const double r = rcp_nr(1.0 + ex);
           const double deq = x > 0.0 ? ex * r : r;
           baseD[t] = Dst[t] + dtau * (chia * deq);
           den0D[t] = 1.0 + dtau * chia;
@@ -271,7 +278,7 @@ struct PointSolver64 {
         const double n = floor(x);
         const double P = exp2(x - n);
         S.colPR[q][0] = P;
-        S.colPR[q][1] = rcp_ge1(P);
+        S.colPR[q][1] = rcp_nr(P);
         S.colGE[q][0] = exp(-2.0 * epsq * invT);
         S.colGE[q][1] = mt.w2[q] * epsq;
         S.coln[q] = (int)n;
@@ -304,8 +311,8 @@ struct PointSolver64 {
         for (int t = 0; t < NS; ++t) {
           const double eta = etaN[t] + etaP[t];
           const double chi = (etaN[t] + outN[t]) + (etaP[t] + annP[t]);
-          Qx[t] = __builtin_fma(dtau, eta, baseD[t]) * rcp_ge1(__builtin_fma(dtau, chi, den0D[t]));
-          Qx[NS + t] = Ist[t] * rcp_ge1(__builtin_fma(dtau, chi, den0I[t]));
+          Qx[t] = __builtin_fma(dtau, eta, baseD[t]) * rcp_nr(__builtin_fma(dtau, chi, den0D[t]));
+          Qx[NS + t] = Ist[t] * rcp_nr(__builtin_fma(dtau, chi, den0I[t]));
           Fx[t] = Qx[t] - D[t];
           Fx[NS + t] = Qx[NS + t] - I[t];
         }
@@ -332,26 +339,8 @@ struct PointSolver64 {
           double gs[4];
           wave_sums4(v4, gs);
           const double G12 = gs[0], G22 = gs[1], b1 = gs[2], b2 = gs[3];
-          double g1 = 0.0, g2 = 0.0;
-          bool two = (mem == 3);
-          if (two) {
-            const double tr = G11 + G22;
-            two = G11 > 1e-14 * tr;
-            if (two) {
-              const double r11 = 1.0 / G11;
-              const double l21 = G12 * r11;
-              const double p2 = G22 - G12 * l21;
-              two = p2 > 1e-14 * tr;
-              if (two) {
-                g2 = (b2 - l21 * b1) / p2;
-                g1 = (b1 - G12 * g2) * r11;
-              }
-            }
-          }
-          if (!two) {
-            g1 = 0.0;
-            g2 = (G22 > 1e-14 * G22) ? b2 / G22 : 0.0;
-          }
+          double g1, g2;
+          anderson2(mem == 3, G11, G12, G22, b1, b2, g1, g2);
 #pragma unroll
           for (int x = 0; x < 2 * NS; ++x) {
             Xn[x] = Qx[x] - g2 * dQ2[x] - g1 * S.hist[2][x][lane];
@@ -432,8 +421,8 @@ struct PointSolver64 {
           mv[1] += md->imult[t] * w3 * dd;
         }
         wave_sums<2>(mv, s);
-        yq0 = a.ye0[p] - S.K * s[0];
-        yq1 = a.e0[p] - S.K * s[1];
+        yq0 = S.ye_st - S.K * s[0];
+        yq1 = S.e_st - S.K * s[1];
       }
       const double f0 = yq0 - S.y[0], f1 = yq1 - S.y[1];
       const int omem = k < a.prm.m_outer ? k : a.prm.m_outer;
@@ -446,27 +435,10 @@ struct PointSolver64 {
         const double df20 = f0 - S.of[0], df21 = f1 - S.of[1];
         const double odf0 = S.odf[0], odf1 = S.odf[1];
         const double G22 = df20 * df20 + df21 * df21, b2 = df20 * f0 + df21 * f1;
-        double g1 = 0.0, g2 = 0.0;
-        bool two = (omem == 3);
-        if (two) {
-          const double G11o = odf0 * odf0 + odf1 * odf1;
-          const double G12 = odf0 * df20 + odf1 * df21, b1 = odf0 * f0 + odf1 * f1;
-          const double tr = G11o + G22;
-          two = G11o > 1e-14 * tr;
-          if (two) {
-            const double l21 = G12 / G11o;
-            const double p2 = G22 - G12 * l21;
-            two = p2 > 1e-14 * tr;
-            if (two) {
-              g2 = (b2 - l21 * b1) / p2;
-              g1 = (b1 - G12 * g2) / G11o;
-            }
-          }
-        }
-        if (!two) {
-          g1 = 0.0;
-          g2 = (G22 > 1e-14 * G22) ? b2 / G22 : 0.0;
-        }
+        const double G11o = odf0 * odf0 + odf1 * odf1;
+        const double G12 = odf0 * df20 + odf1 * df21, b1 = odf0 * f0 + odf1 * f1;
+        double g1, g2;
+        anderson2(omem == 3, G11o, G12, G22, b1, b2, g1, g2);
         yn0 = yq0 - g2 * dq20 - g1 * S.odq[0];
         yn1 = yq1 - g2 * dq21 - g1 * S.odq[1];
         S.odq[0] = dq20;
@@ -483,8 +455,8 @@ struct PointSolver64 {
         fatal = true;
         break;
       }
-      const bool oc = fabs(yn0 - S.y[0]) <= a.prm.tol_outer * fabs(a.ye0[p]) &&
-                      fabs(yn1 - S.y[1]) <= a.prm.tol_outer * fabs(a.e0[p]);
+      const bool oc = fabs(yn0 - S.y[0]) <= a.prm.tol_outer * fabs(S.ye_st) &&
+                      fabs(yn1 - S.y[1]) <= a.prm.tol_outer * fabs(S.e_st);
       S.y[0] = yn0;
       S.y[1] = yn1;
       if (oc) {
@@ -499,7 +471,7 @@ struct PointSolver64 {
     }
 
     // ---- outputs --------------------------------------------------------
-    const double ye_st = a.ye0[p], e_st = a.e0[p];
+    const double ye_st = S.ye_st, e_st = S.e_st;
     double ye_out = ye_st, e_out = e_st, T_out = S.T_last;
     if (!a.prm.fixed_matter) {
       const double w2 = mt.w2[q0], w3 = mt.w3[q0];
@@ -515,7 +487,7 @@ struct PointSolver64 {
       e_out = e_st - S.K * s[1];
       T_out = (e_out - md->eos_b * ye43(ye_out) * S.r3) / (md->eos_a * (1.0 + ye_out));
     } else if (status == NMC_STATUS_EOS_DOMAIN) {
-      T_out = fixedT ? a.T_fixed[p] : (e_st - md->eos_b * ye43(ye_st) * S.r3) / (md->eos_a * (1.0 + ye_st));
+      T_out = fixedT ? S.T_fix : (e_st - md->eos_b * ye43(ye_st) * S.r3) / (md->eos_a * (1.0 + ye_st));
     }
 #pragma unroll
     for (int t = 0; t < NS; ++t) {
@@ -544,12 +516,12 @@ __global__ __launch_bounds__(kLanes) void fwd64_kernel(FwdArgs a) {
     for (int64_t g; (g = wq.next()) >= 0;) {
       const int64_t b0 = g * a.chunk;
       const int64_t end = b0 + a.chunk < a.P ? b0 + a.chunk : a.P;
-      for (int64_t p = b0; p < end; ++p) PointSolver64<NS, COUPLED, PRE>::solve(a, p, S);
+      for (int64_t p = b0; p < end; ++p) PointSolver64<NS, COUPLED, PRE>::solve(a, p, S, [&] { wq.settle(); });
     }
   } else {
     const int64_t b0 = (int64_t)blockIdx.x * a.chunk;
     const int64_t end = b0 + a.chunk < a.P ? b0 + a.chunk : a.P;
-    for (int64_t p = b0; p < end; ++p) PointSolver64<NS, COUPLED, PRE>::solve(a, p, S);
+    for (int64_t p = b0; p < end; ++p) PointSolver64<NS, COUPLED, PRE>::solve(a, p, S, [] {});
   }
 }
 

@@ -180,6 +180,17 @@ __device__ __forceinline__ const T* opaque_ptr(const T* p) {
   asm volatile("" : "+s"(p));
   return p;
 }
+// A uniform pointer to read-only global data viewed in the constant address
+// space, so that loads through it are scalar loads (s_load, scalar cache);
+// laundered like opaque_ptr.
+template <class T>
+using const_ptr = const __attribute__((address_space(4))) T*;
+template <class T>
+__device__ __forceinline__ const_ptr<T> scalar_ptr(const T* p) {
+  const_ptr<T> c = (const_ptr<T>)p;
+  asm volatile("" : "+s"(c));
+  return c;
+}
 
 // Four columns of the contraction for every species and both matrices in one
 // asm block: acc1[t] += bcast(x[t], L0 + jj) * m1[jj], acc2[t] += bcast(x[t], L0 + jj) * m2[jj].
@@ -278,13 +289,34 @@ struct Fmac4<3> {
   }
 };
 
-// reciprocal of x >= 1 (finite): hardware estimate refined by two Newton steps
-__device__ __forceinline__ double rcp_ge1(double x) {
+// 1 / x from the hardware estimate refined by two Newton steps, for finite x
+// of normal magnitude (|x| and 1 / |x| both above the denormal range)
+__device__ __forceinline__ double rcp_nr(double x) {
   double r = __builtin_amdgcn_rcp(x);
   double e = __builtin_fma(-x, r, 1.0);
   r = __builtin_fma(r, e, r);
   e = __builtin_fma(-x, r, 1.0);
   return __builtin_fma(r, e, r);
+}
+
+// Coefficients (g1, g2) of an Anderson step over two difference columns
+// (1 the older, 2 the newer) from their normal equations, by LDL^T (the
+// Cholesky pivots G11 and G22 - G12^2 / G11, without square roots).  A pivot
+// <= 1e-14 trace drops the older column, and with no column left the step is
+// Picard (g = 0).  two_cols says whether the older column exists.
+// Branch-free, with Newton-refined reciprocals of the positive pivots.
+__device__ __forceinline__ void anderson2(bool two_cols, double G11, double G12, double G22, double b1, double b2,
+                                          double& g1, double& g2) {
+  const double tr = G11 + G22;
+  const bool use2 = two_cols && G11 > 1e-14 * tr;
+  const double r11 = rcp_nr(use2 ? G11 : 1.0);
+  const double l21 = G12 * r11;
+  const double p2 = G22 - G12 * l21;
+  const bool two = use2 && p2 > 1e-14 * tr;
+  const bool one = G22 > 1e-14 * G22;
+  const double rp = rcp_nr(two ? p2 : (one ? G22 : 1.0));
+  g2 = two ? (b2 - l21 * b1) * rp : (one ? b2 * rp : 0.0);
+  g1 = two ? (b1 - G12 * g2) * r11 : 0.0;
 }
 
 // Per-node model tables copied into LDS once per work-group (lane-indexed
@@ -323,23 +355,31 @@ constexpr int kQueueStride = 64;  // ints
 struct WorkQueue {
   int* ctr;
   int64_t nchunks;
-  int nq, c, nxt;
+  int nq, c;
+  int pend;  // lane 0: counter value returned by the grab in flight
+  int cur;   // counter value of the next chunk (uniform)
   __device__ __forceinline__ WorkQueue(int* queue, int64_t P, int chunk) {
     nq = gridDim.x < kQueues ? (int)gridDim.x : kQueues;
     c = blockIdx.x % nq;
     ctr = queue + c * kQueueStride;
     nchunks = (P + chunk - 1) / chunk;
-    nxt = 0;
-    if (threadIdx.x == 0) nxt = atomicAdd(ctr, 1);
+    pend = 0;
+    if (threadIdx.x == 0) pend = atomicAdd(ctr, 1);
+    cur = __builtin_amdgcn_readfirstlane(pend);
   }
   // next chunk index of this work-group (uniform), or -1 once drained; the
-  // following grab is issued before the chunk is solved
+  // following grab is issued here and must be settled before the next call
   __device__ __forceinline__ int64_t next() {
-    const int64_t g = (int64_t)__builtin_amdgcn_readfirstlane(nxt) * nq + c;
+    const int64_t g = (int64_t)cur * nq + c;
     if (g >= nchunks) return -1;
-    if (threadIdx.x == 0) nxt = atomicAdd(ctr, 1);
+    if (threadIdx.x == 0) pend = atomicAdd(ctr, 1);
     return g;
   }
+  // takes the result of the grab in flight.  Called once the chunk's inputs
+  // are loaded: the wait for the atomic then overlaps that of the loads
+  // instead of the drain of the chunk's output stores (vector memory
+  // counters complete in order).
+  __device__ __forceinline__ void settle() { cur = __builtin_amdgcn_readfirstlane(pend); }
 };
 
 // Pair partner of internal species s (species sorted by id: nu_e, anti-nu_e
@@ -379,7 +419,7 @@ __device__ __forceinline__ void split_exp_prepare(const ModelLds& m, double invT
     const double n = floor(x);
     const double P = exp2(x - n);
     E.P2[lane] = P;
-    E.R2[lane] = rcp_ge1(P);
+    E.R2[lane] = rcp_nr(P);
     E.n2[lane] = (int)n;
     E.G[lane] = exp(-2.0 * e * invT);
   }
