@@ -274,14 +274,13 @@ struct PointSolver64 {
         }
       }
       if constexpr (COUPLED) {
-        const double x = epsq * (0.5 * invT) * 1.4426950408889634;  // log2(e)
-        const double n = floor(x);
-        const double P = exp2(x - n);
-        S.colPR[q][0] = P;
-        S.colPR[q][1] = rcp_nr(P);
-        S.colGE[q][0] = exp(-2.0 * epsq * invT);
+        const ExpSplit xs = exp_split(epsq, invT);
+        const double R2 = xs.R * xs.R;
+        S.colPR[q][0] = xs.P;
+        S.colPR[q][1] = xs.R;
+        S.colGE[q][0] = ldexp(R2 * R2, -4 * xs.n);  // exp(-2 e / T)
         S.colGE[q][1] = mt.w2[q] * epsq;
-        S.coln[q] = (int)n;
+        S.coln[q] = xs.n;
         if constexpr (PRE) {
           __syncthreads();
           store_rows(S, q, kst);

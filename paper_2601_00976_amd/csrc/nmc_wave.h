@@ -147,15 +147,26 @@ __device__ __forceinline__ void wave_sums4(const double (&v)[4], double (&out)[4
 }
 
 // Per-half sums of 2 K values (K = 1..3): s0 over lanes 0..31, s1 over lanes
-// 32..63, returned in every lane.
+// 32..63, returned in every lane.  The K reduction chains are advanced stage
+// by stage, so that their dependent permute / add steps interleave.
 template <int K>
 __device__ __forceinline__ void half_sums_reg(const double (&v)[2 * K], double (&s0)[2 * K], double (&s1)[2 * K]) {
+  // rows (0, 2): slot k over the row pair; rows (1, 3): slot K + k
+  double r[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) r[k] = halve16(v[k], v[K + k]);
+#pragma unroll
+  for (int k = 0; k < K; ++k) r[k] += dpp<0xB1>(r[k]);   // quad_perm [1,0,3,2]
+#pragma unroll
+  for (int k = 0; k < K; ++k) r[k] += dpp<0x4E>(r[k]);   // quad_perm [2,3,0,1]
+#pragma unroll
+  for (int k = 0; k < K; ++k) r[k] += dpp<0x141>(r[k]);  // row_half_mirror
+#pragma unroll
+  for (int k = 0; k < K; ++k) r[k] += dpp<0x140>(r[k]);  // row_mirror
 #pragma unroll
   for (int k = 0; k < K; ++k) {
-    // rows (0, 2): slot k over the row pair; rows (1, 3): slot K + k
-    const double r = row_allsum(halve16(v[k], v[K + k]));
     double f, sc;
-    swap16(r, f, sc);  // f: slot k of this half, sc: slot K + k
+    swap16(r[k], f, sc);  // f: slot k of this half, sc: slot K + k
     double a0, a1, b0, b1;
     swap32(f, a0, a1);
     swap32(sc, b0, b1);
@@ -410,18 +421,33 @@ struct alignas(16) SplitExp {
   int n2[32];
 };
 
-// lanes 0..31 fill the per-node factors of temperature 1 / invT; ends with a barrier
+// Exponent split of y = v log2(e) / (2T): y = n + f with n = floor(y), and
+// P = 2^f in [1, 2), R = 2^-f.  exp(-v / T) = 2^(-2n) R^2 without exp().
+struct ExpSplit {
+  double P, R;
+  int n;
+};
+__device__ __forceinline__ ExpSplit exp_split(double v, double invT) {
+  const double y = v * (0.5 * invT) * 1.4426950408889634;  // log2(e)
+  const double n = floor(y);
+  ExpSplit r;
+  r.P = exp2(y - n);
+  r.R = rcp_nr(r.P);
+  r.n = (int)n;
+  return r;
+}
+
+// lanes 0..31 fill the per-node factors of temperature 1 / invT
+// (G = exp(-2 e / T) = 2^(-4n) R^4); ends with a barrier
 __device__ __forceinline__ void split_exp_prepare(const ModelLds& m, double invT, SplitExp& E) {
   const int lane = threadIdx.x;
   if (lane < 32) {
-    const double e = m.eps[lane];
-    const double x = e * (0.5 * invT) * 1.4426950408889634;  // log2(e)
-    const double n = floor(x);
-    const double P = exp2(x - n);
-    E.P2[lane] = P;
-    E.R2[lane] = rcp_nr(P);
-    E.n2[lane] = (int)n;
-    E.G[lane] = exp(-2.0 * e * invT);
+    const ExpSplit x = exp_split(m.eps[lane], invT);
+    E.P2[lane] = x.P;
+    E.R2[lane] = x.R;
+    E.n2[lane] = x.n;
+    const double R2 = x.R * x.R;
+    E.G[lane] = ldexp(R2 * R2, -4 * x.n);
   }
   __syncthreads();
 }
