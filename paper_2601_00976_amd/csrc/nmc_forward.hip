@@ -639,8 +639,8 @@ __global__ __launch_bounds__(kLanes, KM == 1 ? 3 : 2) void fwd_kernel(FwdArgs a)
   if (a.queue) {
     WorkQueue wq(a.queue, a.P, a.chunk);
     for (int64_t g; (g = wq.next()) >= 0;) {
-      const int64_t b0 = g * a.chunk;
-      const int64_t end = b0 + a.chunk < a.P ? b0 + a.chunk : a.P;
+      const int64_t b0 = uniform64(g * a.chunk);
+      const int64_t end = uniform64(b0 + a.chunk < a.P ? b0 + a.chunk : a.P);
       for (int64_t p = b0; p < end; ++p) PointSolver<NS, NQ, COUPLED, KM>::solve(a, p, S, [&] { wq.settle(); });
     }
   } else {

@@ -179,6 +179,13 @@ __device__ __forceinline__ void half_sums_reg(const double (&v)[2 * K], double (
 
 __device__ __forceinline__ bool wave_any(bool b) { return __builtin_amdgcn_ballot_w64(b) != 0; }
 
+// a wave-uniform 64-bit integer held in scalar registers
+__device__ __forceinline__ int64_t uniform64(int64_t v) {
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)v >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
 // Opaque copies: values derived from these are recomputed where they are
 // used instead of being hoisted out of the outer loop (hoisted invariants
 // end up spilled, which costs far more than recomputing them).
@@ -356,24 +363,30 @@ __device__ __forceinline__ void load_model(const DevModel* __restrict__ md, cons
 
 // Work queue of the persistent kernels: up to kQueues counters, each on its
 // own 256-byte line, one per class of work-group ids (id mod nq: one per XCD
-// when work-groups are dealt round-robin to the 8 XCDs).  Counter c hands out
-// chunk indices c, c + nq, c + 2 nq, ..., so every queue sees the same mix of
-// cheap and expensive points.  Every work-group loops until its queue is
-// exhausted, so the grid drains before the kernel ends.
+// when work-groups are dealt round-robin to the 8 XCDs).  The chunk indices
+// are cut into blocks of kQueueRun * nq; counter c hands out, in every block,
+// the run of kQueueRun consecutive chunks at offset c * kQueueRun, so every
+// queue sees the same mix of cheap and expensive points while the per-point
+// scalar inputs and outputs of a run share cache lines within one XCD.  The
+// chunks past the last whole block are dealt round-robin (c, c + nq, ...).
+// Every work-group loops until its queue is exhausted, so the grid drains
+// before the kernel ends.
 constexpr int kQueues = 8;
 constexpr int kQueueStride = 64;  // ints
+constexpr int kQueueRun = 32;     // chunks
 
 struct WorkQueue {
   int* ctr;
-  int64_t nchunks;
+  int64_t nchunks, full;  // chunks; tickets per counter inside whole blocks
   int nq, c;
-  int pend;  // lane 0: counter value returned by the grab in flight
-  int cur;   // counter value of the next chunk (uniform)
+  int pend;  // lane 0: ticket returned by the grab in flight
+  int cur;   // ticket of the next chunk (uniform)
   __device__ __forceinline__ WorkQueue(int* queue, int64_t P, int chunk) {
     nq = gridDim.x < kQueues ? (int)gridDim.x : kQueues;
     c = blockIdx.x % nq;
     ctr = queue + c * kQueueStride;
     nchunks = (P + chunk - 1) / chunk;
+    full = nchunks / ((int64_t)kQueueRun * nq) * kQueueRun;
     pend = 0;
     if (threadIdx.x == 0) pend = atomicAdd(ctr, 1);
     cur = __builtin_amdgcn_readfirstlane(pend);
@@ -381,7 +394,9 @@ struct WorkQueue {
   // next chunk index of this work-group (uniform), or -1 once drained; the
   // following grab is issued here and must be settled before the next call
   __device__ __forceinline__ int64_t next() {
-    const int64_t g = (int64_t)cur * nq + c;
+    const int64_t t = cur;
+    const int64_t g = t < full ? (t / kQueueRun) * kQueueRun * nq + (int64_t)c * kQueueRun + t % kQueueRun
+                               : full * nq + (t - full) * nq + c;
     if (g >= nchunks) return -1;
     if (threadIdx.x == 0) pend = atomicAdd(ctr, 1);
     return g;
