@@ -260,7 +260,9 @@ def main():
             "kernel_store": args.kernel_store,
             "anderson_memory": params.m_inner, "launch": {"chunk": launch.chunk,
                                                           "blocks_per_cu": launch.blocks_per_cu,
-                                                          "persistent": launch.persistent},
+                                                          "persistent": launch.persistent,
+                                                          "autotune_key": AT.cache_key(model),
+                                                          "from_cache": AT.cache_key(model) in AT.cache()},
             "iterations": {"inner_min": int(n_in[n_out > 0].min()), "inner_median": float(np.median(n_in[n_out > 0])),
                            "inner_max": int(n_in.max()), "outer_max": int(n_out.max())},
             "status_counts": np.bincount(status.ravel(), minlength=5).tolist(),

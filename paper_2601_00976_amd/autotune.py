@@ -24,13 +24,18 @@ CACHE = os.path.join(HERE, "autotune_cache.json")
 ROOT = os.path.dirname(HERE)
 
 
-def _key(model) -> str:
+def cache_key(model) -> str:
+    """Cache key: problem shape and device (ISA name and compute-unit count;
+    the marketing name is not stable across tools and driver packages)."""
     import torch
-    name = torch.cuda.get_device_name(0) if torch.cuda.is_available() else "cpu"
-    return f"nq{model.nq}-ns{model.ns}-{name}"
+    if not torch.cuda.is_available():
+        return f"nq{model.nq}-ns{model.ns}-cpu"
+    prop = torch.cuda.get_device_properties(0)
+    arch = getattr(prop, "gcnArchName", "unknown").split(":")[0]
+    return f"nq{model.nq}-ns{model.ns}-{arch}-{prop.multi_processor_count}cu"
 
 
-def _load():
+def cache():
     if os.path.exists(CACHE):
         with open(CACHE) as f:
             return json.load(f)
@@ -38,7 +43,7 @@ def _load():
 
 
 def best_launch(model, P: int) -> S.LaunchConfig:
-    ent = _load().get(_key(model))
+    ent = cache().get(cache_key(model))
     if ent:
         return S.LaunchConfig(**ent["launch"])
     return S.LaunchConfig(blocks_per_cu=0, chunk=4, persistent=True)
@@ -92,12 +97,13 @@ def tune(model, params, dtau, D0, I0, rho11, ye0, e0, theta, repeats: int = 5, w
     results = sorted(zip(best_ms, cands), key=lambda r: r[0])
     best = results[0][1]
     if write:
-        cache = _load()
-        cache[_key(model)] = {"launch": {"blocks_per_cu": best.blocks_per_cu, "chunk": best.chunk,
-                                         "persistent": bool(best.persistent), "kernel_store": best.kernel_store},
-                              "ms": results[0][0], "P": P}
+        entries = cache()
+        entries[cache_key(model)] = {"launch": {"blocks_per_cu": best.blocks_per_cu, "chunk": best.chunk,
+                                                "persistent": bool(best.persistent),
+                                                "kernel_store": best.kernel_store},
+                                     "ms": results[0][0], "P": P}
         with open(CACHE, "w") as f:
-            json.dump(cache, f, indent=1, sort_keys=True)
+            json.dump(entries, f, indent=1, sort_keys=True)
     return results
 
 

@@ -122,8 +122,11 @@ def test_profile_sample_and_skip():
     assert np.array_equal(got["I"][skip], got["I0"][skip])
 
 
+# persistent chunk=1 over 1037 points: whole blocks of 32-chunk runs per
+# queue plus a round-robin tail
 @pytest.mark.parametrize("launch", [S.LaunchConfig(persistent=False, chunk=1),
                                     S.LaunchConfig(persistent=True, chunk=3, blocks_per_cu=1),
+                                    S.LaunchConfig(persistent=True, chunk=1, blocks_per_cu=2),
                                     S.LaunchConfig(persistent=False, chunk=7)])
 def test_ragged_launches_bitwise(launch):
     _say(f"ragged launch {launch}")
