@@ -30,7 +30,8 @@ NS = 3
 STEPS_PER_GRAPH = 10
 # name: (energy elements, points, workload id of the draws, traffic tag, kernel label)
 WORKLOADS = {
-    "profile32": (16, 1 << 16, 3, "fwd_kernel_nq32_ns3", "fwd_kernel<3,32> (persistent point solve)"),
+    "profile32": (16, 1 << 16, 3, "fwd_pair_kernel_nq32_ns3",
+                  "fwd_pair_kernel<3> (persistent point solve, two points per wavefront)"),
     "profile64": (32, 1 << 18, 4, "fwd64_kernel_nq64_ns3", "fwd64_kernel<3> (persistent point solve, 64 nodes)"),
 }
 NQ, P_POINTS = 32, 1 << 16  # headline workload
@@ -128,9 +129,11 @@ def main():
     ap.add_argument("--blocks-per-cu", type=int, default=None)
     ap.add_argument("--workload", choices=sorted(WORKLOADS), default="profile32",
                     help="profile32: the headline (2^16 points, 32 nodes); profile64: 2^18 points, 64 nodes")
-    ap.add_argument("--kernel-store", choices=("chip", "regen", "registers", "hbm"), default="chip",
-                    help="chip: library default (regen); regen: kernel entries regenerated every inner iteration; "
-                         "registers (32 nodes): rows held in VGPRs; hbm (64 nodes): kernels precomputed in HBM")
+    ap.add_argument("--kernel-store", choices=("chip", "wave", "regen", "registers", "hbm"), default="chip",
+                    help="chip: library default (32 nodes: two points per wavefront); wave (32 nodes): one point "
+                         "per wavefront, pair factors in VGPRs; regen: kernel entries regenerated every inner "
+                         "iteration; registers (32 nodes): rows held in VGPRs; hbm (64 nodes): kernels precomputed "
+                         "in HBM")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the per-point solve needs no communication, and this "
@@ -164,12 +167,20 @@ def main():
         launch.blocks_per_cu = args.blocks_per_cu
     hbm_store = args.kernel_store == "hbm"
     if args.kernel_store == "regen":
+        assert nq == 32, "--kernel-store regen is the 64-node default; it is a mode of the 32-node solve"
         launch.kernel_store = 2
+        traffic_tag = "fwd_kernel_nq32_ns3_regen"
+        kernel_label = "fwd_kernel<3,32> (one point per wavefront, kernel entries regenerated)"
     if args.kernel_store == "registers":
         assert nq == 32, "--kernel-store registers needs --workload profile32"
         launch.kernel_store = 3
-        traffic_tag += "_registers"
-        kernel_label = "fwd_kernel<3,32> (kernel rows held in VGPRs, DPP contraction)"
+        traffic_tag = "fwd_kernel_nq32_ns3_registers"
+        kernel_label = "fwd_kernel<3,32> (one point per wavefront, kernel rows held in VGPRs, DPP contraction)"
+    if args.kernel_store == "wave":
+        assert nq == 32, "--kernel-store wave needs --workload profile32"
+        launch.kernel_store = 5
+        traffic_tag = "fwd_kernel_nq32_ns3"
+        kernel_label = "fwd_kernel<3,32> (one point per wavefront, pair factors in VGPRs)"
     if hbm_store:
         assert nq == 64, "--kernel-store hbm needs --workload profile64"
         launch.kernel_store = 1

@@ -156,11 +156,9 @@ typedef struct {
   int kernel_store;    /* NMC_KERNELS_ON_CHIP or NMC_KERNELS_HBM (see below) */
 } nmc_launch;
 
-/* Where the energy-coupling kernel matrices live during a solve.
- * ON_CHIP: the library's default.  32 nodes: the kernel entries are
- *   regenerated in every inner iteration from per-node factors and the
- *   lane's pair factors exp(-|e - e'| / (2T)) computed once per outer
- *   iteration (kept in VGPRs); 64 nodes: as REGEN.
+/* Where the energy-coupling kernel matrices live during a solve, and how
+ * the 32-node solve maps points to wavefronts.
+ * ON_CHIP: the library's default.  32 nodes: as PAIRED; 64 nodes: as REGEN.
  * HBM: 64-node solve only, for the roofline study of precomputed kernels:
  *   Phi_in, Phi_out and Phi_ann of every point are written to the workspace
  *   once per outer iteration and re-read by every inner iteration; the
@@ -176,6 +174,16 @@ typedef struct {
  * iteration (LDS tile) and held in VGPRs; the inner iterations contract them
  * with DPP row broadcasts. */
 #define NMC_KERNELS_REGISTERS 3
+/* PAIRED: 32 nodes only: two points per wavefront, one per half; each lane
+ * owns one node of its point (both moments) and contracts all 32 columns of
+ * its row, the columns broadcast from registers (DPP); the lane's pair
+ * factors exp(-|e - e'| / (2T)) are computed once per outer iteration and
+ * kept in VGPRs. */
+#define NMC_KERNELS_PAIRED 4
+/* WAVE: 32 nodes only: one point per wavefront, the two lane halves owning
+ * the number and flux moments and splitting the 32 columns; the lane's 16
+ * pair factors are computed once per outer iteration and kept in VGPRs. */
+#define NMC_KERNELS_WAVE 5
 
 /* Defaults of the descriptors above (values in parentheses). */
 void nmc_model_desc_default(nmc_model_desc* desc);

@@ -54,7 +54,7 @@ def candidates(model=None, persistent_only=True):
     work-queue kernel, so by default only persistent shapes are tuned (one
     work-group per chunk, the hardware dispatcher acting as the queue, is
     available through LaunchConfig(persistent=False))."""
-    stores = (0, 2, 3) if model is None or model.nq == 32 else (0,)
+    stores = (0, 5, 2, 3) if model is None or model.nq == 32 else (0,)
     for store in stores:
         for persistent in ((True,) if persistent_only else (True, False)):
             for chunk in (1, 2, 4, 8):

@@ -171,7 +171,7 @@ struct PointAdjoint {
       const double eq = S.m.eps[q], Gq = S.E.G[q];
       const double b = S.tb[q * ST + p], b2 = b * b, b3 = b2 * b;
       const double fin = p > q ? b : b3, fout = q > p ? b : b3;
-      const double fpro = q > p ? Gq : Gp;
+      const double fpro = fmin(Gq, Gp);  // G of the higher node: G falls with energy
       const double nq = -dwn * eq, pq = dwp * eq;
       // row (s, q), column (sp, p): NES if s = sp, pair if s is sp's partner
       auto nes = [&](double d) { return nq * __builtin_fma(d, fout - fin, fin); };
@@ -278,7 +278,7 @@ struct PointAdjoint {
       const double b = S.tb[q * ST + p], b2 = b * b, b3 = b2 * b;
       const bool up = p > q;
       const double tin = we * (up ? b : b3), tout = we * (up ? b3 : b);
-      const double tann = we * b2, tpro = we * (up ? S.E.G[p] : Gq);
+      const double tann = we * b2, tpro = we * fmin(S.E.G[p], Gq);
 #pragma unroll
       for (int g = 0; g < NG; ++g) {
         const double d = S.D[sg[g]][p], db = S.D[sbg[g]][p];

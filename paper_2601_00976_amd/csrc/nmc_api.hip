@@ -309,11 +309,13 @@ int nmc_solve_batch(const nmc_model* m, const nmc_solver_params* prm, int64_t P,
   if (launch) L = *launch;
   if (L.chunk < 1 || L.chunk > 4096 || L.blocks_per_cu < 0 || L.blocks_per_cu > 64)
     return fail(NMC_E_INVALID_ARG, "solve_batch: bad launch configuration");
-  if (L.kernel_store < NMC_KERNELS_ON_CHIP || L.kernel_store > NMC_KERNELS_REGISTERS)
+  if (L.kernel_store < NMC_KERNELS_ON_CHIP || L.kernel_store > NMC_KERNELS_WAVE)
     return fail(NMC_E_INVALID_ARG, "solve_batch: bad kernel_store %d", L.kernel_store);
   double* kstore = nullptr;
   if (L.kernel_store == NMC_KERNELS_REGISTERS && m->host.nq != 32)
     return fail(NMC_E_UNSUPPORTED, "solve_batch: register-resident kernel rows need 32 nodes");
+  if ((L.kernel_store == NMC_KERNELS_PAIRED || L.kernel_store == NMC_KERNELS_WAVE) && m->host.nq != 32)
+    return fail(NMC_E_UNSUPPORTED, "solve_batch: kernel_store %d needs 32 nodes", L.kernel_store);
   if (L.kernel_store == NMC_KERNELS_HBM) {
     if (m->host.nq != 64 || !(m->host.flags & (NMC_NES | NMC_PAIR)))
       return fail(NMC_E_UNSUPPORTED, "solve_batch: kernels in HBM need 64 nodes and NES or pair physics");

@@ -1,5 +1,7 @@
-// Forward kernel of the implicit neutrino-matter coupling solve on CDNA4,
-// 32 energy nodes.
+// Forward kernels of the implicit neutrino-matter coupling solve on CDNA4,
+// 32 energy nodes, one point per wavefront (kernel_store WAVE, REGEN,
+// REGISTERS; the default is the two-points-per-wave kernel of
+// nmc_forward_pair.hip, dispatched from launch_forward below).
 //
 // One 64-lane wavefront solves one spatial point at a time (Algorithm
 // neutrinoMatterCoupling, Sec. 3.5.3); spatial points are independent because
@@ -10,7 +12,7 @@
 //   h = 1 ("flux lanes"):   own the flux moments I_s[q].
 // Both halves of row q cooperate on the energy-coupling rates of node q
 // (Eqs. nesRatesNodal, pairRatesNodal), in one of three modes (KM):
-//   KM = 2 (default) / 1: the two halves take columns 0..15 / 16..31 of the
+//   KM = 2 (WAVE) / 1 (REGEN): the two halves take columns 0..15 / 16..31 of the
 //     four kernel matrices, regenerate the entries from per-node exponent
 //     splits (KM = 2 keeps the lane's pair factors b in VGPRs across the inner
 //     loop) without their common factor A e_q e_j, contract them against
@@ -107,7 +109,9 @@ struct PointSolver {
         // broadcast vectors X, Y and A e_q is applied to the row sums
         const double b2 = b * b, b3 = b2 * b;
         const double fin = up ? b : b3, fout = up ? b3 : b;
-        const double fann = b2, fpro = up ? Gj : Gq;
+        // G of the higher node of the pair is the smaller one (G falls with
+        // energy and the nodes are in increasing energy)
+        const double fann = b2, fpro = fmin(Gj, Gq);
         double x[NS], y[NS];
 #pragma unroll
         for (int t = 0; t < NS; ++t) {
@@ -693,6 +697,8 @@ hipError_t launch_reset_counter(int* counter, hipStream_t s) {
 hipError_t launch_forward(const FwdArgs& a, int nq, int ns, bool coupled, const nmc_launch& L, int num_cu,
                           hipStream_t s) {
   if (nq == 32) {
+    if (L.kernel_store == NMC_KERNELS_ON_CHIP || L.kernel_store == NMC_KERNELS_PAIRED)
+      return launch_forward_pair(a, ns, coupled, L, num_cu, s);
     if (coupled && L.kernel_store == NMC_KERNELS_REGEN) {
       switch (ns) {
         case 1: return launch_fwd_t<1, 32, true, 1>(a, L, num_cu, s);

@@ -98,7 +98,7 @@ struct PointSolver64 {
     fin = up ? b : b3;
     fout = up ? b3 : b;
     fann = b2;
-    fpro = up ? Gj : r.Gq;
+    fpro = fmin(Gj, r.Gq);  // G of the higher node: G falls with energy
   }
   __device__ __forceinline__ static void accumulate(const Lds64<NS>& S, int j, double fin, double fout, double fann,
                                                     double fpro, double (&etaN)[NS], double (&outN)[NS],
@@ -136,7 +136,7 @@ struct PointSolver64 {
         fin = kst[j * NQ + q];
         fout = kst[(NQ + j) * NQ + q];
         fann = kst[(2 * NQ + j) * NQ + q];
-        fpro = j > q ? S.colGE[j][0] : r.Gq;
+        fpro = fmin(S.colGE[j][0], r.Gq);
       } else {
         entries(S, r, q, j, fin, fout, fann, fpro);
       }

@@ -1,0 +1,610 @@
+// Forward kernel of the implicit coupling solve for 32 energy nodes, two
+// points per wavefront (CDNA4).
+//
+// Same algorithm as the one-point kernels (Algorithm neutrinoMatterCoupling,
+// Sec. 3.5.3), different work decomposition.  Lane = 32 h + q: half h of the
+// wave solves point 2u + h of pair u, and lane q of the half owns D_s[q] and
+// I_s[q] of every species.  Every per-point step that a one-point kernel
+// issues for a whole wave (equation of state, opacities, Anderson solves,
+// convergence tests, matter update) serves two points here, and each lane
+// contracts all 32 columns of its row:
+//   - once per outer iteration a lane forms Phi_in[q][j] and Phi_out[q][j]
+//     for j = 0..31 (without their common factor A e_q e_j) from the
+//     exponent splits of its point's temperature and keeps them in VGPRs;
+//   - in every inner iteration the vectors W e D and W e (1 - D) of the point
+//     are redistributed with v_permlane16_swap, so that each 16-lane row
+//     holds one half of its point's vector, and every FMA takes its column
+//     through a DPP row_newbcast operand (v_fmac_f64_dpp): the contraction
+//     reads no LDS;
+//   - per column, Phi_ann = max(Phi_in, Phi_out)^2 (b <= 1, so b is the
+//     larger of b and b^3) and Phi_pro = min(G_j, G_q) (G falls with energy).
+// The row sums are scaled by A e_q once per inner iteration.
+//
+// Both halves run one instruction stream.  A half whose point has finished
+// (or which has no point, past the end of an odd batch) keeps computing with
+// its state frozen, so no barrier or cross-lane step is ever in divergent
+// control flow; every per-point decision is a per-lane value that is uniform
+// within its half.
+#include "nmc_wave.h"
+
+namespace nmc {
+namespace {
+
+constexpr int NQP = 32;
+
+template <int NS>
+struct PairLds {
+  ModelLds m;
+  SplitExp E[2];                   // per point: exponent splits at its current temperature
+  double hist[4][2 * NS][kLanes];  // Anderson history per lane and owned moment: Q_prev, F_prev, dQ_old, dF_old
+  struct Pt {                      // per-point state of the outer (matter) loop
+    double dref[NS];               // ||D_s^[k,1]||_W^2 of the current inner loop
+    double y[2], oq[2], of[2], odq[2], odf[2];
+    double T_last, r3, K, An, Ap;
+    double ye_st, e_st, chi0, T_fix, mu_fix;
+  } pt[2];
+};
+
+// Sums over the lane's half-wave of 2K values, in every lane of the half:
+// rows (0, 2) carry slot k, rows (1, 3) slot K + k, then a row butterfly and
+// a row swap.  The K chains advance stage by stage.  Fixed order.
+template <int K>
+__device__ __forceinline__ void half_own_sums(const double (&v)[2 * K], double (&s)[2 * K]) {
+  double r[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) r[k] = halve16(v[k], v[K + k]);
+#pragma unroll
+  for (int k = 0; k < K; ++k) r[k] += dpp<0xB1>(r[k]);   // quad_perm [1,0,3,2]
+#pragma unroll
+  for (int k = 0; k < K; ++k) r[k] += dpp<0x4E>(r[k]);   // quad_perm [2,3,0,1]
+#pragma unroll
+  for (int k = 0; k < K; ++k) r[k] += dpp<0x141>(r[k]);  // row_half_mirror
+#pragma unroll
+  for (int k = 0; k < K; ++k) r[k] += dpp<0x140>(r[k]);  // row_mirror
+#pragma unroll
+  for (int k = 0; k < K; ++k) swap16(r[k], s[k], s[K + k]);
+}
+
+// any lane of this lane's half
+__device__ __forceinline__ bool half_any(bool b) {
+  const uint64_t m = __builtin_amdgcn_ballot_w64(b);
+  return ((threadIdx.x >> 5) ? (m >> 32) : (m & 0xffffffffull)) != 0;
+}
+
+// One column of the rate contraction: the moment vectors' column L of each
+// 16-lane row is broadcast into the FMAs (v_fmac_f64_dpp row_newbcast:L, the
+// DPP operand being src0).  eN += Phi_in x_s, oN += Phi_out y_s,
+// aP += Phi_ann x_sbar, eP += Phi_pro y_sbar.  The leading s_nop covers the
+// VALU-write to DPP-read distance for registers written just before.
+template <int NS>
+struct ColFmac;
+
+template <>
+struct ColFmac<3> {
+  template <int L>
+  __device__ __forceinline__ static void run(double (&eN)[3], double (&oN)[3], double (&aP)[3], double (&eP)[3],
+                                             const double (&x)[3], const double (&y)[3], double fi, double fo,
+                                             double fa, double fp) {
+    asm volatile(
+        "s_nop 1\n"
+        "v_fmac_f64_dpp %0, %12, %18 row_newbcast:%22 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %1, %13, %18 row_newbcast:%22 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %2, %14, %18 row_newbcast:%22 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %3, %15, %19 row_newbcast:%22 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %4, %16, %19 row_newbcast:%22 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %5, %17, %19 row_newbcast:%22 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %6, %13, %20 row_newbcast:%22 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %7, %12, %20 row_newbcast:%22 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %8, %14, %20 row_newbcast:%22 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %9, %16, %21 row_newbcast:%22 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %10, %15, %21 row_newbcast:%22 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %11, %17, %21 row_newbcast:%22 row_mask:0xf bank_mask:0xf\n"
+        : "+v"(eN[0]), "+v"(eN[1]), "+v"(eN[2]), "+v"(oN[0]), "+v"(oN[1]), "+v"(oN[2]), "+v"(aP[0]), "+v"(aP[1]),
+          "+v"(aP[2]), "+v"(eP[0]), "+v"(eP[1]), "+v"(eP[2])
+        : "v"(x[0]), "v"(x[1]), "v"(x[2]), "v"(y[0]), "v"(y[1]), "v"(y[2]), "v"(fi), "v"(fo), "v"(fa), "v"(fp),
+          "i"(L));
+  }
+};
+
+template <>
+struct ColFmac<2> {
+  template <int L>
+  __device__ __forceinline__ static void run(double (&eN)[2], double (&oN)[2], double (&aP)[2], double (&eP)[2],
+                                             const double (&x)[2], const double (&y)[2], double fi, double fo,
+                                             double fa, double fp) {
+    asm volatile(
+        "s_nop 1\n"
+        "v_fmac_f64_dpp %0, %8, %12 row_newbcast:%16 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %1, %9, %12 row_newbcast:%16 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %2, %10, %13 row_newbcast:%16 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %3, %11, %13 row_newbcast:%16 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %4, %9, %14 row_newbcast:%16 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %5, %8, %14 row_newbcast:%16 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %6, %11, %15 row_newbcast:%16 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %7, %10, %15 row_newbcast:%16 row_mask:0xf bank_mask:0xf\n"
+        : "+v"(eN[0]), "+v"(eN[1]), "+v"(oN[0]), "+v"(oN[1]), "+v"(aP[0]), "+v"(aP[1]), "+v"(eP[0]), "+v"(eP[1])
+        : "v"(x[0]), "v"(x[1]), "v"(y[0]), "v"(y[1]), "v"(fi), "v"(fo), "v"(fa), "v"(fp), "i"(L));
+  }
+};
+
+template <>
+struct ColFmac<1> {
+  template <int L>
+  __device__ __forceinline__ static void run(double (&eN)[1], double (&oN)[1], double (&aP)[1], double (&eP)[1],
+                                             const double (&x)[1], const double (&y)[1], double fi, double fo,
+                                             double fa, double fp) {
+    asm volatile(
+        "s_nop 1\n"
+        "v_fmac_f64_dpp %0, %4, %6 row_newbcast:%10 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %1, %5, %7 row_newbcast:%10 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %2, %4, %8 row_newbcast:%10 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %3, %5, %9 row_newbcast:%10 row_mask:0xf bank_mask:0xf\n"
+        : "+v"(eN[0]), "+v"(oN[0]), "+v"(aP[0]), "+v"(eP[0])
+        : "v"(x[0]), "v"(y[0]), "v"(fi), "v"(fo), "v"(fa), "v"(fp), "i"(L));
+  }
+};
+
+template <int NS, bool COUPLED>
+struct PairSolver {
+  static constexpr int NQ = NQP;
+  static constexpr int KC = (3 * NS + 1) / 2;  // reduction chains of the convergence test
+
+  // settle() is called once the pair's inputs are loaded (work-queue hook)
+  template <class Settle>
+  __device__ static void solve(const FwdArgs& a, int64_t u, PairLds<NS>& S, Settle&& settle) {
+    const_ptr<DevModel> md = scalar_ptr(a.mdl);
+    const ModelLds& mt = S.m;
+    const int lane = threadIdx.x;
+    const int h = lane >> 5, q0 = lane & 31;
+    const double dtau = a.dtau;
+    // point of this half; past the end of an odd batch the half mirrors its
+    // neighbour and stores nothing
+    const int64_t p_raw = 2 * u + h;
+    const bool has_point = p_raw < a.P;
+    const int64_t p = has_point ? p_raw : p_raw - 1;
+    const int64_t base = p * (int64_t)(NS * NQ);
+    const double rho = a.rho11[p];
+    const bool fixedT = a.prm.fixed_matter && a.T_fixed;
+    typename PairLds<NS>::Pt& pt = S.pt[h];
+
+    double Dst[NS], Ist[NS], D[NS], I[NS];
+#pragma unroll
+    for (int t = 0; t < NS; ++t) {
+      const int64_t o = base + md->ext[t] * NQ + q0;
+      Dst[t] = D[t] = a.D0[o];
+      Ist[t] = I[t] = a.I0[o];
+    }
+    settle();
+
+    // coupling disabled at low density (Sec. 7.2): the state passes through
+    const bool skip = rho < md->rho11_min;
+
+    pt.r3 = cbrt(rho);
+    pt.K = md->kcoup / rho;
+    pt.An = (md->flags & NMC_NES) ? mt.theta[NQ] * rho : 0.0;
+    pt.Ap = (md->flags & NMC_PAIR) ? mt.theta[NQ + 1] * rho : 0.0;
+    pt.ye_st = pt.y[0] = a.ye0[p];
+    pt.e_st = pt.y[1] = a.e0[p];
+    pt.chi0 = a.chi0 ? a.chi0[p] : md->chi_ref * rho;
+    if (fixedT) pt.T_fix = a.T_fixed[p];
+    if (a.prm.fixed_matter && a.mu_fixed) pt.mu_fix = a.mu_fixed[p];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) pt.oq[i] = pt.of[i] = pt.odq[i] = pt.odf[i] = 0.0;
+    pt.T_last = 0.0;
+    {
+      const double w2q = mt.w2[q0];
+      double v[2 * ((NS + 1) / 2)], s[2 * ((NS + 1) / 2)];
+#pragma unroll
+      for (int t = 0; t < 2 * ((NS + 1) / 2); ++t) v[t] = t < NS ? w2q * D[t < NS ? t : 0] * D[t < NS ? t : 0] : 0.0;
+      half_own_sums<(NS + 1) / 2>(v, s);
+#pragma unroll
+      for (int t = 0; t < NS; ++t) pt.dref[t] = s[t];
+    }
+
+    int status = NMC_STATUS_OK;
+    bool fatal = false, inner_failed = false, outer_conv = false;
+    bool run = !skip;  // this half's point is still iterating the outer loop
+    int k_done = 0, total_inner = 0;
+
+    for (int k = 1; k <= a.prm.max_outer && __builtin_amdgcn_ballot_w64(run) != 0; ++k) {
+      const_ptr<DevModel> md = scalar_ptr(a.mdl);
+      const int q = opaque(q0);
+      if (run) k_done = k;
+      // ---- ComputeOpacities(y^[k]) --------------------------------------
+      const double r3 = pt.r3;
+      const double y0 = pt.y[0], y1 = pt.y[1];
+      const double T = fixedT ? pt.T_fix : (y1 - md->eos_b * ye43(y0) * r3) / (md->eos_a * (1.0 + y0));
+      const double mu = (a.prm.fixed_matter && a.mu_fixed)
+                            ? pt.mu_fix
+                            : md->mu_a * (y0 - md->mu_ye0) * r3 + md->mu_b * log(T / md->mu_t0);
+      if (run && (!(T > 0.0) || !(y0 >= 0.0) || !isfinite(T) || !isfinite(mu))) {
+        status = NMC_STATUS_EOS_DOMAIN;
+        fatal = true;
+        run = false;
+      }
+      if (run) pt.T_last = T;
+      // a finished half keeps a harmless temperature
+      const double Tu = run ? T : 1.0, muu = run ? mu : 0.0;
+      const double invT = 1.0 / Tu;
+      double baseD[NS], den0D[NS], den0I[NS];
+      const double epsq = mt.eps[q];
+      {
+        const double shape = pt.chi0 * mt.shape[q];
+        const double sig = (md->flags & NMC_ISO) ? md->sigma_ratio * shape : 0.0;
+        const double emab_q = (md->flags & NMC_EMAB) ? mt.theta[q] * shape : 0.0;
+#pragma unroll
+        for (int t = 0; t < NS; ++t) {
+          const double chia = md->iemab[t] * emab_q;
+          const double x = (epsq - md->imusign[t] * muu) * invT;
+          const double ex = exp(-fabs(x));
+          const double r = rcp_nr(1.0 + ex);
+          const double deq = x > 0.0 ? ex * r : r;
+          baseD[t] = Dst[t] + dtau * (chia * deq);
+          den0D[t] = 1.0 + dtau * chia;
+          den0I[t] = 1.0 + dtau * (chia + sig);
+        }
+      }
+      // pair factors b(q, j) of this lane's row, j = 0..31
+      double B[COUPLED ? NQ : 1];
+      double Gq = 0.0;
+      if constexpr (COUPLED) {
+        SplitExp& E = S.E[h];
+        {
+          const ExpSplit xs = exp_split(epsq, invT);
+          const double R2 = xs.R * xs.R;
+          E.P2[q] = xs.P;
+          E.R2[q] = xs.R;
+          E.n2[q] = xs.n;
+          E.G[q] = ldexp(R2 * R2, -4 * xs.n);  // exp(-2 e / T)
+        }
+        __syncthreads();
+        const double Pq = E.P2[q], Rq = E.R2[q];
+        const int nq = E.n2[q];
+        Gq = E.G[q];
+#pragma unroll
+        for (int j = 0; j < NQ; ++j) {
+          const bool up = j > q;  // q is the lower node of the pair
+          B[j] = ldexp(up ? Pq * E.R2[j] : E.P2[j] * Rq, up ? nq - E.n2[j] : E.n2[j] - nq);
+        }
+      }
+
+      // ---- inner loop over moments at fixed matter ------------------------
+      const double w2q = mt.w2[q], w2eq = w2q * epsq;
+      const double Aeq = pt.An * epsq, Apq = pt.Ap * epsq;
+      double G11 = 0.0;
+      const bool ran = run;  // this half runs this outer iteration
+      bool act = run;        // this half is still iterating the inner loop
+      bool cvd = false;      // this half's inner loop converged
+      int l_done = 0;
+      for (int l = 1; l <= a.prm.max_inner && __builtin_amdgcn_ballot_w64(act) != 0; ++l) {
+        if (act) l_done = l;
+        double etaN[NS], outN[NS], annP[NS], etaP[NS];
+#pragma unroll
+        for (int t = 0; t < NS; ++t) etaN[t] = outN[t] = annP[t] = etaP[t] = 0.0;
+        if constexpr (COUPLED) {
+          // W e D and W e (1 - D) of the point, each 16-lane row holding the
+          // half [16 R, 16 R + 16) of the nodes in XR[.][R], YR[.][R]
+          double XR[2][NS], YR[2][NS];
+          // the pair factors are re-read per iteration: the per-column
+          // products and selects are not hoisted out of the inner loop
+          // (they would need four times the registers)
+#pragma unroll
+          for (int j = 0; j < NQ; ++j) asm volatile("" : "+v"(B[j]));
+#pragma unroll
+          for (int t = 0; t < NS; ++t) {
+            const double xv = w2eq * D[t];
+            swap16(xv, XR[0][t], XR[1][t]);
+            swap16(w2eq - xv, YR[0][t], YR[1][t]);
+          }
+          const double2* __restrict__ G2 = reinterpret_cast<const double2*>(S.E[h].G) + opaque(0);
+          static_for<0, NQ / 2>([&](auto jj) __attribute__((always_inline)) {
+            constexpr int j0 = 2 * decltype(jj)::value;
+            const double2 g = G2[j0 / 2];
+            static_for<0, 2>([&](auto ee) __attribute__((always_inline)) {
+              constexpr int j = j0 + decltype(ee)::value;
+              const double Gj = decltype(ee)::value ? g.y : g.x;
+              const bool up = j > q;
+              const double b = B[j], b2 = b * b, b3 = b2 * b;
+              ColFmac<NS>::template run<j % 16>(etaN, outN, annP, etaP, XR[j / 16], YR[j / 16], up ? b : b3,
+                                                up ? b3 : b, b2, fmin(Gj, Gq));
+            });
+          });
+#pragma unroll
+          for (int t = 0; t < NS; ++t) {
+            etaN[t] *= Aeq;
+            outN[t] *= Aeq;
+            annP[t] *= Apq;
+            etaP[t] *= Apq;
+          }
+        }
+        // Q and residual of both owned moments x = (D_t, I_t)
+        double Qx[2 * NS], Fx[2 * NS];
+#pragma unroll
+        for (int t = 0; t < NS; ++t) {
+          const double eta = etaN[t] + etaP[t];
+          const double chi = (etaN[t] + outN[t]) + (etaP[t] + annP[t]);
+          Qx[t] = __builtin_fma(dtau, eta, baseD[t]) * rcp_nr(__builtin_fma(dtau, chi, den0D[t]));
+          Qx[NS + t] = Ist[t] * rcp_nr(__builtin_fma(dtau, chi, den0I[t]));
+          Fx[t] = Qx[t] - D[t];
+          Fx[NS + t] = Qx[NS + t] - I[t];
+        }
+        // Anderson step over min(l, M_inner) residuals (difference form)
+        const int mem = l < a.prm.m_inner ? l : a.prm.m_inner;
+        double Xn[2 * NS];
+        if (mem == 1) {
+#pragma unroll
+          for (int x = 0; x < 2 * NS; ++x) Xn[x] = Qx[x];
+        } else {
+          const double use1 = (mem == 3) ? 1.0 : 0.0;
+          double dQ2[2 * NS], dF2[2 * NS];
+          double v4[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+          for (int x = 0; x < 2 * NS; ++x) {
+            dQ2[x] = Qx[x] - S.hist[0][x][lane];
+            dF2[x] = Fx[x] - S.hist[1][x][lane];
+            const double dF1 = use1 * S.hist[3][x][lane];
+            v4[0] += dF1 * dF2[x];
+            v4[1] += dF2[x] * dF2[x];
+            v4[2] += dF1 * Fx[x];
+            v4[3] += dF2[x] * Fx[x];
+          }
+          double gs[4];
+          half_own_sums<2>(v4, gs);
+          double g1, g2;
+          anderson2(mem == 3, G11, gs[0], gs[1], gs[2], gs[3], g1, g2);
+#pragma unroll
+          for (int x = 0; x < 2 * NS; ++x) {
+            Xn[x] = Qx[x] - g2 * dQ2[x] - g1 * S.hist[2][x][lane];
+            S.hist[2][x][lane] = dQ2[x];
+            S.hist[3][x][lane] = dF2[x];
+          }
+          G11 = gs[1];
+        }
+#pragma unroll
+        for (int x = 0; x < 2 * NS; ++x) {
+          S.hist[0][x][lane] = Qx[x];
+          S.hist[1][x][lane] = Fx[x];
+        }
+        bool bad = false;
+#pragma unroll
+        for (int x = 0; x < 2 * NS; ++x) bad |= !isfinite(Xn[x]);
+        if (half_any(bad) && act) {
+          status = NMC_STATUS_NONFINITE;
+          fatal = true;
+          act = run = false;
+        }
+        // Algorithm innerConverged (weighted per species, reference guarded
+        // by the new norm), compared squared
+        {
+          double v[2 * KC], s[2 * KC];
+#pragma unroll
+          for (int t = 0; t < NS; ++t) {
+            const double dd = Xn[t] - D[t], di = Xn[NS + t] - I[t];
+            v[t] = w2q * dd * dd;
+            v[NS + t] = w2q * di * di;
+            v[2 * NS + t] = w2q * Xn[t] * Xn[t];
+          }
+#pragma unroll
+          for (int i = 3 * NS; i < 2 * KC; ++i) v[i] = 0.0;
+          half_own_sums<KC>(v, s);
+          bool conv = true;
+#pragma unroll
+          for (int t = 0; t < NS; ++t) {
+            const double dm2 = s[t] > s[NS + t] ? s[t] : s[NS + t];
+            const double d0 = pt.dref[t], dn2 = s[2 * NS + t];
+            const double dref2 = d0 > dn2 ? d0 : dn2;
+            if (!(dm2 <= a.tol_inner2 * dref2)) conv = false;
+          }
+          if (act && conv) {
+            // ||D^[k,*]|| is the reference of the next inner loop
+#pragma unroll
+            for (int t = 0; t < NS; ++t) pt.dref[t] = s[2 * NS + t];
+          }
+          if (act) {
+#pragma unroll
+            for (int t = 0; t < NS; ++t) {
+              D[t] = Xn[t];
+              I[t] = Xn[NS + t];
+            }
+            if (conv) {
+              cvd = true;
+              act = false;
+            }
+          }
+        }
+      }
+      if (ran) total_inner += l_done;
+      if (run && !cvd) inner_failed = true;
+      {
+        // reference for the next loop after a failed inner loop: the norm of
+        // the current moments (uniform steps, applied where needed)
+        double v[2 * ((NS + 1) / 2)], s[2 * ((NS + 1) / 2)];
+#pragma unroll
+        for (int t = 0; t < 2 * ((NS + 1) / 2); ++t) v[t] = t < NS ? w2q * D[t < NS ? t : 0] * D[t < NS ? t : 0] : 0.0;
+        half_own_sums<(NS + 1) / 2>(v, s);
+        if (run && !cvd) {
+#pragma unroll
+          for (int t = 0; t < NS; ++t) pt.dref[t] = s[t];
+        }
+      }
+      if (a.prm.fixed_matter) {
+        if (run) outer_conv = true;
+        run = false;
+      }
+
+      // ---- matter right-hand side (Eq. implicitFluidNodal at v = 0) -------
+      double yq0, yq1;
+      {
+        const double w3 = mt.w3[q];
+        double mv[2] = {0.0, 0.0}, s[2];
+#pragma unroll
+        for (int t = 0; t < NS; ++t) {
+          const double dd = D[t] - Dst[t];
+          mv[0] += md->ig[t] * w2q * dd;
+          mv[1] += md->imult[t] * w3 * dd;
+        }
+        half_own_sums<1>(mv, s);
+        yq0 = pt.ye_st - pt.K * s[0];
+        yq1 = pt.e_st - pt.K * s[1];
+      }
+      if (run) {
+        const double f0 = yq0 - pt.y[0], f1 = yq1 - pt.y[1];
+        const int omem = k < a.prm.m_outer ? k : a.prm.m_outer;
+        double yn0, yn1;
+        if (omem == 1) {
+          yn0 = yq0;
+          yn1 = yq1;
+        } else {
+          const double dq20 = yq0 - pt.oq[0], dq21 = yq1 - pt.oq[1];
+          const double df20 = f0 - pt.of[0], df21 = f1 - pt.of[1];
+          const double odf0 = pt.odf[0], odf1 = pt.odf[1];
+          const double G22 = df20 * df20 + df21 * df21, b2 = df20 * f0 + df21 * f1;
+          const double G11o = odf0 * odf0 + odf1 * odf1;
+          const double G12 = odf0 * df20 + odf1 * df21, b1 = odf0 * f0 + odf1 * f1;
+          double g1, g2;
+          anderson2(omem == 3, G11o, G12, G22, b1, b2, g1, g2);
+          yn0 = yq0 - g2 * dq20 - g1 * pt.odq[0];
+          yn1 = yq1 - g2 * dq21 - g1 * pt.odq[1];
+          pt.odq[0] = dq20;
+          pt.odq[1] = dq21;
+          pt.odf[0] = df20;
+          pt.odf[1] = df21;
+        }
+        pt.oq[0] = yq0;
+        pt.oq[1] = yq1;
+        pt.of[0] = f0;
+        pt.of[1] = f1;
+        if (!isfinite(yn0) || !isfinite(yn1)) {
+          status = NMC_STATUS_NONFINITE;
+          fatal = true;
+          run = false;
+        } else {
+          // Algorithm outerConverged: componentwise against y*
+          const bool oc = fabs(yn0 - pt.y[0]) <= a.prm.tol_outer * fabs(pt.ye_st) &&
+                          fabs(yn1 - pt.y[1]) <= a.prm.tol_outer * fabs(pt.e_st);
+          pt.y[0] = yn0;
+          pt.y[1] = yn1;
+          if (oc) {
+            outer_conv = true;
+            run = false;
+          }
+        }
+      }
+    }
+    if (!skip && !fatal) {
+      if (!outer_conv) status = NMC_STATUS_MAX_OUTER;
+      else if (inner_failed) status = NMC_STATUS_MAX_INNER;
+    }
+
+    // ---- outputs --------------------------------------------------------
+    const double ye_st = pt.ye_st, e_st = pt.e_st;
+    double ye_out = ye_st, e_out = e_st, T_out = pt.T_last;
+    {
+      const double w2 = mt.w2[q0], w3 = mt.w3[q0];
+      double mv[2] = {0.0, 0.0}, s[2];
+#pragma unroll
+      for (int t = 0; t < NS; ++t) {
+        const double dd = D[t] - Dst[t];
+        mv[0] += md->ig[t] * w2 * dd;
+        mv[1] += md->imult[t] * w3 * dd;
+      }
+      half_own_sums<1>(mv, s);
+      if (skip) {
+        T_out = fixedT ? pt.T_fix : (e_st - md->eos_b * ye43(ye_st) * pt.r3) / (md->eos_a * (1.0 + ye_st));
+      } else if (!a.prm.fixed_matter) {
+        ye_out = ye_st - pt.K * s[0];
+        e_out = e_st - pt.K * s[1];
+        T_out = (e_out - md->eos_b * ye43(ye_out) * pt.r3) / (md->eos_a * (1.0 + ye_out));
+      } else if (status == NMC_STATUS_EOS_DOMAIN) {
+        T_out = fixedT ? pt.T_fix : (e_st - md->eos_b * ye43(ye_st) * pt.r3) / (md->eos_a * (1.0 + ye_st));
+      }
+    }
+    if (has_point) {
+#pragma unroll
+      for (int t = 0; t < NS; ++t) {
+        const int64_t o = base + md->ext[t] * NQ + q0;
+        a.D[o] = D[t];
+        a.I[o] = I[t];
+      }
+      if (q0 == 0) {
+        a.ye[p] = ye_out;
+        a.e[p] = e_out;
+        a.T[p] = T_out;
+        a.n_outer[p] = skip ? 0 : k_done;
+        a.n_inner[p] = total_inner;
+        a.status[p] = status;
+      }
+    }
+    __syncthreads();
+  }
+};
+
+template <int NS, bool COUPLED>
+__global__ __launch_bounds__(kLanes, 2) void fwd_pair_kernel(FwdArgs a) {
+  __shared__ PairLds<NS> S;
+  load_model(a.mdl, a.theta, S.m);
+  const int64_t pairs = (a.P + 1) / 2;
+  if (a.queue) {
+    WorkQueue wq(a.queue, pairs, a.chunk);
+    for (int64_t g; (g = wq.next()) >= 0;) {
+      const int64_t b0 = uniform64(g * a.chunk);
+      const int64_t end = uniform64(b0 + a.chunk < pairs ? b0 + a.chunk : pairs);
+      for (int64_t u = b0; u < end; ++u) PairSolver<NS, COUPLED>::solve(a, u, S, [&] { wq.settle(); });
+    }
+  } else {
+    const int64_t b0 = (int64_t)blockIdx.x * a.chunk;
+    const int64_t end = b0 + a.chunk < pairs ? b0 + a.chunk : pairs;
+    for (int64_t u = b0; u < end; ++u) PairSolver<NS, COUPLED>::solve(a, u, S, [] {});
+  }
+}
+
+template <int NS, bool COUPLED>
+hipError_t launch_pair_t(const FwdArgs& a, const nmc_launch& L, int num_cu, hipStream_t s) {
+  auto kern = fwd_pair_kernel<NS, COUPLED>;
+  const int64_t pairs = (a.P + 1) / 2;
+  const int64_t need = (pairs + a.chunk - 1) / a.chunk;
+  int64_t grid;
+  if (a.queue) {
+    int bpc = L.blocks_per_cu;
+    if (bpc <= 0) {
+      static int occ = 0;
+      if (occ <= 0) {
+        int o = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, kern, kLanes, 0) != hipSuccess || o <= 0) o = 8;
+        // the query under-reports resident one-wave work-groups; a surplus is
+        // harmless (late work-groups find the queue drained and exit)
+        occ = o < 16 ? 16 : o;
+      }
+      bpc = occ;
+    }
+    grid = (int64_t)bpc * num_cu;
+    if (grid > need) grid = need;
+  } else {
+    grid = need;
+  }
+  if (grid < 1) grid = 1;
+  hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(kLanes), 0, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_forward_pair(const FwdArgs& a, int ns, bool coupled, const nmc_launch& L, int num_cu,
+                               hipStream_t s) {
+  if (coupled) {
+    switch (ns) {
+      case 1: return launch_pair_t<1, true>(a, L, num_cu, s);
+      case 2: return launch_pair_t<2, true>(a, L, num_cu, s);
+      case 3: return launch_pair_t<3, true>(a, L, num_cu, s);
+    }
+  } else {
+    switch (ns) {
+      case 1: return launch_pair_t<1, false>(a, L, num_cu, s);
+      case 2: return launch_pair_t<2, false>(a, L, num_cu, s);
+      case 3: return launch_pair_t<3, false>(a, L, num_cu, s);
+    }
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace nmc

@@ -76,6 +76,8 @@ hipError_t launch_forward(const FwdArgs& a, int nq, int ns, bool coupled, const 
                           hipStream_t s);
 hipError_t launch_forward64(const FwdArgs& a, int ns, bool coupled, const nmc_launch& L, int num_cu,
                             hipStream_t s);
+hipError_t launch_forward_pair(const FwdArgs& a, int ns, bool coupled, const nmc_launch& L, int num_cu,
+                               hipStream_t s);
 hipError_t launch_reset_counter(int* counter, hipStream_t s);
 hipError_t launch_init_state(const DevModel* mdl, int ns, int nq, int64_t P, const double* T, const double* mu,
                              const double* rho11, const double* ye, const double* uD, const double* uI, double a,

@@ -22,7 +22,7 @@ STATUS_OK, STATUS_MAX_OUTER, STATUS_MAX_INNER, STATUS_NONFINITE, STATUS_EOS_DOMA
 NU_E, NU_E_BAR, NU_X = 0, 1, 2
 EMAB, ISO, NES, PAIR = 1, 2, 4, 8
 ALL_PHYSICS = 15
-KERNELS_ON_CHIP, KERNELS_HBM, KERNELS_REGEN, KERNELS_REGISTERS = 0, 1, 2, 3
+KERNELS_ON_CHIP, KERNELS_HBM, KERNELS_REGEN, KERNELS_REGISTERS, KERNELS_PAIRED, KERNELS_WAVE = 0, 1, 2, 3, 4, 5
 SPACING_LOG, SPACING_ZOOM = 0, 1
 
 EXPORTED = (

@@ -8,8 +8,11 @@ Two steps, each run on the GPU machine:
   python3 <repo>/paper_2601_00976_amd/traffic.py summarize <dir>/fetch/run_results.db <dir>/write/run_results.db
 
 `run` launches a plain device-to-device copy of a known size (the
-calibration: it must read and write exactly that many bytes) and the forward
-solve and adjoint on the first step of the 2^16-point radial profile.
+calibration: it must read and write exactly that many bytes), the forward
+solve (default and one-point-per-wave kernels) and the adjoint on the first
+step of the 2^16-point radial profile, and the 64-node solves (kernels on
+chip and in HBM) on the first step of the 2^18-point profile, each at the
+launch shape of the autotune cache.
 `summarize` scales each kernel's per-dispatch counter by copy bytes / copy
 counter and writes profiles/traffic_<kernel>.txt with the source hash of the
 kernels, so that stale measurements are recognised.
@@ -24,7 +27,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 COPY_BYTES = 1 << 28  # 256 MiB calibration copy
 KERNELS = {
-    "fwd_kernel<3, 32, true, 2>": ("fwd_kernel_nq32_ns3", "radial profile, 2^16 points, 32 nodes, step 1"),
+    "fwd_pair_kernel<3, true>": ("fwd_pair_kernel_nq32_ns3", "radial profile, 2^16 points, 32 nodes, step 1"),
+    "fwd_kernel<3, 32, true, 2>": ("fwd_kernel_nq32_ns3", "radial profile, 2^16 points, 32 nodes, step 1, "
+                                   "one point per wavefront"),
     "adj_kernel<3>": ("adj_kernel_nq32_ns3", "radial profile, 2^16 points, 32 nodes, step 1"),
     "fwd64_kernel<3, true, false>": ("fwd64_kernel_nq64_ns3", "radial profile, 2^18 points, 64 nodes, step 1"),
     "fwd64_kernel<3, true, true>": ("fwd64_kernel_nq64_ns3_hbm",
@@ -51,8 +56,15 @@ def run():
     theta = model.default_theta()
     ws = S.Workspace(model, 1 << 16, dev)
     out = S.alloc_outputs(model, 1 << 16, dev)
-    for _ in range(3):
-        S.solve(model, S.Params(), W.DTAU_KM, D0, I0, t["rho11"], t["ye"], e0, theta, out=out, workspace=ws)
+    from paper_2601_00976_amd import autotune as AT
+
+    # the launch shape bench.py times (autotune cache); the one-point-per-wave
+    # kernel once as well
+    for store in (0, 0, 0, 5):
+        L = AT.best_launch(model, 1 << 16)
+        L.kernel_store = store
+        S.solve(model, S.Params(), W.DTAU_KM, D0, I0, t["rho11"], t["ye"], e0, theta, out=out, workspace=ws,
+                launch=L)
     gbar = torch.ones(1 << 16, 2, dtype=torch.float64, device=dev)
     S.adjoint(model, W.DTAU_KM, t["rho11"], theta, out, gbar, workspace=ws)
     torch.cuda.synchronize()
@@ -66,8 +78,10 @@ def run():
     out = S.alloc_outputs(m64, P64, dev)
     ws = S.Workspace(m64, P64, dev, kernel_store=True)
     for store in (0, 1):
+        L = AT.best_launch(m64, P64)
+        L.kernel_store = store
         S.solve(m64, S.Params(), W.DTAU_KM, D0, I0, t["rho11"], t["ye"], e0, th64, out=out, workspace=ws,
-                launch=S.LaunchConfig(kernel_store=store))
+                launch=L)
     torch.cuda.synchronize()
     print("traffic run done", flush=True)
 

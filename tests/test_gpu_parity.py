@@ -177,9 +177,10 @@ def test_empty_and_single():
     _compare(ref, got, mo.w2, model=mo, rho11=d.rho11)
 
 
-@pytest.mark.parametrize("store", [2, 3])
+@pytest.mark.parametrize("store", [2, 3, 5])
 def test_kernel_modes_profile_and_box(store):
-    _say(f"32 nodes, kernel_store={store} (2: regenerated, 3: register rows): profile P=512, box P=256")
+    _say(f"32 nodes, kernel_store={store} (2: regenerated, 3: register rows, 5: one point per wave): "
+         "profile P=512, box P=256")
     L = S.LaunchConfig(kernel_store=store)
     d = W.radial_profile(P=1 << 16).take(np.arange(0, 1 << 16, 128))
     theta = _theta(32)
