@@ -17,10 +17,11 @@
 // species, pair processes couple a species with its partner, so with species
 // in id order the blocks are (nu_e, anti-nu_e) of size 64 and nu_x of size
 // 32.  Each block is factorised in registers, one wavefront per point: lane r
-// holds row r of A^T (column r of A) and the two right-hand sides.  Gaussian
-// elimination runs without row exchanges (the W-scaled columns of A are
-// strictly diagonally dominant), broadcasting the pivot row of each step
-// through LDS; back substitution follows.  Per-point terms go to a
+// holds row r of A^T (column r of A) and the two right-hand sides.  Block
+// Gaussian elimination with 2 x 2 pivot blocks runs without row exchanges
+// (the W-scaled columns of A are strictly diagonally dominant), broadcasting
+// the two pivot rows of each step through LDS; block back substitution
+// follows.  Per-point terms go to a
 // (P, nq + 2) array and are summed over points by a fixed-order two-stage
 // reduction.
 #include "nmc_wave.h"
@@ -41,7 +42,7 @@ struct AdjLds {
   double b0[NS][NQ], b1[NS][NQ];  // dR_D / dYe, dR_D / de
   double da[NS][NQ], dp[NS][NQ], ds[NS][NQ];  // dR_D / d a_nes, / d a_pair, / d s_q
   double z0[NS][NQ], z1[NS][NQ];  // Z = A^-T C^T
-  alignas(16) double prow[2 * NQ + 2];  // pivot-row broadcast of the block factorisation
+  alignas(16) double prow[2 * (2 * NQ + 2)];  // pivot-row buffers of the block factorisation
 };
 
 __device__ __forceinline__ double readlane_f64(double v, int lane) {
@@ -50,23 +51,6 @@ __device__ __forceinline__ double readlane_f64(double v, int lane) {
   return mk64(lo, hi);
 }
 
-// Solves A^T z = c for one diagonal block of size N (lanes 0..N-1 active):
-// lane r enters with R = row r of A^T and c = (c0, c1) its right-hand sides
-// and leaves with (z0, z1) = entry r of the two solutions.  Returns false if
-// a pivot was zero or non-finite, detected as a non-finite solution entry
-// (such a pivot turns the multipliers or a quotient of the back
-// substitution into inf or NaN, which propagate into z).
-//
-// Gaussian elimination without row exchanges: with D in [0, 1] and
-// non-negative kernels, diag(W) A is strictly diagonally dominant by
-// columns (the off-diagonal column sums of the W-scaled NES and pair terms
-// equal the kernel part of the diagonal opacity, leaving a margin
-// W_p (1 + dtau chi^EmAb_p)), and elimination without pivoting is stable for
-// such matrices.  Step k broadcasts row k of A^T (held by lane k) through
-// the LDS row buffer prow: lane k writes its entries k+1..N-1 and its two
-// right-hand sides, every lane reads them back as 16-byte broadcasts.  A
-// single wavefront runs the work-group, so its LDS accesses complete in
-// program order and no barrier is needed.
 // ds_write2_b64 of (a, b) to LDS bytes base + 8 J and base + 8 (J + 1)
 template <int J>
 __device__ __forceinline__ void lds_write2_f64(uint32_t base, double a, double b) {
@@ -75,65 +59,95 @@ __device__ __forceinline__ void lds_write2_f64(uint32_t base, double a, double b
                : "memory");
 }
 
+// Solves A^T z = c for one diagonal block of size N (lanes 0..N-1 active):
+// lane r enters with R = row r of A^T and c = (c0, c1) its right-hand sides
+// and leaves with (z0, z1) = entry r of the two solutions.  Returns false if
+// a pivot block was singular or non-finite, detected as a non-finite
+// solution entry (such a block turns the multipliers or a quotient of the
+// back substitution into inf or NaN, which propagate into z).
+//
+// Block Gaussian elimination with 2 x 2 pivot blocks and no row exchanges:
+// with D in [0, 1] and non-negative kernels, diag(W) A is strictly
+// diagonally dominant by columns (the off-diagonal column sums of the
+// W-scaled NES and pair terms equal the kernel part of the diagonal opacity,
+// leaving a margin W_p (1 + dtau chi^EmAb_p)); elimination without pivoting is
+// stable for such matrices, and their diagonal blocks and Schur complements
+// stay dominant, so every 2 x 2 pivot block is nonsingular.  Step k (even)
+// broadcasts rows k and k+1 of A^T (lanes k and k+1) through two LDS row
+// buffers: the two lanes write their entries k+2..N-1 and right-hand sides,
+// every lane reads them back as 16-byte broadcasts and removes both rows with
+// the multipliers [R[k], R[k+1]] B^-1 of the pivot block B.  A single
+// wavefront runs the work-group, so its LDS accesses complete in program
+// order and no barrier is needed.  Back substitution solves the 2 x 2
+// diagonal blocks from the last.
 template <int N>
 __device__ __forceinline__ bool solve_block_transposed(double (&R)[N], double c0, double c1, double& z0,
                                                        double& z1, double* prow_generic) {
+  static_assert(N % 2 == 0, "2 x 2 pivot blocks");
   typedef double f64x2 __attribute__((ext_vector_type(2)));
   typedef __attribute__((address_space(3))) double lds_f64;
   typedef __attribute__((address_space(3))) f64x2 lds_f64x2;
+  constexpr int RS = N + 2;  // doubles per row buffer: entries 0..N-1, right-hand sides at N, N+1
   const int lane = opaque((int)threadIdx.x);
-  static_for<0, N>([&](auto kk) __attribute__((always_inline)) {
-    constexpr int k = decltype(kk)::value;
+  static_for<0, N / 2>([&](auto kk) __attribute__((always_inline)) {
+    constexpr int k = 2 * decltype(kk)::value;
     lds_f64* prow = (lds_f64*)prow_generic;
     lds_f64x2* prow2 = (lds_f64x2*)prow;
-    const double piv = readlane_f64(R[k], k);
-    // entries k+1..N-1 and the right-hand sides at N, N+1; 16-byte pairs
-    // start at the first even index
-    constexpr int j2 = (k + 2) & ~1;
-    if (lane == k) {
-      // ds_write2_b64 from one base register with 8-byte-unit offsets (the
-      // writes and the reads below are LDS operations of one wavefront and
-      // complete in program order)
-      const uint32_t base = (uint32_t)(uintptr_t)prow;
-      if constexpr ((k & 1) == 0) prow[k + 1] = R[k + 1];
-      static_for<0, (N - j2) / 2>([&](auto ii) __attribute__((always_inline)) {
-        constexpr int j = j2 + 2 * decltype(ii)::value;
+    // the pivot block B = [[a00, a01], [a10, a11]] (rows k, k+1, columns k, k+1)
+    const double a00 = readlane_f64(R[k], k), a01 = readlane_f64(R[k + 1], k);
+    const double a10 = readlane_f64(R[k], k + 1), a11 = readlane_f64(R[k + 1], k + 1);
+    if (lane == k || lane == k + 1) {
+      // rows k and k+1 to their buffers: ds_write2_b64 from one base register
+      // per lane with 8-byte-unit offsets
+      const uint32_t base = (uint32_t)(uintptr_t)prow + (uint32_t)((lane - k) * RS * 8);
+      static_for<0, (N - k - 2) / 2>([&](auto ii) __attribute__((always_inline)) {
+        constexpr int j = k + 2 + 2 * decltype(ii)::value;
         lds_write2_f64<j>(base, R[j], R[j + 1]);
       });
-      prow[N] = c0;
-      prow[N + 1] = c1;
+      lds_write2_f64<N>(base, c0, c1);
     }
-    if (lane > k) {
-      const double l = R[k] * rcp_nr(piv);
-      if constexpr ((k & 1) == 0) R[k + 1] = __builtin_fma(-l, prow[k + 1], R[k + 1]);
+    if (lane > k + 1) {
+      const double rdet = rcp_nr(a00 * a11 - a01 * a10);
+      const double l0 = (R[k] * a11 - R[k + 1] * a10) * rdet;
+      const double l1 = (R[k + 1] * a00 - R[k] * a01) * rdet;
 #pragma unroll
-      for (int j = j2; j < N; j += 2) {
-        const f64x2 v = prow2[j / 2];
-        R[j] = __builtin_fma(-l, v.x, R[j]);
-        R[j + 1] = __builtin_fma(-l, v.y, R[j + 1]);
+      for (int j = k + 2; j < N; j += 2) {
+        const f64x2 u = prow2[j / 2], v = prow2[(RS + j) / 2];
+        R[j] = __builtin_fma(-l0, u.x, __builtin_fma(-l1, v.x, R[j]));
+        R[j + 1] = __builtin_fma(-l0, u.y, __builtin_fma(-l1, v.y, R[j + 1]));
       }
-      const f64x2 cv = prow2[N / 2];
-      c0 = __builtin_fma(-l, cv.x, c0);
-      c1 = __builtin_fma(-l, cv.y, c1);
+      const f64x2 cu = prow2[N / 2], cv = prow2[(RS + N) / 2];
+      c0 = __builtin_fma(-l0, cu.x, __builtin_fma(-l1, cv.x, c0));
+      c1 = __builtin_fma(-l0, cu.y, __builtin_fma(-l1, cv.y, c1));
     }
   });
-  // back substitution, column by column: z_k from lane k, then every row
-  // above it removes its term
+  // back substitution by 2 x 2 blocks from the last: z of rows k, k+1 from
+  // their (reduced) right-hand sides, then every row above removes its terms
   z0 = z1 = 0.0;
-  static_for<0, N>([&](auto kk) __attribute__((always_inline)) {
-    constexpr int k = N - 1 - decltype(kk)::value;
-    const double r = rcp_nr(readlane_f64(R[k], k));
-    const double zk0 = readlane_f64(c0, k) * r, zk1 = readlane_f64(c1, k) * r;
+  static_for<0, N / 2>([&](auto kk) __attribute__((always_inline)) {
+    constexpr int k = N - 2 - 2 * decltype(kk)::value;
+    const double a00 = readlane_f64(R[k], k), a01 = readlane_f64(R[k + 1], k);
+    const double a10 = readlane_f64(R[k], k + 1), a11 = readlane_f64(R[k + 1], k + 1);
+    const double rdet = rcp_nr(a00 * a11 - a01 * a10);
+    const double p0 = readlane_f64(c0, k), p1 = readlane_f64(c0, k + 1);
+    const double q0 = readlane_f64(c1, k), q1 = readlane_f64(c1, k + 1);
+    const double zk0 = (a11 * p0 - a01 * p1) * rdet, zl0 = (a00 * p1 - a10 * p0) * rdet;
+    const double zk1 = (a11 * q0 - a01 * q1) * rdet, zl1 = (a00 * q1 - a10 * q0) * rdet;
     if (lane == k) {
       z0 = zk0;
       z1 = zk1;
     }
+    if (lane == k + 1) {
+      z0 = zl0;
+      z1 = zl1;
+    }
     if (lane < k) {
-      c0 = __builtin_fma(-R[k], zk0, c0);
-      c1 = __builtin_fma(-R[k], zk1, c1);
+      c0 = __builtin_fma(-R[k], zk0, __builtin_fma(-R[k + 1], zl0, c0));
+      c1 = __builtin_fma(-R[k], zk1, __builtin_fma(-R[k + 1], zl1, c1));
     }
   });
-  // a zero or non-finite pivot makes some entry of the solution non-finite
+  // a singular or non-finite pivot block makes some entry of the solution
+  // non-finite
   return __builtin_amdgcn_ballot_w64(lane < N && !(isfinite(z0) && isfinite(z1))) == 0;
 }
 
