@@ -65,6 +65,14 @@ __device__ __forceinline__ void half_own_sums(const double (&v)[2 * K], double (
   for (int k = 0; k < K; ++k) swap16(r[k], s[k], s[K + k]);
 }
 
+// min(a, b) of two non-NaN values as one v_min_f64 (the library fmin first
+// quiets signalling NaNs, which a value loaded from memory cannot rule out)
+__device__ __forceinline__ double min_f64(double a, double b) {
+  double r;
+  asm("v_min_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+  return r;
+}
+
 // any lane of this lane's half
 __device__ __forceinline__ bool half_any(bool b) {
   const uint64_t m = __builtin_amdgcn_ballot_w64(b);
@@ -244,7 +252,8 @@ struct PairSolver {
           den0I[t] = 1.0 + dtau * (chia + sig);
         }
       }
-      // pair factors b(q, j) of this lane's row, j = 0..31
+      // pair factors of this lane's row, j = 0..31, signed by orientation:
+      // +b(q, j) for j > q (q the lower node), -b(q, j) otherwise
       double B[COUPLED ? NQ : 1];
       double Gq = 0.0;
       if constexpr (COUPLED) {
@@ -264,7 +273,8 @@ struct PairSolver {
 #pragma unroll
         for (int j = 0; j < NQ; ++j) {
           const bool up = j > q;  // q is the lower node of the pair
-          B[j] = ldexp(up ? Pq * E.R2[j] : E.P2[j] * Rq, up ? nq - E.n2[j] : E.n2[j] - nq);
+          const double b = ldexp(up ? Pq * E.R2[j] : E.P2[j] * Rq, up ? nq - E.n2[j] : E.n2[j] - nq);
+          B[j] = up ? b : -b;
         }
       }
 
@@ -286,8 +296,8 @@ struct PairSolver {
           // half [16 R, 16 R + 16) of the nodes in XR[.][R], YR[.][R]
           double XR[2][NS], YR[2][NS];
           // the pair factors are re-read per iteration: the per-column
-          // products and selects are not hoisted out of the inner loop
-          // (they would need four times the registers)
+          // products are not hoisted out of the inner loop (they would need
+          // four times the registers)
 #pragma unroll
           for (int j = 0; j < NQ; ++j) asm volatile("" : "+v"(B[j]));
 #pragma unroll
@@ -303,16 +313,21 @@ struct PairSolver {
             static_for<0, 2>([&](auto ee) __attribute__((always_inline)) {
               constexpr int j = j0 + decltype(ee)::value;
               const double Gj = decltype(ee)::value ? g.y : g.x;
-              const bool up = j > q;
-              const double b = B[j], b2 = b * b, b3 = b2 * b;
-              ColFmac<NS>::template run<j % 16>(etaN, outN, annP, etaP, XR[j / 16], YR[j / 16], up ? b : b3,
-                                                up ? b3 : b, b2, fmin(Gj, Gq));
+              // with s = +-b: P = |s| + s and M = |s| - s are 2b and 0 (j > q) or
+              // 0 and 2b, so fma(M, b^2, P) = 2 Phi_in and fma(P, b^2, M) =
+              // 2 Phi_out exactly (scaled entries), without compares or selects
+              const double sb = B[j], b2 = sb * sb;
+              const double Pp = fabs(sb) + sb, Mm = fabs(sb) - sb;
+              ColFmac<NS>::template run<j % 16>(etaN, outN, annP, etaP, XR[j / 16], YR[j / 16],
+                                                __builtin_fma(Mm, b2, Pp), __builtin_fma(Pp, b2, Mm), b2,
+                                                min_f64(Gj, Gq));
             });
           });
+          const double hAeq = 0.5 * Aeq;  // the NES entries were accumulated doubled
 #pragma unroll
           for (int t = 0; t < NS; ++t) {
-            etaN[t] *= Aeq;
-            outN[t] *= Aeq;
+            etaN[t] *= hAeq;
+            outN[t] *= hAeq;
             annP[t] *= Apq;
             etaP[t] *= Apq;
           }
