@@ -36,7 +36,10 @@ template <int NS>
 struct PairLds {
   ModelLds m;
   SplitExp E[2];                   // per point: exponent splits at its current temperature
-  double hist[4][2 * NS][kLanes];  // Anderson history per lane and owned moment: Q_prev, F_prev, dQ_old, dF_old
+  union {
+    double hist[4][2 * NS][kLanes];  // Anderson history per lane and owned moment: Q_prev, F_prev, dQ_old, dF_old
+    double tile[2][NQP][NQP];        // per point, signed pair factors: [j][q] = +b if j > q, else -b
+  } u;
   struct Pt {                      // per-point state of the outer (matter) loop
     double dref[NS];               // ||D_s^[k,1]||_W^2 of the current inner loop
     double y[2], oq[2], of[2], odq[2], odf[2];
@@ -267,14 +270,28 @@ struct PairSolver {
           E.G[q] = ldexp(R2 * R2, -4 * xs.n);  // exp(-2 e / T)
         }
         __syncthreads();
-        const double Pq = E.P2[q], Rq = E.R2[q];
-        const int nq = E.n2[q];
         Gq = E.G[q];
+        // signed pair factors of the point, each unordered pair (q, q + d mod
+        // 32) once: d = 1..15 by every lane, d = 16 by lanes q < 16 (the
+        // Anderson history is dead between inner loops, its space holds them)
+        {
+          double (*T)[NQ] = S.u.tile[h];
 #pragma unroll
-        for (int j = 0; j < NQ; ++j) {
-          const bool up = j > q;  // q is the lower node of the pair
-          const double b = ldexp(up ? Pq * E.R2[j] : E.P2[j] * Rq, up ? nq - E.n2[j] : E.n2[j] - nq);
-          B[j] = up ? b : -b;
+          for (int d = 1; d <= NQ / 2; ++d) {
+            const int j = (q + d) & (NQ - 1);
+            const int lo = q < j ? q : j, hi = q < j ? j : q;
+            if (d < NQ / 2 || q < NQ / 2) {
+              const double b = ldexp(E.P2[lo] * E.R2[hi], E.n2[lo] - E.n2[hi]);
+              T[hi][lo] = b;
+              T[lo][hi] = -b;
+            }
+          }
+          T[q][q] = -1.0;
+          __syncthreads();
+          // row q of the lane: element [j][q] (consecutive lanes, consecutive words)
+#pragma unroll
+          for (int j = 0; j < NQ; ++j) B[j] = T[j][q];
+          __syncthreads();
         }
       }
 
@@ -355,9 +372,9 @@ struct PairSolver {
           double v4[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
           for (int x = 0; x < 2 * NS; ++x) {
-            dQ2[x] = Qx[x] - S.hist[0][x][lane];
-            dF2[x] = Fx[x] - S.hist[1][x][lane];
-            const double dF1 = use1 * S.hist[3][x][lane];
+            dQ2[x] = Qx[x] - S.u.hist[0][x][lane];
+            dF2[x] = Fx[x] - S.u.hist[1][x][lane];
+            const double dF1 = use1 * S.u.hist[3][x][lane];
             v4[0] += dF1 * dF2[x];
             v4[1] += dF2[x] * dF2[x];
             v4[2] += dF1 * Fx[x];
@@ -369,16 +386,16 @@ struct PairSolver {
           anderson2(mem == 3, G11, gs[0], gs[1], gs[2], gs[3], g1, g2);
 #pragma unroll
           for (int x = 0; x < 2 * NS; ++x) {
-            Xn[x] = Qx[x] - g2 * dQ2[x] - g1 * S.hist[2][x][lane];
-            S.hist[2][x][lane] = dQ2[x];
-            S.hist[3][x][lane] = dF2[x];
+            Xn[x] = Qx[x] - g2 * dQ2[x] - g1 * S.u.hist[2][x][lane];
+            S.u.hist[2][x][lane] = dQ2[x];
+            S.u.hist[3][x][lane] = dF2[x];
           }
           G11 = gs[1];
         }
 #pragma unroll
         for (int x = 0; x < 2 * NS; ++x) {
-          S.hist[0][x][lane] = Qx[x];
-          S.hist[1][x][lane] = Fx[x];
+          S.u.hist[0][x][lane] = Qx[x];
+          S.u.hist[1][x][lane] = Fx[x];
         }
         bool bad = false;
 #pragma unroll
