@@ -8,17 +8,23 @@
 // issues for a whole wave (equation of state, opacities, Anderson solves,
 // convergence tests, matter update) serves two points here, and each lane
 // contracts all 32 columns of its row:
-//   - once per outer iteration a lane forms Phi_in[q][j] and Phi_out[q][j]
-//     for j = 0..31 (without their common factor A e_q e_j) from the
-//     exponent splits of its point's temperature and keeps them in VGPRs;
+//   - once per outer iteration the lanes of a point fill a 32 x 32 LDS tile
+//     with its pair factors b(q, j) = exp(-|e_q - e_j| / (2T)), signed by
+//     orientation (+b where j > q, -b otherwise), each unordered pair by one
+//     lane, and every lane reads its row back into VGPRs (the tile shares
+//     LDS with the Anderson history, which is dead between inner loops);
 //   - in every inner iteration the vectors W e D and W e (1 - D) of the point
 //     are redistributed with v_permlane16_swap, so that each 16-lane row
 //     holds one half of its point's vector, and every FMA takes its column
 //     through a DPP row_newbcast operand (v_fmac_f64_dpp): the contraction
-//     reads no LDS;
-//   - per column, Phi_ann = max(Phi_in, Phi_out)^2 (b <= 1, so b is the
-//     larger of b and b^3) and Phi_pro = min(G_j, G_q) (G falls with energy).
-// The row sums are scaled by A e_q once per inner iteration.
+//     reads no LDS for the moments;
+//   - per column, with s the signed factor, |s| + s and |s| - s are 2b and 0
+//     in one order or the other, so two FMAs against s^2 give the doubled
+//     Phi_in and Phi_out entries without compares or selects; Phi_ann = s^2
+//     and Phi_pro = min(G_j, G_q) (G falls with energy), all without their
+//     common factor A e_q e_j.
+// The row sums are scaled by A e_q (the NES sums by A e_q / 2) once per
+// inner iteration.
 //
 // Both halves run one instruction stream.  A half whose point has finished
 // (or which has no point, past the end of an odd batch) keeps computing with
