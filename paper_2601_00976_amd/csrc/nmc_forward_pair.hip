@@ -18,13 +18,12 @@
 //     holds one half of its point's vector, and every FMA takes its column
 //     through a DPP row_newbcast operand (v_fmac_f64_dpp): the contraction
 //     reads no LDS for the moments;
-//   - per column, with s the signed factor, |s| + s and |s| - s are 2b and 0
-//     in one order or the other, so two FMAs against s^2 give the doubled
-//     Phi_in and Phi_out entries without compares or selects; Phi_ann = s^2
-//     and Phi_pro = min(G_j, G_q) (G falls with energy), all without their
-//     common factor A e_q e_j.
-// The row sums are scaled by A e_q (the NES sums by A e_q / 2) once per
-// inner iteration.
+//   - per column, with s the signed factor and c = s^3 (same sign),
+//     max(s, -c) and max(c, -s) are the Phi_in and Phi_out entries (b and
+//     b^3 in one order or the other) without compares or selects;
+//     Phi_ann = s^2 and Phi_pro = min(G_j, G_q) (G falls with energy), all
+//     without their common factor A e_q e_j.
+// The row sums take their factors A e_q in the Q step.
 //
 // Both halves run one instruction stream.  A half whose point has finished
 // (or which has no point, past the end of an odd batch) keeps computing with
@@ -80,6 +79,47 @@ __device__ __forceinline__ double min_f64(double a, double b) {
   double r;
   asm("v_min_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
   return r;
+}
+
+// max(a, -b) of two non-NaN values as one v_max_f64 with a negated operand
+__device__ __forceinline__ double max_neg_f64(double a, double b) {
+  double r;
+  asm("v_max_f64 %0, %1, -%2" : "=v"(r) : "v"(a), "v"(b));
+  return r;
+}
+
+// Signed pair factors of one point into its 32 x 32 tile T (row-major):
+// for every unordered node pair (lo, hi), T[hi][lo] = +b and T[lo][hi] = -b
+// with b = exp(-|e_lo - e_hi| / (2T)) = P_lo R_hi 2^(n_lo - n_hi).  Lane q
+// forms the pairs (q, q + d mod 32) for d = 1..15 and, if q < 16, d = 16,
+// from its own split (Pq, Rq, nq) and its partner's in LDS.  Of the two
+// orientations 2^(x_q - x_j) and 2^(x_j - x_q) the smaller is b (the other
+// is its reciprocal, or overflows), so no compare picks the formula; the
+// sign goes by whether q is the lower node.
+__device__ __forceinline__ void pair_tile_rows(double* __restrict__ T, const double* __restrict__ P2,
+                                               const double* __restrict__ R2, const int* __restrict__ n2, int q,
+                                               double Pq, double Rq, int nq) {
+  constexpr int N = 32;
+  double Pp[N / 2], Rp[N / 2];
+  int np[N / 2];
+#pragma unroll
+  for (int d = 1; d <= N / 2; ++d) {  // every partner load first: one LDS round trip
+    const int j = (q + d) & (N - 1);
+    Pp[d - 1] = P2[j];
+    Rp[d - 1] = R2[j];
+    np[d - 1] = n2[j];
+  }
+#pragma unroll
+  for (int d = 1; d <= N / 2; ++d) {
+    const int j = (q + d) & (N - 1);
+    const int e = nq - np[d - 1];
+    const double b = min_f64(ldexp(Pq * Rp[d - 1], e), ldexp(Pp[d - 1] * Rq, -e));
+    if (d < N / 2 || q < N / 2) {
+      const double sb = q + d < N ? b : -b;  // + where j is the upper node
+      T[j * N + q] = sb;
+      T[q * N + j] = -sb;
+    }
+  }
 }
 
 // any lane of this lane's half
@@ -267,8 +307,8 @@ struct PairSolver {
       double Gq = 0.0;
       if constexpr (COUPLED) {
         SplitExp& E = S.E[h];
+        const ExpSplit xs = exp_split(epsq, invT);
         {
-          const ExpSplit xs = exp_split(epsq, invT);
           const double R2 = xs.R * xs.R;
           E.P2[q] = xs.P;
           E.R2[q] = xs.R;
@@ -282,16 +322,7 @@ struct PairSolver {
         // Anderson history is dead between inner loops, its space holds them)
         {
           double (*T)[NQ] = S.u.tile[h];
-#pragma unroll
-          for (int d = 1; d <= NQ / 2; ++d) {
-            const int j = (q + d) & (NQ - 1);
-            const int lo = q < j ? q : j, hi = q < j ? j : q;
-            if (d < NQ / 2 || q < NQ / 2) {
-              const double b = ldexp(E.P2[lo] * E.R2[hi], E.n2[lo] - E.n2[hi]);
-              T[hi][lo] = b;
-              T[lo][hi] = -b;
-            }
-          }
+          pair_tile_rows(&T[0][0], E.P2, E.R2, E.n2, q, xs.P, xs.R, xs.n);
           T[q][q] = -1.0;
           __syncthreads();
           // row q of the lane: element [j][q] (consecutive lanes, consecutive words)
@@ -336,33 +367,27 @@ struct PairSolver {
             static_for<0, 2>([&](auto ee) __attribute__((always_inline)) {
               constexpr int j = j0 + decltype(ee)::value;
               const double Gj = decltype(ee)::value ? g.y : g.x;
-              // with s = +-b: P = |s| + s and M = |s| - s are 2b and 0 (j > q) or
-              // 0 and 2b, so fma(M, b^2, P) = 2 Phi_in and fma(P, b^2, M) =
-              // 2 Phi_out exactly (scaled entries), without compares or selects
-              const double sb = B[j], b2 = sb * sb;
-              const double Pp = fabs(sb) + sb, Mm = fabs(sb) - sb;
+              // with s = +-b and c = s^3 = +-b^3 (the same sign): max(s, -c) is
+              // b where s > 0 and b^3 where s < 0, i.e. Phi_in, and max(c, -s)
+              // is Phi_out (scaled entries), without compares or selects
+              const double sb = B[j], b2 = sb * sb, c3 = sb * b2;
               ColFmac<NS>::template run<j % 16>(etaN, outN, annP, etaP, XR[j / 16], YR[j / 16],
-                                                __builtin_fma(Mm, b2, Pp), __builtin_fma(Pp, b2, Mm), b2,
-                                                min_f64(Gj, Gq));
+                                                max_neg_f64(sb, c3), max_neg_f64(c3, sb), b2, min_f64(Gj, Gq));
             });
           });
-          const double hAeq = 0.5 * Aeq;  // the NES entries were accumulated doubled
-#pragma unroll
-          for (int t = 0; t < NS; ++t) {
-            etaN[t] *= hAeq;
-            outN[t] *= hAeq;
-            annP[t] *= Apq;
-            etaP[t] *= Apq;
-          }
         }
-        // Q and residual of both owned moments x = (D_t, I_t)
+        // Q and residual of both owned moments x = (D_t, I_t); the row sums
+        // take their factors A e_q here, and one reciprocal of the product of
+        // the two denominators serves both
         double Qx[2 * NS], Fx[2 * NS];
 #pragma unroll
         for (int t = 0; t < NS; ++t) {
-          const double eta = etaN[t] + etaP[t];
-          const double chi = (etaN[t] + outN[t]) + (etaP[t] + annP[t]);
-          Qx[t] = __builtin_fma(dtau, eta, baseD[t]) * rcp_nr(__builtin_fma(dtau, chi, den0D[t]));
-          Qx[NS + t] = Ist[t] * rcp_nr(__builtin_fma(dtau, chi, den0I[t]));
+          const double eta = __builtin_fma(Aeq, etaN[t], Apq * etaP[t]);
+          const double chi = __builtin_fma(Aeq, outN[t], __builtin_fma(Apq, annP[t], eta));
+          const double dD = __builtin_fma(dtau, chi, den0D[t]), dI = __builtin_fma(dtau, chi, den0I[t]);
+          const double r = rcp_nr(dD * dI);
+          Qx[t] = __builtin_fma(dtau, eta, baseD[t]) * (r * dI);
+          Qx[NS + t] = Ist[t] * (r * dD);
           Fx[t] = Qx[t] - D[t];
           Fx[NS + t] = Qx[NS + t] - I[t];
         }
@@ -453,37 +478,36 @@ struct PairSolver {
       }
       if (ran) total_inner += l_done;
       if (run && !cvd) inner_failed = true;
+      // the reference norms of the next inner loop (applied after a failed
+      // loop: the norm of the current moments) and the sums of the matter
+      // right-hand side (Eq. implicitFluidNodal at v = 0) in one reduction
+      double yq0, yq1;
       {
-        // reference for the next loop after a failed inner loop: the norm of
-        // the current moments (uniform steps, applied where needed)
-        double v[2 * ((NS + 1) / 2)], s[2 * ((NS + 1) / 2)];
+        constexpr int KR = (NS + 3) / 2;
+        const double w3 = mt.w3[q];
+        double v[2 * KR], s[2 * KR], m0 = 0.0, m1 = 0.0;
 #pragma unroll
-        for (int t = 0; t < 2 * ((NS + 1) / 2); ++t) v[t] = t < NS ? w2q * D[t < NS ? t : 0] * D[t < NS ? t : 0] : 0.0;
-        half_own_sums<(NS + 1) / 2>(v, s);
+        for (int t = 0; t < NS; ++t) {
+          v[t] = w2q * D[t] * D[t];
+          const double dd = D[t] - Dst[t];
+          m0 += md->ig[t] * w2q * dd;
+          m1 += md->imult[t] * w3 * dd;
+        }
+        v[NS] = m0;
+        v[NS + 1] = m1;
+#pragma unroll
+        for (int t = NS + 2; t < 2 * KR; ++t) v[t] = 0.0;
+        half_own_sums<KR>(v, s);
         if (run && !cvd) {
 #pragma unroll
           for (int t = 0; t < NS; ++t) pt.dref[t] = s[t];
         }
+        yq0 = pt.ye_st - pt.K * s[NS];
+        yq1 = pt.e_st - pt.K * s[NS + 1];
       }
       if (a.prm.fixed_matter) {
         if (run) outer_conv = true;
         run = false;
-      }
-
-      // ---- matter right-hand side (Eq. implicitFluidNodal at v = 0) -------
-      double yq0, yq1;
-      {
-        const double w3 = mt.w3[q];
-        double mv[2] = {0.0, 0.0}, s[2];
-#pragma unroll
-        for (int t = 0; t < NS; ++t) {
-          const double dd = D[t] - Dst[t];
-          mv[0] += md->ig[t] * w2q * dd;
-          mv[1] += md->imult[t] * w3 * dd;
-        }
-        half_own_sums<1>(mv, s);
-        yq0 = pt.ye_st - pt.K * s[0];
-        yq1 = pt.e_st - pt.K * s[1];
       }
       if (run) {
         const double f0 = yq0 - pt.y[0], f1 = yq1 - pt.y[1];
