@@ -291,6 +291,10 @@ def main():
             "algorithmic_hbm_gbs": hbm_bytes_per_launch / kern_s_per_launch / 1e9,
         },
     }
+    # the denominator checked on this device: a pure FP64 FMA probe
+    fma_peak = S.probe_fma_tflops(dev)
+    line["roofline"]["measured_fma_peak"] = fma_peak
+    line["roofline"]["frac_of_measured_fma_peak"] = achieved / fma_peak
     if nq == 32:
         line["adjoint"] = adjoint_ratio(model, params, theta, D0, I0, t, e0, ws, launch)
     if not args.no_cpu and args.workload == "profile32":

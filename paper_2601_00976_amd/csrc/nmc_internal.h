@@ -79,6 +79,8 @@ hipError_t launch_forward64(const FwdArgs& a, int ns, bool coupled, const nmc_la
 hipError_t launch_forward_pair(const FwdArgs& a, int ns, bool coupled, const nmc_launch& L, int num_cu,
                                hipStream_t s);
 hipError_t launch_reset_counter(int* counter, hipStream_t s);
+// FP64 FMA throughput probe (measurement only)
+hipError_t launch_probe_fma(int64_t waves, int iters, double* out, hipStream_t s);
 hipError_t launch_init_state(const DevModel* mdl, int ns, int nq, int64_t P, const double* T, const double* mu,
                              const double* rho11, const double* ye, const double* uD, const double* uI, double a,
                              double b, double c, double* D0, double* I0, double* e0, hipStream_t s);

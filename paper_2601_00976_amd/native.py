@@ -28,7 +28,7 @@ SPACING_LOG, SPACING_ZOOM = 0, 1
 EXPORTED = (
     "nmc_model_desc_default", "nmc_solver_params_default", "nmc_grid_create", "nmc_grid_query",
     "nmc_grid_destroy", "nmc_model_create", "nmc_model_destroy", "nmc_workspace_bytes", "nmc_kernel_store_bytes",
-    "nmc_solve_batch", "nmc_solve_batch_adjoint", "nmc_init_state", "nmc_error_string",
+    "nmc_solve_batch", "nmc_solve_batch_adjoint", "nmc_init_state", "nmc_probe_fma_f64", "nmc_error_string",
     "nmc_last_error",
 )
 
@@ -100,12 +100,13 @@ def lib():
                                               vp, vp, vp, vp, C.c_size_t, vp]
         L.nmc_init_state.argtypes = [vp, C.c_int64, vp, vp, vp, vp, vp, vp, C.c_double, C.c_double, C.c_double,
                                      vp, vp, vp, vp]
+        L.nmc_probe_fma_f64.argtypes = [C.c_int64, C.c_int, vp, vp]
         L.nmc_error_string.argtypes = [C.c_int]
         L.nmc_error_string.restype = C.c_char_p
         L.nmc_last_error.argtypes = []
         L.nmc_last_error.restype = C.c_char_p
         for f in ("nmc_grid_create", "nmc_grid_query", "nmc_grid_destroy", "nmc_model_create", "nmc_model_destroy",
-                  "nmc_solve_batch", "nmc_solve_batch_adjoint", "nmc_init_state"):
+                  "nmc_solve_batch", "nmc_solve_batch_adjoint", "nmc_init_state", "nmc_probe_fma_f64"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib

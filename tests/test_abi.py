@@ -90,6 +90,8 @@ def test_solve_rejects_null_arguments_before_launch():
     assert L.nmc_error_string(N.NMC_E_UNSUPPORTED) == b"unsupported configuration"
     rc = L.nmc_init_state(None, 1, None, None, None, None, None, None, 1.0, 0.1, 0.1, None, None, None, None)
     assert rc == N.NMC_E_INVALID_ARG
+    for waves, iters, out in ((0, 8, 1), (1, 0, 1), (1, 8, None), (1 << 21, 8, 1)):
+        assert L.nmc_probe_fma_f64(waves, iters, out, None) == N.NMC_E_INVALID_ARG
 
 
 def test_default_descriptors():
