@@ -17,7 +17,7 @@
 //     are redistributed with v_permlane16_swap, so that each 16-lane row
 //     holds one half of its point's vector, and every FMA takes its column
 //     through a DPP row_newbcast operand (v_fmac_f64_dpp): the contraction
-//     reads no LDS for the moments;
+//     reads no LDS (the moments and G_j come by broadcast from registers);
 //   - per column, with s the signed factor and c = s^3 (same sign),
 //     max(s, -c) and max(c, -s) are the Phi_in and Phi_out entries (b and
 //     b^3 in one order or the other) without compares or selects;
@@ -304,7 +304,7 @@ struct PairSolver {
       // pair factors of this lane's row, j = 0..31, signed by orientation:
       // +b(q, j) for j > q (q the lower node), -b(q, j) otherwise
       double B[COUPLED ? NQ : 1];
-      double Gq = 0.0;
+      double Gq = 0.0, GR[2] = {0.0, 0.0};
       if constexpr (COUPLED) {
         SplitExp& E = S.E[h];
         const ExpSplit xs = exp_split(epsq, invT);
@@ -317,6 +317,9 @@ struct PairSolver {
         }
         __syncthreads();
         Gq = E.G[q];
+        // G of the point's nodes, each 16-lane row holding one half, for the
+        // column broadcasts of the contraction
+        swap16(Gq, GR[0], GR[1]);
         // signed pair factors of the point, each unordered pair (q, q + d mod
         // 32) once: d = 1..15 by every lane, d = 16 by lanes q < 16 (the
         // Anderson history is dead between inner loops, its space holds them)
@@ -360,13 +363,13 @@ struct PairSolver {
             swap16(xv, XR[0][t], XR[1][t]);
             swap16(w2eq - xv, YR[0][t], YR[1][t]);
           }
-          const double2* __restrict__ G2 = reinterpret_cast<const double2*>(S.E[h].G) + opaque(0);
           static_for<0, NQ / 2>([&](auto jj) __attribute__((always_inline)) {
             constexpr int j0 = 2 * decltype(jj)::value;
-            const double2 g = G2[j0 / 2];
             static_for<0, 2>([&](auto ee) __attribute__((always_inline)) {
               constexpr int j = j0 + decltype(ee)::value;
-              const double Gj = decltype(ee)::value ? g.y : g.x;
+              // G_j broadcast from registers (an LDS read here stalled every
+              // column pair on its latency)
+              const double Gj = row_bcast<j % 16>(GR[j / 16]);
               // with s = +-b and c = s^3 = +-b^3 (the same sign): max(s, -c) is
               // b where s > 0 and b^3 where s < 0, i.e. Phi_in, and max(c, -s)
               // is Phi_out (scaled entries), without compares or selects
