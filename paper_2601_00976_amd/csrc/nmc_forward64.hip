@@ -88,27 +88,44 @@ struct PointSolver64 {
     r.Apq = S.Ap * eq;
     return r;
   }
-  __device__ __forceinline__ static void entries(const Lds64<NS>& S, const Row& r, int q, int j, double& fin,
-                                                 double& fout, double& fann, double& fpro) {
-    const double Pj = S.colPR[j][0], Rj = S.colPR[j][1], Gj = S.colGE[j][0];
-    const int nj = S.coln[j];
-    const bool up = j > q;  // q is the lower node of the pair
-    const double b = ldexp(up ? r.Pq * Rj : Pj * r.Rq, up ? r.nq - nj : nj - r.nq);
-    const double b2 = b * b, b3 = b2 * b;
-    fin = up ? b : b3;
-    fout = up ? b3 : b;
-    fann = b2;
-    fpro = fmin(Gj, r.Gq);  // G of the higher node: G falls with energy
+  // per-node data of column j, read from LDS one column ahead of its use
+  struct Col {
+    double P, R, G, w, x[NS];
+    int n;
+  };
+  __device__ __forceinline__ static Col load_col(const Lds64<NS>& S, int j) {
+    Col c;
+    c.P = S.colPR[j][0];
+    c.R = S.colPR[j][1];
+    c.G = S.colGE[j][0];
+    c.w = S.colGE[j][1];
+    c.n = S.coln[j];
+#pragma unroll
+    for (int t = 0; t < NS; ++t) c.x[t] = S.X[t][j];
+    return c;
   }
-  __device__ __forceinline__ static void accumulate(const Lds64<NS>& S, int j, double fin, double fout, double fann,
-                                                    double fpro, double (&etaN)[NS], double (&outN)[NS],
-                                                    double (&annP)[NS], double (&etaP)[NS]) {
-    const double wj = S.colGE[j][1];
+  // u = 2^(x_q - x_j) and v = 2^(x_j - x_q): the one not above 1 is
+  // b = exp(-|e_q - e_j| / (2T)), the other its reciprocal (or +inf), so
+  // Phi_in = (j > q ? b : b^3) = min(u, v^3), Phi_out = min(u^3, v) and
+  // Phi_ann = b^2 = min(u^2, v^2) without a compare or select
+  __device__ __forceinline__ static void entries(const Col& c, const Row& r, double& fin, double& fout,
+                                                 double& fann, double& fpro) {
+    const int e = r.nq - c.n;
+    const double u = ldexp(r.Pq * c.R, e), v = ldexp(c.P * r.Rq, -e);
+    const double u2 = u * u, v2 = v * v;
+    fin = min_f64(u, v2 * v);
+    fout = min_f64(u2 * u, v);
+    fann = min_f64(u2, v2);
+    fpro = min_f64(c.G, r.Gq);  // G of the higher node: G falls with energy
+  }
+  __device__ __forceinline__ static void accumulate(const Col& c, double fin, double fout, double fann, double fpro,
+                                                    double (&etaN)[NS], double (&outN)[NS], double (&annP)[NS],
+                                                    double (&etaP)[NS]) {
     double x[NS], y[NS];
 #pragma unroll
     for (int t = 0; t < NS; ++t) {
-      x[t] = S.X[t][j];
-      y[t] = wj - x[t];
+      x[t] = c.x[t];
+      y[t] = c.w - x[t];
     }
 #pragma unroll
     for (int t = 0; t < NS; ++t) {
@@ -129,18 +146,27 @@ struct PointSolver64 {
 #pragma unroll
     for (int t = 0; t < NS; ++t) etaN[t] = outN[t] = annP[t] = etaP[t] = 0.0;
     const Row r = row_consts(S, q);
-#pragma unroll 4
-    for (int j = 0; j < NQ; ++j) {
+    auto column = [&](const Col& c, int j) __attribute__((always_inline)) {
       double fin, fout, fann, fpro;
       if constexpr (PRE) {
         fin = kst[j * NQ + q];
         fout = kst[(NQ + j) * NQ + q];
         fann = kst[(2 * NQ + j) * NQ + q];
-        fpro = fmin(S.colGE[j][0], r.Gq);
+        fpro = min_f64(c.G, r.Gq);
       } else {
-        entries(S, r, q, j, fin, fout, fann, fpro);
+        entries(c, r, fin, fout, fann, fpro);
       }
-      accumulate(S, j, fin, fout, fann, fpro, etaN, outN, annP, etaP);
+      accumulate(c, fin, fout, fann, fpro, etaN, outN, annP, etaP);
+    };
+    // two column buffers in turn: the reads of one overlap the work on the
+    // other (the last trip re-reads column 0, unused)
+    Col ca = load_col(S, 0), cb;
+#pragma unroll 2
+    for (int j = 0; j < NQ; j += 2) {
+      cb = load_col(S, j + 1);
+      column(ca, j);
+      ca = load_col(S, (j + 2) & (NQ - 1));
+      column(cb, j + 1);
     }
 #pragma unroll
     for (int t = 0; t < NS; ++t) {
@@ -157,7 +183,7 @@ struct PointSolver64 {
 #pragma unroll 4
     for (int j = 0; j < NQ; ++j) {
       double fin, fout, fann, fpro;
-      entries(S, r, q, j, fin, fout, fann, fpro);
+      entries(load_col(S, j), r, fin, fout, fann, fpro);
       kst[j * NQ + q] = fin;
       kst[(NQ + j) * NQ + q] = fout;
       kst[(2 * NQ + j) * NQ + q] = fann;

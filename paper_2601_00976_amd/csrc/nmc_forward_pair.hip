@@ -73,13 +73,6 @@ __device__ __forceinline__ void half_own_sums(const double (&v)[2 * K], double (
   for (int k = 0; k < K; ++k) swap16(r[k], s[k], s[K + k]);
 }
 
-// min(a, b) of two non-NaN values as one v_min_f64 (the library fmin first
-// quiets signalling NaNs, which a value loaded from memory cannot rule out)
-__device__ __forceinline__ double min_f64(double a, double b) {
-  double r;
-  asm("v_min_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
-  return r;
-}
 
 // max(a, -b) of two non-NaN values as one v_max_f64 with a negated operand
 __device__ __forceinline__ double max_neg_f64(double a, double b) {

@@ -120,6 +120,14 @@ __device__ __forceinline__ double halve32(double a, double b) {
   return mk64(x[0], y[0]) + mk64(x[1], y[1]);
 }
 
+// min(a, b) of two non-NaN values as one v_min_f64 (the library fmin first
+// quiets signalling NaNs, which a value loaded from memory cannot rule out)
+__device__ __forceinline__ double min_f64(double a, double b) {
+  double r;
+  asm("v_min_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+  return r;
+}
+
 // rows (0, 2) keep a summed with the partner row, rows (1, 3) keep b
 __device__ __forceinline__ double halve16(double a, double b) {
   auto x = __builtin_amdgcn_permlane16_swap(lo32(a), lo32(b), false, false);
