@@ -124,8 +124,10 @@ __device__ __forceinline__ bool half_any(bool b) {
 // One column of the rate contraction: the moment vectors' column L of each
 // 16-lane row is broadcast into the FMAs (v_fmac_f64_dpp row_newbcast:L, the
 // DPP operand being src0).  eN += Phi_in x_s, oN += Phi_out y_s,
-// aP += Phi_ann x_sbar, eP += Phi_pro y_sbar.  The leading s_nop covers the
-// VALU-write to DPP-read distance for registers written just before.
+// aP += Phi_ann x_sbar, eP += Phi_ann (h y)_sbar, the last being Phi_pro y_sbar
+// by detailed balance once the row sum is scaled by h_q (h = exp(-e / T)).
+// The leading s_nop covers the VALU-write to DPP-read distance for registers
+// written just before.
 template <int NS>
 struct ColFmac;
 
@@ -133,26 +135,26 @@ template <>
 struct ColFmac<3> {
   template <int L>
   __device__ __forceinline__ static void run(double (&eN)[3], double (&oN)[3], double (&aP)[3], double (&eP)[3],
-                                             const double (&x)[3], const double (&y)[3], double fi, double fo,
-                                             double fa, double fp) {
+                                             const double (&x)[3], const double (&y)[3], const double (&hy)[3],
+                                             double fi, double fo, double fa) {
     asm volatile(
         "s_nop 1\n"
-        "v_fmac_f64_dpp %0, %12, %18 row_newbcast:%22 row_mask:0xf bank_mask:0xf\n"
-        "v_fmac_f64_dpp %1, %13, %18 row_newbcast:%22 row_mask:0xf bank_mask:0xf\n"
-        "v_fmac_f64_dpp %2, %14, %18 row_newbcast:%22 row_mask:0xf bank_mask:0xf\n"
-        "v_fmac_f64_dpp %3, %15, %19 row_newbcast:%22 row_mask:0xf bank_mask:0xf\n"
-        "v_fmac_f64_dpp %4, %16, %19 row_newbcast:%22 row_mask:0xf bank_mask:0xf\n"
-        "v_fmac_f64_dpp %5, %17, %19 row_newbcast:%22 row_mask:0xf bank_mask:0xf\n"
-        "v_fmac_f64_dpp %6, %13, %20 row_newbcast:%22 row_mask:0xf bank_mask:0xf\n"
-        "v_fmac_f64_dpp %7, %12, %20 row_newbcast:%22 row_mask:0xf bank_mask:0xf\n"
-        "v_fmac_f64_dpp %8, %14, %20 row_newbcast:%22 row_mask:0xf bank_mask:0xf\n"
-        "v_fmac_f64_dpp %9, %16, %21 row_newbcast:%22 row_mask:0xf bank_mask:0xf\n"
-        "v_fmac_f64_dpp %10, %15, %21 row_newbcast:%22 row_mask:0xf bank_mask:0xf\n"
-        "v_fmac_f64_dpp %11, %17, %21 row_newbcast:%22 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %0, %12, %21 row_newbcast:%24 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %1, %13, %21 row_newbcast:%24 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %2, %14, %21 row_newbcast:%24 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %3, %15, %22 row_newbcast:%24 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %4, %16, %22 row_newbcast:%24 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %5, %17, %22 row_newbcast:%24 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %6, %13, %23 row_newbcast:%24 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %7, %12, %23 row_newbcast:%24 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %8, %14, %23 row_newbcast:%24 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %9, %19, %23 row_newbcast:%24 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %10, %18, %23 row_newbcast:%24 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %11, %20, %23 row_newbcast:%24 row_mask:0xf bank_mask:0xf\n"
         : "+v"(eN[0]), "+v"(eN[1]), "+v"(eN[2]), "+v"(oN[0]), "+v"(oN[1]), "+v"(oN[2]), "+v"(aP[0]), "+v"(aP[1]),
           "+v"(aP[2]), "+v"(eP[0]), "+v"(eP[1]), "+v"(eP[2])
-        : "v"(x[0]), "v"(x[1]), "v"(x[2]), "v"(y[0]), "v"(y[1]), "v"(y[2]), "v"(fi), "v"(fo), "v"(fa), "v"(fp),
-          "i"(L));
+        : "v"(x[0]), "v"(x[1]), "v"(x[2]), "v"(y[0]), "v"(y[1]), "v"(y[2]), "v"(hy[0]), "v"(hy[1]), "v"(hy[2]),
+          "v"(fi), "v"(fo), "v"(fa), "i"(L));
   }
 };
 
@@ -160,20 +162,20 @@ template <>
 struct ColFmac<2> {
   template <int L>
   __device__ __forceinline__ static void run(double (&eN)[2], double (&oN)[2], double (&aP)[2], double (&eP)[2],
-                                             const double (&x)[2], const double (&y)[2], double fi, double fo,
-                                             double fa, double fp) {
+                                             const double (&x)[2], const double (&y)[2], const double (&hy)[2],
+                                             double fi, double fo, double fa) {
     asm volatile(
         "s_nop 1\n"
-        "v_fmac_f64_dpp %0, %8, %12 row_newbcast:%16 row_mask:0xf bank_mask:0xf\n"
-        "v_fmac_f64_dpp %1, %9, %12 row_newbcast:%16 row_mask:0xf bank_mask:0xf\n"
-        "v_fmac_f64_dpp %2, %10, %13 row_newbcast:%16 row_mask:0xf bank_mask:0xf\n"
-        "v_fmac_f64_dpp %3, %11, %13 row_newbcast:%16 row_mask:0xf bank_mask:0xf\n"
-        "v_fmac_f64_dpp %4, %9, %14 row_newbcast:%16 row_mask:0xf bank_mask:0xf\n"
-        "v_fmac_f64_dpp %5, %8, %14 row_newbcast:%16 row_mask:0xf bank_mask:0xf\n"
-        "v_fmac_f64_dpp %6, %11, %15 row_newbcast:%16 row_mask:0xf bank_mask:0xf\n"
-        "v_fmac_f64_dpp %7, %10, %15 row_newbcast:%16 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %0, %8, %14 row_newbcast:%17 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %1, %9, %14 row_newbcast:%17 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %2, %10, %15 row_newbcast:%17 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %3, %11, %15 row_newbcast:%17 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %4, %9, %16 row_newbcast:%17 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %5, %8, %16 row_newbcast:%17 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %6, %13, %16 row_newbcast:%17 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %7, %12, %16 row_newbcast:%17 row_mask:0xf bank_mask:0xf\n"
         : "+v"(eN[0]), "+v"(eN[1]), "+v"(oN[0]), "+v"(oN[1]), "+v"(aP[0]), "+v"(aP[1]), "+v"(eP[0]), "+v"(eP[1])
-        : "v"(x[0]), "v"(x[1]), "v"(y[0]), "v"(y[1]), "v"(fi), "v"(fo), "v"(fa), "v"(fp), "i"(L));
+        : "v"(x[0]), "v"(x[1]), "v"(y[0]), "v"(y[1]), "v"(hy[0]), "v"(hy[1]), "v"(fi), "v"(fo), "v"(fa), "i"(L));
   }
 };
 
@@ -181,16 +183,16 @@ template <>
 struct ColFmac<1> {
   template <int L>
   __device__ __forceinline__ static void run(double (&eN)[1], double (&oN)[1], double (&aP)[1], double (&eP)[1],
-                                             const double (&x)[1], const double (&y)[1], double fi, double fo,
-                                             double fa, double fp) {
+                                             const double (&x)[1], const double (&y)[1], const double (&hy)[1],
+                                             double fi, double fo, double fa) {
     asm volatile(
         "s_nop 1\n"
-        "v_fmac_f64_dpp %0, %4, %6 row_newbcast:%10 row_mask:0xf bank_mask:0xf\n"
-        "v_fmac_f64_dpp %1, %5, %7 row_newbcast:%10 row_mask:0xf bank_mask:0xf\n"
-        "v_fmac_f64_dpp %2, %4, %8 row_newbcast:%10 row_mask:0xf bank_mask:0xf\n"
-        "v_fmac_f64_dpp %3, %5, %9 row_newbcast:%10 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %0, %4, %7 row_newbcast:%10 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %1, %5, %8 row_newbcast:%10 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %2, %4, %9 row_newbcast:%10 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %3, %6, %9 row_newbcast:%10 row_mask:0xf bank_mask:0xf\n"
         : "+v"(eN[0]), "+v"(oN[0]), "+v"(aP[0]), "+v"(eP[0])
-        : "v"(x[0]), "v"(y[0]), "v"(fi), "v"(fo), "v"(fa), "v"(fp), "i"(L));
+        : "v"(x[0]), "v"(y[0]), "v"(hy[0]), "v"(fi), "v"(fo), "v"(fa), "i"(L));
   }
 };
 
@@ -276,7 +278,8 @@ struct PairSolver {
       // a finished half keeps a harmless temperature
       const double Tu = run ? T : 1.0, muu = run ? mu : 0.0;
       const double invT = 1.0 / Tu;
-      double baseD[NS], den0D[NS], den0I[NS];
+      double baseD[NS], den0D[NS];
+      double dsig = 0.0;  // dtau sigma: 1 + dtau kappa = 1 + dtau chi + dsig
       const double epsq = mt.eps[q];
       {
         const double shape = pt.chi0 * mt.shape[q];
@@ -291,28 +294,21 @@ struct PairSolver {
           const double deq = x > 0.0 ? ex * r : r;
           baseD[t] = Dst[t] + dtau * (chia * deq);
           den0D[t] = 1.0 + dtau * chia;
-          den0I[t] = 1.0 + dtau * (chia + sig);
         }
+        dsig = dtau * sig;
       }
       // pair factors of this lane's row, j = 0..31, signed by orientation:
       // +b(q, j) for j > q (q the lower node), -b(q, j) otherwise
       double B[COUPLED ? NQ : 1];
-      double Gq = 0.0, GR[2] = {0.0, 0.0};
+      double hq = 0.0;  // exp(-e_q / T)
       if constexpr (COUPLED) {
         SplitExp& E = S.E[h];
         const ExpSplit xs = exp_split(epsq, invT);
-        {
-          const double R2 = xs.R * xs.R;
-          E.P2[q] = xs.P;
-          E.R2[q] = xs.R;
-          E.n2[q] = xs.n;
-          E.G[q] = ldexp(R2 * R2, -4 * xs.n);  // exp(-2 e / T)
-        }
+        E.P2[q] = xs.P;
+        E.R2[q] = xs.R;
+        E.n2[q] = xs.n;
+        hq = ldexp(xs.R * xs.R, -2 * xs.n);  // 2^(-2x) = exp(-e / T)
         __syncthreads();
-        Gq = E.G[q];
-        // G of the point's nodes, each 16-lane row holding one half, for the
-        // column broadcasts of the contraction
-        swap16(Gq, GR[0], GR[1]);
         // signed pair factors of the point, each unordered pair (q, q + d mod
         // 32) once: d = 1..15 by every lane, d = 16 by lanes q < 16 (the
         // Anderson history is dead between inner loops, its space holds them)
@@ -330,7 +326,7 @@ struct PairSolver {
 
       // ---- inner loop over moments at fixed matter ------------------------
       const double w2q = mt.w2[q], w2eq = w2q * epsq;
-      const double Aeq = pt.An * epsq, Apq = pt.Ap * epsq;
+      const double Aeq = pt.An * epsq, Apq = pt.Ap * epsq, Apqh = Apq * hq;
       double G11 = 0.0;
       const bool ran = run;  // this half runs this outer iteration
       bool act = run;        // this half is still iterating the inner loop
@@ -342,9 +338,10 @@ struct PairSolver {
 #pragma unroll
         for (int t = 0; t < NS; ++t) etaN[t] = outN[t] = annP[t] = etaP[t] = 0.0;
         if constexpr (COUPLED) {
-          // W e D and W e (1 - D) of the point, each 16-lane row holding the
-          // half [16 R, 16 R + 16) of the nodes in XR[.][R], YR[.][R]
-          double XR[2][NS], YR[2][NS];
+          // W e D, W e (1 - D) and h W e (1 - D) of the point, each 16-lane
+          // row holding the half [16 R, 16 R + 16) of the nodes in XR[.][R],
+          // YR[.][R], HR[.][R]
+          double XR[2][NS], YR[2][NS], HR[2][NS];
           // the pair factors are re-read per iteration: the per-column
           // products are not hoisted out of the inner loop (they would need
           // four times the registers)
@@ -352,23 +349,23 @@ struct PairSolver {
           for (int j = 0; j < NQ; ++j) asm volatile("" : "+v"(B[j]));
 #pragma unroll
           for (int t = 0; t < NS; ++t) {
-            const double xv = w2eq * D[t];
+            const double xv = w2eq * D[t], yv = w2eq - xv;
             swap16(xv, XR[0][t], XR[1][t]);
-            swap16(w2eq - xv, YR[0][t], YR[1][t]);
+            swap16(yv, YR[0][t], YR[1][t]);
+            swap16(hq * yv, HR[0][t], HR[1][t]);
           }
           static_for<0, NQ / 2>([&](auto jj) __attribute__((always_inline)) {
             constexpr int j0 = 2 * decltype(jj)::value;
             static_for<0, 2>([&](auto ee) __attribute__((always_inline)) {
               constexpr int j = j0 + decltype(ee)::value;
-              // G_j broadcast from registers (an LDS read here stalled every
-              // column pair on its latency)
-              const double Gj = row_bcast<j % 16>(GR[j / 16]);
               // with s = +-b and c = s^3 = +-b^3 (the same sign): max(s, -c) is
               // b where s > 0 and b^3 where s < 0, i.e. Phi_in, and max(c, -s)
-              // is Phi_out (scaled entries), without compares or selects
+              // is Phi_out (scaled entries), without compares or selects;
+              // Phi_ann = b^2 serves the pair production term as well
+              // (detailed balance: Phi_pro = Phi_ann h_q h_j)
               const double sb = B[j], b2 = sb * sb, c3 = sb * b2;
-              ColFmac<NS>::template run<j % 16>(etaN, outN, annP, etaP, XR[j / 16], YR[j / 16],
-                                                max_neg_f64(sb, c3), max_neg_f64(c3, sb), b2, min_f64(Gj, Gq));
+              ColFmac<NS>::template run<j % 16>(etaN, outN, annP, etaP, XR[j / 16], YR[j / 16], HR[j / 16],
+                                                max_neg_f64(sb, c3), max_neg_f64(c3, sb), b2);
             });
           });
         }
@@ -378,9 +375,9 @@ struct PairSolver {
         double Qx[2 * NS], Fx[2 * NS];
 #pragma unroll
         for (int t = 0; t < NS; ++t) {
-          const double eta = __builtin_fma(Aeq, etaN[t], Apq * etaP[t]);
+          const double eta = __builtin_fma(Aeq, etaN[t], Apqh * etaP[t]);
           const double chi = __builtin_fma(Aeq, outN[t], __builtin_fma(Apq, annP[t], eta));
-          const double dD = __builtin_fma(dtau, chi, den0D[t]), dI = __builtin_fma(dtau, chi, den0I[t]);
+          const double dD = __builtin_fma(dtau, chi, den0D[t]), dI = dD + dsig;
           const double r = rcp_nr(dD * dI);
           Qx[t] = __builtin_fma(dtau, eta, baseD[t]) * (r * dI);
           Qx[NS + t] = Ist[t] * (r * dD);
