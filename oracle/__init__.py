@@ -100,6 +100,14 @@ def lib():
         L.ora_adjoint_batch.restype = C.c_int
         L.ora_init_state.argtypes = [C.POINTER(_Model), C.c_long, dp, vp, dp, dp, dp, dp,
                                      C.c_double, C.c_double, C.c_double, dp, dp, vp]
+        L.ora_minerbo_psi.argtypes = [C.c_double]
+        L.ora_minerbo_psi.restype = C.c_double
+        L.ora_flux_factor.argtypes = [C.c_double, C.c_double]
+        L.ora_flux_factor.restype = C.c_double
+        L.ora_eddington.argtypes = [C.c_double, dp, dp]
+        L.ora_solve_batch_v.argtypes = [C.POINTER(_Model), C.POINTER(_Params), dp, C.c_long, C.c_double,
+                                        dp, dp, dp, dp, dp, dp, vp,
+                                        dp, dp, dp, dp, dp, dp, ip, ip, ip, C.c_int]
         _lib = L
     return _lib
 
@@ -315,3 +323,44 @@ def adjoint_batch(model: Model, theta, dtau, rho11, D, ye, e, gbar, chi0=None, p
         raise RuntimeError("singular Jacobian in the oracle adjoint")
     return (g, gpp.reshape(P, nt)) if per_point else g
 
+
+
+# ---------------------------------------------------------------------------
+# O(v) coupling (nonzero fluid velocity)
+
+MU_C2 = 931.49410242  # atomic mass unit rest energy [MeV]
+
+
+def minerbo_psi(h: float) -> float:
+    return lib().ora_minerbo_psi(h)
+
+
+def flux_factor(D: float, Imag: float) -> float:
+    return lib().ora_flux_factor(D, Imag)
+
+
+def eddington(D: float, I3) -> np.ndarray:
+    K = np.zeros(9)
+    lib().ora_eddington(D, _f64(I3), K)
+    return K.reshape(3, 3)
+
+
+def solve_batch_v(model: Model, params: Params, theta, dtau, D0, I0, rho11, ye0, ef0, v0, chi0=None,
+                  nthreads: int = 0):
+    """Batched O(v) forward solve.  D0 (P, ns, nq), I0 (P, ns, 3, nq), v0 (P, 3);
+    ef0 is the specific fluid energy (internal plus kinetic) [MeV/baryon]."""
+    D0 = _f64(D0)
+    P = D0.shape[0]
+    nn = model.ns * model.nq
+    D, I = np.zeros(P * nn), np.zeros(P * 3 * nn)
+    ye, ef, v, T = np.zeros(P), np.zeros(P), np.zeros(P * 3), np.zeros(P)
+    no, ni, st = np.zeros(P, np.int32), np.zeros(P, np.int32), np.zeros(P, np.int32)
+    chi0 = None if chi0 is None else _f64(chi0)
+    pc = params.c()
+    rc = lib().ora_solve_batch_v(model.ref(), C.byref(pc), _f64(theta), P, dtau, D0.ravel(),
+                                 _f64(I0).ravel(), _f64(rho11), _f64(ye0), _f64(ef0), _f64(v0).ravel(),
+                                 _vp(chi0), D, I, ye, ef, v, T, no, ni, st, nthreads)
+    if rc != 0:
+        raise ValueError("oracle rejected the arguments")
+    return dict(D=D.reshape(P, model.ns, model.nq), I=I.reshape(P, model.ns, 3, model.nq), ye=ye, ef=ef,
+                v=v.reshape(P, 3), T=T, n_outer=no, n_inner=ni, status=st)

@@ -17,8 +17,12 @@
  * implicitNumberFluxNodal, emissivityEmAbNodal), the equilibrium fixed point,
  * the large-dtau equilibrium limit, Newton on tiny problems, Anderson finite
  * termination on linear maps, and finite differences for the Jacobian and the
- * adjoint.  Exact iteration counts and intermediate iterates are parity
- * unpinned.
+ * adjoint.  The O(v) solve is pinned by the Minerbo closure's limits, trace
+ * and eigen-structure and its fit to the exact maximum-entropy closure, the
+ * dtau = 0 identity, the moving-equilibrium fixed point, the reduction to the
+ * static solve at v = 0 without flux, and dense Newton on the unrearranged
+ * implicit equations.  Exact iteration counts and intermediate iterates are
+ * parity unpinned.
  */
 #include "nmc_oracle.h"
 
@@ -932,6 +936,301 @@ int ora_adjoint_batch(const ora_model* m, const double* theta, long P, double dt
 }
 
 /* ------------------------------------------------------------------------ */
+/* ------------------------------------------------------------------------ */
+/* O(v) coupling: the moment equations and matter update of Sec. 3.5.1 with a
+ * nonzero fluid velocity.  Unknowns D (ns, nq) and I (ns, 3, nq); matter
+ * y = (Ye, ef, v_1, v_2, v_3) with ef the specific fluid energy (internal
+ * plus kinetic, MeV per baryon) and v in units of c. */
+
+/* Minerbo closure: Eddington factor as a polynomial in the flux factor
+ * (Eq. eddingtonFactorMinerbo). */
+double ora_minerbo_psi(double h) { return 1.0 / 3.0 + (2.0 / 15.0) * (3.0 - h + 3.0 * h * h) * h * h; }
+
+/* flux factor h = |I| / D, taken as 0 without flux and limited to the
+ * realizable range [0, 1] (1 also when D <= 0 carries a flux) */
+double ora_flux_factor(double D, double Imag) {
+  if (!(Imag > 0.0)) return 0.0;
+  if (!(D > 0.0)) return 1.0;
+  double h = Imag / D;
+  return h < 1.0 ? h : 1.0;
+}
+
+/* K_ij = k_ij D with k_ij = ((1 - psi) delta_ij + (3 psi - 1) n_i n_j) / 2,
+ * n = I / |I| (Eq. eddingtonTensor, flat metric) */
+void ora_eddington(double D, const double* I3, double* K9) {
+  double Imag = sqrt(I3[0] * I3[0] + I3[1] * I3[1] + I3[2] * I3[2]);
+  double psi = ora_minerbo_psi(ora_flux_factor(D, Imag));
+  double a = 0.5 * (1.0 - psi), b = 0.5 * (3.0 * psi - 1.0);
+  double n[3] = {0.0, 0.0, 0.0};
+  if (Imag > 0.0)
+    for (int i = 0; i < 3; ++i) n[i] = I3[i] / Imag;
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) K9[3 * i + j] = D * ((i == j ? a : 0.0) + b * n[i] * n[j]);
+}
+
+/* the three flux components of species s at node q */
+static void flux3(const ora_model* m, const double* I, int s, int q, double* I3) {
+  for (int j = 0; j < 3; ++j) I3[j] = I[(s * 3 + j) * m->nq + q];
+}
+
+/* Eulerian neutrino lepton number, energy and momentum with the LG
+ * quadrature (Eqs. eulerianNumberLG, eulerianEnergyLG, eulerianMomentumLG;
+ * the common factor 4 pi / h^3 is folded into the coupling constant):
+ * X = (N, E, F_1, F_2, F_3) */
+static void eulerian_v(const ora_model* m, const double* D, const double* I, const double* v, double* X) {
+  int nq = m->nq, ns = m->ns;
+  for (int i = 0; i < 5; ++i) X[i] = 0.0;
+  for (int s = 0; s < ns; ++s) {
+    int id = m->species[s];
+    for (int q = 0; q < nq; ++q) {
+      double Dq = D[s * nq + q], I3[3], K9[9];
+      flux3(m, I, s, q, I3);
+      ora_eddington(Dq, I3, K9);
+      double vI = v[0] * I3[0] + v[1] * I3[1] + v[2] * I3[2];
+      X[0] += sp_g(id) * m->w2[q] * (Dq + vI);
+      X[1] += sp_d(id) * m->w3[q] * (Dq + 2.0 * vI);
+      for (int j = 0; j < 3; ++j) {
+        double vK = v[0] * K9[3 * j] + v[1] * K9[3 * j + 1] + v[2] * K9[3 * j + 2];
+        X[2 + j] += sp_d(id) * m->w3[q] * (I3[j] + v[j] * Dq + vK);
+      }
+    }
+  }
+}
+
+/* matter right-hand side q(M, y) (Eq. implicitFluidNodal): the changes of
+ * the Eulerian neutrino lepton number, energy and momentum per baryon are
+ * removed from the matter; the momentum change per baryon divided by the
+ * baryon rest energy m_u c^2 is the velocity change. */
+static void matter_rhs_v(const ora_model* m, double rho11, const double* D, const double* I, const double* y,
+                         const double* X0, const double* ystar, double* yq) {
+  double X[5], K = m->kcoup / rho11;
+  eulerian_v(m, D, I, y + 2, X);
+  yq[0] = ystar[0] - K * (X[0] - X0[0]);
+  yq[1] = ystar[1] - K * (X[1] - X0[1]);
+  for (int j = 0; j < 3; ++j) yq[2 + j] = ystar[2 + j] - (K / ORA_MU_C2) * (X[2 + j] - X0[2 + j]);
+}
+
+static double norm3(const double* v) { return sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]); }
+
+/* temperature from the EOS at the internal energy ef - m_u c^2 |v|^2 / 2 */
+static double eos_temperature_v(const ora_model* m, const double* y, double rho11) {
+  double vm = norm3(y + 2);
+  return ora_eos_temperature(m, y[1] - 0.5 * ORA_MU_C2 * vm * vm, y[0], rho11);
+}
+
+#define MAXNV (4 * ORA_MAX_NS * ORA_MAX_NQ)
+typedef struct {
+  double M[MAXNV], Mnew[MAXNV], Q[MAXNV], F[MAXNV];
+  double Qh[MAXMEM * MAXNV], Fh[MAXMEM * MAXNV];
+  double Nst[ORA_MAX_NS * ORA_MAX_NQ], Gst[3 * ORA_MAX_NS * ORA_MAX_NQ];
+  double eta[ORA_MAX_NS * ORA_MAX_NQ], chi[ORA_MAX_NS * ORA_MAX_NQ], kap[ORA_MAX_NS * ORA_MAX_NQ];
+  opac o;
+} work_v;
+
+/* Algorithm neutrinoMatterCoupling for one spatial point with v != 0. */
+static int solve_point_v(const ora_model* m, const ora_params* prm, const double* theta, double dtau,
+                         const double* Dst, const double* Ist, double rho11, const double* ystar, double chi0,
+                         double* D, double* I, double* yout, double* T_out, int* n_outer, int* n_inner,
+                         work_v* w) {
+  int nq = m->nq, ns = m->ns, nn = ns * nq, n = 4 * nn;
+  double y[5], yused[5], X0[5];
+  double qh[MAXMEM * 5], fh[MAXMEM * 5];
+  int ocount = 0;
+  int status = ORA_OK, inner_failed = 0, outer_conv = 0, fatal = 0;
+  int total_inner = 0, k;
+  for (int i = 0; i < 5; ++i) y[i] = yused[i] = ystar[i];
+  double T_last = eos_temperature_v(m, ystar, rho11);
+
+  /* number and number-flux densities of the old state, N* = D* + v*.I* and
+   * G*_j = I*_j + v*^i K*_ij (Eq. numberDensityEulerian and the left-hand
+   * sides of Eqs. implicitNumberNodal, implicitNumberFluxNodal at M*, v*), and
+   * the old Eulerian lepton number, energy and momentum */
+  for (int s = 0; s < ns; ++s)
+    for (int q = 0; q < nq; ++q) {
+      double Dq = Dst[s * nq + q], I3[3], K9[9];
+      const double* vs = ystar + 2;
+      flux3(m, Ist, s, q, I3);
+      ora_eddington(Dq, I3, K9);
+      w->Nst[s * nq + q] = Dq + (vs[0] * I3[0] + vs[1] * I3[1] + vs[2] * I3[2]);
+      for (int j = 0; j < 3; ++j)
+        w->Gst[(s * 3 + j) * nq + q] = I3[j] + (vs[0] * K9[3 * j] + vs[1] * K9[3 * j + 1] + vs[2] * K9[3 * j + 2]);
+    }
+  eulerian_v(m, Dst, Ist, ystar + 2, X0);
+
+  /* initial guesses: y^[1] = y*, M^[1,1] = M* */
+  for (int i = 0; i < nn; ++i) w->M[i] = Dst[i];
+  for (int i = 0; i < 3 * nn; ++i) w->M[nn + i] = Ist[i];
+
+  for (k = 1; k <= prm->max_outer; ++k) {
+    const double* v = y + 2;
+    double vmag = norm3(v);
+    /* step-size parameter lambda = 1 / (1 + |v|) (remark on the choice of lambda) */
+    double lam = 1.0 / (1.0 + vmag);
+    double T = eos_temperature_v(m, prm->fixed_matter ? ystar : y, rho11);
+    double mu = ora_eos_mu(m, y[0], T, rho11);
+    if (!(T > 0.0) || !(y[0] >= 0.0) || !isfinite(T) || !isfinite(mu)) {
+      status = ORA_EOS_DOMAIN;
+      fatal = 1;
+      break;
+    }
+    T_last = T;
+    for (int i = 0; i < 5; ++i) yused[i] = y[i];
+    compute_opacities(m, theta, rho11, chi0, T, mu, &w->o);
+
+    double dref0[ORA_MAX_NS];
+    for (int s = 0; s < ns; ++s) dref0[s] = wnorm(m, w->M + s * nq);
+    int icount = 0, conv = 0, l;
+    for (l = 1; l <= prm->max_inner; ++l) {
+      /* ComputeRates and the moment right-hand side Q (Eq. implicitMomentsNodal):
+       * Q_D = ((1 - lam) D + lam (N* - v.I + dtau eta)) / (1 + lam dtau chi),
+       * Q_Ij = ((1 - lam) I_j + lam (G*_j - v^i K_ij)) / (1 + lam dtau kappa) */
+      rates(m, &w->o, w->M, w->eta, w->chi, w->kap);
+      for (int s = 0; s < ns; ++s)
+        for (int q = 0; q < nq; ++q) {
+          int i = s * nq + q;
+          double Dq = w->M[i], I3[3], K9[9];
+          flux3(m, w->M + nn, s, q, I3);
+          ora_eddington(Dq, I3, K9);
+          double vI = v[0] * I3[0] + v[1] * I3[1] + v[2] * I3[2];
+          w->Q[i] = ((1.0 - lam) * Dq + lam * (w->Nst[i] - vI + dtau * w->eta[i])) / (1.0 + lam * dtau * w->chi[i]);
+          for (int j = 0; j < 3; ++j) {
+            int ij = (s * 3 + j) * nq + q;
+            double vK = v[0] * K9[3 * j] + v[1] * K9[3 * j + 1] + v[2] * K9[3 * j + 2];
+            w->Q[nn + ij] = ((1.0 - lam) * I3[j] + lam * (w->Gst[ij] - vK)) / (1.0 + lam * dtau * w->kap[i]);
+          }
+        }
+      for (int i = 0; i < n; ++i) w->F[i] = w->Q[i] - w->M[i];
+      hist_push(w->Qh, w->Fh, &icount, prm->m_inner, n, w->Q, w->F);
+      ora_anderson(n, icount, w->Qh, w->Fh, w->Mnew);
+      if (!all_finite(w->Mnew, n)) {
+        status = ORA_NONFINITE;
+        fatal = 1;
+        break;
+      }
+      /* Algorithm innerConverged over the four moments D, I_1, I_2, I_3 */
+      conv = 1;
+      for (int s = 0; s < ns; ++s) {
+        double sm[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int q = 0; q < nq; ++q) {
+          double dd = w->Mnew[s * nq + q] - w->M[s * nq + q];
+          sm[0] += m->w2[q] * dd * dd;
+          for (int j = 0; j < 3; ++j) {
+            int ij = nn + (s * 3 + j) * nq + q;
+            double di = w->Mnew[ij] - w->M[ij];
+            sm[1 + j] += m->w2[q] * di * di;
+          }
+        }
+        double mx = sm[0];
+        for (int j = 1; j < 4; ++j)
+          if (sm[j] > mx) mx = sm[j];
+        double dnew = wnorm(m, w->Mnew + s * nq);
+        double dref = dref0[s] > dnew ? dref0[s] : dnew;
+        if (!(sqrt(mx) <= prm->tol_inner * dref)) conv = 0;
+      }
+      memcpy(w->M, w->Mnew, sizeof(double) * n);
+      if (conv) break;
+    }
+    total_inner += (l > prm->max_inner ? prm->max_inner : l);
+    if (fatal) break;
+    if (!conv) inner_failed = 1;
+
+    if (prm->fixed_matter) {
+      outer_conv = 1;
+      break;
+    }
+
+    /* matter right-hand side, residual and outer Anderson step on y */
+    double yq[5], f[5], ynew[5];
+    matter_rhs_v(m, rho11, w->M, w->M + nn, y, X0, ystar, yq);
+    for (int i = 0; i < 5; ++i) f[i] = yq[i] - y[i];
+    hist_push(qh, fh, &ocount, prm->m_outer, 5, yq, f);
+    ora_anderson(5, ocount, qh, fh, ynew);
+    if (!all_finite(ynew, 5)) {
+      status = ORA_NONFINITE;
+      fatal = 1;
+      break;
+    }
+    /* Algorithm outerConverged: Ye and ef componentwise against y*; each
+     * velocity component against the speed max(|v*|, |v^[k+1]|) */
+    double vref = norm3(ystar + 2), vn = norm3(ynew + 2);
+    if (vn > vref) vref = vn;
+    int oc = fabs(ynew[0] - y[0]) <= prm->tol_outer * fabs(ystar[0]) &&
+             fabs(ynew[1] - y[1]) <= prm->tol_outer * fabs(ystar[1]);
+    for (int j = 0; j < 3; ++j) oc = oc && fabs(ynew[2 + j] - y[2 + j]) <= prm->tol_outer * vref;
+    for (int i = 0; i < 5; ++i) y[i] = ynew[i];
+    if (oc) {
+      outer_conv = 1;
+      break;
+    }
+  }
+  if (k > prm->max_outer) k = prm->max_outer;
+  if (!fatal) {
+    if (!outer_conv) status = ORA_MAX_OUTER;
+    else if (inner_failed) status = ORA_MAX_INNER;
+  }
+
+  for (int i = 0; i < nn; ++i) D[i] = w->M[i];
+  for (int i = 0; i < 3 * nn; ++i) I[i] = w->M[nn + i];
+  if (prm->fixed_matter) {
+    for (int i = 0; i < 5; ++i) yout[i] = ystar[i];
+    *T_out = T_last;
+  } else {
+    /* output matter state: the matter right-hand side at the final moments
+     * and the matter iterate they were solved at */
+    matter_rhs_v(m, rho11, w->M, w->M + nn, yused, X0, ystar, yout);
+    *T_out = eos_temperature_v(m, yout, rho11);
+  }
+  *n_outer = k;
+  *n_inner = total_inner;
+  return status;
+}
+
+int ora_solve_batch_v(const ora_model* m, const ora_params* prm, const double* theta, long P, double dtau,
+                      const double* D0, const double* I0, const double* rho11, const double* ye0,
+                      const double* ef0, const double* v0, const double* chi0,
+                      double* D, double* I, double* ye, double* ef, double* v, double* T,
+                      int* n_outer, int* n_inner, int* status, int nthreads) {
+  if (m->nq < 1 || m->nq > ORA_MAX_NQ || m->ns < 1 || m->ns > ORA_MAX_NS) return -1;
+  if (prm->m_inner < 1 || prm->m_inner > MAXMEM || prm->m_outer < 1 || prm->m_outer > MAXMEM) return -1;
+  if (prm->max_inner < 1 || prm->max_outer < 1) return -1;
+  if ((m->flags & ORA_PAIR))
+    for (int s = 0; s < m->ns; ++s)
+      if (partner_index(m, s) < 0) return -1;
+  int nn = m->ns * m->nq;
+#ifdef _OPENMP
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel
+#endif
+  {
+    work_v* w = (work_v*)malloc(sizeof(work_v));
+#ifdef _OPENMP
+#pragma omp for schedule(dynamic, 16)
+#endif
+    for (long p = 0; p < P; ++p) {
+      double c0 = chi0 ? chi0[p] : m->chi_ref * rho11[p];
+      double ystar[5] = {ye0[p], ef0[p], v0[3 * p], v0[3 * p + 1], v0[3 * p + 2]}, yo[5];
+      if (rho11[p] < m->rho11_min) {
+        /* coupling disabled at low density (Sec. 7.2): pass through */
+        for (int i = 0; i < nn; ++i) D[p * nn + i] = D0[p * nn + i];
+        for (int i = 0; i < 3 * nn; ++i) I[p * 3 * nn + i] = I0[p * 3 * nn + i];
+        for (int i = 0; i < 5; ++i) yo[i] = ystar[i];
+        T[p] = eos_temperature_v(m, ystar, rho11[p]);
+        n_outer[p] = 0;
+        n_inner[p] = 0;
+        status[p] = ORA_OK;
+      } else {
+        status[p] = solve_point_v(m, prm, theta, dtau, D0 + p * nn, I0 + p * 3 * nn, rho11[p], ystar, c0,
+                                  D + p * nn, I + p * 3 * nn, yo, T + p, n_outer + p, n_inner + p, w);
+      }
+      ye[p] = yo[0];
+      ef[p] = yo[1];
+      for (int j = 0; j < 3; ++j) v[3 * p + j] = yo[2 + j];
+    }
+    free(w);
+  }
+  return 0;
+}
+
 /* Initial state from raw draws: e* from the EOS, D* = clip(D_eq (a + b uD),
  * 0, 1 - 1e-12), I* = c D* uI.  If mu is NULL it follows from the EOS. */
 int ora_init_state(const ora_model* m, long P, const double* T, const double* mu, const double* rho11,

@@ -106,6 +106,28 @@ int ora_adjoint_batch(const ora_model* m, const double* theta, long P, double dt
                       const double* chi0, const double* D, const double* ye, const double* e,
                       const double* gbar, double* grad_theta, double* grad_pp, int nthreads);
 
+/* ---- O(v) coupling: nonzero fluid velocity (Sec. 3.5.1 in full) ----------
+ * Moments per point: D (ns, nq) and the three flux components I (ns, 3, nq);
+ * matter y = (Ye, ef, v_1, v_2, v_3) with ef the specific fluid energy
+ * (internal plus kinetic) in MeV per baryon and v in units of c. */
+#define ORA_MU_C2 931.49410242 /* atomic mass unit rest energy [MeV] */
+
+/* Minerbo Eddington factor psi(h) (Eq. eddingtonFactorMinerbo) */
+double ora_minerbo_psi(double h);
+/* flux factor h = |I| / D used by the closure, in [0, 1] */
+double ora_flux_factor(double D, double Imag);
+/* K_ij = k_ij D (Eq. eddingtonTensor with the Minerbo factor), 3x3 row-major */
+void ora_eddington(double D, const double* I3, double* K9);
+
+/* batched O(v) forward solve (Algorithm neutrinoMatterCoupling with
+ * Eqs. implicitMomentsNodal at lambda = 1/(1+|v|), implicitFluidNodal,
+ * eulerianMomentumLG, eulerianEnergyLG, eulerianNumberLG) */
+int ora_solve_batch_v(const ora_model* m, const ora_params* prm, const double* theta, long P, double dtau,
+                      const double* D0, const double* I0, const double* rho11, const double* ye0,
+                      const double* ef0, const double* v0, const double* chi0,
+                      double* D, double* I, double* ye, double* ef, double* v, double* T,
+                      int* n_outer, int* n_inner, int* status, int nthreads);
+
 /* initial state from raw draws */
 int ora_init_state(const ora_model* m, long P, const double* T, const double* mu, const double* rho11,
                    const double* ye, const double* uD, const double* uI, double a, double b, double c,

@@ -35,6 +35,8 @@ class Draws:
     a: float = 1.0            # D* = clip(D_eq (a + b uD))
     b: float = 0.1
     c: float = 0.1            # I* = c D* uI
+    v: np.ndarray | None = None    # (P, 3) fluid velocity [c] (O(v) workloads)
+    uI3: np.ndarray | None = None  # (P, ns, 3, nq) noise in [-1, 1) for three flux components
 
     @property
     def P(self):
@@ -44,7 +46,8 @@ class Draws:
         idx = np.asarray(idx)
         sel = lambda x: None if x is None else np.ascontiguousarray(x[idx])
         return Draws(sel(self.T), sel(self.rho11), sel(self.ye), sel(self.uD), sel(self.uI),
-                     sel(self.mu), sel(self.chi0), sel(self.r_km), self.a, self.b, self.c)
+                     sel(self.mu), sel(self.chi0), sel(self.r_km), self.a, self.b, self.c,
+                     sel(self.v), sel(self.uI3))
 
 
 def emab_iso_fixed(P: int = 1000, ns: int = 2, nq: int = 32, seed: int = 0) -> Draws:
@@ -91,6 +94,22 @@ def radial_profile(P: int = 1 << 16, ns: int = 3, nq: int = 32, seed: int = 0, w
     uD = rng.uniform(-1.0, 1.0, (P, ns, nq))
     uI = rng.uniform(-1.0, 1.0, (P, ns, nq))
     return Draws(T, rho11, ye, uD, uI, r_km=r)
+
+
+def radial_profile_v(P: int = 1 << 16, ns: int = 3, nq: int = 32, seed: int = 0, wid: int = 6) -> Draws:
+    """The radial profile of ``radial_profile`` with fluid motion, for the
+    O(v) solve: every point sits at its radius in a random direction n (uniform
+    on the sphere) and moves with v = v_r(r) n + 0.005 Z3 (c units),
+    v_r = -0.1 (1 - exp(-r/50)) (infall that vanishes at the centre); the
+    three flux components get independent noise (I*_j = 0.1 D* uI3_j)."""
+    d = radial_profile(P, ns, nq, seed, wid)
+    rng = np.random.default_rng([wid, seed, 1])
+    n = rng.standard_normal((P, 3))
+    n /= np.linalg.norm(n, axis=1, keepdims=True)
+    vr = -0.1 * (1.0 - np.exp(-d.r_km / 50.0))
+    d.v = np.ascontiguousarray(vr[:, None] * n + 0.005 * rng.standard_normal((P, 3)))
+    d.uI3 = rng.uniform(-1.0, 1.0, (P, ns, 3, nq))
+    return d
 
 
 def fd_sample(P_total: int, n: int, seed: int = 0) -> np.ndarray:
