@@ -9,7 +9,8 @@
  *
  * with neutrino number moments D and number fluxes I on an energy-node grid
  * for up to three species (nu_e, anti-nu_e, and nu_x standing for the four
- * heavy-lepton flavours), and matter state y = (Ye, e) at zero fluid velocity.
+ * heavy-lepton flavours), and matter state y = (Ye, e) at zero fluid velocity
+ * (nmc_solve_batch) or y = (Ye, ef, v) with the O(v) terms (nmc_solve_batch_v).
  * The moment equations are Eqs. implicitNumberNodal / implicitNumberFluxNodal,
  * the rates Eqs. emissivityNodal ... pairRatesNodal, the matter update Eq.
  * implicitFluidNodal, and the iteration the nested fixed point with Anderson
@@ -236,6 +237,57 @@ int nmc_solve_batch(const nmc_model* m, const nmc_solver_params* prm, int64_t P,
 int nmc_solve_batch_adjoint(const nmc_model* m, int64_t P, double dtau, const nmc_batch_in* in,
                             const nmc_batch_out* fwd, const double* gbar, double* grad_theta,
                             double* grad_pp, void* ws, size_t ws_bytes, void* stream);
+
+/* O(v) solve: nonzero fluid velocity (the O(v/c) two-moment model of
+ * Sec. 2, solved as in Sec. 3.5).  The moment equations keep every velocity
+ * term of Eqs. implicitNumberNodal / implicitNumberFluxNodal and are
+ * iterated in the fixed-point form of Eq. implicitMomentsNodal with
+ * lambda = 1 / (1 + |v|); the flux equation is closed with the Minerbo
+ * Eddington tensor (Eqs. eddingtonFactorMinerbo, eddingtonTensor; flux
+ * factor |I| / D limited to [0, 1]).  The matter state y = (Ye, ef, v) holds
+ * the specific fluid energy ef = e + m_u c^2 |v|^2 / 2 [MeV/baryon] (the EOS
+ * sees e) and the velocity v in units of c; Eq. implicitFluidNodal moves
+ * into it the changes of the Eulerian neutrino lepton number, energy and
+ * momentum of Eqs. eulerianNumberLG, eulerianEnergyLG, eulerianMomentumLG
+ * (momentum per baryon divided by m_u c^2 = 931.494 MeV).  The old state is
+ * given in primitive moments; the old conserved moments N* = D* + v*.I* and
+ * G*_j = I*_j + v*^i K*_ij are formed from it.  The outer test compares Ye
+ * and ef against y* componentwise and each velocity component against the
+ * speed max(|v*|, |v^[k+1]|).  The output matter state is the matter
+ * right-hand side at the final moments and the matter iterate they were
+ * solved at.  Same status codes, skip rule and in-place aliasing as
+ * nmc_solve_batch. */
+typedef struct {
+  const double* D0;    /* (P, ns, nq) number moments D* */
+  const double* I0;    /* (P, ns, 3, nq) number-flux moments: component j of species s at [p][s][j][:] */
+  const double* rho11; /* (P) */
+  const double* ye0;   /* (P) Ye* */
+  const double* ef0;   /* (P) ef* [MeV/baryon], internal plus kinetic */
+  const double* v0;    /* (P, 3) fluid velocity v* [c] */
+  const double* chi0;  /* (P) absorption scale [1/km] or NULL for chi_ref * rho11 */
+  const double* theta; /* (nq + 2) as in nmc_batch_in */
+} nmc_batch_v_in;
+
+typedef struct {
+  double* D;           /* (P, ns, nq); may alias D0 */
+  double* I;           /* (P, ns, 3, nq); may alias I0 */
+  double* ye;          /* (P); may alias ye0 */
+  double* ef;          /* (P); may alias ef0 */
+  double* v;           /* (P, 3); may alias v0 */
+  double* T;           /* (P) temperature of the output state */
+  int32_t* n_outer;    /* (P) */
+  int32_t* n_inner;    /* (P) */
+  int32_t* status;     /* (P) NMC_STATUS_* */
+} nmc_batch_v_out;
+
+/* Batched O(v) forward solve.  32-node grids only (NMC_E_UNSUPPORTED
+ * otherwise); one point per wavefront with the kernel entries regenerated on
+ * chip (launch->kernel_store must be NMC_KERNELS_ON_CHIP).  Workspace,
+ * launch, stream and error rules as for nmc_solve_batch; dtau must be
+ * positive. */
+int nmc_solve_batch_v(const nmc_model* m, const nmc_solver_params* prm, int64_t P, double dtau,
+                      const nmc_batch_v_in* in, const nmc_batch_v_out* out, void* ws, size_t ws_bytes,
+                      const nmc_launch* launch, void* stream);
 
 /* Initial neutrino state from raw draws: e0 = EOS(T, Ye, rho11),
  * D0 = clip(D_eq(T, mu) (a + b uD), 0, 1 - 1e-12), I0 = c D0 uI, with mu from

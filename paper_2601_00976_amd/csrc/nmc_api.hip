@@ -373,6 +373,74 @@ int nmc_solve_batch(const nmc_model* m, const nmc_solver_params* prm, int64_t P,
   return NMC_OK;
 }
 
+int nmc_solve_batch_v(const nmc_model* m, const nmc_solver_params* prm, int64_t P, double dtau,
+                      const nmc_batch_v_in* in, const nmc_batch_v_out* out, void* ws, size_t ws_bytes,
+                      const nmc_launch* launch, void* stream) {
+  if (!m || !in || !out) return fail(NMC_E_INVALID_ARG, "solve_batch_v: null handle or descriptor");
+  int rc = check_params(prm);
+  if (rc) return rc;
+  if (P < 0 || P > (int64_t(1) << 30)) return fail(NMC_E_INVALID_ARG, "solve_batch_v: P out of range (%lld)", (long long)P);
+  if (!(dtau > 0.0) || !isfinite(dtau)) return fail(NMC_E_INVALID_ARG, "solve_batch_v: dtau must be positive");
+  if (m->host.nq != 32)
+    return fail(NMC_E_UNSUPPORTED, "solve_batch_v: implemented for 32 energy nodes (model has %d)", m->host.nq);
+  if (P == 0) return NMC_OK;
+  if (!in->D0 || !in->I0 || !in->rho11 || !in->ye0 || !in->ef0 || !in->v0 || !in->theta)
+    return fail(NMC_E_INVALID_ARG, "solve_batch_v: null input array");
+  if (!out->D || !out->I || !out->ye || !out->ef || !out->v || !out->T || !out->n_outer || !out->n_inner ||
+      !out->status)
+    return fail(NMC_E_INVALID_ARG, "solve_batch_v: null output array");
+  nmc_launch L = {0, 1, 1, NMC_KERNELS_ON_CHIP};
+  if (launch) L = *launch;
+  if (L.chunk < 1 || L.chunk > 4096 || L.blocks_per_cu < 0 || L.blocks_per_cu > 64)
+    return fail(NMC_E_INVALID_ARG, "solve_batch_v: bad launch configuration");
+  if (L.kernel_store != NMC_KERNELS_ON_CHIP)
+    return fail(NMC_E_UNSUPPORTED, "solve_batch_v: kernel_store must be NMC_KERNELS_ON_CHIP");
+  if (L.persistent && (!ws || !aligned256(ws) || ws_bytes < kCounterBytes))
+    return fail(NMC_E_WORKSPACE, "solve_batch_v: persistent launch needs a 256-byte aligned workspace");
+  nmc::FwdVArgs a;
+  memset(&a, 0, sizeof(a));
+  a.mdl = m->dev;
+  a.prm.tol_inner = prm->tol_inner;
+  a.prm.tol_outer = prm->tol_outer;
+  a.prm.m_inner = prm->m_inner;
+  a.prm.m_outer = prm->m_outer;
+  a.prm.max_inner = prm->max_inner;
+  a.prm.max_outer = prm->max_outer;
+  a.prm.fixed_matter = prm->fixed_matter ? 1 : 0;
+  a.tol_inner2 = prm->tol_inner * prm->tol_inner;
+  a.P = P;
+  a.dtau = dtau;
+  a.D0 = in->D0;
+  a.I0 = in->I0;
+  a.rho11 = in->rho11;
+  a.ye0 = in->ye0;
+  a.ef0 = in->ef0;
+  a.v0 = in->v0;
+  a.chi0 = in->chi0;
+  a.theta = in->theta;
+  a.D = out->D;
+  a.I = out->I;
+  a.ye = out->ye;
+  a.ef = out->ef;
+  a.v = out->v;
+  a.T = out->T;
+  a.n_outer = out->n_outer;
+  a.n_inner = out->n_inner;
+  a.status = out->status;
+  a.chunk = L.chunk;
+  hipStream_t s = (hipStream_t)stream;
+  if (L.persistent) {
+    a.queue = (int*)ws;
+    hipError_t e = nmc::launch_reset_counter(a.queue, s);
+    if (e != hipSuccess) return hip_fail(e, "solve_batch_v: counter reset");
+  }
+  const bool coupled = (m->host.flags & (NMC_NES | NMC_PAIR)) != 0;
+  hipError_t e = nmc::launch_forward_v(a, m->host.ns, coupled, L, m->num_cu, s);
+  if (e == hipErrorInvalidValue) return fail(NMC_E_UNSUPPORTED, "solve_batch_v: no kernel for ns=%d", m->host.ns);
+  if (e != hipSuccess) return hip_fail(e, "solve_batch_v: launch");
+  return NMC_OK;
+}
+
 int nmc_solve_batch_adjoint(const nmc_model* m, int64_t P, double dtau, const nmc_batch_in* in,
                             const nmc_batch_out* fwd, const double* gbar, double* grad_theta, double* grad_pp,
                             void* ws, size_t ws_bytes, void* stream) {

@@ -60,6 +60,21 @@ struct FwdArgs {
   int chunk;   // points per grab
 };
 
+// O(v) forward solve (nonzero fluid velocity): moments D (P, ns, nq) and I
+// (P, ns, 3, nq), matter (Ye, ef, v) with v (P, 3)
+struct FwdVArgs {
+  const DevModel* mdl;
+  SolverParams prm;
+  double tol_inner2;
+  int64_t P;
+  double dtau;
+  const double *D0, *I0, *rho11, *ye0, *ef0, *v0, *chi0, *theta;
+  double *D, *I, *ye, *ef, *v, *T;
+  int32_t *n_outer, *n_inner, *status;
+  int* queue;
+  int chunk;
+};
+
 struct AdjArgs {
   const DevModel* mdl;
   int64_t P;
@@ -78,6 +93,8 @@ hipError_t launch_forward64(const FwdArgs& a, int ns, bool coupled, const nmc_la
                             hipStream_t s);
 hipError_t launch_forward_pair(const FwdArgs& a, int ns, bool coupled, const nmc_launch& L, int num_cu,
                                hipStream_t s);
+hipError_t launch_forward_v(const FwdVArgs& a, int ns, bool coupled, const nmc_launch& L, int num_cu,
+                            hipStream_t s);
 hipError_t launch_reset_counter(int* counter, hipStream_t s);
 // FP64 FMA throughput probe (measurement only)
 hipError_t launch_probe_fma(int64_t waves, int iters, double* out, hipStream_t s);

@@ -192,6 +192,51 @@ def solve(model: Model, params: Params, dtau: float, D0, I0, rho11, ye0, e0, the
     return out
 
 
+def alloc_outputs_v(model: Model, P: int, device="cuda"):
+    f64 = dict(dtype=torch.float64, device=device)
+    i32 = dict(dtype=torch.int32, device=device)
+    return dict(D=torch.empty(P, model.ns, model.nq, **f64), I=torch.empty(P, model.ns, 3, model.nq, **f64),
+                ye=torch.empty(P, **f64), ef=torch.empty(P, **f64), v=torch.empty(P, 3, **f64),
+                T=torch.empty(P, **f64), n_outer=torch.empty(P, **i32), n_inner=torch.empty(P, **i32),
+                status=torch.empty(P, **i32))
+
+
+def solve_v(model: Model, params: Params, dtau: float, D0, I0, rho11, ye0, ef0, v0, theta, chi0=None, out=None,
+            workspace: Workspace | None = None, launch: LaunchConfig | None = None, stream=None):
+    """Enqueue one batched O(v) solve (nonzero fluid velocity): D0 (P, ns, nq),
+    I0 (P, ns, 3, nq), v0 (P, 3), ef0 the specific fluid energy (internal plus
+    kinetic) per baryon.  Returns the output dict (not synchronized)."""
+    P = D0.shape[0]
+    ns, nq = model.ns, model.nq
+    _req(D0, "D0", (P, ns, nq))
+    _req(I0, "I0", (P, ns, 3, nq))
+    for n, t in (("rho11", rho11), ("ye0", ye0), ("ef0", ef0)):
+        _req(t, n, (P,))
+    _req(v0, "v0", (P, 3))
+    _req(theta, "theta", (nq + 2,))
+    if chi0 is not None:
+        _req(chi0, "chi0", (P,))
+    if out is None:
+        out = alloc_outputs_v(model, P, D0.device)
+    _req(out["D"], "D", (P, ns, nq))
+    _req(out["I"], "I", (P, ns, 3, nq))
+    for n in ("ye", "ef", "T"):
+        _req(out[n], n, (P,))
+    _req(out["v"], "v", (P, 3))
+    for n in ("n_outer", "n_inner", "status"):
+        _req(out[n], n, (P,), torch.int32)
+    bi = N.BatchVIn(*[None if t is None else t.data_ptr() for t in (D0, I0, rho11, ye0, ef0, v0, chi0, theta)])
+    bo = N.BatchVOut(*[out[n].data_ptr() for n in ("D", "I", "ye", "ef", "v", "T", "n_outer", "n_inner", "status")])
+    launch = launch or LaunchConfig(chunk=1)
+    if workspace is None:
+        workspace = Workspace(model, P, D0.device)
+    pc, lc = params.c(), launch.c()
+    N.check(N.lib().nmc_solve_batch_v(model._h, C.byref(pc), P, float(dtau), C.byref(bi), C.byref(bo),
+                                      C.c_void_p(workspace.ptr), workspace.nbytes, C.byref(lc),
+                                      _stream_handle(stream)))
+    return out
+
+
 def adjoint(model: Model, dtau: float, rho11, theta, fwd, gbar, chi0=None, grad_theta=None, per_point=False,
             workspace: Workspace | None = None, stream=None):
     """Enqueue the implicit-function-theorem adjoint of a converged forward
@@ -299,4 +344,17 @@ def to_device(draws, device="cuda"):
     """Move a workloads.Draws bundle to the GPU as float64 tensors."""
     f = lambda x: None if x is None else torch.as_tensor(x, dtype=torch.float64, device=device).contiguous()
     return dict(T=f(draws.T), rho11=f(draws.rho11), ye=f(draws.ye), uD=f(draws.uD), uI=f(draws.uI),
-                mu=f(draws.mu), chi0=f(draws.chi0))
+                mu=f(draws.mu), chi0=f(draws.chi0), v=f(draws.v), uI3=f(draws.uI3))
+
+
+MU_C2 = 931.49410242  # atomic mass unit rest energy [MeV]
+
+
+def init_state_v(model: Model, t: dict, c: float = 0.1):
+    """Old state of an O(v) workload from device draws ``t`` (see
+    ``to_device``): D* and e* from ``init_state``, I*_j = c D* uI3_j and the
+    specific fluid energy ef* = e* + m_u c^2 |v|^2 / 2."""
+    D0, _, e0 = init_state(model, t["T"], t["rho11"], t["ye"], t["uD"], t["uI"])
+    I0 = (c * D0[:, :, None, :] * t["uI3"]).contiguous()
+    ef0 = e0 + 0.5 * MU_C2 * (t["v"] * t["v"]).sum(dim=1)
+    return D0, I0, ef0

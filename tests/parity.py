@@ -69,3 +69,57 @@ def reservoir_ratios(kcoup, rho11, D, ye, e, w2, w3, species=(0, 1, 2)):
     RY = K * np.sum(g * w2 * D, axis=(1, 2)) / np.abs(ye)
     RE = K * np.sum(mult * w3 * D, axis=(1, 2)) / np.abs(e)
     return RY, RE
+
+
+# ---- O(v) solve (nonzero fluid velocity) ------------------------------------
+
+def run_oracle_v(draws: W.Draws, dtau, params: O.Params, theta, c=0.1):
+    m = O.Model()
+    D0, _, e0 = m.init_state(draws.T, draws.rho11, draws.ye, draws.uD, draws.uI)
+    I0 = c * D0[:, :, None, :] * draws.uI3
+    ef0 = e0 + 0.5 * O.MU_C2 * np.sum(draws.v * draws.v, axis=1)
+    r = O.solve_batch_v(m, params, theta, dtau, D0, I0, draws.rho11, draws.ye, ef0, draws.v)
+    r["D0"], r["I0"], r["ef0"] = D0, I0, ef0
+    return m, r
+
+
+def run_gpu_v(draws: W.Draws, dtau, params: S.Params, theta_np, launch=None, inplace=False):
+    import torch
+    m = S.Model(S.Grid())
+    t = S.to_device(draws)
+    D0, I0, ef0 = S.init_state_v(m, t)
+    theta = torch.as_tensor(theta_np, dtype=torch.float64, device="cuda")
+    keep = dict(D0=D0.cpu().numpy(), I0=I0.cpu().numpy(), ef0=ef0.cpu().numpy())
+    out = None
+    if inplace:
+        P = D0.shape[0]
+        i32 = dict(dtype=torch.int32, device="cuda")
+        out = dict(D=D0, I=I0, ye=t["ye"], ef=ef0, v=t["v"], T=torch.empty_like(ef0),
+                   n_outer=torch.empty(P, **i32), n_inner=torch.empty(P, **i32), status=torch.empty(P, **i32))
+    out = S.solve_v(m, params, dtau, D0, I0, t["rho11"], t["ye"], ef0, t["v"], theta, out=out, launch=launch)
+    torch.cuda.synchronize()
+    res = {k: v.cpu().numpy() for k, v in out.items()}
+    res.update(keep)
+    return m, res
+
+
+def parity_errors_v(ref, got, w2, w3, kcoup, rho11):
+    """Per point and species W-weighted relative errors of D and of the flux
+    vector (reference ||D||); Ye and ef relative errors divided by the
+    neutrino/matter reservoir ratio (at least 1); velocity errors relative to
+    the larger of |v| and the neutrino momentum scale K / (m_u c^2) sum W3 D."""
+    dref = wnorm(ref["D"], w2)
+    scale = np.where(dref > 0, dref, 1.0)
+    eD = wnorm(got["D"] - ref["D"], w2) / scale
+    dI = got["I"] - ref["I"]
+    eI = np.sqrt(np.sum(w2 * dI * dI, axis=(-2, -1))) / scale
+    mult = np.array([1.0, 1.0, 4.0])[None, :, None]
+    g = np.array([1.0, 1.0, 0.0])[None, :, None]
+    K = kcoup / rho11
+    RY = np.maximum(K * np.sum(g * w2 * ref["D"], axis=(1, 2)) / np.abs(ref["ye"]), 1.0)
+    RE = np.maximum(K * np.sum(mult * w3 * ref["D"], axis=(1, 2)) / np.abs(ref["ef"]), 1.0)
+    eY = np.abs(got["ye"] - ref["ye"]) / np.abs(ref["ye"]) / RY
+    eE = np.abs(got["ef"] - ref["ef"]) / np.abs(ref["ef"]) / RE
+    vs = np.maximum(np.linalg.norm(ref["v"], axis=1), K / O.MU_C2 * np.sum(mult * w3 * ref["D"], axis=(1, 2)))
+    eV = np.max(np.abs(got["v"] - ref["v"]), axis=1) / vs
+    return eD, eI, eY, eE, eV
