@@ -53,6 +53,147 @@ def bytes_per_point(nq=32, ns=NS):
     return 2 * ns * nq * 8 + 3 * 8 + 2 * ns * nq * 8 + 3 * 8 + 3 * 4
 
 
+def bytes_per_point_v(nq=32, ns=NS):
+    """Algorithmic HBM bytes of one O(v) point-solve: read D*, the three flux
+    components and 6 scalars (rho11, Ye*, ef*, v*), write D, I, 6 scalars
+    (Ye, ef, v, T) and 3 int32 counters."""
+    return 2 * 4 * ns * nq * 8 + 6 * 8 + 6 * 8 + 3 * 4
+
+
+# O(v) workload: the inner loop is solved 100 times tighter than the outer one
+# (its lambda < 1 fixed-point map converges linearly, and the residual error,
+# amplified by the neutrino/matter reservoir ratio at the low-density edge of
+# the profile, would otherwise exceed the outer tolerance there)
+V_TOL_INNER, V_TOL_OUTER = 1e-12, 1e-10
+V_WID = 6
+
+
+def cpu_baseline_v(steps: int, threads: int):
+    """The oracle's O(v) solve on the moving profile: all 2^16 points, `steps`
+    chained implicit steps from the initial state."""
+    import numpy as np
+
+    import oracle as O
+    from paper_2601_00976_amd import solver as S
+    from paper_2601_00976_amd import workloads as W
+
+    O.build(force=False)
+    d = W.radial_profile_v(P=P_POINTS, wid=V_WID)
+    m = O.Model(n_elem=16)
+    theta = m.default_theta(S.DEFAULT_A_NES, S.DEFAULT_A_PAIR)
+    D, _, e0 = m.init_state(d.T, d.rho11, d.ye, d.uD, d.uI)
+    I = 0.1 * D[:, :, None, :] * d.uI3
+    ef = e0 + 0.5 * O.MU_C2 * np.sum(d.v * d.v, axis=1)
+    ye, v = d.ye.copy(), d.v.copy()
+    prm = O.Params(tol_inner=V_TOL_INNER, tol_outer=V_TOL_OUTER)
+    solved = 0
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        r = O.solve_batch_v(m, prm, theta, W.DTAU_KM, D, I, d.rho11, ye, ef, v, nthreads=threads)
+        D, I, ye, ef, v = r["D"], r["I"], r["ye"], r["ef"], r["v"]
+        solved += int(np.sum(r["n_outer"] > 0))
+    dt = time.perf_counter() - t0
+    return dict(value=solved / dt, unit="point-solves/s", cores=threads, kind="oracle",
+                sample=f"all {P_POINTS} moving-profile points, {steps} chained steps, {solved} solves in {dt:.1f} s")
+
+
+def run_velocity(args):
+    """The O(v) solve (nonzero fluid velocity) on the moving radial profile:
+    2^16 points, 3 species, 32 nodes, 10 chained in-place steps per captured
+    graph, timed and accounted as the static workload."""
+    import numpy as np
+    import torch
+
+    from paper_2601_00976_amd import autotune as AT
+    from paper_2601_00976_amd import solver as S
+    from paper_2601_00976_amd import workloads as W
+
+    dev = torch.device("cuda:0")
+    model = S.Model(S.Grid(16))
+    params = S.Params(tol_inner=V_TOL_INNER, tol_outer=V_TOL_OUTER)
+    t = S.to_device(W.radial_profile_v(P=P_POINTS, wid=V_WID), dev)
+    D0, I0, ef0 = S.init_state_v(model, t)
+    theta = model.default_theta()
+    launch = S.LaunchConfig(chunk=args.chunk or 1, blocks_per_cu=args.blocks_per_cu or 0)
+    work = dict(D=D0.clone(), I=I0.clone(), ye=t["ye"].clone(), ef=ef0.clone(), v=t["v"].clone())
+    outs = [S.alloc_outputs_v(model, P_POINTS, dev) for _ in range(STEPS_PER_GRAPH)]
+    for o in outs:
+        for k in work:
+            o[k] = work[k]
+    ws = S.Workspace(model, P_POINTS, dev)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(STEPS_PER_GRAPH)]
+
+    def one_pass(record=False):
+        work["D"].copy_(D0)
+        work["I"].copy_(I0)
+        work["ye"].copy_(t["ye"])
+        work["ef"].copy_(ef0)
+        work["v"].copy_(t["v"])
+        for i in range(STEPS_PER_GRAPH):
+            if record:
+                ev[i][0].record()
+            S.solve_v(model, params, W.DTAU_KM, work["D"], work["I"], t["rho11"], work["ye"], work["ef"],
+                      work["v"], theta, out=outs[i], workspace=ws, launch=launch)
+            if record:
+                ev[i][1].record()
+
+    one_pass()
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        one_pass()
+    for _ in range(args.warmup):
+        g.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        g.replay()
+    torch.cuda.synchronize()
+    ms_per_step = 1e3 * (time.perf_counter() - t0) / args.steps
+    kern_ms = 0.0
+    n_timed = max(2, min(args.steps, 5))
+    for _ in range(n_timed):
+        one_pass(record=True)
+        torch.cuda.synchronize()
+        kern_ms += sum(a.elapsed_time(b) for a, b in ev)
+    n_in = np.stack([o["n_inner"].cpu().numpy() for o in outs]).astype(np.float64)
+    n_out = np.stack([o["n_outer"].cpu().numpy() for o in outs]).astype(np.float64)
+    status = np.stack([o["status"].cpu().numpy() for o in outs])
+    solved = int(np.sum(n_out > 0))
+    flops = float(np.sum(flops_per_point(n_in, n_out, 32)))
+    kern_s = kern_ms * 1e-3 / (n_timed * STEPS_PER_GRAPH)
+    achieved = flops / STEPS_PER_GRAPH / kern_s / 1e12
+    line = {
+        "metric": "implicit O(v) point-solves/sec at 32 energy nodes, 3 species (FP64)",
+        "value": solved / (ms_per_step * 1e-3), "unit": "point-solves/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {
+            "workload": "moving radial-profile (O(v) solve, fluid velocity up to 0.1 c), 2^16 points, 3 species, "
+                        "32 energy nodes, full physics, 10 chained implicit steps per captured graph",
+            "points": P_POINTS, "solved_point_steps_per_step": solved, "species": NS, "energy_nodes": 32,
+            "implicit_steps_per_step": STEPS_PER_GRAPH, "dtau_km": W.DTAU_KM, "tol_inner": params.tol_inner,
+            "tol_outer": params.tol_outer, "anderson_memory": params.m_inner,
+            "launch": {"chunk": launch.chunk, "blocks_per_cu": launch.blocks_per_cu, "persistent": launch.persistent},
+            "iterations": {"inner_min": int(n_in[n_out > 0].min()), "inner_median": float(np.median(n_in[n_out > 0])),
+                           "inner_max": int(n_in.max()), "outer_max": int(n_out.max())},
+            "status_counts": np.bincount(status.ravel(), minlength=5).tolist(),
+        },
+        "roofline": {
+            "kernel": "fwd_v_kernel<3, true> (persistent O(v) point solve, one point per wavefront)",
+            "bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP64_TFLOPS, "traffic": AT.stored_traffic("fwd_v_kernel_nq32_ns3"),
+            "kernel_ms_per_launch": kern_s * 1e3, "flops_per_launch": flops / STEPS_PER_GRAPH,
+            "algorithmic_hbm_gbs": bytes_per_point_v() * P_POINTS / kern_s / 1e9,
+        },
+    }
+    if not args.no_cpu:
+        threads = int(os.environ.get("OMP_NUM_THREADS") or os.cpu_count() or 1)
+        line["cpu_baseline"] = cpu_baseline_v(args.cpu_steps_v, threads)
+    print(json.dumps(line), flush=True)
+
+
 def cpu_baseline(repeats: int, threads: int):
     """The oracle (as it stands) on the same workload: the 10-step chain over
     all 2^16 profile points, repeated `repeats` times from the initial state."""
@@ -127,8 +268,10 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--chunk", type=int, default=None)
     ap.add_argument("--blocks-per-cu", type=int, default=None)
-    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="profile32",
-                    help="profile32: the headline (2^16 points, 32 nodes); profile64: 2^18 points, 64 nodes")
+    ap.add_argument("--workload", choices=sorted(WORKLOADS) + ["profile-v"], default="profile32",
+                    help="profile32: the headline (2^16 points, 32 nodes); profile64: 2^18 points, 64 nodes; "
+                         "profile-v: the O(v) solve on the moving profile (2^16 points, 32 nodes)")
+    ap.add_argument("--cpu-steps-v", type=int, default=4, help="chained steps of the O(v) oracle baseline")
     ap.add_argument("--kernel-store", choices=("chip", "wave", "regen", "registers", "hbm"), default="chip",
                     help="chip: library default (32 nodes: two points per wavefront); wave (32 nodes): one point "
                          "per wavefront, pair factors in VGPRs; regen: kernel entries regenerated every inner "
@@ -150,6 +293,8 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.workload == "profile-v":
+        return run_velocity(args)
 
     n_elem, P_POINTS, wid, traffic_tag, kernel_label = WORKLOADS[args.workload]
     nq = 2 * n_elem

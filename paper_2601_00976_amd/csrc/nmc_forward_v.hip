@@ -69,6 +69,10 @@ __device__ __forceinline__ void closure_terms(double D, const double (&I)[3], co
 template <int NS, bool COUPLED>
 struct PointSolverV {
   static constexpr int NQ = 32;
+  // the lane's 16 pair factors are kept in VGPRs across the inner loop (2);
+  // recomputing them from the per-node splits in every inner iteration (1)
+  // frees the registers the three-species kernel spills but measured slower
+  static constexpr int KMV = 2;
 
   // lane contributions (number lanes only) to the Eulerian integrals
   // (N, E, F_1, F_2, F_3) of the moments (Df, If) at velocity v; per-half
@@ -274,9 +278,9 @@ struct PointSolverV {
           S.den0[t][1][lane] = 1.0 + ldt * (chia + sig);
         }
       }
-      double Bq[16];
-      if constexpr (COUPLED) {
-        split_exp_prepare(S.m, invT, S.E);
+      double Bq[KMV == 2 ? 16 : 1];
+      if constexpr (COUPLED) split_exp_prepare(S.m, invT, S.E);
+      if constexpr (COUPLED && KMV == 2) {
         const double Pq = S.E.P2[q], Rq = S.E.R2[q];
         const int nq = S.E.n2[q];
 #pragma unroll
@@ -306,7 +310,7 @@ struct PointSolverV {
           }
           __syncthreads();
           double e_p[NS], c_p[NS];
-          regen_rates_half<NS, 2>(S, q, 16 * h, Bq, e_p, c_p);
+          regen_rates_half<NS, KMV>(S, q, 16 * h, Bq, e_p, c_p);
           __syncthreads();
 #pragma unroll
           for (int t = 0; t < NS; ++t) {

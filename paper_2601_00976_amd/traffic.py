@@ -10,7 +10,8 @@ Two steps, each run on the GPU machine:
 `run` launches a plain device-to-device copy of a known size (the
 calibration: it must read and write exactly that many bytes), the forward
 solve (default and one-point-per-wave kernels) and the adjoint on the first
-step of the 2^16-point radial profile, and the 64-node solves (kernels on
+step of the 2^16-point radial profile, the O(v) solve on the first step of
+the 2^16-point moving profile, and the 64-node solves (kernels on
 chip and in HBM) on the first step of the 2^18-point profile, each at the
 launch shape of the autotune cache.
 `summarize` scales each kernel's per-dispatch counter by copy bytes / copy
@@ -31,6 +32,8 @@ KERNELS = {
     "fwd_kernel<3, 32, true, 2>": ("fwd_kernel_nq32_ns3", "radial profile, 2^16 points, 32 nodes, step 1, "
                                    "one point per wavefront"),
     "adj_kernel<3>": ("adj_kernel_nq32_ns3", "radial profile, 2^16 points, 32 nodes, step 1"),
+    "fwd_v_kernel<3, true>": ("fwd_v_kernel_nq32_ns3", "moving radial profile (O(v) solve), 2^16 points, "
+                              "32 nodes, step 1"),
     "fwd64_kernel<3, true, false>": ("fwd64_kernel_nq64_ns3", "radial profile, 2^18 points, 64 nodes, step 1"),
     "fwd64_kernel<3, true, true>": ("fwd64_kernel_nq64_ns3_hbm",
                                     "radial profile, 2^18 points, 64 nodes, step 1, kernels in HBM"),
@@ -68,7 +71,14 @@ def run():
     gbar = torch.ones(1 << 16, 2, dtype=torch.float64, device=dev)
     S.adjoint(model, W.DTAU_KM, t["rho11"], theta, out, gbar, workspace=ws)
     torch.cuda.synchronize()
-    del ws, out, gbar, D0, I0, e0, t
+    # the O(v) solve on the moving profile, at the launch shape bench.py uses
+    tv = S.to_device(W.radial_profile_v(P=1 << 16, wid=6), dev)
+    Dv, Iv, efv = S.init_state_v(model, tv)
+    outv = S.alloc_outputs_v(model, 1 << 16, dev)
+    S.solve_v(model, S.Params(tol_inner=1e-12, tol_outer=1e-10), W.DTAU_KM, Dv, Iv, tv["rho11"], tv["ye"], efv,
+              tv["v"], theta, out=outv, workspace=ws, launch=S.LaunchConfig(chunk=1))
+    torch.cuda.synchronize()
+    del ws, out, gbar, D0, I0, e0, t, tv, Dv, Iv, efv, outv
     # 64 nodes, 2^18 points: kernels on chip, then precomputed in HBM
     P64 = 1 << 18
     m64 = S.Model(S.Grid(32))
