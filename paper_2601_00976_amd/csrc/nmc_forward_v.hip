@@ -54,10 +54,12 @@ __device__ __forceinline__ void closure_terms(double D, const double (&I)[3], co
                                               double (&vK)[3]) {
   const double Imag = sqrt(I[0] * I[0] + I[1] * I[1] + I[2] * I[2]);
   double h = 0.0;
-  if (Imag > 0.0) h = D > 0.0 ? fmin(Imag / D, 1.0) : 1.0;
+  // Imag < D keeps D normal where its reciprocal is taken (a nonzero Imag is
+  // at least ~1e-162: its components' squares underflow below that)
+  if (Imag > 0.0) h = Imag < D ? Imag * rcp_nr(D) : 1.0;
   const double psi = 1.0 / 3.0 + (2.0 / 15.0) * (3.0 - h + 3.0 * h * h) * h * h;
   const double a = 0.5 * (1.0 - psi), b = 0.5 * (3.0 * psi - 1.0);
-  const double rI = Imag > 0.0 ? 1.0 / Imag : 0.0;
+  const double rI = Imag > 0.0 ? rcp_nr(Imag) : 0.0;
   const double n0 = I[0] * rI, n1 = I[1] * rI, n2 = I[2] * rI;
   const double bvn = b * (v[0] * n0 + v[1] * n1 + v[2] * n2);
   vI = v[0] * I[0] + v[1] * I[1] + v[2] * I[2];
@@ -336,8 +338,8 @@ struct PointSolverV {
           const double n1 = __builtin_fma(oml, u[t][1], S.base[t][1][lane]) - lam * V1;
           const double d0 = __builtin_fma(ldt, chi_c[t], S.den0[t][0][lane]);
           const double d1 = __builtin_fma(ldt, chi_c[t], S.den0[t][1][lane]);
-          Q[t][0] = n0 / d0;
-          Q[t][1] = n1 / d1;
+          Q[t][0] = n0 * rcp_nr(d0);
+          Q[t][1] = n1 * rcp_nr(d1);
           F[t][0] = Q[t][0] - u[t][0];
           F[t][1] = Q[t][1] - u[t][1];
         }
