@@ -1,6 +1,6 @@
 """HBM traffic of the solve kernels from rocprofv3 counters.
 
-Two steps, each run on the GPU machine:
+Two steps, each run on a machine with the GPU:
 
   cd /tmp && export TMPDIR=/tmp
   rocprofv3 --pmc FETCH_SIZE -d <dir>/fetch -o run -- python3 <repo>/paper_2601_00976_amd/traffic.py run
@@ -138,7 +138,7 @@ def summarize(fetch_db, write_db):
         path = os.path.join(ROOT, "profiles", f"traffic_{tag}.txt")
         with open(path, "w") as o:
             o.write(f"# HBM traffic of {key} ({what})\n")
-            o.write("# commands (GPU box, from the repository root; source_hash = code-only hash of csrc/, "
+            o.write("# commands (GPU host, from the repository root; source_hash = code-only hash of csrc/, "
                     "see autotune.kernel_source_hash):\n")
             o.write("#   cd /tmp && export TMPDIR=/tmp\n")
             o.write("#   rocprofv3 --pmc FETCH_SIZE -d <dir>/fetch -o run -- python3 <repo>/paper_2601_00976_amd/traffic.py run\n")
