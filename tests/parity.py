@@ -73,8 +73,8 @@ def reservoir_ratios(kcoup, rho11, D, ye, e, w2, w3, species=(0, 1, 2)):
 
 # ---- O(v) solve (nonzero fluid velocity) ------------------------------------
 
-def run_oracle_v(draws: W.Draws, dtau, params: O.Params, theta, c=0.1):
-    m = O.Model()
+def run_oracle_v(draws: W.Draws, dtau, params: O.Params, theta, c=0.1, species=(0, 1, 2), flags=O.ALL_PHYSICS):
+    m = O.Model(species=tuple(species), flags=flags)
     D0, _, e0 = m.init_state(draws.T, draws.rho11, draws.ye, draws.uD, draws.uI)
     I0 = c * D0[:, :, None, :] * draws.uI3
     ef0 = e0 + 0.5 * O.MU_C2 * np.sum(draws.v * draws.v, axis=1)
@@ -83,9 +83,10 @@ def run_oracle_v(draws: W.Draws, dtau, params: O.Params, theta, c=0.1):
     return m, r
 
 
-def run_gpu_v(draws: W.Draws, dtau, params: S.Params, theta_np, launch=None, inplace=False):
+def run_gpu_v(draws: W.Draws, dtau, params: S.Params, theta_np, launch=None, inplace=False, species=(0, 1, 2),
+              flags=O.ALL_PHYSICS):
     import torch
-    m = S.Model(S.Grid())
+    m = S.Model(S.Grid(), species=tuple(species), flags=flags)
     t = S.to_device(draws)
     D0, I0, ef0 = S.init_state_v(m, t)
     theta = torch.as_tensor(theta_np, dtype=torch.float64, device="cuda")
@@ -103,7 +104,7 @@ def run_gpu_v(draws: W.Draws, dtau, params: S.Params, theta_np, launch=None, inp
     return m, res
 
 
-def parity_errors_v(ref, got, w2, w3, kcoup, rho11):
+def parity_errors_v(ref, got, w2, w3, kcoup, rho11, species=None):
     """Per point and species W-weighted relative errors of D and of the flux
     vector (reference ||D||); Ye and ef relative errors divided by the
     neutrino/matter reservoir ratio (at least 1); velocity errors relative to
@@ -113,8 +114,9 @@ def parity_errors_v(ref, got, w2, w3, kcoup, rho11):
     eD = wnorm(got["D"] - ref["D"], w2) / scale
     dI = got["I"] - ref["I"]
     eI = np.sqrt(np.sum(w2 * dI * dI, axis=(-2, -1))) / scale
-    mult = np.array([1.0, 1.0, 4.0])[None, :, None]
-    g = np.array([1.0, 1.0, 0.0])[None, :, None]
+    sp = species if species is not None else (0, 1, 2)
+    mult = np.array([[1.0, 1.0, 4.0][s] for s in sp])[None, :, None]
+    g = np.array([[1.0, 1.0, 0.0][s] for s in sp])[None, :, None]
     K = kcoup / rho11
     RY = np.maximum(K * np.sum(g * w2 * ref["D"], axis=(1, 2)) / np.abs(ref["ye"]), 1.0)
     RE = np.maximum(K * np.sum(mult * w3 * ref["D"], axis=(1, 2)) / np.abs(ref["ef"]), 1.0)

@@ -166,3 +166,29 @@ def test_full_size_chain_sampled_parity():
     # three chained steps carry the tolerance-level differences forward
     assert eD.max() <= 3 * TOL and eI.max() <= 3 * TOL
     assert eY.max() <= 3 * TOL and eE.max() <= 3 * TOL and eV.max() <= 3 * TOL
+
+
+@pytest.mark.parametrize("species,flags,fixed", [
+    ((O.NU_E, O.NU_E_BAR, O.NU_X), O.EMAB | O.ISO, False),
+    ((O.NU_E, O.NU_E_BAR), O.ALL_PHYSICS, False),
+    ((O.NU_X,), O.NES | O.PAIR | O.ISO, False),
+    ((O.NU_E, O.NU_E_BAR, O.NU_X), O.ALL_PHYSICS, True),
+])
+def test_species_physics_and_fixed_matter(species, flags, fixed):
+    _say(f"O(v) species {species} flags {flags} fixed_matter {fixed}")
+    d = W.radial_profile_v(P=1 << 16, ns=len(species)).take(np.linspace(0, 45000, 200).astype(np.int64))
+    m, ref = PT.run_oracle_v(d, W.DTAU_KM, O.Params(fixed_matter=fixed, **ORA_PRM), _theta(), species=species,
+                             flags=flags)
+    _, got = PT.run_gpu_v(d, W.DTAU_KM, S.Params(fixed_matter=fixed, **ORA_PRM), _theta(), species=species,
+                          flags=flags)
+    assert np.array_equal(ref["status"], got["status"])
+    ok = ref["status"] == 0
+    assert ok.mean() > 0.99
+    eD, eI, eY, eE, eV = PT.parity_errors_v({k: v[ok] for k, v in ref.items()}, {k: v[ok] for k, v in got.items()},
+                                            m.w2, m.w3, m.c.kcoup, d.rho11[ok], species=species)
+    print(f"max errors D {eD.max():.2e} I {eI.max():.2e} Ye {eY.max():.2e} ef {eE.max():.2e} v {eV.max():.2e}",
+          flush=True)
+    assert max(eD.max(), eI.max(), eY.max(), eE.max(), eV.max()) <= TOL
+    if fixed:
+        assert np.array_equal(got["ye"], d.ye) and np.array_equal(got["v"], d.v)
+        assert np.array_equal(got["ef"], got["ef0"])
