@@ -121,6 +121,24 @@ def test_argument_checks():
     with pytest.raises(N.NmcError) as e:
         S.solve_v(m, S.Params(), 0.0, f(P, 3, 32), f(P, 3, 3, 32), f(P) + 1, f(P) + 0.3, f(P) + 10, f(P, 3), f(34))
     assert e.value.code == N.NMC_E_INVALID_ARG
+    # an empty batch enqueues nothing
+    S.solve_v(m, S.Params(), 1e-3, f(0, 3, 32), f(0, 3, 3, 32), f(0), f(0), f(0), f(0, 3), f(34))
+
+
+def test_single_point_and_all_skipped():
+    _say("O(v) one point; a batch entirely below the coupling density")
+    d = _profile(1, 20000, 20001)
+    m, ref = PT.run_oracle_v(d, W.DTAU_KM, O.Params(**ORA_PRM), _theta())
+    _, got = PT.run_gpu_v(d, W.DTAU_KM, S.Params(**ORA_PRM), _theta())
+    assert got["status"][0] == ref["status"][0] == 0 and got["n_outer"][0] > 0
+    eD, eI, eY, eE, eV = PT.parity_errors_v(ref, got, m.w2, m.w3, m.c.kcoup, d.rho11)
+    assert max(eD.max(), eI.max(), eY.max(), eE.max(), eV.max()) <= TOL
+    low = _profile(50, 62000, 65535)
+    assert np.all(low.rho11 < 1e-4)
+    _, got = PT.run_gpu_v(low, W.DTAU_KM, S.Params(**ORA_PRM), _theta())
+    assert np.all(got["n_outer"] == 0) and np.all(got["status"] == 0)
+    assert np.array_equal(got["D"], got["D0"]) and np.array_equal(got["I"], got["I0"])
+    assert np.array_equal(got["v"], low.v) and np.array_equal(got["ef"], got["ef0"])
 
 
 def test_full_size_chain_sampled_parity():
