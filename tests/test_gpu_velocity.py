@@ -210,3 +210,25 @@ def test_species_physics_and_fixed_matter(species, flags, fixed):
     if fixed:
         assert np.array_equal(got["ye"], d.ye) and np.array_equal(got["v"], d.v)
         assert np.array_equal(got["ef"], got["ef0"])
+
+
+def test_fast_flow_parity():
+    """Speeds 0.2-0.4 c, up to the bound below which the fixed-point map of
+    the moment equations is a contraction."""
+    _say("O(v) fast flow, |v| in [0.2, 0.4), P=256")
+    d = _profile(256, 0, 45000)
+    rng = np.random.default_rng(41)
+    n = d.v / np.linalg.norm(d.v, axis=1, keepdims=True)
+    d.v = np.ascontiguousarray(n * rng.uniform(0.2, 0.4, (256, 1)))
+    m, ref = PT.run_oracle_v(d, W.DTAU_KM, O.Params(**ORA_PRM), _theta())
+    _, got = PT.run_gpu_v(d, W.DTAU_KM, S.Params(**ORA_PRM), _theta())
+    either = (ref["status"] == O.MAX_OUTER) | (got["status"] == O.MAX_OUTER)
+    assert np.array_equal(ref["status"][~either], got["status"][~either])
+    ok = (ref["status"] == 0) & (got["status"] == 0)
+    assert ok.mean() > 0.97
+    eD, eI, eY, eE, eV = PT.parity_errors_v({k: v[ok] for k, v in ref.items()}, {k: v[ok] for k, v in got.items()},
+                                            m.w2, m.w3, m.c.kcoup, d.rho11[ok])
+    print(f"status {np.bincount(ref['status'], minlength=5)}; max errors D {eD.max():.2e} I {eI.max():.2e} "
+          f"Ye {eY.max():.2e} ef {eE.max():.2e} v {eV.max():.2e}; median inner {np.median(got['n_inner'])}",
+          flush=True)
+    assert max(eD.max(), eI.max(), eY.max(), eE.max(), eV.max()) <= TOL
