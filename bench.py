@@ -188,6 +188,9 @@ def run_velocity(args):
             "algorithmic_hbm_gbs": bytes_per_point_v() * P_POINTS / kern_s / 1e9,
         },
     }
+    fma_peak = S.probe_fma_tflops(dev)
+    line["roofline"]["measured_fma_peak"] = fma_peak
+    line["roofline"]["frac_of_measured_fma_peak"] = achieved / fma_peak
     if not args.no_cpu:
         threads = int(os.environ.get("OMP_NUM_THREADS") or os.cpu_count() or 1)
         line["cpu_baseline"] = cpu_baseline_v(args.cpu_steps_v, threads)
