@@ -1,0 +1,29 @@
+"""Host-side checks of bench.py (no GPU): the one-GPU guard and the
+accounting conventions of the roofline line."""
+import os
+import subprocess
+import sys
+
+import bench
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+
+
+def test_flop_and_byte_conventions():
+    # per inner iteration: four energy-coupling mat-vecs per species (8 Ns Nq^2)
+    # and the pointwise and Anderson work (40 Ns Nq); per outer iteration the
+    # kernel build and matter update (4 Nq^2 + 30 Ns Nq)
+    assert bench.flops_per_point(1, 0, 32, 3) == 24576 + 3840
+    assert bench.flops_per_point(1, 0, 64, 3) == 98304 + 7680
+    assert bench.flops_per_point(0, 1, 32, 3) == 4 * 1024 + 30 * 96
+    # D*, I* and three scalars in; D, I, three scalars and three counters out
+    assert bench.bytes_per_point(32, 3) == 2 * 96 * 8 + 24 + 2 * 96 * 8 + 24 + 12
+    # O(v): D and three flux components each way, six scalars each way
+    assert bench.bytes_per_point_v(32, 3) == 2 * 4 * 96 * 8 + 48 + 48 + 12
