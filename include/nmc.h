@@ -223,7 +223,10 @@ int nmc_solve_batch(const nmc_model* m, const nmc_solver_params* prm, int64_t P,
                     const nmc_launch* launch, void* stream);
 
 /* Implicit-function-theorem adjoint of the forward solve at its converged
- * state (fwd holds the forward outputs for inputs `in`).  With per-point loss
+ * state (fwd holds the forward outputs for inputs `in`, solved with `prm`;
+ * NULL means the defaults).  The adjoint differentiates the coupled system
+ * (moments and matter), so a forward run with prm->fixed_matter set is
+ * rejected with NMC_E_UNSUPPORTED.  With per-point loss
  * L_p = gbar[2p] (e*_p - e_p) + gbar[2p+1] (Ye_p - Ye*_p), it ADDS
  * dL/dtheta = sum_p -lambda_p^T dR_p/dtheta to grad_theta (nq + 2), where
  * R_x^T lambda_p = dL_p/dx at x = (D, Ye, e); grad_pp (P, nq + 2) receives the
@@ -234,9 +237,9 @@ int nmc_solve_batch(const nmc_model* m, const nmc_solver_params* prm, int64_t P,
  * call (nmc_workspace_bytes(m, P), 256-byte aligned).  32-node grids only
  * (NMC_E_UNSUPPORTED otherwise).  A singular Jacobian (a zero or non-finite
  * pivot) makes that point's terms NaN. */
-int nmc_solve_batch_adjoint(const nmc_model* m, int64_t P, double dtau, const nmc_batch_in* in,
-                            const nmc_batch_out* fwd, const double* gbar, double* grad_theta,
-                            double* grad_pp, void* ws, size_t ws_bytes, void* stream);
+int nmc_solve_batch_adjoint(const nmc_model* m, const nmc_solver_params* prm, int64_t P, double dtau,
+                            const nmc_batch_in* in, const nmc_batch_out* fwd, const double* gbar,
+                            double* grad_theta, double* grad_pp, void* ws, size_t ws_bytes, void* stream);
 
 /* O(v) solve: nonzero fluid velocity (the O(v/c) two-moment model of
  * Sec. 2, solved as in Sec. 3.5).  The moment equations keep every velocity

@@ -290,43 +290,47 @@ static int check_params(const nmc_solver_params* p) {
   return NMC_OK;
 }
 
-int nmc_solve_batch(const nmc_model* m, const nmc_solver_params* prm, int64_t P, double dtau,
-                    const nmc_batch_in* in, const nmc_batch_out* out, void* ws, size_t ws_bytes,
-                    const nmc_launch* launch, void* stream) {
-  if (!m || !in || !out) return fail(NMC_E_INVALID_ARG, "solve_batch: null handle or descriptor");
+// The batched forward solve behind nmc_solve_batch: validation, then the launch with the work-queue
+// counters at `ws` and, for kernels stored in HBM, the kernel store at
+// `ws + kstore_off`.  `who` names the entry point in error messages.
+static int solve_batch_impl(const char* who, const nmc_model* m, const nmc_solver_params* prm, int64_t P,
+                            double dtau, const nmc_batch_in* in, const nmc_batch_out* out, void* ws,
+                            size_t ws_bytes, size_t kstore_off, const nmc_launch* launch, void* stream) {
+  if (!m || !in || !out) return fail(NMC_E_INVALID_ARG, "%s: null handle or descriptor", who);
   int rc = check_params(prm);
   if (rc) return rc;
-  if (P < 0 || P > (int64_t(1) << 30)) return fail(NMC_E_INVALID_ARG, "solve_batch: P out of range (%lld)", (long long)P);
-  if (!(dtau > 0.0) || !isfinite(dtau)) return fail(NMC_E_INVALID_ARG, "solve_batch: dtau must be positive");
+  if (P < 0 || P > (int64_t(1) << 30)) return fail(NMC_E_INVALID_ARG, "%s: P out of range (%lld)", who, (long long)P);
+  if (!(dtau > 0.0) || !isfinite(dtau)) return fail(NMC_E_INVALID_ARG, "%s: dtau must be positive", who);
   if (P == 0) return NMC_OK;
   if (!in->D0 || !in->I0 || !in->rho11 || !in->ye0 || !in->e0 || !in->theta)
-    return fail(NMC_E_INVALID_ARG, "solve_batch: null input array");
+    return fail(NMC_E_INVALID_ARG, "%s: null input array", who);
   if (!out->D || !out->I || !out->ye || !out->e || !out->T || !out->n_outer || !out->n_inner || !out->status)
-    return fail(NMC_E_INVALID_ARG, "solve_batch: null output array");
+    return fail(NMC_E_INVALID_ARG, "%s: null output array", who);
   if ((in->T_fixed || in->mu_fixed) && !prm->fixed_matter)
-    return fail(NMC_E_INVALID_ARG, "solve_batch: T_fixed / mu_fixed need fixed_matter");
+    return fail(NMC_E_INVALID_ARG, "%s: T_fixed / mu_fixed need fixed_matter", who);
   nmc_launch L = {0, 1, 1, NMC_KERNELS_ON_CHIP};
   if (launch) L = *launch;
   if (L.chunk < 1 || L.chunk > 4096 || L.blocks_per_cu < 0 || L.blocks_per_cu > 64)
-    return fail(NMC_E_INVALID_ARG, "solve_batch: bad launch configuration");
+    return fail(NMC_E_INVALID_ARG, "%s: bad launch configuration", who);
   if (L.kernel_store < NMC_KERNELS_ON_CHIP || L.kernel_store > NMC_KERNELS_WAVE)
-    return fail(NMC_E_INVALID_ARG, "solve_batch: bad kernel_store %d", L.kernel_store);
+    return fail(NMC_E_INVALID_ARG, "%s: bad kernel_store %d", who, L.kernel_store);
   double* kstore = nullptr;
   if (L.kernel_store == NMC_KERNELS_REGISTERS && m->host.nq != 32)
-    return fail(NMC_E_UNSUPPORTED, "solve_batch: register-resident kernel rows need 32 nodes");
+    return fail(NMC_E_UNSUPPORTED, "%s: register-resident kernel rows need 32 nodes", who);
   if ((L.kernel_store == NMC_KERNELS_PAIRED || L.kernel_store == NMC_KERNELS_WAVE) && m->host.nq != 32)
-    return fail(NMC_E_UNSUPPORTED, "solve_batch: kernel_store %d needs 32 nodes", L.kernel_store);
+    return fail(NMC_E_UNSUPPORTED, "%s: kernel_store %d needs 32 nodes", who, L.kernel_store);
   if (L.kernel_store == NMC_KERNELS_HBM) {
     if (m->host.nq != 64 || !(m->host.flags & (NMC_NES | NMC_PAIR)))
-      return fail(NMC_E_UNSUPPORTED, "solve_batch: kernels in HBM need 64 nodes and NES or pair physics");
-    const size_t need = nmc_workspace_bytes(m, P) + nmc_kernel_store_bytes(m, P);
+      return fail(NMC_E_UNSUPPORTED, "%s: kernels in HBM need 64 nodes and NES or pair physics", who);
+    const size_t need = kstore_off + nmc_kernel_store_bytes(m, P);
     if (!ws || !aligned256(ws) || ws_bytes < need)
-      return fail(NMC_E_WORKSPACE, "solve_batch: kernels in HBM need %zu workspace bytes", need);
-    kstore = (double*)((char*)ws + nmc_workspace_bytes(m, P));
+      return fail(NMC_E_WORKSPACE, "%s: kernels in HBM need %zu workspace bytes (%zu available)", who, need,
+                  ws_bytes);
+    kstore = (double*)((char*)ws + kstore_off);
   }
   if (L.persistent) {
     if (!ws || !aligned256(ws) || ws_bytes < kCounterBytes)
-      return fail(NMC_E_WORKSPACE, "solve_batch: persistent launch needs a 256-byte aligned workspace");
+      return fail(NMC_E_WORKSPACE, "%s: persistent launch needs a 256-byte aligned workspace", who);
   }
   nmc::FwdArgs a;
   memset(&a, 0, sizeof(a));
@@ -364,13 +368,21 @@ int nmc_solve_batch(const nmc_model* m, const nmc_solver_params* prm, int64_t P,
   if (L.persistent) {
     a.queue = (int*)ws;
     hipError_t e = nmc::launch_reset_counter(a.queue, s);
-    if (e != hipSuccess) return hip_fail(e, "solve_batch: counter reset");
+    if (e != hipSuccess) return hip_fail(e, "counter reset");
   }
   const bool coupled = (m->host.flags & (NMC_NES | NMC_PAIR)) != 0;
   hipError_t e = nmc::launch_forward(a, m->host.nq, m->host.ns, coupled, L, m->num_cu, s);
-  if (e == hipErrorInvalidValue) return fail(NMC_E_UNSUPPORTED, "solve_batch: no kernel for nq=%d ns=%d", m->host.nq, m->host.ns);
-  if (e != hipSuccess) return hip_fail(e, "solve_batch: launch");
+  if (e == hipErrorInvalidValue)
+    return fail(NMC_E_UNSUPPORTED, "%s: no kernel for nq=%d ns=%d", who, m->host.nq, m->host.ns);
+  if (e != hipSuccess) return hip_fail(e, "forward launch");
   return NMC_OK;
+}
+
+int nmc_solve_batch(const nmc_model* m, const nmc_solver_params* prm, int64_t P, double dtau,
+                    const nmc_batch_in* in, const nmc_batch_out* out, void* ws, size_t ws_bytes,
+                    const nmc_launch* launch, void* stream) {
+  return solve_batch_impl("solve_batch", m, prm, P, dtau, in, out, ws, ws_bytes, m ? nmc_workspace_bytes(m, P) : 0,
+                          launch, stream);
 }
 
 int nmc_solve_batch_v(const nmc_model* m, const nmc_solver_params* prm, int64_t P, double dtau,
@@ -441,10 +453,13 @@ int nmc_solve_batch_v(const nmc_model* m, const nmc_solver_params* prm, int64_t 
   return NMC_OK;
 }
 
-int nmc_solve_batch_adjoint(const nmc_model* m, int64_t P, double dtau, const nmc_batch_in* in,
-                            const nmc_batch_out* fwd, const double* gbar, double* grad_theta, double* grad_pp,
-                            void* ws, size_t ws_bytes, void* stream) {
+int nmc_solve_batch_adjoint(const nmc_model* m, const nmc_solver_params* prm, int64_t P, double dtau,
+                            const nmc_batch_in* in, const nmc_batch_out* fwd, const double* gbar,
+                            double* grad_theta, double* grad_pp, void* ws, size_t ws_bytes, void* stream) {
   if (!m || !in || !fwd) return fail(NMC_E_INVALID_ARG, "adjoint: null model, inputs or forward outputs");
+  if (prm && prm->fixed_matter)
+    return fail(NMC_E_UNSUPPORTED, "adjoint: the forward solve held the matter fixed; the adjoint differentiates "
+                                   "the coupled system");
   if (P < 0 || P > (int64_t(1) << 30)) return fail(NMC_E_INVALID_ARG, "adjoint: P out of range");
   if (!(dtau > 0.0) || !isfinite(dtau)) return fail(NMC_E_INVALID_ARG, "adjoint: dtau must be positive and finite");
   if (!grad_theta) return fail(NMC_E_INVALID_ARG, "adjoint: null grad_theta");

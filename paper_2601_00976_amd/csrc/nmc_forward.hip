@@ -371,8 +371,14 @@ struct PointSolver {
         const int mem = l < a.prm.m_inner ? l : a.prm.m_inner;
         double Mnew[NS];
         if (mem == 1) {
+          // clear the older difference column (weighted zero at the second
+          // iterate), so that no stale LDS word enters that product
 #pragma unroll
-          for (int t = 0; t < NS; ++t) Mnew[t] = Q[t];
+          for (int t = 0; t < NS; ++t) {
+            Mnew[t] = Q[t];
+            S.u.it.hist[2][t][lane] = 0.0;
+            S.u.it.hist[3][t][lane] = 0.0;
+          }
         } else {
           const double use1 = (mem == 3) ? 1.0 : 0.0;
           double dQ2[NS], dF2[NS];

@@ -345,8 +345,14 @@ struct PointSolver64 {
         const int mem = l < a.prm.m_inner ? l : a.prm.m_inner;
         double Xn[2 * NS];
         if (mem == 1) {
+          // clear the older difference column (weighted zero at the second
+          // iterate), so that no stale LDS word enters that product
 #pragma unroll
-          for (int x = 0; x < 2 * NS; ++x) Xn[x] = Qx[x];
+          for (int x = 0; x < 2 * NS; ++x) {
+            Xn[x] = Qx[x];
+            S.hist[2][x][lane] = 0.0;
+            S.hist[3][x][lane] = 0.0;
+          }
         } else {
           const double use1 = (mem == 3) ? 1.0 : 0.0;
           double dQ2[2 * NS], dF2[2 * NS];

@@ -388,8 +388,15 @@ struct PairSolver {
         const int mem = l < a.prm.m_inner ? l : a.prm.m_inner;
         double Xn[2 * NS];
         if (mem == 1) {
+          // the older difference column is weighted zero at the second
+          // iterate: clear it, so that no stale LDS word (a NaN pattern left
+          // by another point or kernel) enters that product
 #pragma unroll
-          for (int x = 0; x < 2 * NS; ++x) Xn[x] = Qx[x];
+          for (int x = 0; x < 2 * NS; ++x) {
+            Xn[x] = Qx[x];
+            S.u.hist[2][x][lane] = 0.0;
+            S.u.hist[3][x][lane] = 0.0;
+          }
         } else {
           const double use1 = (mem == 3) ? 1.0 : 0.0;
           double dQ2[2 * NS], dF2[2 * NS];

@@ -349,10 +349,17 @@ struct PointSolverV {
         const int mem = l < a.prm.m_inner ? l : a.prm.m_inner;
         double Mn[NS][2];
         if (mem == 1) {
+          // clear the older difference column (weighted zero at the second
+          // iterate), so that no stale LDS word enters that product
 #pragma unroll
           for (int t = 0; t < NS; ++t) {
             Mn[t][0] = Q[t][0];
             Mn[t][1] = Q[t][1];
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+              S.hist[2][t][c][lane] = 0.0;
+              S.hist[3][t][c][lane] = 0.0;
+            }
           }
         } else {
           const double use1 = (mem == 3) ? 1.0 : 0.0;

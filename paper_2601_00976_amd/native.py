@@ -106,8 +106,8 @@ def lib():
                                       C.POINTER(BatchOut), vp, C.c_size_t, C.POINTER(Launch), vp]
         L.nmc_solve_batch_v.argtypes = [vp, C.POINTER(SolverParams), C.c_int64, C.c_double, C.POINTER(BatchVIn),
                                         C.POINTER(BatchVOut), vp, C.c_size_t, C.POINTER(Launch), vp]
-        L.nmc_solve_batch_adjoint.argtypes = [vp, C.c_int64, C.c_double, C.POINTER(BatchIn), C.POINTER(BatchOut),
-                                              vp, vp, vp, vp, C.c_size_t, vp]
+        L.nmc_solve_batch_adjoint.argtypes = [vp, C.POINTER(SolverParams), C.c_int64, C.c_double, C.POINTER(BatchIn),
+                                              C.POINTER(BatchOut), vp, vp, vp, vp, C.c_size_t, vp]
         L.nmc_init_state.argtypes = [vp, C.c_int64, vp, vp, vp, vp, vp, vp, C.c_double, C.c_double, C.c_double,
                                      vp, vp, vp, vp]
         L.nmc_probe_fma_f64.argtypes = [C.c_int64, C.c_int, vp, vp]

@@ -238,13 +238,15 @@ def solve_v(model: Model, params: Params, dtau: float, D0, I0, rho11, ye0, ef0, 
 
 
 def adjoint(model: Model, dtau: float, rho11, theta, fwd, gbar, chi0=None, grad_theta=None, per_point=False,
-            workspace: Workspace | None = None, stream=None):
+            workspace: Workspace | None = None, stream=None, params: Params | None = None):
     """Enqueue the implicit-function-theorem adjoint of a converged forward
-    solve (``fwd`` = its output dict) for the per-point loss
+    solve (``fwd`` = its output dict, solved with ``params``, default
+    ``Params()``) for the per-point loss
     L_p = gbar[p, 0] (e*_p - e_p) + gbar[p, 1] (Ye_p - Ye*_p).
 
     Adds dL/dtheta into ``grad_theta`` (allocated zero if None) and returns it,
-    with the (P, nq + 2) per-point terms when ``per_point``."""
+    with the (P, nq + 2) per-point terms when ``per_point``.  A forward solve
+    with fixed matter is rejected (NmcError, NMC_E_UNSUPPORTED)."""
     P = rho11.shape[0]
     nq = model.nq
     _req(rho11, "rho11", (P,))
@@ -261,7 +263,9 @@ def adjoint(model: Model, dtau: float, rho11, theta, fwd, gbar, chi0=None, grad_
     gpp = torch.empty(P, nq + 2, dtype=torch.float64, device=rho11.device) if per_point else None
     if workspace is None:
         workspace = Workspace(model, P, rho11.device)
-    N.check(N.lib().nmc_solve_batch_adjoint(model._h, P, float(dtau), C.byref(bi), C.byref(bo), gbar.data_ptr(),
+    pc = (params or Params()).c()
+    N.check(N.lib().nmc_solve_batch_adjoint(model._h, C.byref(pc), P, float(dtau), C.byref(bi), C.byref(bo),
+                                            gbar.data_ptr(),
                                             grad_theta.data_ptr(), None if gpp is None else gpp.data_ptr(),
                                             C.c_void_p(workspace.ptr), workspace.nbytes, _stream_handle(stream)))
     return (grad_theta, gpp) if per_point else grad_theta
@@ -277,8 +281,11 @@ class NMCSolve(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, theta, model, params, dtau, D0, I0, rho11, ye0, e0):
+        if params.fixed_matter:
+            raise NotImplementedError("NMCSolve: the adjoint differentiates the coupled system; "
+                                      "fixed_matter is not supported")
         out = solve(model, params, dtau, D0, I0, rho11, ye0, e0, theta)
-        ctx.model, ctx.dtau = model, dtau
+        ctx.model, ctx.dtau, ctx.params = model, dtau, params
         ctx.out = out
         ctx.save_for_backward(theta, rho11)
         return out["D"], out["I"], out["ye"], out["e"], e0 - out["e"], out["ye"] - ye0
@@ -294,7 +301,7 @@ class NMCSolve(torch.autograd.Function):
         gE = (gLE if gLE is not None else z) - (ge if ge is not None else z)
         gY = (gLY if gLY is not None else z) + (gYe if gYe is not None else z)
         gbar = torch.stack([gE, gY], dim=1).contiguous()
-        g = adjoint(ctx.model, ctx.dtau, rho11, theta, ctx.out, gbar)
+        g = adjoint(ctx.model, ctx.dtau, rho11, theta, ctx.out, gbar, params=ctx.params)
         return g, None, None, None, None, None, None, None, None
 
 

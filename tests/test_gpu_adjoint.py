@@ -192,3 +192,54 @@ def test_adjoint_against_gpu_finite_differences():
         assert err.max() <= 1e-4, f"L_{name}: FD mismatch {err.max():.3e}"
         assert np.median(err) <= 1e-6, f"L_{name}: median FD mismatch {np.median(err):.3e}"
     assert checked >= 100
+
+
+def test_adjoint_full_size_every_point():
+    """The adjoint at the size the benchmark runs it: all 2^16 points of the
+    profile's first step, at the oracle's converged state.  The launch then
+    runs its grid-stride loop (several points per work-group, each on the LDS
+    state the previous one left) and the first reduction stage sums many rows
+    per block.  Every live row is compared with the oracle's dense-LU adjoint
+    (1e-9 relative to the row's largest entry), the summed gradient with the
+    oracle's sum (1e-9 of its largest component), and with the float64 sum of
+    the GPU's own rows (1e-12)."""
+    _say("adjoint, all 2^16 profile points at the oracle state, random gbar")
+    d = W.radial_profile(P=1 << 16)
+    theta = _theta()
+    gbar = np.random.default_rng(13).uniform(-1, 1, (1 << 16, 2))
+    m, r = PT.run_oracle(d, ALL3, O.ALL_PHYSICS, W.DTAU_KM, O.Params(), theta)
+    assert np.all(r["status"] == 0)
+    g_ref, gpp_ref = O.adjoint_batch(m, theta, W.DTAU_KM, d.rho11, r["D"], r["ye"], r["e"], gbar, per_point=True)
+    mg = S.Model(S.Grid(16))
+    g, gpp = _gpu_adjoint_at(mg, d, r, theta, gbar)
+    live = d.rho11 >= m.c.rho11_min
+    assert np.all(gpp[~live] == 0.0)
+    assert np.all(np.isfinite(gpp))
+    err = _rel_rows(gpp[live], gpp_ref[live])
+    print(f"{int(live.sum())} live points: per-point adjoint error max {err.max():.2e}, median {np.median(err):.2e}",
+          flush=True)
+    assert err.max() <= 1e-9, f"per-point adjoint error {err.max():.3e}"
+    gscale = np.max(np.abs(g_ref))
+    print(f"summed gradient error {np.max(np.abs(g - g_ref)) / gscale:.2e}", flush=True)
+    assert np.max(np.abs(g - g_ref)) <= 1e-9 * gscale
+    assert np.max(np.abs(gpp.sum(0) - g)) <= 1e-12 * np.max(np.abs(g))
+
+
+def test_adjoint_rejects_fixed_matter():
+    import torch
+    from paper_2601_00976_amd import native as N
+    _say("adjoint of a fixed-matter forward solve is rejected")
+    d = _profile(16, seed=2)
+    mg = S.Model(S.Grid(16))
+    t = S.to_device(d)
+    D0, I0, e0 = S.init_state(mg, t["T"], t["rho11"], t["ye"], t["uD"], t["uI"])
+    theta = torch.as_tensor(_theta(), device="cuda")
+    prm = S.Params(fixed_matter=True)
+    out = S.solve(mg, prm, W.DTAU_KM, D0, I0, t["rho11"], t["ye"], e0, theta)
+    gbar = torch.ones(16, 2, dtype=torch.float64, device="cuda")
+    with pytest.raises(N.NmcError) as ei:
+        S.adjoint(mg, W.DTAU_KM, t["rho11"], theta, out, gbar, params=prm)
+    assert ei.value.code == N.NMC_E_UNSUPPORTED
+    with pytest.raises(NotImplementedError):
+        S.NMCSolve.apply(theta.clone().requires_grad_(True), mg, prm, W.DTAU_KM, D0, I0, t["rho11"], t["ye"], e0)
+    torch.cuda.synchronize()

@@ -1,8 +1,17 @@
 """Parity at the benchmark's full sizes and launch shapes: the whole radial
 profile (2^16 points at 32 nodes, 2^18 at 64 nodes) is solved on the GPU for
 three chained in-place steps at the launch shape bench.py times (autotune
-cache); every point is independent, so the oracle's chain on a sample of
-points is their exact reference."""
+cache), and every point of every step is compared with the oracle's own
+chain of the same three steps.
+
+Bar: the statuses agree at every point of every step; after step k the
+moments agree to k * 1e-9 in the per-species W-norm, and Ye and e to
+k * 1e-9 times the neutrino/matter reservoir ratio (at least 1).  Each step
+solves to the relative tolerance 1e-10 and agrees with the oracle's step to
+1e-9 from the same input; the chained input differences are carried through
+the next step's implicit map, whose response to the old state is damped
+(1 / (1 + dtau chi) per node), so the differences add at most linearly over
+the steps.  The measured per-step maxima are printed."""
 import numpy as np
 import pytest
 
@@ -14,12 +23,15 @@ from tests import parity as PT
 
 pytestmark = pytest.mark.gpu
 
+STEPS = 3
+
 
 @pytest.mark.parametrize("n_elem,P,wid", [(16, 1 << 16, 3), (32, 1 << 18, 4)])
-def test_full_size_chain_sampled(n_elem, P, wid):
+def test_full_size_chain_every_point(n_elem, P, wid):
     import torch
     nq = 2 * n_elem
-    print(f"[case] full size {P} points, {nq} nodes, 3 chained steps at the bench launch", flush=True)
+    print(f"[case] full size {P} points, {nq} nodes, {STEPS} chained steps at the bench launch, every point",
+          flush=True)
     full = W.radial_profile(P=P, nq=nq, wid=wid)
     m = S.Model(S.Grid(n_elem))
     t = S.to_device(full)
@@ -29,28 +41,22 @@ def test_full_size_chain_sampled(n_elem, P, wid):
     launch = AT.best_launch(m, P)
     out = S.alloc_outputs(m, P)
     out.update(D=D, I=I, ye=ye, e=e)
-    idx = W.fd_sample(P, 256, seed=11)
-    ok = np.ones(len(idx), dtype=bool)
-    for _ in range(3):
-        S.solve(m, S.Params(), W.DTAU_KM, D, I, t["rho11"], ye, e, theta, out=out, launch=launch)
-        ok &= out["status"].cpu().numpy()[idx] == 0
-    torch.cuda.synchronize()
-    got = {k: x.cpu().numpy()[idx] for k, x in out.items()}
-    d = full.take(idx)
     om = O.Model(n_elem=n_elem)
     th = theta.cpu().numpy()
-    Do, Io, eo = om.init_state(d.T, d.rho11, d.ye, d.uD, d.uI)
-    yeo = d.ye.copy()
-    for _ in range(3):
-        r = O.solve_batch(om, O.Params(), th, W.DTAU_KM, Do, Io, d.rho11, yeo, eo)
+    Do, Io, eo = om.init_state(full.T, full.rho11, full.ye, full.uD, full.uI)
+    yeo = full.ye.copy()
+    for k in range(1, STEPS + 1):
+        S.solve(m, S.Params(), W.DTAU_KM, D, I, t["rho11"], ye, e, theta, out=out, launch=launch)
+        torch.cuda.synchronize()
+        got = {n: x.cpu().numpy() for n, x in out.items()}
+        r = O.solve_batch(om, O.Params(), th, W.DTAU_KM, Do, Io, full.rho11, yeo, eo)
         Do, Io, yeo, eo = r["D"], r["I"], r["ye"], r["e"]
-        ok &= r["status"] == 0
-    assert ok.mean() > 0.98
-    ref = {k: v[ok] for k, v in r.items()}
-    sub = {k: v[ok] for k, v in got.items()}
-    eD, eI, eY, eE = PT.parity_errors(ref, sub, om.w2)
-    RY, RE = PT.reservoir_ratios(om.c.kcoup, d.rho11[ok], ref["D"], ref["ye"], ref["e"], om.w2, om.w3)
-    eY, eE = eY / np.maximum(RY, 1.0), eE / np.maximum(RE, 1.0)
-    print(f"max errors D {eD.max():.2e} I {eI.max():.2e} Ye {eY.max():.2e} e {eE.max():.2e}", flush=True)
-    # three chained steps carry the tolerance-level differences forward
-    assert max(eD.max(), eI.max(), eY.max(), eE.max()) <= 3e-9
+        assert np.array_equal(r["status"], got["status"]), f"step {k}: status mismatch"
+        assert np.all(r["status"] == O.OK)
+        assert np.array_equal(r["n_outer"] == 0, got["n_outer"] == 0)
+        eD, eI, eY, eE = PT.parity_errors(r, got, om.w2)
+        RY, RE = PT.reservoir_ratios(om.c.kcoup, full.rho11, r["D"], r["ye"], r["e"], om.w2, om.w3)
+        eY, eE = eY / np.maximum(RY, 1.0), eE / np.maximum(RE, 1.0)
+        print(f"step {k}: max errors D {eD.max():.2e} I {eI.max():.2e} Ye {eY.max():.2e} e {eE.max():.2e}; "
+              f"solved {int(np.sum(got['n_outer'] > 0))}", flush=True)
+        assert max(eD.max(), eI.max(), eY.max(), eE.max()) <= k * 1e-9, f"step {k}"

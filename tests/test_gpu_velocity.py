@@ -141,11 +141,36 @@ def test_single_point_and_all_skipped():
     assert np.array_equal(got["v"], low.v) and np.array_equal(got["ef"], got["ef0"])
 
 
-def test_full_size_chain_sampled_parity():
+def _oracle_status_spread(om, idx, D, I, rho11, ye, ef, v, draws=64):
+    """Statuses the oracle itself returns at points idx when every entry of
+    the old moments D* moves by a seeded random -1, 0 or +1 ulp (``draws``
+    runs per point)."""
+    rng = np.random.default_rng(17)
+    rep = np.repeat(idx, draws)
+    Dp = D[rep] * (1.0 + rng.integers(-1, 2, D[rep].shape) * 2.0 ** -52)
+    r = O.solve_batch_v(om, O.Params(**ORA_PRM), _theta(), W.DTAU_KM, Dp, I[rep], rho11[rep], ye[rep], ef[rep],
+                        v[rep])
+    return [set(int(x) for x in r["status"][i * draws:(i + 1) * draws]) for i in range(len(idx))]
+
+
+def test_full_size_chain_every_point():
     """The 2^16-point moving profile at the launch shape bench.py times, three
-    chained in-place steps on the GPU; every point is independent, so the
-    oracle's chain on a sample of 384 points is its exact reference there."""
-    _say("O(v) full size 2^16, 3 chained steps, sampled parity")
+    chained in-place steps on the GPU and in the oracle, every point of every
+    step compared.
+
+    Statuses: equal at every point, except where the oracle's own status is
+    decided by rounding.  At the low-density edge of the profile the outer
+    iteration of a few points hovers at its noise floor (the neutrino/matter
+    reservoir ratio amplifies the inner loop's residual), and whether it meets
+    the outer tolerance within max_outer there flips with 1-ulp changes of
+    the old moments.  A status mismatch is accepted only where the GPU's
+    status is one the oracle returns under such a perturbation of its own
+    input (64 seeded draws), and on at most 0.1% of the points.  Points
+    that are not OK on either side are not converged states: their moments
+    are not compared, and from then on their chained inputs differ.
+    Moments and matter of every other point: after step k, k * 1e-9 (as for
+    the static chain)."""
+    _say("O(v) full size 2^16, 3 chained steps, every point")
     import torch
     full = W.radial_profile_v(P=1 << 16)
     m = S.Model(S.Grid())
@@ -156,34 +181,36 @@ def test_full_size_chain_sampled_parity():
     prm = S.Params(**ORA_PRM)
     out = S.alloc_outputs_v(m, 1 << 16)
     out.update(D=D, I=I, ye=ye, ef=ef, v=v)
-    idx = W.fd_sample(1 << 16, 384, seed=7)
-    ok = np.ones(len(idx), dtype=bool)
-    for _ in range(3):
-        S.solve_v(m, prm, W.DTAU_KM, D, I, t["rho11"], ye, ef, v, theta, out=out, launch=S.LaunchConfig(chunk=1))
-        ok &= out["status"].cpu().numpy()[idx] == 0
-    torch.cuda.synchronize()
-    got = {k: x.cpu().numpy() for k, x in out.items()}
-    d = full.take(idx)
     om = O.Model()
-    D0, _, e0 = om.init_state(d.T, d.rho11, d.ye, d.uD, d.uI)
-    Io = 0.1 * D0[:, :, None, :] * d.uI3
-    efo = e0 + 0.5 * O.MU_C2 * np.sum(d.v * d.v, axis=1)
-    Do, yeo, vo = D0, d.ye.copy(), d.v.copy()
-    for _ in range(3):
-        r = O.solve_batch_v(om, O.Params(**ORA_PRM), _theta(), W.DTAU_KM, Do, Io, d.rho11, yeo, efo, vo)
+    D0, _, e0 = om.init_state(full.T, full.rho11, full.ye, full.uD, full.uI)
+    Io = 0.1 * D0[:, :, None, :] * full.uI3
+    efo = e0 + 0.5 * O.MU_C2 * np.sum(full.v * full.v, axis=1)
+    Do, yeo, vo = D0, full.ye.copy(), full.v.copy()
+    live = np.ones(1 << 16, dtype=bool)  # converged on both sides in every step so far
+    for k in range(1, 4):
+        S.solve_v(m, prm, W.DTAU_KM, D, I, t["rho11"], ye, ef, v, theta, out=out, launch=S.LaunchConfig(chunk=1))
+        torch.cuda.synchronize()
+        got = {n: x.cpu().numpy() for n, x in out.items()}
+        r = O.solve_batch_v(om, O.Params(**ORA_PRM), _theta(), W.DTAU_KM, Do, Io, full.rho11, yeo, efo, vo)
+        mism = np.where(live & (r["status"] != got["status"]))[0]
+        print(f"step {k}: oracle status {np.bincount(r['status'], minlength=5)}, "
+              f"GPU {np.bincount(got['status'], minlength=5)}, {len(mism)} mismatches", flush=True)
+        if len(mism):
+            seen = _oracle_status_spread(om, mism, Do, Io, full.rho11, yeo, efo, vo)
+            for i, p in enumerate(mism):
+                print(f"  point {p} (rho11 {full.rho11[p]:.2e}): oracle {r['status'][p]}, GPU {got['status'][p]}, "
+                      f"oracle under 1-ulp changes of D* {sorted(seen[i])}", flush=True)
+            assert all(int(got["status"][p]) in seen[i] for i, p in enumerate(mism)), f"step {k}: status mismatch"
+            assert len(mism) <= 1e-3 * len(live)
         Do, Io, yeo, efo, vo = r["D"], r["I"], r["ye"], r["ef"], r["v"]
-        ok &= r["status"] == 0
-    sub = {k: x[idx] for k, x in got.items()}
-    # a point stalled at max_outer in one step is not a converged state: its
-    # later steps start from different (noise-floor) iterates on both sides
-    assert ok.mean() > 0.98
-    eD, eI, eY, eE, eV = PT.parity_errors_v({k: x[ok] for k, x in r.items()}, {k: x[ok] for k, x in sub.items()},
-                                            om.w2, om.w3, om.c.kcoup, d.rho11[ok])
-    print(f"max errors D {eD.max():.2e} I {eI.max():.2e} Ye {eY.max():.2e} ef {eE.max():.2e} v {eV.max():.2e}",
-          flush=True)
-    # three chained steps carry the tolerance-level differences forward
-    assert eD.max() <= 3 * TOL and eI.max() <= 3 * TOL
-    assert eY.max() <= 3 * TOL and eE.max() <= 3 * TOL and eV.max() <= 3 * TOL
+        live &= (r["status"] == 0) & (got["status"] == 0)
+        assert live.mean() > 0.999
+        eD, eI, eY, eE, eV = PT.parity_errors_v({n: x[live] for n, x in r.items()},
+                                                {n: x[live] for n, x in got.items()},
+                                                om.w2, om.w3, om.c.kcoup, full.rho11[live])
+        print(f"step {k}: max errors D {eD.max():.2e} I {eI.max():.2e} Ye {eY.max():.2e} ef {eE.max():.2e} "
+              f"v {eV.max():.2e} over {int(live.sum())} points", flush=True)
+        assert max(eD.max(), eI.max(), eY.max(), eE.max(), eV.max()) <= k * TOL, f"step {k}"
 
 
 @pytest.mark.parametrize("species,flags,fixed", [
