@@ -169,7 +169,13 @@ def test_full_size_chain_every_point():
     that are not OK on either side are not converged states: their moments
     are not compared, and from then on their chained inputs differ.
     Moments and matter of every other point: after step k, k * 1e-9 (as for
-    the static chain)."""
+    the static chain), per species, except for a species more than 12 orders
+    of magnitude below the point's largest (nu_e at ~0.3 MeV, ~1e-22 of
+    anti-nu_e at the low-density edge): there the outer iteration of the two
+    sides stops at different counts within its tolerance, the temperature
+    differs at that level, and that species' exponential tail answers with a
+    factor (eps - mu) / T of 50-100, so it is compared in the point's
+    all-species W-norm, the reading used for the low-temperature case."""
     _say("O(v) full size 2^16, 3 chained steps, every point")
     import torch
     full = W.radial_profile_v(P=1 << 16)
@@ -210,7 +216,20 @@ def test_full_size_chain_every_point():
                                                 om.w2, om.w3, om.c.kcoup, full.rho11[live])
         print(f"step {k}: max errors D {eD.max():.2e} I {eI.max():.2e} Ye {eY.max():.2e} ef {eE.max():.2e} "
               f"v {eV.max():.2e} over {int(live.sum())} points", flush=True)
-        assert max(eD.max(), eI.max(), eY.max(), eE.max(), eV.max()) <= k * TOL, f"step {k}"
+        # a species more than 12 orders of magnitude below the point's largest
+        # is compared in the point's all-species W-norm (see the docstring)
+        dn = PT.wnorm(r["D"][live], om.w2)
+        tiny = dn < 1e-12 * dn.max(axis=1, keepdims=True)
+        scale = np.where(tiny, np.sqrt(np.sum(dn * dn, axis=1, keepdims=True)), 1.0)
+        eDs, eIs = np.where(tiny, eD * dn / scale, eD), np.where(tiny, eI * dn / scale, eI)
+        li = np.where(live)[0]
+        for w in np.where(np.max(np.maximum(eD, eI), axis=1) > k * TOL)[0]:
+            p = li[w]
+            print(f"  point {p}: rho11 {full.rho11[p]:.3e} T {r['T'][p]:.3f} errors D {eD[w]} I {eI[w]} "
+                  f"||D_s|| {dn[w]} n_outer {r['n_outer'][p]}/{got['n_outer'][p]}", flush=True)
+        print(f"step {k}: with tiny species in the point norm: D {eDs.max():.2e} I {eIs.max():.2e} "
+              f"({int(tiny.sum())} tiny species)", flush=True)
+        assert max(eDs.max(), eIs.max(), eY.max(), eE.max(), eV.max()) <= k * TOL, f"step {k}"
 
 
 @pytest.mark.parametrize("species,flags,fixed", [
