@@ -222,6 +222,24 @@ int nmc_solve_batch(const nmc_model* m, const nmc_solver_params* prm, int64_t P,
                     const nmc_batch_in* in, const nmc_batch_out* out, void* ws, size_t ws_bytes,
                     const nmc_launch* launch, void* stream);
 
+/* The batched forward solve of nmc_solve_batch for callers that cannot
+ * allocate device memory: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation.  It takes no workspace: the work-queue
+ * counters live in a static device array of 4 MiB (one copy per device,
+ * held until the process ends) that the call clears with a kernel before
+ * its solve.  Inputs, outputs, launch and stream are as for
+ * nmc_solve_batch, with the same results; nothing is allocated or freed.
+ * With launch->kernel_store = NMC_KERNELS_HBM the kernel store also lives
+ * there, so P is limited to what fits (NMC_E_WORKSPACE beyond: 2 KiB of
+ * counters plus nmc_kernel_store_bytes(m, P) must not exceed 4 MiB).
+ * Every call on a device shares that device's array, so calls that overlap
+ * on one device (concurrent streams, threads) race and must be serialised
+ * by the caller; a call on a model whose device has no scratch address
+ * returns NMC_E_HIP. */
+int nmc_solve_batch_noalloc(const nmc_model* m, const nmc_solver_params* prm, int64_t P, double dtau,
+                            const nmc_batch_in* in, const nmc_batch_out* out, const nmc_launch* launch,
+                            void* stream);
+
 /* Implicit-function-theorem adjoint of the forward solve at its converged
  * state (fwd holds the forward outputs for inputs `in`, solved with `prm`;
  * NULL means the defaults).  The adjoint differentiates the coupled system

@@ -4,6 +4,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <mutex>
 #include <new>
 #include <string>
 
@@ -23,7 +24,17 @@ struct nmc_model {
   nmc::DevModel* dev;
   int device;
   int num_cu;
+  void* scratch;  // device address of the static scratch on `device`
+  hipError_t scratch_err;  // result of its lookup
 };
+
+// Static scratch of nmc_solve_batch_noalloc: the work-queue counters (and,
+// for kernels stored in HBM, the kernel store) of solves that may not
+// allocate.  Each device holds its own copy for the life of the process.  In
+// host code `scratch` is a host-side stand-in, never a device address: the
+// device address comes from hipGetSymbolAddress, once per device.
+static constexpr size_t kScratchBytes = size_t(4) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
 
 namespace {
 
@@ -47,6 +58,26 @@ int hip_fail(hipError_t e, const char* what) {
 bool aligned256(const void* p) { return ((uintptr_t)p & 255u) == 0; }
 
 constexpr size_t kCounterBytes = 2048;  // work-queue counters: 8 lines of 256 bytes
+
+// per-device addresses of the static scratch
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices];
+
+// device address of `scratch` on device `dev` (current), looked up once
+hipError_t scratch_address(int dev, void** out) {
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!ptr) return hipErrorInvalidSymbol;
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
 
 int partner_id(int id) { return id == NMC_NU_E ? NMC_NU_E_BAR : (id == NMC_NU_E_BAR ? NMC_NU_E : NMC_NU_X); }
 
@@ -253,6 +284,10 @@ int nmc_model_create(const nmc_grid* g, const nmc_model_desc* d, nmc_model** out
     delete mm;
     return hip_fail(e, "model_create");
   }
+  // the static scratch of the no-allocation solve, looked up with the
+  // model's device current; a failed lookup disables only that entry point
+  mm->scratch_err = scratch_address(mm->device, &mm->scratch);
+  if (mm->scratch_err != hipSuccess) mm->scratch = nullptr;
   *out = mm;
   return NMC_OK;
 }
@@ -290,7 +325,8 @@ static int check_params(const nmc_solver_params* p) {
   return NMC_OK;
 }
 
-// The batched forward solve behind nmc_solve_batch: validation, then the launch with the work-queue
+// The batched forward solve behind nmc_solve_batch and
+// nmc_solve_batch_noalloc: validation, then the launch with the work-queue
 // counters at `ws` and, for kernels stored in HBM, the kernel store at
 // `ws + kstore_off`.  `who` names the entry point in error messages.
 static int solve_batch_impl(const char* who, const nmc_model* m, const nmc_solver_params* prm, int64_t P,
@@ -383,6 +419,25 @@ int nmc_solve_batch(const nmc_model* m, const nmc_solver_params* prm, int64_t P,
                     const nmc_launch* launch, void* stream) {
   return solve_batch_impl("solve_batch", m, prm, P, dtau, in, out, ws, ws_bytes, m ? nmc_workspace_bytes(m, P) : 0,
                           launch, stream);
+}
+
+int nmc_solve_batch_noalloc(const nmc_model* m, const nmc_solver_params* prm, int64_t P, double dtau,
+                            const nmc_batch_in* in, const nmc_batch_out* out, const nmc_launch* launch,
+                            void* stream) {
+  if (!m) return fail(NMC_E_INVALID_ARG, "solve_batch_noalloc: null model");
+  if (!m->scratch)
+    return fail(NMC_E_HIP, "solve_batch_noalloc: no static scratch address on device %d: %s", m->device,
+                hipGetErrorString(m->scratch_err));
+  if (launch && launch->kernel_store == NMC_KERNELS_HBM && P > 0) {
+    const size_t need = kCounterBytes + nmc_kernel_store_bytes(m, P);
+    if (need > kScratchBytes)
+      return fail(NMC_E_WORKSPACE,
+                  "solve_batch_noalloc: %lld points with kernels in HBM need %zu bytes of scratch; the static "
+                  "scratch holds %zu",
+                  (long long)P, need, kScratchBytes);
+  }
+  return solve_batch_impl("solve_batch_noalloc", m, prm, P, dtau, in, out, m->scratch, kScratchBytes,
+                          kCounterBytes, launch, stream);
 }
 
 int nmc_solve_batch_v(const nmc_model* m, const nmc_solver_params* prm, int64_t P, double dtau,

@@ -28,7 +28,7 @@ SPACING_LOG, SPACING_ZOOM = 0, 1
 EXPORTED = (
     "nmc_model_desc_default", "nmc_solver_params_default", "nmc_grid_create", "nmc_grid_query",
     "nmc_grid_destroy", "nmc_model_create", "nmc_model_destroy", "nmc_workspace_bytes", "nmc_kernel_store_bytes",
-    "nmc_solve_batch", "nmc_solve_batch_v", "nmc_solve_batch_adjoint", "nmc_init_state", "nmc_probe_fma_f64", "nmc_error_string",
+    "nmc_solve_batch", "nmc_solve_batch_noalloc", "nmc_solve_batch_v", "nmc_solve_batch_adjoint", "nmc_init_state", "nmc_probe_fma_f64", "nmc_error_string",
     "nmc_last_error",
 )
 
@@ -104,6 +104,8 @@ def lib():
         L.nmc_kernel_store_bytes.restype = C.c_size_t
         L.nmc_solve_batch.argtypes = [vp, C.POINTER(SolverParams), C.c_int64, C.c_double, C.POINTER(BatchIn),
                                       C.POINTER(BatchOut), vp, C.c_size_t, C.POINTER(Launch), vp]
+        L.nmc_solve_batch_noalloc.argtypes = [vp, C.POINTER(SolverParams), C.c_int64, C.c_double, C.POINTER(BatchIn),
+                                              C.POINTER(BatchOut), C.POINTER(Launch), vp]
         L.nmc_solve_batch_v.argtypes = [vp, C.POINTER(SolverParams), C.c_int64, C.c_double, C.POINTER(BatchVIn),
                                         C.POINTER(BatchVOut), vp, C.c_size_t, C.POINTER(Launch), vp]
         L.nmc_solve_batch_adjoint.argtypes = [vp, C.POINTER(SolverParams), C.c_int64, C.c_double, C.POINTER(BatchIn),
@@ -116,7 +118,7 @@ def lib():
         L.nmc_last_error.argtypes = []
         L.nmc_last_error.restype = C.c_char_p
         for f in ("nmc_grid_create", "nmc_grid_query", "nmc_grid_destroy", "nmc_model_create", "nmc_model_destroy",
-                  "nmc_solve_batch", "nmc_solve_batch_v", "nmc_solve_batch_adjoint", "nmc_init_state",
+                  "nmc_solve_batch", "nmc_solve_batch_noalloc", "nmc_solve_batch_v", "nmc_solve_batch_adjoint", "nmc_init_state",
                   "nmc_probe_fma_f64"):
             getattr(L, f).restype = C.c_int
         _lib = L

@@ -192,6 +192,21 @@ def solve(model: Model, params: Params, dtau: float, D0, I0, rho11, ye0, e0, the
     return out
 
 
+def solve_noalloc(model: Model, params: Params, dtau: float, D0, I0, rho11, ye0, e0, theta, out, chi0=None,
+                  T_fixed=None, mu_fixed=None, launch: LaunchConfig | None = None, stream=None):
+    """``solve`` through nmc_solve_batch_noalloc: no workspace, the outputs
+    ``out`` given by the caller (see ``alloc_outputs``); the library's static
+    per-device scratch holds the work-queue counters, so calls that overlap on
+    one device race.  Returns ``out`` (not synchronized)."""
+    P = D0.shape[0]
+    bi = _batch_in(model, P, D0, I0, rho11, ye0, e0, theta, chi0, T_fixed, mu_fixed)
+    bo = _batch_out(model, P, out)
+    pc, lc = params.c(), (launch or LaunchConfig()).c()
+    N.check(N.lib().nmc_solve_batch_noalloc(model._h, C.byref(pc), P, float(dtau), C.byref(bi), C.byref(bo),
+                                            C.byref(lc), _stream_handle(stream)))
+    return out
+
+
 def alloc_outputs_v(model: Model, P: int, device="cuda"):
     f64 = dict(dtype=torch.float64, device=device)
     i32 = dict(dtype=torch.int32, device=device)
