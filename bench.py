@@ -146,11 +146,29 @@ def run_velocity(args):
     for _ in range(args.warmup):
         g.replay()
     torch.cuda.synchronize()
+    stream = torch.cuda.current_stream(dev)
+    g0, g1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
+    g0.record(stream)
     for _ in range(args.steps):
         g.replay()
+    g1.record(stream)
     torch.cuda.synchronize()
     ms_per_step = 1e3 * (time.perf_counter() - t0) / args.steps
+    graph_ms = g0.elapsed_time(g1) / args.steps
+    # per launch: the replay's time on its stream less the pristine copy (as
+    # for the static workload)
+    cev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(5)]
+    for a, b in cev:
+        a.record(stream)
+        work["D"].copy_(D0)
+        work["I"].copy_(I0)
+        work["ye"].copy_(t["ye"])
+        work["ef"].copy_(ef0)
+        work["v"].copy_(t["v"])
+        b.record(stream)
+    torch.cuda.synchronize()
+    copy_ms = sorted(a.elapsed_time(b) for a, b in cev)[2]
     kern_ms = 0.0
     n_timed = max(2, min(args.steps, 5))
     for _ in range(n_timed):
@@ -162,7 +180,8 @@ def run_velocity(args):
     status = np.stack([o["status"].cpu().numpy() for o in outs])
     solved = int(np.sum(n_out > 0))
     flops = float(np.sum(flops_per_point(n_in, n_out, 32)))
-    kern_s = kern_ms * 1e-3 / (n_timed * STEPS_PER_GRAPH)
+    eager_s = kern_ms * 1e-3 / (n_timed * STEPS_PER_GRAPH)
+    kern_s = (graph_ms - copy_ms) * 1e-3 / STEPS_PER_GRAPH
     achieved = flops / STEPS_PER_GRAPH / kern_s / 1e12
     line = {
         "metric": "implicit O(v) point-solves/sec at 32 energy nodes, 3 species (FP64)",
@@ -176,15 +195,17 @@ def run_velocity(args):
             "implicit_steps_per_step": STEPS_PER_GRAPH, "dtau_km": W.DTAU_KM, "tol_inner": params.tol_inner,
             "tol_outer": params.tol_outer, "anderson_memory": params.m_inner,
             "launch": {"chunk": launch.chunk, "blocks_per_cu": launch.blocks_per_cu, "persistent": launch.persistent},
-            "iterations": {"inner_min": int(n_in[n_out > 0].min()), "inner_median": float(np.median(n_in[n_out > 0])),
-                           "inner_max": int(n_in.max()), "outer_max": int(n_out.max())},
+            "iterations": iteration_summary(n_in, n_out),
             "status_counts": np.bincount(status.ravel(), minlength=5).tolist(),
         },
         "roofline": {
             "kernel": "fwd_v_kernel<3, true> (persistent O(v) point solve, one point per wavefront)",
             "bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP64_TFLOPS, "traffic": AT.stored_traffic("fwd_v_kernel_nq32_ns3"),
-            "kernel_ms_per_launch": kern_s * 1e3, "flops_per_launch": flops / STEPS_PER_GRAPH,
+            "kernel_ms_per_launch": kern_s * 1e3,
+            "kernel_ms_per_launch_from": "graph replay time (HIP events, timed region) less the pristine copy, / 10",
+            "graph_ms_per_step": graph_ms, "pristine_copy_ms": copy_ms, "eager_ms_per_launch": eager_s * 1e3,
+            "flops_per_launch": flops / STEPS_PER_GRAPH,
             "algorithmic_hbm_gbs": bytes_per_point_v() * P_POINTS / kern_s / 1e9,
         },
     }
@@ -197,9 +218,25 @@ def run_velocity(args):
     print(json.dumps(line), flush=True)
 
 
-def cpu_baseline(repeats: int, threads: int):
+def iteration_summary(n_in, n_out):
+    """Iteration statistics of the solved point-steps, with histograms:
+    inner_hist[k] / outer_hist[k] = point-steps with k inner / outer
+    iterations."""
+    import numpy as np
+
+    solved = n_out > 0
+    ni, no = n_in[solved].astype(np.int64), n_out[solved].astype(np.int64)
+    return {"inner_min": int(ni.min()), "inner_median": float(np.median(ni)), "inner_max": int(ni.max()),
+            "outer_median": float(np.median(no)), "outer_max": int(no.max()),
+            "inner_hist": np.bincount(ni).tolist(), "outer_hist": np.bincount(no).tolist()}
+
+
+def cpu_baseline(repeats: int, threads: int, all_points: bool = False):
     """The oracle (as it stands) on the same workload: the 10-step chain over
-    all 2^16 profile points, repeated `repeats` times from the initial state."""
+    all 2^16 profile points, repeated `repeats` times from the initial state,
+    on `threads` host threads; then the chain over every 16th point on one
+    thread.  Also returns the FLOPs of one chain priced from the oracle's own
+    iteration counts (the convention of flops_per_point)."""
     import numpy as np
 
     import oracle as O
@@ -208,21 +245,38 @@ def cpu_baseline(repeats: int, threads: int):
 
     O.build(force=False)
     d = W.radial_profile(P=P_POINTS)
-    m = O.Model(n_elem=16)
+    m = O.Model(n_elem=16, overrides=dict(rho11_min=0.0) if all_points else {})
     theta = m.default_theta(S.DEFAULT_A_NES, S.DEFAULT_A_PAIR)
-    D0, I0, e0 = m.init_state(d.T, d.rho11, d.ye, d.uD, d.uI)
-    solved = 0
-    t0 = time.perf_counter()
-    for _ in range(repeats):
-        D, I, ye, e = D0, I0, d.ye.copy(), e0
+
+    def chain(dd, nthreads):
+        D, I, e = m.init_state(dd.T, dd.rho11, dd.ye, dd.uD, dd.uI)
+        ye = dd.ye.copy()
+        solved, flops = 0, 0.0
         for _ in range(STEPS_PER_GRAPH):
-            r = O.solve_batch(m, O.Params(), theta, W.DTAU_KM, D, I, d.rho11, ye, e, nthreads=threads)
+            r = O.solve_batch(m, O.Params(), theta, W.DTAU_KM, D, I, dd.rho11, ye, e, nthreads=nthreads)
             D, I, ye, e = r["D"], r["I"], r["ye"], r["e"]
             solved += int(np.sum(r["n_outer"] > 0))
+            flops += float(np.sum(flops_per_point(r["n_inner"].astype(np.float64),
+                                                  r["n_outer"].astype(np.float64), 32)))
+        return solved, flops
+
+    solved, flops_chain = 0, 0.0
+    t0 = time.perf_counter()
+    for _ in range(repeats):
+        s1, flops_chain = chain(d, threads)
+        solved += s1
     dt = time.perf_counter() - t0
+    sub = d.take(np.arange(0, P_POINTS, 16))
+    t1 = time.perf_counter()
+    solved1, _ = chain(sub, 1)
+    dt1 = time.perf_counter() - t1
     return dict(value=solved / dt, unit="point-solves/s", cores=threads, kind="oracle",
                 sample=f"all {P_POINTS} profile points, {STEPS_PER_GRAPH} chained steps x {repeats}, "
-                       f"{solved} solves in {dt:.1f} s")
+                       f"{solved} solves in {dt:.1f} s",
+                one_core={"value": solved1 / dt1, "unit": "point-solves/s", "cores": 1,
+                          "sample": f"every 16th profile point, {STEPS_PER_GRAPH} chained steps, {solved1} solves "
+                                    f"in {dt1:.1f} s"},
+                _flops_per_chain=flops_chain)
 
 
 def adjoint_ratio(model, params, theta, D0, I0, t, e0, ws, launch, reps=5):
@@ -269,6 +323,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--cpu-repeats", type=int, default=4, help="repeats of the 10-step chain in the oracle baseline")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
+    ap.add_argument("--no-adjoint", action="store_true",
+                    help="skip the adjoint-ratio leg (its step-1 forward launches would mix into a kernel profile)")
+    ap.add_argument("--all-points", action="store_true",
+                    help="solve every point of the profile (no low-density pass-through), down to T ~ 0.07 MeV")
     ap.add_argument("--chunk", type=int, default=None)
     ap.add_argument("--blocks-per-cu", type=int, default=None)
     ap.add_argument("--workload", choices=sorted(WORKLOADS) + ["profile-v"], default="profile32",
@@ -302,7 +360,7 @@ def main():
     n_elem, P_POINTS, wid, traffic_tag, kernel_label = WORKLOADS[args.workload]
     nq = 2 * n_elem
     grid = S.Grid(n_elem)
-    model = S.Model(grid)
+    model = S.Model(grid, rho11_min=0.0) if args.all_points else S.Model(grid)
     params = S.Params()
     draws = W.radial_profile(P=P_POINTS, nq=nq, wid=wid)
     t = S.to_device(draws, dev)
@@ -368,16 +426,38 @@ def main():
     torch.cuda.synchronize()
 
     torch.cuda.synchronize()
+    stream = torch.cuda.current_stream(dev)
+    g0, g1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
+    g0.record(stream)
     for _ in range(args.steps):
         g.replay()
+    g1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms_per_step = 1e3 * wall / args.steps
+    graph_ms = g0.elapsed_time(g1) / args.steps
 
-    # solve-kernel duration: HIP events around every launch of the same
-    # 10-step chain, run eagerly on the launch stream (events recorded inside
-    # a captured graph are not timeable on ROCm)
+    # solve-kernel duration per launch: the graph replay's time on its stream
+    # (HIP events over the timed region) less its pristine-state copy, per
+    # launch; the remainder also holds the 10 counter-reset kernels (a few
+    # microseconds each), so it slightly over-states the solve kernel
+    def copies():
+        work["D"].copy_(D0)
+        work["I"].copy_(I0)
+        work["ye"].copy_(t["ye"])
+        work["e"].copy_(e0)
+
+    cev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(5)]
+    for a, b in cev:
+        a.record(stream)
+        copies()
+        b.record(stream)
+    torch.cuda.synchronize()
+    copy_ms = sorted(a.elapsed_time(b) for a, b in cev)[2]
+    kern_s_per_launch = (graph_ms - copy_ms) * 1e-3 / STEPS_PER_GRAPH
+    # the same chain run eagerly with HIP events around every launch (reset
+    # kernel, solve kernel and launch gaps), reported beside it
     kern_ms = 0.0
     n_timed = max(2, min(args.steps, 5))
     for _ in range(n_timed):
@@ -392,7 +472,7 @@ def main():
     solved = int(np.sum(n_out > 0))
     flops = float(np.sum(flops_per_point(n_in, n_out, nq)))
     value = solved / (ms_per_step * 1e-3)
-    kern_s_per_launch = kern_ms * 1e-3 / (n_timed * STEPS_PER_GRAPH)
+    eager_s_per_launch = kern_ms * 1e-3 / (n_timed * STEPS_PER_GRAPH)
     flops_per_launch = flops / STEPS_PER_GRAPH
     achieved = flops_per_launch / kern_s_per_launch / 1e12
     hbm_bytes_per_launch = bytes_per_point(nq) * P_POINTS
@@ -422,9 +502,9 @@ def main():
                                                           "persistent": launch.persistent,
                                                           "autotune_key": AT.cache_key(model),
                                                           "from_cache": AT.cache_key(model) in AT.cache()},
-            "iterations": {"inner_min": int(n_in[n_out > 0].min()), "inner_median": float(np.median(n_in[n_out > 0])),
-                           "inner_max": int(n_in.max()), "outer_max": int(n_out.max())},
+            "iterations": iteration_summary(n_in, n_out),
             "status_counts": np.bincount(status.ravel(), minlength=5).tolist(),
+            "all_points": bool(args.all_points),
         },
         "roofline": {
             "kernel": kernel_label,
@@ -435,6 +515,10 @@ def main():
             "frac": achieved / PEAK_FP64_TFLOPS,
             "traffic": traffic,
             "kernel_ms_per_launch": kern_s_per_launch * 1e3,
+            "kernel_ms_per_launch_from": "graph replay time (HIP events, timed region) less the pristine copy, / 10",
+            "graph_ms_per_step": graph_ms,
+            "pristine_copy_ms": copy_ms,
+            "eager_ms_per_launch": eager_s_per_launch * 1e3,
             "flops_per_launch": flops_per_launch,
             "algorithmic_hbm_gbs": hbm_bytes_per_launch / kern_s_per_launch / 1e9,
         },
@@ -443,11 +527,16 @@ def main():
     fma_peak = S.probe_fma_tflops(dev)
     line["roofline"]["measured_fma_peak"] = fma_peak
     line["roofline"]["frac_of_measured_fma_peak"] = achieved / fma_peak
-    if nq == 32:
+    if nq == 32 and not args.no_adjoint and not args.all_points:
         line["adjoint"] = adjoint_ratio(model, params, theta, D0, I0, t, e0, ws, launch)
     if not args.no_cpu and args.workload == "profile32":
         threads = int(os.environ.get("OMP_NUM_THREADS") or os.cpu_count() or 1)
-        line["cpu_baseline"] = cpu_baseline(args.cpu_repeats, threads)
+        cb = cpu_baseline(args.cpu_repeats, threads, args.all_points)
+        # the oracle's own iteration counts priced by the same convention:
+        # FLOPs the GPU line claims per chain against those of the oracle
+        cb["flops_per_chain"] = cb.pop("_flops_per_chain")
+        cb["gpu_flops_per_chain"] = flops
+        line["cpu_baseline"] = cb
     print(json.dumps(line), flush=True)
 
 

@@ -36,6 +36,10 @@ namespace nmc {
 namespace {
 
 constexpr int NQP = 32;
+// widest exponent range (powers of two of exp(-e / (2T)) over the grid) of
+// the symmetric contraction: its scaled vectors and row factors then stay
+// within 2^(+-(kSymBits / 2 + 1)), far from overflow
+constexpr int kSymBits = 1800;
 
 template <int NS>
 struct PairLds {
@@ -81,7 +85,8 @@ __device__ __forceinline__ double max_neg_f64(double a, double b) {
   return r;
 }
 
-// Signed pair factors of one point into its 32 x 32 tile T (row-major):
+// Pair factors of one point into its 32 x 32 tile T (row-major).  SYM: the
+// symmetric core b^2 (diagonal written by the caller).  Otherwise signed:
 // for every unordered node pair (lo, hi), T[hi][lo] = +b and T[lo][hi] = -b
 // with b = exp(-|e_lo - e_hi| / (2T)) = P_lo R_hi 2^(n_lo - n_hi).  Lane q
 // forms the pairs (q, q + d mod 32) for d = 1..15 and, if q < 16, d = 16,
@@ -89,6 +94,7 @@ __device__ __forceinline__ double max_neg_f64(double a, double b) {
 // orientations 2^(x_q - x_j) and 2^(x_j - x_q) the smaller is b (the other
 // is its reciprocal, or overflows), so no compare picks the formula; the
 // sign goes by whether q is the lower node.
+template <bool SYM>
 __device__ __forceinline__ void pair_tile_rows(double* __restrict__ T, const double* __restrict__ P2,
                                                const double* __restrict__ R2, const int* __restrict__ n2, int q,
                                                double Pq, double Rq, int nq) {
@@ -108,9 +114,15 @@ __device__ __forceinline__ void pair_tile_rows(double* __restrict__ T, const dou
     const int e = nq - np[d - 1];
     const double b = min_f64(ldexp(Pq * Rp[d - 1], e), ldexp(Pp[d - 1] * Rq, -e));
     if (d < N / 2 || q < N / 2) {
-      const double sb = q + d < N ? b : -b;  // + where j is the upper node
-      T[j * N + q] = sb;
-      T[q * N + j] = -sb;
+      if constexpr (SYM) {
+        const double b2 = b * b;
+        T[j * N + q] = b2;
+        T[q * N + j] = b2;
+      } else {
+        const double sb = q + d < N ? b : -b;  // + where j is the upper node
+        T[j * N + q] = sb;
+        T[q * N + j] = -sb;
+      }
     }
   }
 }
@@ -193,6 +205,151 @@ struct ColFmac<1> {
         "v_fmac_f64_dpp %3, %6, %9 row_newbcast:%10 row_mask:0xf bank_mask:0xf\n"
         : "+v"(eN[0]), "+v"(oN[0]), "+v"(aP[0]), "+v"(eP[0])
         : "v"(x[0]), "v"(y[0]), "v"(hy[0]), "v"(fi), "v"(fo), "v"(fa), "i"(L));
+  }
+};
+
+// Four columns L0 .. L0 + 3 of the rate contraction on the symmetric core
+// B2 = b^2 of the kernels (the per-node exponential factors ride on the
+// vectors, see the solver): eN += B2 a_s, oN += B2 b_s, aP += B2 c_sbar,
+// eP += B2 d_sbar, the vectors' column broadcast into the FMAs
+// (row_newbcast) and B2 from VGPRs m0 .. m3.  12 FMAs per column for three
+// species and nothing else; one leading s_nop per four columns covers the
+// VALU-write to DPP-read distance of the vectors.
+template <int NS>
+struct ColSym;
+
+template <>
+struct ColSym<3> {
+  template <int L0>
+  __device__ __forceinline__ static void run(double (&eN)[3], double (&oN)[3], double (&aP)[3], double (&eP)[3],
+                                             const double (&a)[3], const double (&b)[3], const double (&c)[3],
+                                             const double (&d)[3], double m0, double m1, double m2, double m3) {
+    asm volatile(
+        "s_nop 1\n"
+        "v_fmac_f64_dpp %0, %12, %24 row_newbcast:%28 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %1, %13, %24 row_newbcast:%28 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %2, %14, %24 row_newbcast:%28 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %3, %15, %24 row_newbcast:%28 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %4, %16, %24 row_newbcast:%28 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %5, %17, %24 row_newbcast:%28 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %6, %19, %24 row_newbcast:%28 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %7, %18, %24 row_newbcast:%28 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %8, %20, %24 row_newbcast:%28 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %9, %22, %24 row_newbcast:%28 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %10, %21, %24 row_newbcast:%28 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %11, %23, %24 row_newbcast:%28 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %0, %12, %25 row_newbcast:%29 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %1, %13, %25 row_newbcast:%29 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %2, %14, %25 row_newbcast:%29 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %3, %15, %25 row_newbcast:%29 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %4, %16, %25 row_newbcast:%29 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %5, %17, %25 row_newbcast:%29 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %6, %19, %25 row_newbcast:%29 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %7, %18, %25 row_newbcast:%29 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %8, %20, %25 row_newbcast:%29 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %9, %22, %25 row_newbcast:%29 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %10, %21, %25 row_newbcast:%29 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %11, %23, %25 row_newbcast:%29 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %0, %12, %26 row_newbcast:%30 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %1, %13, %26 row_newbcast:%30 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %2, %14, %26 row_newbcast:%30 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %3, %15, %26 row_newbcast:%30 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %4, %16, %26 row_newbcast:%30 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %5, %17, %26 row_newbcast:%30 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %6, %19, %26 row_newbcast:%30 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %7, %18, %26 row_newbcast:%30 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %8, %20, %26 row_newbcast:%30 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %9, %22, %26 row_newbcast:%30 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %10, %21, %26 row_newbcast:%30 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %11, %23, %26 row_newbcast:%30 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %0, %12, %27 row_newbcast:%31 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %1, %13, %27 row_newbcast:%31 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %2, %14, %27 row_newbcast:%31 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %3, %15, %27 row_newbcast:%31 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %4, %16, %27 row_newbcast:%31 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %5, %17, %27 row_newbcast:%31 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %6, %19, %27 row_newbcast:%31 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %7, %18, %27 row_newbcast:%31 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %8, %20, %27 row_newbcast:%31 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %9, %22, %27 row_newbcast:%31 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %10, %21, %27 row_newbcast:%31 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %11, %23, %27 row_newbcast:%31 row_mask:0xf bank_mask:0xf\n"
+        : "+v"(eN[0]), "+v"(eN[1]), "+v"(eN[2]), "+v"(oN[0]), "+v"(oN[1]), "+v"(oN[2]), "+v"(aP[0]), "+v"(aP[1]), "+v"(aP[2]), "+v"(eP[0]), "+v"(eP[1]), "+v"(eP[2])
+        : "v"(a[0]), "v"(a[1]), "v"(a[2]), "v"(b[0]), "v"(b[1]), "v"(b[2]), "v"(c[0]), "v"(c[1]), "v"(c[2]), "v"(d[0]), "v"(d[1]), "v"(d[2]), "v"(m0), "v"(m1), "v"(m2), "v"(m3), "i"(L0 + 0), "i"(L0 + 1), "i"(L0 + 2), "i"(L0 + 3));
+  }
+};
+
+template <>
+struct ColSym<2> {
+  template <int L0>
+  __device__ __forceinline__ static void run(double (&eN)[2], double (&oN)[2], double (&aP)[2], double (&eP)[2],
+                                             const double (&a)[2], const double (&b)[2], const double (&c)[2],
+                                             const double (&d)[2], double m0, double m1, double m2, double m3) {
+    asm volatile(
+        "s_nop 1\n"
+        "v_fmac_f64_dpp %0, %8, %16 row_newbcast:%20 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %1, %9, %16 row_newbcast:%20 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %2, %10, %16 row_newbcast:%20 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %3, %11, %16 row_newbcast:%20 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %4, %13, %16 row_newbcast:%20 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %5, %12, %16 row_newbcast:%20 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %6, %15, %16 row_newbcast:%20 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %7, %14, %16 row_newbcast:%20 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %0, %8, %17 row_newbcast:%21 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %1, %9, %17 row_newbcast:%21 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %2, %10, %17 row_newbcast:%21 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %3, %11, %17 row_newbcast:%21 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %4, %13, %17 row_newbcast:%21 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %5, %12, %17 row_newbcast:%21 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %6, %15, %17 row_newbcast:%21 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %7, %14, %17 row_newbcast:%21 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %0, %8, %18 row_newbcast:%22 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %1, %9, %18 row_newbcast:%22 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %2, %10, %18 row_newbcast:%22 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %3, %11, %18 row_newbcast:%22 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %4, %13, %18 row_newbcast:%22 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %5, %12, %18 row_newbcast:%22 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %6, %15, %18 row_newbcast:%22 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %7, %14, %18 row_newbcast:%22 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %0, %8, %19 row_newbcast:%23 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %1, %9, %19 row_newbcast:%23 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %2, %10, %19 row_newbcast:%23 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %3, %11, %19 row_newbcast:%23 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %4, %13, %19 row_newbcast:%23 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %5, %12, %19 row_newbcast:%23 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %6, %15, %19 row_newbcast:%23 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %7, %14, %19 row_newbcast:%23 row_mask:0xf bank_mask:0xf\n"
+        : "+v"(eN[0]), "+v"(eN[1]), "+v"(oN[0]), "+v"(oN[1]), "+v"(aP[0]), "+v"(aP[1]), "+v"(eP[0]), "+v"(eP[1])
+        : "v"(a[0]), "v"(a[1]), "v"(b[0]), "v"(b[1]), "v"(c[0]), "v"(c[1]), "v"(d[0]), "v"(d[1]), "v"(m0), "v"(m1), "v"(m2), "v"(m3), "i"(L0 + 0), "i"(L0 + 1), "i"(L0 + 2), "i"(L0 + 3));
+  }
+};
+
+template <>
+struct ColSym<1> {
+  template <int L0>
+  __device__ __forceinline__ static void run(double (&eN)[1], double (&oN)[1], double (&aP)[1], double (&eP)[1],
+                                             const double (&a)[1], const double (&b)[1], const double (&c)[1],
+                                             const double (&d)[1], double m0, double m1, double m2, double m3) {
+    asm volatile(
+        "s_nop 1\n"
+        "v_fmac_f64_dpp %0, %4, %8 row_newbcast:%12 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %1, %5, %8 row_newbcast:%12 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %2, %6, %8 row_newbcast:%12 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %3, %7, %8 row_newbcast:%12 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %0, %4, %9 row_newbcast:%13 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %1, %5, %9 row_newbcast:%13 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %2, %6, %9 row_newbcast:%13 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %3, %7, %9 row_newbcast:%13 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %0, %4, %10 row_newbcast:%14 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %1, %5, %10 row_newbcast:%14 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %2, %6, %10 row_newbcast:%14 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %3, %7, %10 row_newbcast:%14 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %0, %4, %11 row_newbcast:%15 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %1, %5, %11 row_newbcast:%15 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %2, %6, %11 row_newbcast:%15 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %3, %7, %11 row_newbcast:%15 row_mask:0xf bank_mask:0xf\n"
+        : "+v"(eN[0]), "+v"(oN[0]), "+v"(aP[0]), "+v"(eP[0])
+        : "v"(a[0]), "v"(b[0]), "v"(c[0]), "v"(d[0]), "v"(m0), "v"(m1), "v"(m2), "v"(m3), "i"(L0 + 0), "i"(L0 + 1), "i"(L0 + 2), "i"(L0 + 3));
   }
 };
 
@@ -297,10 +454,21 @@ struct PairSolver {
         }
         dsig = dtau * sig;
       }
-      // pair factors of this lane's row, j = 0..31, signed by orientation:
-      // +b(q, j) for j > q (q the lower node), -b(q, j) otherwise
+      // Pair factors of this lane's row, j = 0..31.  Symmetric form (sym):
+      // B2(q, j) = b^2 = exp(-|e_q - e_j| / T), the core shared by all four
+      // kernels: with g = exp(-e / (2T)) and h = g^2,
+      //   Phi_in[q][j] = A e e' B2 g_q / g_j,  Phi_out[q][j] = A e e' B2 g_j / g_q,
+      //   Phi_ann = A' e e' B2,  Phi_pro = A' e e' B2 h_q h_j,
+      // so 1 / g_j and g_j ride on the contracted vectors and g_q, 1 / g_q on
+      // the row sums, each scaled by 2^-+c (c centres the point's exponents,
+      // so both stay in range while the grid spans at most kSymBits powers of
+      // two in g, T above ~0.12 MeV).  Otherwise (colder points) the signed
+      // orientation form: +b(q, j) for j > q (q the lower node), -b(q, j)
+      // otherwise, every entry a product of factors <= 1.
       double B[COUPLED ? NQ : 1];
       double hq = 0.0;  // exp(-e_q / T)
+      double gq = 1.0, rgq = 1.0;  // g_q 2^c and 2^-c / g_q (symmetric form)
+      bool sym = false;  // wave-uniform
       if constexpr (COUPLED) {
         SplitExp& E = S.E[h];
         const ExpSplit xs = exp_split(epsq, invT);
@@ -309,13 +477,27 @@ struct PairSolver {
         E.n2[q] = xs.n;
         hq = ldexp(xs.R * xs.R, -2 * xs.n);  // 2^(-2x) = exp(-e / T)
         __syncthreads();
-        // signed pair factors of the point, each unordered pair (q, q + d mod
-        // 32) once: d = 1..15 by every lane, d = 16 by lanes q < 16 (the
-        // Anderson history is dead between inner loops, its space holds them)
+        {
+          // g = 2^-x with x = n + f increasing along the grid
+          const int nlo = E.n2[0], nhi = E.n2[NQ - 1];
+          sym = __builtin_amdgcn_readfirstlane(
+                    (uint32_t)(__builtin_amdgcn_ballot_w64(run && nhi - nlo > kSymBits) == 0)) != 0;
+          const int c = (nlo + nhi) >> 1;
+          gq = sym ? ldexp(xs.R, c - xs.n) : 1.0;
+          rgq = sym ? ldexp(xs.P, xs.n - c) : 1.0;
+        }
+        // pair factors of the point, each unordered pair (q, q + d mod 32)
+        // once: d = 1..15 by every lane, d = 16 by lanes q < 16 (the Anderson
+        // history is dead between inner loops, its space holds them)
         {
           double (*T)[NQ] = S.u.tile[h];
-          pair_tile_rows(&T[0][0], E.P2, E.R2, E.n2, q, xs.P, xs.R, xs.n);
-          T[q][q] = -1.0;
+          if (sym) {
+            pair_tile_rows<true>(&T[0][0], E.P2, E.R2, E.n2, q, xs.P, xs.R, xs.n);
+            T[q][q] = 1.0;
+          } else {
+            pair_tile_rows<false>(&T[0][0], E.P2, E.R2, E.n2, q, xs.P, xs.R, xs.n);
+            T[q][q] = -1.0;
+          }
           __syncthreads();
           // row q of the lane: element [j][q] (consecutive lanes, consecutive words)
 #pragma unroll
@@ -327,6 +509,7 @@ struct PairSolver {
       // ---- inner loop over moments at fixed matter ------------------------
       const double w2q = mt.w2[q], w2eq = w2q * epsq;
       const double Aeq = pt.An * epsq, Apq = pt.Ap * epsq, Apqh = Apq * hq;
+
       double G11 = 0.0;
       const bool ran = run;  // this half runs this outer iteration
       bool act = run;        // this half is still iterating the inner loop
@@ -338,36 +521,56 @@ struct PairSolver {
 #pragma unroll
         for (int t = 0; t < NS; ++t) etaN[t] = outN[t] = annP[t] = etaP[t] = 0.0;
         if constexpr (COUPLED) {
-          // W e D, W e (1 - D) and h W e (1 - D) of the point, each 16-lane
-          // row holding the half [16 R, 16 R + 16) of the nodes in XR[.][R],
-          // YR[.][R], HR[.][R]
-          double XR[2][NS], YR[2][NS], HR[2][NS];
           // the pair factors are re-read per iteration: the per-column
           // products are not hoisted out of the inner loop (they would need
           // four times the registers)
 #pragma unroll
           for (int j = 0; j < NQ; ++j) asm volatile("" : "+v"(B[j]));
+          if (sym) {
+            // W e D / g, g W e (1 - D), W e D and h W e (1 - D) of the point
+            // (g scaled by 2^c), each 16-lane row holding the half
+            // [16 R, 16 R + 16) of the nodes in [.][R][.]
+            double AR[2][NS], BR[2][NS], CR[2][NS], DR[2][NS];
 #pragma unroll
-          for (int t = 0; t < NS; ++t) {
-            const double xv = w2eq * D[t], yv = w2eq - xv;
-            swap16(xv, XR[0][t], XR[1][t]);
-            swap16(yv, YR[0][t], YR[1][t]);
-            swap16(hq * yv, HR[0][t], HR[1][t]);
-          }
-          static_for<0, NQ / 2>([&](auto jj) __attribute__((always_inline)) {
-            constexpr int j0 = 2 * decltype(jj)::value;
-            static_for<0, 2>([&](auto ee) __attribute__((always_inline)) {
-              constexpr int j = j0 + decltype(ee)::value;
-              // with s = +-b and c = s^3 = +-b^3 (the same sign): max(s, -c) is
-              // b where s > 0 and b^3 where s < 0, i.e. Phi_in, and max(c, -s)
-              // is Phi_out (scaled entries), without compares or selects;
-              // Phi_ann = b^2 serves the pair production term as well
-              // (detailed balance: Phi_pro = Phi_ann h_q h_j)
-              const double sb = B[j], b2 = sb * sb, c3 = sb * b2;
-              ColFmac<NS>::template run<j % 16>(etaN, outN, annP, etaP, XR[j / 16], YR[j / 16], HR[j / 16],
-                                                max_neg_f64(sb, c3), max_neg_f64(c3, sb), b2);
+            for (int t = 0; t < NS; ++t) {
+              const double xv = w2eq * D[t], yv = w2eq - xv;
+              swap16(xv * rgq, AR[0][t], AR[1][t]);
+              swap16(yv * gq, BR[0][t], BR[1][t]);
+              swap16(xv, CR[0][t], CR[1][t]);
+              swap16(hq * yv, DR[0][t], DR[1][t]);
+            }
+            static_for<0, NQ / 4>([&](auto jj) __attribute__((always_inline)) {
+              constexpr int j = 4 * decltype(jj)::value;
+              ColSym<NS>::template run<j % 16>(etaN, outN, annP, etaP, AR[j / 16], BR[j / 16], CR[j / 16],
+                                               DR[j / 16], B[j], B[j + 1], B[j + 2], B[j + 3]);
             });
-          });
+          } else {
+            // W e D, W e (1 - D) and h W e (1 - D) of the point, each 16-lane
+            // row holding the half [16 R, 16 R + 16) of the nodes in XR[.][R],
+            // YR[.][R], HR[.][R]
+            double XR[2][NS], YR[2][NS], HR[2][NS];
+#pragma unroll
+            for (int t = 0; t < NS; ++t) {
+              const double xv = w2eq * D[t], yv = w2eq - xv;
+              swap16(xv, XR[0][t], XR[1][t]);
+              swap16(yv, YR[0][t], YR[1][t]);
+              swap16(hq * yv, HR[0][t], HR[1][t]);
+            }
+            static_for<0, NQ / 2>([&](auto jj) __attribute__((always_inline)) {
+              constexpr int j0 = 2 * decltype(jj)::value;
+              static_for<0, 2>([&](auto ee) __attribute__((always_inline)) {
+                constexpr int j = j0 + decltype(ee)::value;
+                // with s = +-b and c = s^3 = +-b^3 (the same sign): max(s, -c)
+                // is b where s > 0 and b^3 where s < 0, i.e. Phi_in, and
+                // max(c, -s) is Phi_out (scaled entries), without compares or
+                // selects; Phi_ann = b^2 serves the pair production term as
+                // well (detailed balance: Phi_pro = Phi_ann h_q h_j)
+                const double sb = B[j], b2 = sb * sb, c3 = sb * b2;
+                ColFmac<NS>::template run<j % 16>(etaN, outN, annP, etaP, XR[j / 16], YR[j / 16], HR[j / 16],
+                                                  max_neg_f64(sb, c3), max_neg_f64(c3, sb), b2);
+              });
+            });
+          }
         }
         // Q and residual of both owned moments x = (D_t, I_t); the row sums
         // take their factors A e_q here, and one reciprocal of the product of
@@ -375,8 +578,8 @@ struct PairSolver {
         double Qx[2 * NS], Fx[2 * NS];
 #pragma unroll
         for (int t = 0; t < NS; ++t) {
-          const double eta = __builtin_fma(Aeq, etaN[t], Apqh * etaP[t]);
-          const double chi = __builtin_fma(Aeq, outN[t], __builtin_fma(Apq, annP[t], eta));
+          const double eta = __builtin_fma(Aeq * gq, etaN[t], Apqh * etaP[t]);
+          const double chi = __builtin_fma(Aeq * rgq, outN[t], __builtin_fma(Apq, annP[t], eta));
           const double dD = __builtin_fma(dtau, chi, den0D[t]), dI = dD + dsig;
           const double r = rcp_nr(dD * dI);
           Qx[t] = __builtin_fma(dtau, eta, baseD[t]) * (r * dI);

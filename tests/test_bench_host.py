@@ -27,3 +27,14 @@ def test_flop_and_byte_conventions():
     assert bench.bytes_per_point(32, 3) == 2 * 96 * 8 + 24 + 2 * 96 * 8 + 24 + 12
     # O(v): D and three flux components each way, six scalars each way
     assert bench.bytes_per_point_v(32, 3) == 2 * 4 * 96 * 8 + 48 + 48 + 12
+
+
+def test_iteration_summary_histograms():
+    import numpy as np
+    n_in = np.array([[3, 0, 7], [3, 5, 0]], dtype=float)
+    n_out = np.array([[1, 0, 2], [1, 2, 0]], dtype=float)  # zeros: points passed through
+    s = bench.iteration_summary(n_in, n_out)
+    assert s["inner_hist"] == [0, 0, 0, 2, 0, 1, 0, 1]
+    assert s["outer_hist"] == [0, 2, 2]
+    assert (s["inner_min"], s["inner_max"], s["outer_max"]) == (3, 7, 2)
+    assert sum(s["inner_hist"]) == 4
