@@ -47,6 +47,7 @@ class _Model(C.Structure):
         ("eos_a", C.c_double), ("eos_b", C.c_double), ("mu_a", C.c_double), ("mu_ye0", C.c_double),
         ("mu_b", C.c_double), ("mu_t0", C.c_double),
         ("kcoup", C.c_double), ("rho11_min", C.c_double),
+        ("phi1_nes", C.c_double), ("phi1_pair", C.c_double),
     ]
 
 
@@ -105,6 +106,7 @@ def lib():
         L.ora_flux_factor.argtypes = [C.c_double, C.c_double]
         L.ora_flux_factor.restype = C.c_double
         L.ora_eddington.argtypes = [C.c_double, dp, dp]
+        L.ora_phi1_terms.argtypes = [C.POINTER(_Model), dp, C.c_double, C.c_double, dp, dp, dp, dp]
         L.ora_solve_batch_v.argtypes = [C.POINTER(_Model), C.POINTER(_Params), dp, C.c_long, C.c_double,
                                         dp, dp, dp, dp, dp, dp, vp,
                                         dp, dp, dp, dp, dp, dp, ip, ip, ip, C.c_int]
@@ -343,6 +345,15 @@ def eddington(D: float, I3) -> np.ndarray:
     K = np.zeros(9)
     lib().ora_eddington(D, _f64(I3), K)
     return K.reshape(3, 3)
+
+
+def phi1_terms(model: Model, theta, rho11, T, D, I):
+    """Linear-order corrections of the NES and pair collision terms at one
+    point: (C1D (ns, nq), C1I (ns, 3, nq)) for moments D (ns, nq), I (ns, 3, nq)."""
+    ns, nq = model.ns, model.nq
+    C1D, C1I = np.zeros(ns * nq), np.zeros(3 * ns * nq)
+    lib().ora_phi1_terms(model.ref(), _f64(theta), rho11, T, _f64(D).ravel(), _f64(I).ravel(), C1D, C1I)
+    return C1D.reshape(ns, nq), C1I.reshape(ns, 3, nq)
 
 
 def solve_batch_v(model: Model, params: Params, theta, dtau, D0, I0, rho11, ye0, ef0, v0, chi0=None,

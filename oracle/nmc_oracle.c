@@ -1018,12 +1018,76 @@ static double eos_temperature_v(const ora_model* m, const double* y, double rho1
   return ora_eos_temperature(m, y[1] - 0.5 * ORA_MU_C2 * vm * vm, y[0], rho11);
 }
 
+/* Linear-order corrections (Sec. 2.4): with the angular kernels expanded to
+ * linear order in the scattering angle, the number and flux equations of
+ * species s gain, at node q,
+ *   NES:  L_in^i  = sum_p W_p Phi_1^In[q][p] I_s^i(p),   L_out^i likewise
+ *         (Eq. linearCorrectionsNES);
+ *   pair: L_pro^i = sum_p W_p Phi_1^Pro[q][p] Ibar_s^i(p), L_ann^i likewise,
+ *         Ibar the flux of the pair partner (Eq. linearCorrectionsPair);
+ *   number equation: -(L_in^i - L_out^i) I_i + (L_pro^i - L_ann^i) I_i
+ *         (Eqs. zerothMomentCollisionTerm_NES, zerothMomentCollisionTerm_Pair);
+ *   flux equation j: (1/3)(delta_ij - 3 K_ij) L_in^i + K_ij L_out^i
+ *         - (1/3)(delta_ij - 3 K_ij) L_pro^i - K_ij L_ann^i
+ *         (Eqs. firstMomentCollisionTerm_NES, firstMomentCollisionTerm_Pair),
+ * K_ij the Eddington tensor of species s at node q (flat metric).  The
+ * synthetic Phi_1 are fixed fractions of the isotropic kernels (model fields
+ * phi1_nes, phi1_pair), which keeps their in-out invariance and detailed
+ * balance. */
+static void phi1_terms(const ora_model* m, const opac* o, const double* D, const double* I, double* C1D,
+                       double* C1I) {
+  int nq = m->nq, ns = m->ns;
+  for (int s = 0; s < ns; ++s) {
+    int sb = partner_index(m, s);
+    for (int q = 0; q < nq; ++q) {
+      double Lin[3] = {0.0, 0.0, 0.0}, Lout[3] = {0.0, 0.0, 0.0};
+      double Lpro[3] = {0.0, 0.0, 0.0}, Lann[3] = {0.0, 0.0, 0.0};
+      for (int i = 0; i < 3; ++i)
+        for (int p = 0; p < nq; ++p) {
+          if (m->flags & ORA_NES) {
+            double Ii = I[(s * 3 + i) * nq + p];
+            Lin[i] += m->w2[p] * (m->phi1_nes * o->phi_in[q * nq + p]) * Ii;
+            Lout[i] += m->w2[p] * (m->phi1_nes * o->phi_out[q * nq + p]) * Ii;
+          }
+          if ((m->flags & ORA_PAIR) && sb >= 0) {
+            double Ib = I[(sb * 3 + i) * nq + p];
+            Lpro[i] += m->w2[p] * (m->phi1_pair * o->phi_pro[q * nq + p]) * Ib;
+            Lann[i] += m->w2[p] * (m->phi1_pair * o->phi_ann[q * nq + p]) * Ib;
+          }
+        }
+      double I3[3], K9[9];
+      flux3(m, I, s, q, I3);
+      ora_eddington(D[s * nq + q], I3, K9);
+      double c0 = 0.0;
+      for (int i = 0; i < 3; ++i) c0 += -(Lin[i] - Lout[i]) * I3[i] + (Lpro[i] - Lann[i]) * I3[i];
+      C1D[s * nq + q] = c0;
+      for (int j = 0; j < 3; ++j) {
+        double cj = 0.0;
+        for (int i = 0; i < 3; ++i) {
+          double g3 = ((i == j ? 1.0 : 0.0) - 3.0 * K9[3 * i + j]) / 3.0;
+          cj += g3 * Lin[i] + K9[3 * i + j] * Lout[i] - g3 * Lpro[i] - K9[3 * i + j] * Lann[i];
+        }
+        C1I[(s * 3 + j) * nq + q] = cj;
+      }
+    }
+  }
+}
+
+void ora_phi1_terms(const ora_model* m, const double* theta, double rho11, double T, const double* D,
+                    const double* I, double* C1D, double* C1I) {
+  opac* o = (opac*)malloc(sizeof(opac));
+  compute_opacities(m, theta, rho11, m->chi_ref * rho11, T, 0.0, o);
+  phi1_terms(m, o, D, I, C1D, C1I);
+  free(o);
+}
+
 #define MAXNV (4 * ORA_MAX_NS * ORA_MAX_NQ)
 typedef struct {
   double M[MAXNV], Mnew[MAXNV], Q[MAXNV], F[MAXNV];
   double Qh[MAXMEM * MAXNV], Fh[MAXMEM * MAXNV];
   double Nst[ORA_MAX_NS * ORA_MAX_NQ], Gst[3 * ORA_MAX_NS * ORA_MAX_NQ];
   double eta[ORA_MAX_NS * ORA_MAX_NQ], chi[ORA_MAX_NS * ORA_MAX_NQ], kap[ORA_MAX_NS * ORA_MAX_NQ];
+  double c1d[ORA_MAX_NS * ORA_MAX_NQ], c1i[3 * ORA_MAX_NS * ORA_MAX_NQ];
   opac o;
 } work_v;
 
@@ -1085,6 +1149,10 @@ static int solve_point_v(const ora_model* m, const ora_params* prm, const double
        * Q_D = ((1 - lam) D + lam (N* - v.I + dtau eta)) / (1 + lam dtau chi),
        * Q_Ij = ((1 - lam) I_j + lam (G*_j - v^i K_ij)) / (1 + lam dtau kappa) */
       rates(m, &w->o, w->M, w->eta, w->chi, w->kap);
+      /* the linear-order corrections are evaluated at the current iterate,
+       * as the emissivity is, and join the right-hand sides */
+      int lin = m->phi1_nes != 0.0 || m->phi1_pair != 0.0;
+      if (lin) phi1_terms(m, &w->o, w->M, w->M + nn, w->c1d, w->c1i);
       for (int s = 0; s < ns; ++s)
         for (int q = 0; q < nq; ++q) {
           int i = s * nq + q;
@@ -1092,11 +1160,14 @@ static int solve_point_v(const ora_model* m, const ora_params* prm, const double
           flux3(m, w->M + nn, s, q, I3);
           ora_eddington(Dq, I3, K9);
           double vI = v[0] * I3[0] + v[1] * I3[1] + v[2] * I3[2];
-          w->Q[i] = ((1.0 - lam) * Dq + lam * (w->Nst[i] - vI + dtau * w->eta[i])) / (1.0 + lam * dtau * w->chi[i]);
+          double srcD = lin ? w->eta[i] + w->c1d[i] : w->eta[i];
+          w->Q[i] = ((1.0 - lam) * Dq + lam * (w->Nst[i] - vI + dtau * srcD)) / (1.0 + lam * dtau * w->chi[i]);
           for (int j = 0; j < 3; ++j) {
             int ij = (s * 3 + j) * nq + q;
             double vK = v[0] * K9[3 * j] + v[1] * K9[3 * j + 1] + v[2] * K9[3 * j + 2];
-            w->Q[nn + ij] = ((1.0 - lam) * I3[j] + lam * (w->Gst[ij] - vK)) / (1.0 + lam * dtau * w->kap[i]);
+            double num = (1.0 - lam) * I3[j] + lam * (w->Gst[ij] - vK);
+            if (lin) num = (1.0 - lam) * I3[j] + lam * (w->Gst[ij] - vK + dtau * w->c1i[ij]);
+            w->Q[nn + ij] = num / (1.0 + lam * dtau * w->kap[i]);
           }
         }
       for (int i = 0; i < n; ++i) w->F[i] = w->Q[i] - w->M[i];

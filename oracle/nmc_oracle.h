@@ -50,6 +50,12 @@ typedef struct {
   double eos_a, eos_b, mu_a, mu_ye0, mu_b, mu_t0;
   double kcoup; /* (4 pi/(hc)^3) * m_u / 1e11 [MeV^-3]; K = kcoup / rho11 */
   double rho11_min; /* coupling disabled below this density (Sec. 7.2) */
+  /* linear-order (l = 1) Legendre coefficients of the NES and pair kernels as
+   * fractions of the isotropic ones: Phi_1^{In/Out} = phi1_nes Phi_0^{In/Out},
+   * Phi_1^{Pro/Ann} = phi1_pair Phi_0^{Pro/Ann} (0: isotropic kernels).  They
+   * enter the O(v) solve through Eqs. zerothMomentCollisionTerm_NES/_Pair and
+   * firstMomentCollisionTerm_NES/_Pair. */
+  double phi1_nes, phi1_pair;
 } ora_model;
 
 typedef struct {
@@ -118,6 +124,14 @@ double ora_minerbo_psi(double h);
 double ora_flux_factor(double D, double Imag);
 /* K_ij = k_ij D (Eq. eddingtonTensor with the Minerbo factor), 3x3 row-major */
 void ora_eddington(double D, const double* I3, double* K9);
+
+/* linear-order corrections of the NES and pair collision terms at one point
+ * (Eqs. linearCorrectionsNES, linearCorrectionsPair and their use in Eqs.
+ * zerothMomentCollisionTerm_NES/_Pair, firstMomentCollisionTerm_NES/_Pair):
+ * C1D (ns, nq) adds to the number equation, C1I (ns, 3, nq) to the flux
+ * equations, at moments D (ns, nq), I (ns, 3, nq) and temperature T */
+void ora_phi1_terms(const ora_model* m, const double* theta, double rho11, double T, const double* D,
+                    const double* I, double* C1D, double* C1I);
 
 /* batched O(v) forward solve (Algorithm neutrinoMatterCoupling with
  * Eqs. implicitMomentsNodal at lambda = 1/(1+|v|), implicitFluidNodal,
