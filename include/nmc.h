@@ -115,6 +115,13 @@ typedef struct {
   double hc_mev_cm;    /* (1.239841984e-10) */
   double m_u_g;        /* (1.66053906660e-24) */
   double rho11_min;    /* points below this density are passed through unsolved (1e-4 = 1e7 g/cm^3) */
+  /* linear-order (l = 1) NES and pair kernels as fractions of the isotropic
+   * ones, Phi_1 = phi1 Phi_0 (0, 0); nonzero values add the Phi_1 terms of
+   * Eqs. zerothMomentCollisionTerm_NES/_Pair and
+   * firstMomentCollisionTerm_NES/_Pair to nmc_solve_batch_v (the zero-velocity
+   * solve, with one flux component and no closure, ignores them); each in
+   * [-1/3, 1/3], the range that keeps the linear angular kernel non-negative */
+  double phi1_nes, phi1_pair;
 } nmc_model_desc;
 
 typedef struct {

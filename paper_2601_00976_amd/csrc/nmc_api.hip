@@ -248,7 +248,8 @@ int nmc_model_create(const nmc_grid* g, const nmc_model_desc* d, nmc_model** out
     ++k;
   }
   const double vals[] = {d->chi_ref, d->eps_ref, d->chi_power, d->sigma_ratio, d->eos_a, d->eos_b, d->mu_a,
-                         d->mu_ye0, d->mu_b, d->mu_t0, d->hc_mev_cm, d->m_u_g, d->rho11_min};
+                         d->mu_ye0, d->mu_b, d->mu_t0, d->hc_mev_cm, d->m_u_g, d->rho11_min, d->phi1_nes,
+                         d->phi1_pair};
   for (double v : vals)
     if (!isfinite(v)) return fail(NMC_E_INVALID_ARG, "model_create: non-finite constant");
   if (!(d->eps_ref > 0) || !(d->eos_a > 0) || !(d->mu_t0 > 0) || !(d->hc_mev_cm > 0) || !(d->m_u_g > 0))
@@ -271,6 +272,10 @@ int nmc_model_create(const nmc_grid* g, const nmc_model_desc* d, nmc_model** out
   const double hc = d->hc_mev_cm;
   m.kcoup = 4.0 * pi / (hc * hc * hc) * d->m_u_g / 1.0e11;
   m.rho11_min = d->rho11_min;
+  if (!(fabs(d->phi1_nes) <= 1.0 / 3.0) || !(fabs(d->phi1_pair) <= 1.0 / 3.0))
+    return fail(NMC_E_INVALID_ARG, "model_create: phi1_nes and phi1_pair must lie in [-1/3, 1/3]");
+  m.phi1_nes = d->phi1_nes;
+  m.phi1_pair = d->phi1_pair;
 
   nmc_model* mm = new (std::nothrow) nmc_model();
   if (!mm) return fail(NMC_E_INVALID_ARG, "model_create: out of host memory");
@@ -502,7 +507,8 @@ int nmc_solve_batch_v(const nmc_model* m, const nmc_solver_params* prm, int64_t 
     if (e != hipSuccess) return hip_fail(e, "solve_batch_v: counter reset");
   }
   const bool coupled = (m->host.flags & (NMC_NES | NMC_PAIR)) != 0;
-  hipError_t e = nmc::launch_forward_v(a, m->host.ns, coupled, L, m->num_cu, s);
+  const bool phi1 = coupled && (m->host.phi1_nes != 0.0 || m->host.phi1_pair != 0.0);
+  hipError_t e = nmc::launch_forward_v(a, m->host.ns, coupled, phi1, L, m->num_cu, s);
   if (e == hipErrorInvalidValue) return fail(NMC_E_UNSUPPORTED, "solve_batch_v: no kernel for ns=%d", m->host.ns);
   if (e != hipSuccess) return hip_fail(e, "solve_batch_v: launch");
   return NMC_OK;

@@ -26,7 +26,7 @@ namespace {
 
 constexpr double kMuC2 = 931.49410242;  // atomic mass unit rest energy [MeV]
 
-template <int NS>
+template <int NS, bool PHI1>
 struct VLds {
   ModelLds m;
   double cst[NS][2][kLanes];      // owned moment of the old conserved state: N* or G*_j
@@ -36,6 +36,7 @@ struct VLds {
   SplitExp E;                     // per-node factors of the current temperature
   alignas(16) double X[NS][32];   // W e D of the current iterate
   alignas(16) double Y[NS][32];   // W e (1 - D) of the current iterate
+  alignas(16) double XI[PHI1 ? NS : 1][3][32];  // W e I_i of the current iterate (linear-order kernels)
   // uniform per-point state
   double dref[NS];
   double y[5];      // matter iterate (Ye, ef, v_1, v_2, v_3)
@@ -68,7 +69,66 @@ __device__ __forceinline__ void closure_terms(double D, const double (&I)[3], co
   vK[2] = D * (a * v[2] + bvn * n2);
 }
 
-template <int NS, bool COUPLED>
+// Linear-order kernel integrals of one kernel row over columns j0 .. j0 + 15
+// (partial sums), flux component i: with the isotropic kernels' entries
+// regenerated as in regen_rates_half (without their factor A e_q e_j),
+//   Lin[s]  += Phi_in  W e I_s,i     Lout[s] += Phi_out W e I_s,i
+//   Lpro[s] += Phi_pro W e I_sbar,i  Lann[s] += Phi_ann W e I_sbar,i
+// (Eqs. linearCorrectionsNES, linearCorrectionsPair; Phi_1 = phi1 Phi_0, the
+// fractions and A e_q are applied by the caller)
+template <int NS, class L>
+__device__ __forceinline__ void phi1_half(const L& S, int q, int j0, const double (&Bq)[16], int i,
+                                          double (&Lin)[NS], double (&Lout)[NS], double (&Lpro)[NS],
+                                          double (&Lann)[NS]) {
+  const SplitExp& E = S.E;
+  const double Gq = E.G[q];
+#pragma unroll
+  for (int t = 0; t < NS; ++t) Lin[t] = Lout[t] = Lpro[t] = Lann[t] = 0.0;
+#pragma unroll 4
+  for (int jj = 0; jj < 16; ++jj) {
+    const int j = j0 + jj;
+    const bool up = j > q;
+    const double b = Bq[jj], b2 = b * b, b3 = b2 * b;
+    const double fin = up ? b : b3, fout = up ? b3 : b;
+    const double fann = b2, fpro = fmin(E.G[j], Gq);
+    double x[NS];
+#pragma unroll
+    for (int t = 0; t < NS; ++t) x[t] = S.XI[t][i][j];
+#pragma unroll
+    for (int t = 0; t < NS; ++t) {
+      const int tb = pair_partner<NS>(t);
+      Lin[t] = __builtin_fma(fin, x[t], Lin[t]);
+      Lout[t] = __builtin_fma(fout, x[t], Lout[t]);
+      Lpro[t] = __builtin_fma(fpro, x[tb], Lpro[t]);
+      Lann[t] = __builtin_fma(fann, x[tb], Lann[t]);
+    }
+  }
+}
+
+// Linear-order collision terms of one species at one node (Eqs.
+// zerothMomentCollisionTerm_NES/_Pair, firstMomentCollisionTerm_NES/_Pair):
+// with P = L_in - L_pro and R = L_out - L_ann (vectors over i),
+//   number equation: (R - P).I
+//   flux equation j: P_j / 3 + (K (R - P))_j,  K = D ((1 - psi) 1 + (3 psi - 1) n n) / 2
+// (the Minerbo tensor of the node, as in closure_terms)
+__device__ __forceinline__ void phi1_collision(double D, const double (&I)[3], const double (&P)[3],
+                                               const double (&R)[3], double& c0, double (&c1)[3]) {
+  const double Imag = sqrt(I[0] * I[0] + I[1] * I[1] + I[2] * I[2]);
+  double h = 0.0;
+  if (Imag > 0.0) h = Imag < D ? Imag * rcp_nr(D) : 1.0;
+  const double psi = 1.0 / 3.0 + (2.0 / 15.0) * (3.0 - h + 3.0 * h * h) * h * h;
+  const double a = 0.5 * (1.0 - psi), b = 0.5 * (3.0 * psi - 1.0);
+  const double rI = Imag > 0.0 ? rcp_nr(Imag) : 0.0;
+  const double n0 = I[0] * rI, n1 = I[1] * rI, n2 = I[2] * rI;
+  const double d0 = R[0] - P[0], d1 = R[1] - P[1], d2 = R[2] - P[2];
+  const double bnd = b * (n0 * d0 + n1 * d1 + n2 * d2);
+  c0 = d0 * I[0] + d1 * I[1] + d2 * I[2];
+  c1[0] = P[0] * (1.0 / 3.0) + D * (a * d0 + bnd * n0);
+  c1[1] = P[1] * (1.0 / 3.0) + D * (a * d1 + bnd * n1);
+  c1[2] = P[2] * (1.0 / 3.0) + D * (a * d2 + bnd * n2);
+}
+
+template <int NS, bool COUPLED, bool PHI1>
 struct PointSolverV {
   static constexpr int NQ = 32;
   // the lane's 16 pair factors are kept in VGPRs across the inner loop (2);
@@ -102,7 +162,7 @@ struct PointSolverV {
   }
 
   // matter right-hand side q(M, y) (Eq. implicitFluidNodal)
-  __device__ __forceinline__ static void matter_rhs(const VLds<NS>& S, const double (&X)[5], double (&yq)[5]) {
+  __device__ __forceinline__ static void matter_rhs(const VLds<NS, PHI1>& S, const double (&X)[5], double (&yq)[5]) {
     yq[0] = S.yst[0] - S.K * (X[0] - S.X0[0]);
     yq[1] = S.yst[1] - S.K * (X[1] - S.X0[1]);
     const double Kv = S.K * (1.0 / kMuC2);
@@ -133,7 +193,7 @@ struct PointSolverV {
   }
 
   template <class Settle>
-  __device__ static void solve(const FwdVArgs& a, int64_t p, VLds<NS>& S, Settle&& settle) {
+  __device__ static void solve(const FwdVArgs& a, int64_t p, VLds<NS, PHI1>& S, Settle&& settle) {
     const_ptr<DevModel> md = scalar_ptr(a.mdl);
     const ModelLds& mt = S.m;
     const int lane = threadIdx.x;
@@ -324,9 +384,45 @@ struct PointSolverV {
           for (int t = 0; t < NS; ++t) eta_c[t] = chi_c[t] = 0.0;
         }
 
+        // linear-order corrections at the current iterate, added to the
+        // right-hand sides like the emissivity: c_own[t][c] for the owned
+        // moment c of species t (number equation, or flux component)
+        double c_own[NS][2];
+#pragma unroll
+        for (int t = 0; t < NS; ++t) c_own[t][0] = c_own[t][1] = 0.0;
+        if constexpr (PHI1) {
+          if (h == 0) {
+#pragma unroll
+            for (int t = 0; t < NS; ++t)
+#pragma unroll
+              for (int i = 0; i < 3; ++i) S.XI[t][i][q] = w2eq * If[t][i];
+          }
+          __syncthreads();
+          const double rN = md->phi1_nes * S.An * mt.eps[q], rP = md->phi1_pair * S.Ap * mt.eps[q];
+          double P[NS][3], R[NS][3];
+#pragma unroll
+          for (int i = 0; i < 3; ++i) {
+            double Lin[NS], Lout[NS], Lpro[NS], Lann[NS];
+            phi1_half<NS>(S, q, 16 * h, Bq, i, Lin, Lout, Lpro, Lann);
+#pragma unroll
+            for (int t = 0; t < NS; ++t) {
+              P[t][i] = sum_halves(__builtin_fma(rN, Lin[t], -rP * Lpro[t]));
+              R[t][i] = sum_halves(__builtin_fma(rN, Lout[t], -rP * Lann[t]));
+            }
+          }
+          __syncthreads();
+#pragma unroll
+          for (int t = 0; t < NS; ++t) {
+            double c0, c1[3];
+            phi1_collision(Df[t], If[t], P[t], R[t], c0, c1);
+            c_own[t][0] = h ? c1[1] : c0;
+            c_own[t][1] = h ? c1[2] : c1[0];
+          }
+        }
+
         // moment right-hand side Q (Eq. implicitMomentsNodal) and residual:
-        // Q_D = ((1 - lam) D - lam v.I + lam (N* + dtau eta)) / (1 + lam dtau chi),
-        // Q_Ij = ((1 - lam) I_j - lam v^i K_ij + lam G*_j) / (1 + lam dtau kappa)
+        // Q_D = ((1 - lam) D - lam v.I + lam (N* + dtau (eta + c))) / (1 + lam dtau chi),
+        // Q_Ij = ((1 - lam) I_j - lam v^i K_ij + lam (G*_j + dtau c_j)) / (1 + lam dtau kappa)
         double Q[NS][2], F[NS][2];
 #pragma unroll
         for (int t = 0; t < NS; ++t) {
@@ -334,8 +430,12 @@ struct PointSolverV {
           closure_terms(Df[t], If[t], v, vI, vK);
           const double V0 = h ? vK[1] : vI, V1 = h ? vK[2] : vK[0];
           const double ex0 = h ? 0.0 : ldt * eta_c[t];
-          const double n0 = __builtin_fma(oml, u[t][0], S.base[t][0][lane]) - lam * V0 + ex0;
-          const double n1 = __builtin_fma(oml, u[t][1], S.base[t][1][lane]) - lam * V1;
+          double n0 = __builtin_fma(oml, u[t][0], S.base[t][0][lane]) - lam * V0 + ex0;
+          double n1 = __builtin_fma(oml, u[t][1], S.base[t][1][lane]) - lam * V1;
+          if constexpr (PHI1) {
+            n0 = __builtin_fma(ldt, c_own[t][0], n0);
+            n1 = __builtin_fma(ldt, c_own[t][1], n1);
+          }
           const double d0 = __builtin_fma(ldt, chi_c[t], S.den0[t][0][lane]);
           const double d1 = __builtin_fma(ldt, chi_c[t], S.den0[t][1][lane]);
           Q[t][0] = n0 * rcp_nr(d0);
@@ -560,27 +660,27 @@ struct PointSolverV {
   }
 };
 
-template <int NS, bool COUPLED>
+template <int NS, bool COUPLED, bool PHI1>
 __global__ __launch_bounds__(kLanes, 2) void fwd_v_kernel(FwdVArgs a) {
-  __shared__ VLds<NS> S;
+  __shared__ VLds<NS, PHI1> S;
   load_model(a.mdl, a.theta, S.m);
   if (a.queue) {
     WorkQueue wq(a.queue, a.P, a.chunk);
     for (int64_t g; (g = wq.next()) >= 0;) {
       const int64_t b0 = uniform64(g * a.chunk);
       const int64_t end = uniform64(b0 + a.chunk < a.P ? b0 + a.chunk : a.P);
-      for (int64_t p = b0; p < end; ++p) PointSolverV<NS, COUPLED>::solve(a, p, S, [&] { wq.settle(); });
+      for (int64_t p = b0; p < end; ++p) PointSolverV<NS, COUPLED, PHI1>::solve(a, p, S, [&] { wq.settle(); });
     }
   } else {
     const int64_t b0 = (int64_t)blockIdx.x * a.chunk;
     const int64_t end = b0 + a.chunk < a.P ? b0 + a.chunk : a.P;
-    for (int64_t p = b0; p < end; ++p) PointSolverV<NS, COUPLED>::solve(a, p, S, [] {});
+    for (int64_t p = b0; p < end; ++p) PointSolverV<NS, COUPLED, PHI1>::solve(a, p, S, [] {});
   }
 }
 
-template <int NS, bool COUPLED>
+template <int NS, bool COUPLED, bool PHI1 = false>
 hipError_t launch_v_t(const FwdVArgs& a, const nmc_launch& L, int num_cu, hipStream_t s) {
-  auto kern = fwd_v_kernel<NS, COUPLED>;
+  auto kern = fwd_v_kernel<NS, COUPLED, PHI1>;
   int64_t grid;
   if (a.queue) {
     int bpc = L.blocks_per_cu;
@@ -606,9 +706,15 @@ hipError_t launch_v_t(const FwdVArgs& a, const nmc_launch& L, int num_cu, hipStr
 
 }  // namespace
 
-hipError_t launch_forward_v(const FwdVArgs& a, int ns, bool coupled, const nmc_launch& L, int num_cu,
+hipError_t launch_forward_v(const FwdVArgs& a, int ns, bool coupled, bool phi1, const nmc_launch& L, int num_cu,
                             hipStream_t s) {
-  if (coupled) {
+  if (phi1) {
+    switch (ns) {
+      case 1: return launch_v_t<1, true, true>(a, L, num_cu, s);
+      case 2: return launch_v_t<2, true, true>(a, L, num_cu, s);
+      case 3: return launch_v_t<3, true, true>(a, L, num_cu, s);
+    }
+  } else if (coupled) {
     switch (ns) {
       case 1: return launch_v_t<1, true>(a, L, num_cu, s);
       case 2: return launch_v_t<2, true>(a, L, num_cu, s);

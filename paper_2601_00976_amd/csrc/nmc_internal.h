@@ -39,6 +39,7 @@ struct DevModel {
   double eos_a, eos_b, mu_a, mu_ye0, mu_b, mu_t0;
   double kcoup;           // K * rho11 [MeV^-3]
   double rho11_min;
+  double phi1_nes, phi1_pair;  // Phi_1 / Phi_0 of the NES and pair kernels
 };
 
 struct SolverParams {
@@ -93,7 +94,7 @@ hipError_t launch_forward64(const FwdArgs& a, int ns, bool coupled, const nmc_la
                             hipStream_t s);
 hipError_t launch_forward_pair(const FwdArgs& a, int ns, bool coupled, const nmc_launch& L, int num_cu,
                                hipStream_t s);
-hipError_t launch_forward_v(const FwdVArgs& a, int ns, bool coupled, const nmc_launch& L, int num_cu,
+hipError_t launch_forward_v(const FwdVArgs& a, int ns, bool coupled, bool phi1, const nmc_launch& L, int num_cu,
                             hipStream_t s);
 hipError_t launch_reset_counter(int* counter, hipStream_t s);
 // FP64 FMA throughput probe (measurement only)

@@ -49,7 +49,8 @@ class ModelDesc(C.Structure):
                 ("chi_ref", C.c_double), ("eps_ref", C.c_double), ("chi_power", C.c_double),
                 ("sigma_ratio", C.c_double), ("eos_a", C.c_double), ("eos_b", C.c_double),
                 ("mu_a", C.c_double), ("mu_ye0", C.c_double), ("mu_b", C.c_double), ("mu_t0", C.c_double),
-                ("hc_mev_cm", C.c_double), ("m_u_g", C.c_double), ("rho11_min", C.c_double)]
+                ("hc_mev_cm", C.c_double), ("m_u_g", C.c_double), ("rho11_min", C.c_double),
+                ("phi1_nes", C.c_double), ("phi1_pair", C.c_double)]
 
 
 class SolverParams(C.Structure):
