@@ -106,6 +106,11 @@ def lib():
         L.ora_flux_factor.argtypes = [C.c_double, C.c_double]
         L.ora_flux_factor.restype = C.c_double
         L.ora_eddington.argtypes = [C.c_double, dp, dp]
+        L.ora_primitive_batch.argtypes = [C.POINTER(_Model), C.c_long, dp, dp, dp, C.c_int, C.c_double, C.c_int,
+                                          dp, dp, ip, C.c_int]
+        L.ora_pdars_step_v.argtypes = [C.POINTER(_Model), C.POINTER(_Params), dp, C.c_long, C.c_double,
+                                       dp, dp, dp, dp, dp, dp, vp, C.c_int, C.c_double, C.c_int,
+                                       dp, dp, dp, dp, dp, dp, ip, ip, ip, C.c_int]
         L.ora_phi1_terms.argtypes = [C.POINTER(_Model), dp, C.c_double, C.c_double, dp, dp, dp, dp]
         L.ora_solve_batch_v.argtypes = [C.POINTER(_Model), C.POINTER(_Params), dp, C.c_long, C.c_double,
                                         dp, dp, dp, dp, dp, dp, vp,
@@ -371,6 +376,40 @@ def solve_batch_v(model: Model, params: Params, theta, dtau, D0, I0, rho11, ye0,
     rc = lib().ora_solve_batch_v(model.ref(), C.byref(pc), _f64(theta), P, dtau, D0.ravel(),
                                  _f64(I0).ravel(), _f64(rho11), _f64(ye0), _f64(ef0), _f64(v0).ravel(),
                                  _vp(chi0), D, I, ye, ef, v, T, no, ni, st, nthreads)
+    if rc != 0:
+        raise ValueError("oracle rejected the arguments")
+    return dict(D=D.reshape(P, model.ns, model.nq), I=I.reshape(P, model.ns, 3, model.nq), ye=ye, ef=ef,
+                v=v.reshape(P, 3), T=T, n_outer=no, n_inner=ni, status=st)
+
+
+def primitive_batch(model: Model, N, G, v, mem=3, tol=1e-8, max_it=100, nthreads: int = 0):
+    """Primitive-moment recovery (Sec. 3.4): conserved N (P, ns, nq), G (P, ns, 3, nq)
+    at velocity v (P, 3) -> (D, I, iters); iters = -1 at the cap, -2 non-finite."""
+    N = _f64(N)
+    P = N.shape[0]
+    nn = model.ns * model.nq
+    D, I, it = np.zeros(P * nn), np.zeros(P * 3 * nn), np.zeros(P * nn, np.int32)
+    rc = lib().ora_primitive_batch(model.ref(), P, N.ravel(), _f64(G).ravel(), _f64(v).ravel(), mem, tol, max_it,
+                                   D, I, it, nthreads)
+    if rc != 0:
+        raise ValueError("oracle rejected the arguments")
+    return D.reshape(P, model.ns, model.nq), I.reshape(P, model.ns, 3, model.nq), it.reshape(P, model.ns, model.nq)
+
+
+def pdars_step_v(model: Model, params: Params, theta, dt, D0, I0, rho11, ye0, ef0, v0, chi0=None, c2p_mem=3,
+                 c2p_tol=1e-8, c2p_max=100, nthreads: int = 0):
+    """One PD-ARS IMEX step (Eq. butcherPDARS) of the coupling alone, O(v) form."""
+    D0 = _f64(D0)
+    P = D0.shape[0]
+    nn = model.ns * model.nq
+    D, I = np.zeros(P * nn), np.zeros(P * 3 * nn)
+    ye, ef, v, T = np.zeros(P), np.zeros(P), np.zeros(P * 3), np.zeros(P)
+    no, ni, st = np.zeros(P, np.int32), np.zeros(P, np.int32), np.zeros(P, np.int32)
+    chi0 = None if chi0 is None else _f64(chi0)
+    pc = params.c()
+    rc = lib().ora_pdars_step_v(model.ref(), C.byref(pc), _f64(theta), P, dt, D0.ravel(), _f64(I0).ravel(),
+                                _f64(rho11), _f64(ye0), _f64(ef0), _f64(v0).ravel(), _vp(chi0), c2p_mem, c2p_tol,
+                                c2p_max, D, I, ye, ef, v, T, no, ni, st, nthreads)
     if rc != 0:
         raise ValueError("oracle rejected the arguments")
     return dict(D=D.reshape(P, model.ns, model.nq), I=I.reshape(P, model.ns, 3, model.nq), ye=ye, ef=ef,

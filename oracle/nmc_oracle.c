@@ -1302,6 +1302,151 @@ int ora_solve_batch_v(const ora_model* m, const ora_params* prm, const double* t
   return 0;
 }
 
+/* ------------------------------------------------------------------------ */
+/* Primitive-moment recovery (Sec. 3.4): for one species at one node, given
+ * the conserved moments U = (N, G_j) and the velocity v, find M = (D, I_j)
+ * with N = D + v^i I_i and G_j = I_j + v^i K_ij(M) (Eq.
+ * conservedToPrimitive) by the fixed-point sequence of Eqs. c2p_FP,
+ * c2p_sequence,
+ *   M^[k+1] = (1 - lam) M^[k] + lam (N - v.I^[k], G_j - v^i K_ij(M^[k])),
+ * lam = 1 / (1 + |v|), from M^[0] = U, with Anderson acceleration over the
+ * last `mem` residuals, until ||M^[k+1] - M^[k]|| <= tol ||U|| (Euclidean).
+ * Returns the iterations taken, or -1 when max_it is reached, -2 on a
+ * non-finite iterate. */
+static int c2p_node(double N, const double* G, const double* v, int mem, double tol, int max_it, double* M) {
+  double lam = 1.0 / (1.0 + norm3(v));
+  double U[4] = {N, G[0], G[1], G[2]};
+  double unorm = sqrt(U[0] * U[0] + U[1] * U[1] + U[2] * U[2] + U[3] * U[3]);
+  double Qh[MAXMEM * 4], Fh[MAXMEM * 4], Mn[4];
+  int count = 0;
+  for (int i = 0; i < 4; ++i) M[i] = U[i];
+  for (int k = 1; k <= max_it; ++k) {
+    double K9[9], g[4], f[4];
+    ora_eddington(M[0], M + 1, K9);
+    g[0] = (1.0 - lam) * M[0] + lam * (N - (v[0] * M[1] + v[1] * M[2] + v[2] * M[3]));
+    for (int j = 0; j < 3; ++j)
+      g[1 + j] = (1.0 - lam) * M[1 + j] + lam * (G[j] - (v[0] * K9[3 * j] + v[1] * K9[3 * j + 1] + v[2] * K9[3 * j + 2]));
+    for (int i = 0; i < 4; ++i) f[i] = g[i] - M[i];
+    hist_push(Qh, Fh, &count, mem, 4, g, f);
+    ora_anderson(4, count, Qh, Fh, Mn);
+    if (!all_finite(Mn, 4)) return -2;
+    double d2 = 0.0;
+    for (int i = 0; i < 4; ++i) d2 += (Mn[i] - M[i]) * (Mn[i] - M[i]);
+    for (int i = 0; i < 4; ++i) M[i] = Mn[i];
+    if (sqrt(d2) <= tol * unorm) return k;
+  }
+  return -1;
+}
+
+int ora_primitive_batch(const ora_model* m, long P, const double* N, const double* G, const double* v, int mem,
+                        double tol, int max_it, double* D, double* I, int* iters, int nthreads) {
+  if (m->nq < 1 || m->nq > ORA_MAX_NQ || m->ns < 1 || m->ns > ORA_MAX_NS) return -1;
+  if (mem < 1 || mem > MAXMEM || max_it < 1 || !(tol > 0.0)) return -1;
+  int nq = m->nq, ns = m->ns;
+#ifdef _OPENMP
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 64)
+#endif
+  for (long p = 0; p < P; ++p)
+    for (int s = 0; s < ns; ++s)
+      for (int q = 0; q < nq; ++q) {
+        long i = (p * ns + s) * nq + q;
+        double Gq[3], M[4];
+        for (int j = 0; j < 3; ++j) Gq[j] = G[((p * ns + s) * 3 + j) * nq + q];
+        iters[i] = c2p_node(N[i], Gq, v + 3 * p, mem, tol, max_it, M);
+        D[i] = M[0];
+        for (int j = 0; j < 3; ++j) I[((p * ns + s) * 3 + j) * nq + q] = M[1 + j];
+      }
+  return 0;
+}
+
+/* conserved moments of primitive ones at velocity v: N = D + v.I,
+ * G_j = I_j + v^i K_ij (Eq. conservedToPrimitive), for one point */
+static void p2c_point(const ora_model* m, const double* D, const double* I, const double* v, double* N, double* G) {
+  int nq = m->nq, ns = m->ns;
+  for (int s = 0; s < ns; ++s)
+    for (int q = 0; q < nq; ++q) {
+      double I3[3], K9[9];
+      flux3(m, I, s, q, I3);
+      ora_eddington(D[s * nq + q], I3, K9);
+      N[s * nq + q] = D[s * nq + q] + v[0] * I3[0] + v[1] * I3[1] + v[2] * I3[2];
+      for (int j = 0; j < 3; ++j)
+        G[(s * 3 + j) * nq + q] = I3[j] + v[0] * K9[3 * j] + v[1] * K9[3 * j + 1] + v[2] * K9[3 * j + 2];
+    }
+}
+
+/* One time step of the IMEX scheme with the PD-ARS tableau (Eq.
+ * butcherPDARS) for the neutrino-matter coupling alone (the explicit
+ * operator, phase-space advection, is zero here).  Stage i takes the
+ * intermediate state U^(i*) = U^n + dt sum_{j<i} a_ij C^(j) (conserved
+ * moments; the matter state likewise) and solves the modified backward-Euler
+ * problem with step a_ii dt (Algorithm neutrinoMatterCoupling through
+ * ora_solve_batch_v); C^(j) = (U^(j) - U^(j*)) / (a_jj dt) is the collision
+ * term the stage-j solve applied.  Stage 1 has a_11 = 0 (U^(1) = U^n) and
+ * enters no later stage (a_21 = a_31 = 0).  The stage-3 intermediate state is
+ * recovered to primitive moments (primitive recovery, c2p parameters) before
+ * its solve.  The scheme is globally stiffly accurate, so the step's result
+ * is U^(3).  n_outer / n_inner sum over the two solves; status: the first
+ * non-OK of stage 2, the primitive recovery (ORA_MAX_INNER when it does not
+ * converge, ORA_NONFINITE), stage 3. */
+int ora_pdars_step_v(const ora_model* m, const ora_params* prm, const double* theta, long P, double dt,
+                     const double* D0, const double* I0, const double* rho11, const double* ye0,
+                     const double* ef0, const double* v0, const double* chi0, int c2p_mem, double c2p_tol,
+                     int c2p_max, double* D, double* I, double* ye, double* ef, double* v, double* T,
+                     int* n_outer, int* n_inner, int* status, int nthreads) {
+  static const double a[3][3] = {{0.0, 0.0, 0.0}, {0.0, 1.0, 0.0}, {0.0, 0.5, 0.5}};
+  int nq = m->nq, ns = m->ns, nn = ns * nq;
+  if (!(dt > 0.0)) return -1;
+  size_t szD = (size_t)P * nn, szI = (size_t)P * 3 * nn;
+  double *D2 = malloc(szD * 8), *I2 = malloc(szI * 8), *y2e = malloc(P * 8), *y2f = malloc(P * 8);
+  double *v2 = malloc(P * 3 * 8), *T2 = malloc(P * 8);
+  double *D3 = malloc(szD * 8), *I3 = malloc(szI * 8), *y3e = malloc(P * 8), *y3f = malloc(P * 8),
+         *v3 = malloc(P * 3 * 8);
+  double *Nn = malloc(szD * 8), *Gn = malloc(szI * 8), *N2 = malloc(szD * 8), *G2 = malloc(szI * 8);
+  double *N3 = malloc(szD * 8), *G3 = malloc(szI * 8);
+  int *no2 = malloc(P * 4), *ni2 = malloc(P * 4), *st2 = malloc(P * 4), *it = malloc(szD * 4);
+  int rc = 0;
+  /* stage 2: U^(2*) = U^n; backward Euler with a_22 dt */
+  rc = ora_solve_batch_v(m, prm, theta, P, a[1][1] * dt, D0, I0, rho11, ye0, ef0, v0, chi0, D2, I2, y2e, y2f, v2,
+                         T2, no2, ni2, st2, nthreads);
+  if (rc == 0) {
+    /* stage 3: U^(3*) = U^n + dt a_32 C^(2), C^(2) = (U^(2) - U^(2*)) / (a_22 dt);
+     * likewise the matter state */
+    double w = a[2][1] / a[1][1];
+    for (long p = 0; p < P; ++p) {
+      p2c_point(m, D0 + p * nn, I0 + p * 3 * nn, v0 + 3 * p, Nn + p * nn, Gn + p * 3 * nn);
+      p2c_point(m, D2 + p * nn, I2 + p * 3 * nn, v2 + 3 * p, N2 + p * nn, G2 + p * 3 * nn);
+      for (int i = 0; i < nn; ++i) N3[p * nn + i] = Nn[p * nn + i] + w * (N2[p * nn + i] - Nn[p * nn + i]);
+      for (int i = 0; i < 3 * nn; ++i)
+        G3[p * 3 * nn + i] = Gn[p * 3 * nn + i] + w * (G2[p * 3 * nn + i] - Gn[p * 3 * nn + i]);
+      y3e[p] = ye0[p] + w * (y2e[p] - ye0[p]);
+      y3f[p] = ef0[p] + w * (y2f[p] - ef0[p]);
+      for (int j = 0; j < 3; ++j) v3[3 * p + j] = v0[3 * p + j] + w * (v2[3 * p + j] - v0[3 * p + j]);
+    }
+    rc = ora_primitive_batch(m, P, N3, G3, v3, c2p_mem, c2p_tol, c2p_max, D3, I3, it, nthreads);
+  }
+  if (rc == 0)
+    rc = ora_solve_batch_v(m, prm, theta, P, a[2][2] * dt, D3, I3, rho11, y3e, y3f, v3, chi0, D, I, ye, ef, v, T,
+                           n_outer, n_inner, status, nthreads);
+  if (rc == 0)
+    for (long p = 0; p < P; ++p) {
+      int c2p = ORA_OK;
+      for (int i = 0; i < nn; ++i) {
+        if (it[p * nn + i] == -2) c2p = ORA_NONFINITE;
+        if (it[p * nn + i] == -1 && c2p == ORA_OK) c2p = ORA_MAX_INNER;
+      }
+      if (st2[p] != ORA_OK) status[p] = st2[p];
+      else if (c2p != ORA_OK) status[p] = c2p;
+      n_outer[p] += no2[p];
+      n_inner[p] += ni2[p];
+    }
+  free(D2); free(I2); free(y2e); free(y2f); free(v2); free(T2);
+  free(D3); free(I3); free(y3e); free(y3f); free(v3);
+  free(Nn); free(Gn); free(N2); free(G2); free(N3); free(G3);
+  free(no2); free(ni2); free(st2); free(it);
+  return rc;
+}
+
 /* Initial state from raw draws: e* from the EOS, D* = clip(D_eq (a + b uD),
  * 0, 1 - 1e-12), I* = c D* uI.  If mu is NULL it follows from the EOS. */
 int ora_init_state(const ora_model* m, long P, const double* T, const double* mu, const double* rho11,

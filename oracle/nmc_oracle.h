@@ -142,6 +142,21 @@ int ora_solve_batch_v(const ora_model* m, const ora_params* prm, const double* t
                       double* D, double* I, double* ye, double* ef, double* v, double* T,
                       int* n_outer, int* n_inner, int* status, int nthreads);
 
+/* primitive-moment recovery (Sec. 3.4, Eqs. c2p_FP, c2p_sequence): conserved
+ * N (P, ns, nq), G (P, ns, 3, nq) at velocity v (P, 3) -> primitive D, I;
+ * iters (P, ns, nq): iterations, -1 at the cap, -2 on a non-finite iterate */
+int ora_primitive_batch(const ora_model* m, long P, const double* N, const double* G, const double* v, int mem,
+                        double tol, int max_it, double* D, double* I, int* iters, int nthreads);
+
+/* one IMEX step with the PD-ARS tableau (Eq. butcherPDARS) of the coupling
+ * alone: two modified backward-Euler solves (steps dt, dt/2) with the stage
+ * combination in conserved variables and primitive recovery between them */
+int ora_pdars_step_v(const ora_model* m, const ora_params* prm, const double* theta, long P, double dt,
+                     const double* D0, const double* I0, const double* rho11, const double* ye0,
+                     const double* ef0, const double* v0, const double* chi0, int c2p_mem, double c2p_tol,
+                     int c2p_max, double* D, double* I, double* ye, double* ef, double* v, double* T,
+                     int* n_outer, int* n_inner, int* status, int nthreads);
+
 /* initial state from raw draws */
 int ora_init_state(const ora_model* m, long P, const double* T, const double* mu, const double* rho11,
                    const double* ye, const double* uD, const double* uI, double a, double b, double c,
