@@ -317,6 +317,47 @@ int nmc_solve_batch_v(const nmc_model* m, const nmc_solver_params* prm, int64_t 
                       const nmc_batch_v_in* in, const nmc_batch_v_out* out, void* ws, size_t ws_bytes,
                       const nmc_launch* launch, void* stream);
 
+/* Primitive-moment recovery (Sec. 3.4): for every point, species and node,
+ * the primitive moments M = (D, I_j) of the conserved ones U = (N, G_j) at
+ * fluid velocity v, i.e. N = D + v^i I_i, G_j = I_j + v^i K_ij(M) with the
+ * Minerbo tensor (Eq. conservedToPrimitive), by the fixed-point sequence of
+ * Eqs. c2p_FP / c2p_sequence (lambda = 1 / (1 + |v|), from M = U) with
+ * Anderson acceleration, until ||M^[k+1] - M^[k]|| <= tol ||U||
+ * (Euclidean over the four moments). */
+typedef struct {
+  int mem;       /* Anderson memory, 1 (Picard) .. 3 (3) */
+  double tol;    /* relative tolerance (1e-8) */
+  int max_it;    /* iteration cap (100) */
+} nmc_c2p_params;
+void nmc_c2p_params_default(nmc_c2p_params* cp);
+
+/* N (P, ns, nq), G (P, ns, 3, nq), v (P, 3) -> D (P, ns, nq), I (P, ns, 3, nq);
+ * iters (P, ns, nq) int32: iterations taken, -1 where the cap was reached
+ * (the last iterate is returned), -2 on a non-finite iterate.  Device arrays;
+ * D and I must not alias N and G.  Any node count and species set of the
+ * model. */
+int nmc_primitive_recovery(const nmc_model* m, const nmc_c2p_params* cp, int64_t P, const double* N,
+                           const double* G, const double* v, double* D, double* I, int32_t* iters, void* stream);
+
+/* One time step of the IMEX scheme with the PD-ARS tableau (Eq.
+ * butcherPDARS) for the neutrino-matter coupling alone (the explicit
+ * operator, phase-space advection, is outside this library and zero here):
+ * stage 2 solves the modified backward-Euler problem of nmc_solve_batch_v
+ * with step dt from the initial state; the stage-3 initial state is
+ * U^n + (a_32 / a_22)(U^(2) - U^n) in conserved moments (and likewise the
+ * matter state), recovered to primitive moments as nmc_primitive_recovery
+ * does; stage 3 solves with step dt / 2 from it, and its solution is the
+ * step's result (the scheme is globally stiffly accurate).  Points below
+ * the coupling density pass through.  n_outer / n_inner count both solves;
+ * status is the first non-OK of stage 2, the recovery (MAX_INNER where it hit
+ * its cap, NONFINITE) and stage 3.  Inputs, outputs, aliasing and launch as
+ * for nmc_solve_batch_v; ws: nmc_pdars_workspace_bytes(m, P) bytes,
+ * 256-byte aligned. */
+size_t nmc_pdars_workspace_bytes(const nmc_model* m, int64_t P);
+int nmc_pdars_step_v(const nmc_model* m, const nmc_solver_params* prm, const nmc_c2p_params* cp, int64_t P,
+                     double dt, const nmc_batch_v_in* in, const nmc_batch_v_out* out, void* ws, size_t ws_bytes,
+                     const nmc_launch* launch, void* stream);
+
 /* Initial neutrino state from raw draws: e0 = EOS(T, Ye, rho11),
  * D0 = clip(D_eq(T, mu) (a + b uD), 0, 1 - 1e-12), I0 = c D0 uI, with mu from
  * the EOS when mu is NULL.  All arrays are device pointers; e0 may be NULL. */

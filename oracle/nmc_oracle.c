@@ -1312,8 +1312,27 @@ int ora_solve_batch_v(const ora_model* m, const ora_params* prm, const double* t
  * lam = 1 / (1 + |v|), from M^[0] = U, with Anderson acceleration over the
  * last `mem` residuals, until ||M^[k+1] - M^[k]|| <= tol ||U|| (Euclidean).
  * Returns the iterations taken, or -1 when max_it is reached, -2 on a
- * non-finite iterate. */
+ * non-finite iterate.  The map is homogeneous of degree one in U (K_ij = D
+ * k_ij(|I| / D)), and so is the stopping test: the node is solved for U / s,
+ * s = max_i |U_i|, and the result multiplied by s, so that the squared norms
+ * and Anderson's Gram products of a faint node (a cold tail's 1e-200) do not
+ * underflow; s is the power of two at max_i |U_i|, so the scaling is exact. */
+static int c2p_scaled(double N, const double* G, const double* v, int mem, double tol, int max_it, double* M);
+
 static int c2p_node(double N, const double* G, const double* v, int mem, double tol, int max_it, double* M) {
+  double s = fabs(N);
+  for (int j = 0; j < 3; ++j)
+    if (fabs(G[j]) > s) s = fabs(G[j]);
+  int e = 0;
+  if (s > 0.0 && isfinite(s)) frexp(s, &e);
+  s = ldexp(1.0, e);
+  double Gs[3] = {G[0] / s, G[1] / s, G[2] / s};
+  int it = c2p_scaled(N / s, Gs, v, mem, tol, max_it, M);
+  for (int i = 0; i < 4; ++i) M[i] *= s;
+  return it;
+}
+
+static int c2p_scaled(double N, const double* G, const double* v, int mem, double tol, int max_it, double* M) {
   double lam = 1.0 / (1.0 + norm3(v));
   double U[4] = {N, G[0], G[1], G[2]};
   double unorm = sqrt(U[0] * U[0] + U[1] * U[1] + U[2] * U[2] + U[3] * U[3]);
@@ -1424,6 +1443,18 @@ int ora_pdars_step_v(const ora_model* m, const ora_params* prm, const double* th
       for (int j = 0; j < 3; ++j) v3[3 * p + j] = v0[3 * p + j] + w * (v2[3 * p + j] - v0[3 * p + j]);
     }
     rc = ora_primitive_batch(m, P, N3, G3, v3, c2p_mem, c2p_tol, c2p_max, D3, I3, it, nthreads);
+    /* points below the coupling density pass through the whole step */
+    for (long p = 0; p < P && rc == 0; ++p)
+      if (rho11[p] < m->rho11_min) {
+        for (int i = 0; i < nn; ++i) {
+          D3[p * nn + i] = D0[p * nn + i];
+          it[p * nn + i] = 0;
+        }
+        for (int i = 0; i < 3 * nn; ++i) I3[p * 3 * nn + i] = I0[p * 3 * nn + i];
+        y3e[p] = ye0[p];
+        y3f[p] = ef0[p];
+        for (int j = 0; j < 3; ++j) v3[3 * p + j] = v0[3 * p + j];
+      }
   }
   if (rc == 0)
     rc = ora_solve_batch_v(m, prm, theta, P, a[2][2] * dt, D3, I3, rho11, y3e, y3f, v3, chi0, D, I, ye, ef, v, T,

@@ -514,6 +514,145 @@ int nmc_solve_batch_v(const nmc_model* m, const nmc_solver_params* prm, int64_t 
   return NMC_OK;
 }
 
+void nmc_c2p_params_default(nmc_c2p_params* cp) {
+  if (!cp) return;
+  cp->mem = 3;
+  cp->tol = 1e-8;
+  cp->max_it = 100;
+}
+
+static int check_c2p(const nmc_c2p_params* cp, const char* who) {
+  if (!cp) return fail(NMC_E_INVALID_ARG, "%s: null recovery parameters", who);
+  if (cp->mem < 1 || cp->mem > 3) return fail(NMC_E_UNSUPPORTED, "%s: recovery memory must be 1..3", who);
+  if (!(cp->tol > 0.0) || !isfinite(cp->tol) || cp->max_it < 1 || cp->max_it > 100000)
+    return fail(NMC_E_INVALID_ARG, "%s: recovery tolerance must be positive, cap in 1..100000", who);
+  return NMC_OK;
+}
+
+int nmc_primitive_recovery(const nmc_model* m, const nmc_c2p_params* cp, int64_t P, const double* N, const double* G,
+                           const double* v, double* D, double* I, int32_t* iters, void* stream) {
+  if (!m) return fail(NMC_E_INVALID_ARG, "primitive_recovery: null model");
+  int rc = check_c2p(cp, "primitive_recovery");
+  if (rc) return rc;
+  if (P < 0 || P > (int64_t(1) << 30)) return fail(NMC_E_INVALID_ARG, "primitive_recovery: P out of range");
+  if (P == 0) return NMC_OK;
+  if (!N || !G || !v || !D || !I || !iters) return fail(NMC_E_INVALID_ARG, "primitive_recovery: null array");
+  hipError_t e = nmc::launch_c2p(P, m->host.ns, m->host.nq, N, G, v, cp->mem, cp->tol, cp->max_it, D, I, iters,
+                                 m->num_cu, (hipStream_t)stream);
+  return e == hipSuccess ? NMC_OK : hip_fail(e, "primitive_recovery: launch");
+}
+
+namespace {
+// PD-ARS tableau of the implicit part (Eq. butcherPDARS): a_22 = 1, a_32 = a_33 = 1/2
+constexpr double kA22 = 1.0, kA32 = 0.5, kA33 = 0.5;
+
+// workspace of a PD-ARS step: the solve's own, then the stage-2 solution and
+// the stage-3 initial state
+struct PdarsWs {
+  char* solve;
+  double *D2, *I2, *ye2, *ef2, *T2, *v2;
+  int32_t *no2, *ni2, *st2;
+  double *D3, *I3, *ye3, *ef3, *v3;
+  int32_t* iters;
+  size_t total;
+};
+
+size_t al256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+PdarsWs pdars_layout(const nmc_model* m, int64_t P, char* base) {
+  PdarsWs w;
+  const size_t nn = (size_t)m->host.ns * m->host.nq, pp = (size_t)P;
+  size_t off = al256(nmc_workspace_bytes(m, P));
+  auto take = [&](size_t bytes) {
+    char* p = base ? base + off : nullptr;
+    off += al256(bytes);
+    return p;
+  };
+  w.solve = base;
+  w.D2 = (double*)take(pp * nn * 8);
+  w.I2 = (double*)take(pp * 3 * nn * 8);
+  w.ye2 = (double*)take(pp * 8);
+  w.ef2 = (double*)take(pp * 8);
+  w.T2 = (double*)take(pp * 8);
+  w.v2 = (double*)take(pp * 3 * 8);
+  w.no2 = (int32_t*)take(pp * 4);
+  w.ni2 = (int32_t*)take(pp * 4);
+  w.st2 = (int32_t*)take(pp * 4);
+  w.D3 = (double*)take(pp * nn * 8);
+  w.I3 = (double*)take(pp * 3 * nn * 8);
+  w.ye3 = (double*)take(pp * 8);
+  w.ef3 = (double*)take(pp * 8);
+  w.v3 = (double*)take(pp * 3 * 8);
+  w.iters = (int32_t*)take(pp * nn * 4);
+  w.total = off;
+  return w;
+}
+}  // namespace
+
+size_t nmc_pdars_workspace_bytes(const nmc_model* m, int64_t P) {
+  if (!m || P < 0) return 0;
+  return pdars_layout(m, P, nullptr).total;
+}
+
+int nmc_pdars_step_v(const nmc_model* m, const nmc_solver_params* prm, const nmc_c2p_params* cp, int64_t P,
+                     double dt, const nmc_batch_v_in* in, const nmc_batch_v_out* out, void* ws, size_t ws_bytes,
+                     const nmc_launch* launch, void* stream) {
+  if (!m || !in || !out) return fail(NMC_E_INVALID_ARG, "pdars_step_v: null handle or descriptor");
+  int rc = check_c2p(cp, "pdars_step_v");
+  if (rc) return rc;
+  if (!(dt > 0.0) || !isfinite(dt)) return fail(NMC_E_INVALID_ARG, "pdars_step_v: dt must be positive");
+  if (P < 0 || P > (int64_t(1) << 30)) return fail(NMC_E_INVALID_ARG, "pdars_step_v: P out of range");
+  if (P == 0) return NMC_OK;
+  if (!ws || !aligned256(ws) || ws_bytes < nmc_pdars_workspace_bytes(m, P))
+    return fail(NMC_E_WORKSPACE, "pdars_step_v: workspace must be 256-byte aligned and at least "
+                                 "nmc_pdars_workspace_bytes");
+  if (!in->D0 || !in->I0 || !in->rho11 || !in->ye0 || !in->ef0 || !in->v0 || !in->theta)
+    return fail(NMC_E_INVALID_ARG, "pdars_step_v: null input array");
+  const PdarsWs w = pdars_layout(m, P, (char*)ws);
+  hipStream_t s = (hipStream_t)stream;
+  // stage 2: U^(2*) = U^n (a_21 = 0, no explicit operator), step a_22 dt
+  nmc_batch_v_out o2 = {w.D2, w.I2, w.ye2, w.ef2, w.v2, w.T2, w.no2, w.ni2, w.st2};
+  rc = nmc_solve_batch_v(m, prm, P, kA22 * dt, in, &o2, w.solve, nmc_workspace_bytes(m, P), launch, stream);
+  if (rc) return rc;
+  // stage 3: U^(3*) = U^n + dt a_32 C^(2) = U^n + (a_32 / a_22)(U^(2) - U^n), recovered to primitive moments
+  nmc::PdarsArgs a;
+  memset(&a, 0, sizeof(a));
+  a.P = P;
+  a.ns = m->host.ns;
+  a.nq = m->host.nq;
+  a.w = kA32 / kA22;
+  a.rho11_min = m->host.rho11_min;
+  a.rho11 = in->rho11;
+  a.D0 = in->D0;
+  a.I0 = in->I0;
+  a.ye0 = in->ye0;
+  a.ef0 = in->ef0;
+  a.v0 = in->v0;
+  a.D2 = w.D2;
+  a.I2 = w.I2;
+  a.ye2 = w.ye2;
+  a.ef2 = w.ef2;
+  a.v2 = w.v2;
+  a.D3 = w.D3;
+  a.I3 = w.I3;
+  a.ye3 = w.ye3;
+  a.ef3 = w.ef3;
+  a.v3 = w.v3;
+  a.iters = w.iters;
+  a.mem = cp->mem;
+  a.max_it = cp->max_it;
+  a.tol2 = cp->tol * cp->tol;
+  hipError_t e = nmc::launch_pdars_stage3(a, m->num_cu, s);
+  if (e != hipSuccess) return hip_fail(e, "pdars_step_v: stage-3 input");
+  nmc_batch_v_in i3 = {w.D3, w.I3, in->rho11, w.ye3, w.ef3, w.v3, in->chi0, in->theta};
+  rc = nmc_solve_batch_v(m, prm, P, kA33 * dt, &i3, out, w.solve, nmc_workspace_bytes(m, P), launch, stream);
+  if (rc) return rc;
+  // globally stiffly accurate: the step's result is the stage-3 solution
+  e = nmc::launch_pdars_merge(P, m->host.ns * m->host.nq, w.no2, w.ni2, w.st2, w.iters, out->n_outer, out->n_inner,
+                              out->status, m->num_cu, s);
+  return e == hipSuccess ? NMC_OK : hip_fail(e, "pdars_step_v: merge");
+}
+
 int nmc_solve_batch_adjoint(const nmc_model* m, const nmc_solver_params* prm, int64_t P, double dtau,
                             const nmc_batch_in* in, const nmc_batch_out* fwd, const double* gbar,
                             double* grad_theta, double* grad_pp, void* ws, size_t ws_bytes, void* stream) {

@@ -1,0 +1,31 @@
+// Minerbo closure of the O(v) two-moment model (Eqs. eddingtonFactorMinerbo,
+// eddingtonTensor), shared by the O(v) solve and the primitive recovery.
+#pragma once
+
+#include "nmc_wave.h"
+
+namespace nmc {
+
+// Minerbo closure at one node: v.I and (v^i K_ij)_j with K_ij = k_ij D,
+// k_ij = ((1 - psi) delta_ij + (3 psi - 1) n_i n_j) / 2, n = I / |I|, psi the
+// polynomial Eddington factor of the flux factor h = |I| / D, taken as 0
+// without flux and limited to [0, 1] (1 when D <= 0 carries a flux).
+__device__ __forceinline__ void closure_terms(double D, const double (&I)[3], const double (&v)[3], double& vI,
+                                              double (&vK)[3]) {
+  const double Imag = sqrt(I[0] * I[0] + I[1] * I[1] + I[2] * I[2]);
+  double h = 0.0;
+  // Imag < D keeps D normal where its reciprocal is taken (a nonzero Imag is
+  // at least ~1e-162: its components' squares underflow below that)
+  if (Imag > 0.0) h = Imag < D ? Imag * rcp_nr(D) : 1.0;
+  const double psi = 1.0 / 3.0 + (2.0 / 15.0) * (3.0 - h + 3.0 * h * h) * h * h;
+  const double a = 0.5 * (1.0 - psi), b = 0.5 * (3.0 * psi - 1.0);
+  const double rI = Imag > 0.0 ? rcp_nr(Imag) : 0.0;
+  const double n0 = I[0] * rI, n1 = I[1] * rI, n2 = I[2] * rI;
+  const double bvn = b * (v[0] * n0 + v[1] * n1 + v[2] * n2);
+  vI = v[0] * I[0] + v[1] * I[1] + v[2] * I[2];
+  vK[0] = D * (a * v[0] + bvn * n0);
+  vK[1] = D * (a * v[1] + bvn * n1);
+  vK[2] = D * (a * v[2] + bvn * n2);
+}
+
+}  // namespace nmc

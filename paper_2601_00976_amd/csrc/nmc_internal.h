@@ -76,6 +76,20 @@ struct FwdVArgs {
   int chunk;
 };
 
+// the stage-3 input of a PD-ARS step (see nmc_primitive.hip)
+struct PdarsArgs {
+  int64_t P;
+  int ns, nq;
+  double w;          // a_32 / a_22: weight of stage 2 in U^(3*)
+  double rho11_min;  // coupling density
+  const double *rho11, *D0, *I0, *ye0, *ef0, *v0;  // the step's initial state
+  const double *D2, *I2, *ye2, *ef2, *v2;          // stage-2 solution
+  double *D3, *I3, *ye3, *ef3, *v3;                // stage-3 initial state
+  int32_t* iters;    // recovery iterations per (point, species, node)
+  int mem, max_it;   // recovery: Anderson memory and cap
+  double tol2;       // recovery: squared relative tolerance
+};
+
 struct AdjArgs {
   const DevModel* mdl;
   int64_t P;
@@ -97,6 +111,12 @@ hipError_t launch_forward_pair(const FwdArgs& a, int ns, bool coupled, const nmc
 hipError_t launch_forward_v(const FwdVArgs& a, int ns, bool coupled, bool phi1, const nmc_launch& L, int num_cu,
                             hipStream_t s);
 hipError_t launch_reset_counter(int* counter, hipStream_t s);
+hipError_t launch_c2p(int64_t P, int ns, int nq, const double* N, const double* G, const double* v, int mem,
+                      double tol, int max_it, double* D, double* I, int32_t* iters, int num_cu, hipStream_t s);
+hipError_t launch_pdars_stage3(const PdarsArgs& a, int num_cu, hipStream_t s);
+hipError_t launch_pdars_merge(int64_t P, int nn, const int32_t* no2, const int32_t* ni2, const int32_t* st2,
+                              const int32_t* iters, int32_t* n_outer, int32_t* n_inner, int32_t* status, int num_cu,
+                              hipStream_t s);
 // FP64 FMA throughput probe (measurement only)
 hipError_t launch_probe_fma(int64_t waves, int iters, double* out, hipStream_t s);
 hipError_t launch_init_state(const DevModel* mdl, int ns, int nq, int64_t P, const double* T, const double* mu,

@@ -28,7 +28,9 @@ SPACING_LOG, SPACING_ZOOM = 0, 1
 EXPORTED = (
     "nmc_model_desc_default", "nmc_solver_params_default", "nmc_grid_create", "nmc_grid_query",
     "nmc_grid_destroy", "nmc_model_create", "nmc_model_destroy", "nmc_workspace_bytes", "nmc_kernel_store_bytes",
-    "nmc_solve_batch", "nmc_solve_batch_noalloc", "nmc_solve_batch_v", "nmc_solve_batch_adjoint", "nmc_init_state", "nmc_probe_fma_f64", "nmc_error_string",
+    "nmc_solve_batch", "nmc_solve_batch_noalloc", "nmc_solve_batch_v", "nmc_solve_batch_adjoint",
+    "nmc_c2p_params_default", "nmc_primitive_recovery", "nmc_pdars_workspace_bytes", "nmc_pdars_step_v",
+    "nmc_init_state", "nmc_probe_fma_f64", "nmc_error_string",
     "nmc_last_error",
 )
 
@@ -75,6 +77,10 @@ class BatchVOut(C.Structure):
     _fields_ = [(n, C.c_void_p) for n in ("D", "I", "ye", "ef", "v", "T", "n_outer", "n_inner", "status")]
 
 
+class C2pParams(C.Structure):
+    _fields_ = [("mem", C.c_int), ("tol", C.c_double), ("max_it", C.c_int)]
+
+
 class Launch(C.Structure):
     _fields_ = [("blocks_per_cu", C.c_int), ("chunk", C.c_int), ("persistent", C.c_int), ("kernel_store", C.c_int)]
 
@@ -109,6 +115,14 @@ def lib():
                                               C.POINTER(BatchOut), C.POINTER(Launch), vp]
         L.nmc_solve_batch_v.argtypes = [vp, C.POINTER(SolverParams), C.c_int64, C.c_double, C.POINTER(BatchVIn),
                                         C.POINTER(BatchVOut), vp, C.c_size_t, C.POINTER(Launch), vp]
+        L.nmc_c2p_params_default.argtypes = [C.POINTER(C2pParams)]
+        L.nmc_c2p_params_default.restype = None
+        L.nmc_primitive_recovery.argtypes = [vp, C.POINTER(C2pParams), C.c_int64, vp, vp, vp, vp, vp, vp, vp]
+        L.nmc_pdars_workspace_bytes.argtypes = [vp, C.c_int64]
+        L.nmc_pdars_workspace_bytes.restype = C.c_size_t
+        L.nmc_pdars_step_v.argtypes = [vp, C.POINTER(SolverParams), C.POINTER(C2pParams), C.c_int64, C.c_double,
+                                       C.POINTER(BatchVIn), C.POINTER(BatchVOut), vp, C.c_size_t, C.POINTER(Launch),
+                                       vp]
         L.nmc_solve_batch_adjoint.argtypes = [vp, C.POINTER(SolverParams), C.c_int64, C.c_double, C.POINTER(BatchIn),
                                               C.POINTER(BatchOut), vp, vp, vp, vp, C.c_size_t, vp]
         L.nmc_init_state.argtypes = [vp, C.c_int64, vp, vp, vp, vp, vp, vp, C.c_double, C.c_double, C.c_double,
@@ -120,7 +134,7 @@ def lib():
         L.nmc_last_error.restype = C.c_char_p
         for f in ("nmc_grid_create", "nmc_grid_query", "nmc_grid_destroy", "nmc_model_create", "nmc_model_destroy",
                   "nmc_solve_batch", "nmc_solve_batch_noalloc", "nmc_solve_batch_v", "nmc_solve_batch_adjoint", "nmc_init_state",
-                  "nmc_probe_fma_f64"):
+                  "nmc_primitive_recovery", "nmc_pdars_step_v", "nmc_probe_fma_f64"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib

@@ -252,6 +252,75 @@ def solve_v(model: Model, params: Params, dtau: float, D0, I0, rho11, ye0, ef0, 
     return out
 
 
+@dataclass
+class C2pParams:
+    """Primitive-moment recovery: Anderson memory, relative tolerance, cap."""
+    mem: int = 3
+    tol: float = 1e-8
+    max_it: int = 100
+
+    def c(self):
+        return N.C2pParams(self.mem, self.tol, self.max_it)
+
+
+def primitive_recovery(model: Model, Nc, G, v, params: C2pParams | None = None, stream=None):
+    """Primitive moments (D (P, ns, nq), I (P, ns, 3, nq)) of conserved ones
+    Nc (P, ns, nq), G (P, ns, 3, nq) at velocity v (P, 3), with the iteration
+    counts (P, ns, nq) int32 (-1 at the cap, -2 non-finite).  Not synchronized."""
+    P = Nc.shape[0]
+    ns, nq = model.ns, model.nq
+    _req(Nc, "N", (P, ns, nq))
+    _req(G, "G", (P, ns, 3, nq))
+    _req(v, "v", (P, 3))
+    D = torch.empty_like(Nc)
+    I = torch.empty_like(G)
+    it = torch.empty(P, ns, nq, dtype=torch.int32, device=Nc.device)
+    pc = (params or C2pParams()).c()
+    N.check(N.lib().nmc_primitive_recovery(model._h, C.byref(pc), P, Nc.data_ptr(), G.data_ptr(), v.data_ptr(),
+                                           D.data_ptr(), I.data_ptr(), it.data_ptr(), _stream_handle(stream)))
+    return D, I, it
+
+
+class PdarsWorkspace:
+    """Device workspace of ``pdars_step_v`` (allocated once, reused)."""
+
+    def __init__(self, model: Model, P: int, device="cuda"):
+        nb = max(int(N.lib().nmc_pdars_workspace_bytes(model._h, P)), 256)
+        self.buf = torch.empty(nb + 256, dtype=torch.uint8, device=device)
+        self.ptr = self.buf.data_ptr() + (-self.buf.data_ptr()) % 256
+        self.nbytes = nb
+
+
+def pdars_step_v(model: Model, params: Params, dt: float, D0, I0, rho11, ye0, ef0, v0, theta, chi0=None, out=None,
+                 c2p: C2pParams | None = None, workspace: PdarsWorkspace | None = None,
+                 launch: LaunchConfig | None = None, stream=None):
+    """One PD-ARS IMEX step of the coupling (O(v) form): two solves (dt,
+    dt/2) with the stage combination in conserved moments and primitive
+    recovery between them.  Arguments as for ``solve_v``; returns the output
+    dict (not synchronized)."""
+    P = D0.shape[0]
+    ns, nq = model.ns, model.nq
+    _req(D0, "D0", (P, ns, nq))
+    _req(I0, "I0", (P, ns, 3, nq))
+    for n, t in (("rho11", rho11), ("ye0", ye0), ("ef0", ef0)):
+        _req(t, n, (P,))
+    _req(v0, "v0", (P, 3))
+    _req(theta, "theta", (nq + 2,))
+    if chi0 is not None:
+        _req(chi0, "chi0", (P,))
+    if out is None:
+        out = alloc_outputs_v(model, P, D0.device)
+    bi = N.BatchVIn(*[None if t is None else t.data_ptr() for t in (D0, I0, rho11, ye0, ef0, v0, chi0, theta)])
+    bo = N.BatchVOut(*[out[n].data_ptr() for n in ("D", "I", "ye", "ef", "v", "T", "n_outer", "n_inner", "status")])
+    if workspace is None:
+        workspace = PdarsWorkspace(model, P, D0.device)
+    pc, cc, lc = params.c(), (c2p or C2pParams()).c(), (launch or LaunchConfig(chunk=1)).c()
+    N.check(N.lib().nmc_pdars_step_v(model._h, C.byref(pc), C.byref(cc), P, float(dt), C.byref(bi), C.byref(bo),
+                                     C.c_void_p(workspace.ptr), workspace.nbytes, C.byref(lc),
+                                     _stream_handle(stream)))
+    return out
+
+
 def adjoint(model: Model, dtau: float, rho11, theta, fwd, gbar, chi0=None, grad_theta=None, per_point=False,
             workspace: Workspace | None = None, stream=None, params: Params | None = None):
     """Enqueue the implicit-function-theorem adjoint of a converged forward
