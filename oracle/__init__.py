@@ -48,6 +48,8 @@ class _Model(C.Structure):
         ("mu_b", C.c_double), ("mu_t0", C.c_double),
         ("kcoup", C.c_double), ("rho11_min", C.c_double),
         ("phi1_nes", C.c_double), ("phi1_pair", C.c_double),
+        ("fd_projection", C.c_int), ("deq_min", C.c_double), ("deq_max", C.c_double),
+        ("edges", C.c_double * (MAX_NQ // 2 + 1)),
     ]
 
 
@@ -71,7 +73,7 @@ def lib():
         dp = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
         ip = np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS")
         vp = C.c_void_p
-        L.ora_grid_loguniform.argtypes = [C.c_int, C.c_double, C.c_double, dp, dp, dp]
+        L.ora_grid_loguniform.argtypes = [C.c_int, C.c_double, C.c_double, dp, dp, dp, dp]
         L.ora_grid_zoom.argtypes = [C.c_int, C.c_double, C.c_double, dp, dp, dp, dp]
         L.ora_model_defaults.argtypes = [C.POINTER(_Model)]
         for f in ("ora_fermi_dirac", "ora_fermi_dirac_complement"):
@@ -111,6 +113,10 @@ def lib():
         L.ora_pdars_step_v.argtypes = [C.POINTER(_Model), C.POINTER(_Params), dp, C.c_long, C.c_double,
                                        dp, dp, dp, dp, dp, dp, vp, C.c_int, C.c_double, C.c_int,
                                        dp, dp, dp, dp, dp, dp, ip, ip, ip, C.c_int]
+        L.ora_gauss_legendre.argtypes = [C.c_int, dp, dp]
+        L.ora_gauss_legendre.restype = C.c_int
+        L.ora_fd_projection.argtypes = [C.POINTER(_Model), C.c_double, C.c_double, dp, dp, dp]
+        L.ora_kernels_odds.argtypes = [C.POINTER(_Model), dp, C.c_double, C.c_double, dp, dp, dp, dp, dp]
         L.ora_phi1_terms.argtypes = [C.POINTER(_Model), dp, C.c_double, C.c_double, dp, dp, dp, dp]
         L.ora_solve_batch_v.argtypes = [C.POINTER(_Model), C.POINTER(_Params), dp, C.c_long, C.c_double,
                                         dp, dp, dp, dp, dp, dp, vp,
@@ -130,12 +136,12 @@ def _f64(a):
 # ---------------------------------------------------------------------------
 # grids
 
-def grid_loguniform(n_elem: int, eps_lo: float = 1.0, eps_hi: float = 300.0):
+def grid_loguniform(n_elem: int, eps_lo: float = 1.0, eps_hi: float = 300.0, with_edges: bool = False):
     nq = 2 * n_elem
-    eps, w2, w3 = np.zeros(nq), np.zeros(nq), np.zeros(nq)
-    if lib().ora_grid_loguniform(n_elem, eps_lo, eps_hi, eps, w2, w3) != 0:
+    edges, eps, w2, w3 = np.zeros(n_elem + 1), np.zeros(nq), np.zeros(nq), np.zeros(nq)
+    if lib().ora_grid_loguniform(n_elem, eps_lo, eps_hi, edges, eps, w2, w3) != 0:
         raise ValueError("bad grid")
-    return eps, w2, w3
+    return (edges, eps, w2, w3) if with_edges else (eps, w2, w3)
 
 
 def grid_zoom(n_elem: int, zoom: float, width: float = 300.0):
@@ -157,14 +163,18 @@ class Model:
     species: tuple = (NU_E, NU_E_BAR, NU_X)
     flags: int = ALL_PHYSICS
     overrides: dict = field(default_factory=dict)
+    zoom: float | None = None  # geometric grid of Table energyGrids on [0, eps_hi]
 
     def __post_init__(self):
         m = _Model()
         lib().ora_model_defaults(C.byref(m))
-        eps, w2, w3 = grid_loguniform(self.n_elem, self.eps_lo, self.eps_hi)
-        self.set_grid(eps, w2, w3, m)
+        if self.zoom:
+            edges, eps, w2, w3 = grid_zoom(self.n_elem, self.zoom, self.eps_hi)
+        else:
+            edges, eps, w2, w3 = grid_loguniform(self.n_elem, self.eps_lo, self.eps_hi, with_edges=True)
+        self.set_grid(edges, eps, w2, w3, m)
 
-    def set_grid(self, eps, w2, w3, m=None):
+    def set_grid(self, edges, eps, w2, w3, m=None):
         m = m if m is not None else self.c
         m.nq = len(eps)
         m.ns = len(self.species)
@@ -172,6 +182,8 @@ class Model:
             m.species[i] = s
         for i in range(len(eps)):
             m.eps[i], m.w2[i], m.w3[i] = eps[i], w2[i], w3[i]
+        for i in range(len(edges)):
+            m.edges[i] = edges[i]
         m.flags = self.flags
         for k, v in self.overrides.items():
             setattr(m, k, v)
@@ -196,6 +208,10 @@ class Model:
     @property
     def w3(self):
         return np.array(self.c.w3[: self.nq])
+
+    @property
+    def edges(self):
+        return np.array(self.c.edges[: self.nq // 2 + 1])
 
     def ref(self):
         return C.byref(self.c)
@@ -414,3 +430,30 @@ def pdars_step_v(model: Model, params: Params, theta, dt, D0, I0, rho11, ye0, ef
         raise ValueError("oracle rejected the arguments")
     return dict(D=D.reshape(P, model.ns, model.nq), I=I.reshape(P, model.ns, 3, model.nq), ye=ye, ef=ef,
                 v=v.reshape(P, 3), T=T, n_outer=no, n_inner=ni, status=st)
+
+
+def gauss_legendre(n: int):
+    """Gauss-Legendre rule with n points on (-1, 1)."""
+    x, w = np.zeros(n), np.zeros(n)
+    if lib().ora_gauss_legendre(n, x, w) != 0:
+        raise ValueError("bad rule size")
+    return x, w
+
+
+def fd_projection(model: Model, T, mu):
+    """Nodal values of the weighted L2 projection of f(eps; mu, T) per energy
+    element before the bound-enforcing limiter, after it, and the limited
+    complement 1 - D."""
+    dt, dl, cl = np.zeros(model.nq), np.zeros(model.nq), np.zeros(model.nq)
+    lib().ora_fd_projection(model.ref(), T, mu, dt, dl, cl)
+    return dt, dl, cl
+
+
+def kernels_odds(model: Model, theta, rho11, T, odds):
+    """Kernels with detailed balance for equilibrium odds (ns, nq):
+    phi_in, phi_out, phi_pro (ns, nq, nq), phi_ann (nq, nq)."""
+    ns, nq = model.ns, model.nq
+    pin, pout, ppro = np.zeros(ns * nq * nq), np.zeros(ns * nq * nq), np.zeros(ns * nq * nq)
+    pann = np.zeros(nq * nq)
+    lib().ora_kernels_odds(model.ref(), _f64(theta), rho11, T, _f64(odds).ravel(), pin, pout, ppro, pann)
+    return (pin.reshape(ns, nq, nq), pout.reshape(ns, nq, nq), ppro.reshape(ns, nq, nq), pann.reshape(nq, nq))

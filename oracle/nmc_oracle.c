@@ -65,10 +65,10 @@ static void fill_nodes(int n_elem, const double* edges, double* eps, double* w2,
   }
 }
 
-int ora_grid_loguniform(int n_elem, double eps_lo, double eps_hi, double* eps, double* w2, double* w3) {
+int ora_grid_loguniform(int n_elem, double eps_lo, double eps_hi, double* edges, double* eps, double* w2,
+                        double* w3) {
   /* geometric element edges eps_lo * (eps_hi/eps_lo)^(e/n_elem) */
   if (n_elem < 1 || 2 * n_elem > ORA_MAX_NQ || !(eps_lo > 0) || !(eps_hi > eps_lo)) return -1;
-  double edges[ORA_MAX_NQ + 1];
   for (int e = 0; e <= n_elem; ++e) edges[e] = eps_lo * pow(eps_hi / eps_lo, (double)e / n_elem);
   edges[n_elem] = eps_hi;
   fill_nodes(n_elem, edges, eps, w2, w3);
@@ -111,6 +111,9 @@ void ora_model_defaults(ora_model* m) {
     m->kcoup = 4.0 * pi / (hc * hc * hc) * m_u / 1.0e11;
   }
   m->rho11_min = 1.0e-4; /* 1e7 g/cm^3 */
+  m->fd_projection = 0;
+  m->deq_min = 1.0e-150;
+  m->deq_max = 1.0 - 1.0e-12;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -200,6 +203,174 @@ void ora_kernels(const ora_model* m, const double* theta, double rho11, double T
   kernels_unit(m, T, a_nes, a_pair, phi_in, phi_out, phi_pro, phi_ann);
 }
 
+/* ------------------------------------------------------------------------ */
+/* Equilibrium by projection (Sec. 3.5.2, Eq. fermiDiracProjection): on every
+ * energy element the linear polynomial D~ with
+ *   int_K D~ l_a eps^2 deps = int_K f l_a eps^2 deps   (a = 1, 2),
+ * l_a the Lagrange basis on the element's two Legendre-Gauss nodes, followed by
+ * the bound-enforcing limiter (Zhang & Shu): D = Dbar + theta (D~ - Dbar) with
+ * Dbar the eps^2-weighted element average and the largest theta in [0, 1]
+ * that keeps D in [D_min, D_max] at the nodes and at both element edges.
+ * The complement 1 - D is projected and limited alongside from 1 - f, so
+ * that it keeps its relative accuracy where D is close to one. */
+
+int ora_gauss_legendre(int n, double* x, double* w) {
+  const double pi = 3.14159265358979323846;
+  if (n < 1 || n > 128) return -1;
+  for (int i = 0; i < n; ++i) {
+    /* Newton on P_n(z) from the usual cosine guess for its i-th largest root;
+     * P_n and P_{n-1} by the three-term recurrence */
+    double z = cos(pi * (i + 0.75) / (n + 0.5)), pn = 0.0, pm = 0.0;
+    for (int it = 0; it < 100; ++it) {
+      pm = 1.0;
+      pn = z;
+      for (int k = 2; k <= n; ++k) {
+        double nx = ((2.0 * k - 1.0) * z * pn - (k - 1.0) * pm) / k;
+        pm = pn;
+        pn = nx;
+      }
+      double dz = pn / (n * (z * pn - pm) / (z * z - 1.0));
+      z -= dz;
+      if (fabs(dz) <= 1e-16) break;
+    }
+    pm = 1.0;
+    pn = z;
+    for (int k = 2; k <= n; ++k) {
+      double nx = ((2.0 * k - 1.0) * z * pn - (k - 1.0) * pm) / k;
+      pm = pn;
+      pn = nx;
+    }
+    double dp = n * (z * pn - pm) / (z * z - 1.0);
+    x[n - 1 - i] = z;
+    w[n - 1 - i] = 2.0 / ((1.0 - z * z) * dp * dp);
+  }
+  return 0;
+}
+
+/* int_a^b eps^2 l_k(eps) g(eps) deps for k = 1, 2, with g = f (comp = 0) or
+ * g = 1 - f (comp = 1): composite 16-point Legendre-Gauss rule on pieces no
+ * wider than 2T (the Fermi-Dirac function is analytic within pi T of the real
+ * axis, so each piece converges to rounding) */
+static void fd_moments(double a, double b, double e1, double e2, double mu, double T, int comp,
+                       const double* gx, const double* gw, double* out) {
+  out[0] = out[1] = 0.0;
+  if (!(b > a)) return;
+  int npc = (int)ceil((b - a) / (2.0 * T));
+  if (npc < 1) npc = 1;
+  double h = (b - a) / npc;
+  for (int j = 0; j < npc; ++j) {
+    double lo = a + j * h, hi = (j == npc - 1) ? b : a + (j + 1) * h;
+    double c = 0.5 * (lo + hi), r = 0.5 * (hi - lo);
+    for (int k = 0; k < 16; ++k) {
+      double e = c + r * gx[k];
+      double g = comp ? ora_fermi_dirac_complement(e, mu, T) : ora_fermi_dirac(e, mu, T);
+      double wt = r * gw[k] * e * e * g;
+      out[0] += wt * (e - e2) / (e1 - e2);
+      out[1] += wt * (e - e1) / (e2 - e1);
+    }
+  }
+}
+
+static void fd_project(const ora_model* m, double T, double mu, double* dtil, double* ctil, double* dlim,
+                       double* clim) {
+  double gx[16], gw[16], x3[3], w3[3];
+  ora_gauss_legendre(16, gx, gw);
+  ora_gauss_legendre(3, x3, w3);
+  const double dmin = m->deq_min, dmax = m->deq_max, cmin = 1.0 - m->deq_max;
+  for (int el = 0; el < m->nq / 2; ++el) {
+    double lo = m->edges[el], hi = m->edges[el + 1];
+    double e1 = m->eps[2 * el], e2 = m->eps[2 * el + 1];
+    /* mass matrix int_K l_a l_b eps^2 (degree 4: the 3-point rule is exact) */
+    double M11 = 0.0, M12 = 0.0, M22 = 0.0;
+    for (int k = 0; k < 3; ++k) {
+      double e = 0.5 * (lo + hi) + 0.5 * (hi - lo) * x3[k], wt = 0.5 * (hi - lo) * w3[k] * e * e;
+      double l1 = (e - e2) / (e1 - e2), l2 = (e - e1) / (e2 - e1);
+      M11 += wt * l1 * l1;
+      M12 += wt * l1 * l2;
+      M22 += wt * l2 * l2;
+    }
+    /* right-hand sides; beyond 100 T past the chemical potential the
+     * integrand is below exp(-100) of its value there and is dropped */
+    double bf[2], bc[2];
+    fd_moments(lo, fmin(hi, fmax(lo, mu) + 100.0 * T), e1, e2, mu, T, 0, gx, gw, bf);
+    fd_moments(fmax(lo, fmin(hi, mu) - 100.0 * T), hi, e1, e2, mu, T, 1, gx, gw, bc);
+    double det = M11 * M22 - M12 * M12;
+    double d[2] = {(M22 * bf[0] - M12 * bf[1]) / det, (M11 * bf[1] - M12 * bf[0]) / det};
+    double cc[2] = {(M22 * bc[0] - M12 * bc[1]) / det, (M11 * bc[1] - M12 * bc[0]) / det};
+    double m0 = (hi * hi * hi - lo * lo * lo) / 3.0;
+    double dbar = (bf[0] + bf[1]) / m0, cbar = (bc[0] + bc[1]) / m0;
+    /* values at the nodes and at the element edges */
+    double lo1 = (lo - e2) / (e1 - e2), lo2 = (lo - e1) / (e2 - e1);
+    double hi1 = (hi - e2) / (e1 - e2), hi2 = (hi - e1) / (e2 - e1);
+    double mD = fmin(fmin(d[0], d[1]), fmin(d[0] * lo1 + d[1] * lo2, d[0] * hi1 + d[1] * hi2));
+    double mC = fmin(fmin(cc[0], cc[1]), fmin(cc[0] * lo1 + cc[1] * lo2, cc[0] * hi1 + cc[1] * hi2));
+    for (int a = 0; a < 2; ++a) {
+      if (dtil) dtil[2 * el + a] = d[a];
+      if (ctil) ctil[2 * el + a] = cc[a];
+    }
+    double th = 1.0, Dn[2], Cn[2];
+    if (dbar < dmin) {
+      /* the element average itself lies below the bound: the element takes
+       * the bound */
+      Dn[0] = Dn[1] = dmin;
+      Cn[0] = Cn[1] = 1.0 - dmin;
+    } else if (cbar < cmin) {
+      Dn[0] = Dn[1] = dmax;
+      Cn[0] = Cn[1] = cmin;
+    } else {
+      if (mD < dmin) th = fmin(th, (dbar - dmin) / (dbar - mD));
+      if (mC < cmin) th = fmin(th, (cbar - cmin) / (cbar - mC));
+      for (int a = 0; a < 2; ++a) {
+        Dn[a] = dbar + th * (d[a] - dbar);
+        Cn[a] = cbar + th * (cc[a] - cbar);
+      }
+    }
+    for (int a = 0; a < 2; ++a) {
+      if (dlim) dlim[2 * el + a] = Dn[a];
+      if (clim) clim[2 * el + a] = Cn[a];
+    }
+  }
+}
+
+void ora_fd_projection(const ora_model* m, double T, double mu, double* dtil, double* dlim, double* clim) {
+  fd_project(m, T, mu, dtil, NULL, dlim, clim);
+}
+
+/* Kernels of one species with detailed balance for its equilibrium odds o and
+ * its pair partner's ob (Eqs. detailedBalanceNES, detailedBalancePair) and
+ * in-out invariance (Eqs. inOutInvarianceNES, inOutInvariancePair): the
+ * symmetric S splits as Phi_in = S sqrt(o_q / o_p), Phi_out = S sqrt(o_p / o_q),
+ * and Phi_pro = o_q ob_p Phi_ann.  With pointwise equilibrium, o = exp((mu -
+ * eps)/T), these are the kernels above. */
+static void kernels_odds_species(const ora_model* m, double T, double a_nes, double a_pair, const double* o,
+                                 const double* ob, double* phi_in, double* phi_out, double* phi_pro,
+                                 double* phi_ann) {
+  int nq = m->nq;
+  for (int q = 0; q < nq; ++q) {
+    for (int p = 0; p < nq; ++p) {
+      double eq = m->eps[q], ep = m->eps[p];
+      double base = eq * ep * exp(-fabs(eq - ep) / T);
+      double S = a_nes * base;
+      phi_in[q * nq + p] = S * sqrt(o[q] / o[p]);
+      phi_out[q * nq + p] = S * sqrt(o[p] / o[q]);
+      phi_ann[q * nq + p] = a_pair * base;
+      phi_pro[q * nq + p] = ob ? o[q] * ob[p] * (a_pair * base) : 0.0;
+    }
+  }
+}
+
+void ora_kernels_odds(const ora_model* m, const double* theta, double rho11, double T, const double* odds,
+                      double* phi_in, double* phi_out, double* phi_pro, double* phi_ann) {
+  int nq = m->nq;
+  double a_nes = (m->flags & ORA_NES) ? theta[nq] * rho11 : 0.0;
+  double a_pair = (m->flags & ORA_PAIR) ? theta[nq + 1] * rho11 : 0.0;
+  for (int s = 0; s < m->ns; ++s) {
+    int sb = partner_index(m, s);
+    kernels_odds_species(m, T, a_nes, a_pair, odds + s * nq, sb >= 0 ? odds + sb * nq : NULL,
+                         phi_in + s * nq * nq, phi_out + s * nq * nq, phi_pro + s * nq * nq, phi_ann);
+  }
+}
+
 /* per-point opacity state, recomputed once per outer iteration
  * (ComputeOpacities in Algorithm neutrinoMatterCoupling) */
 typedef struct {
@@ -207,9 +378,11 @@ typedef struct {
   double deq[ORA_MAX_NS * ORA_MAX_NQ];
   double chia[ORA_MAX_NS * ORA_MAX_NQ];
   double sig[ORA_MAX_NS * ORA_MAX_NQ];
-  double phi_in[ORA_MAX_NQ * ORA_MAX_NQ];
-  double phi_out[ORA_MAX_NQ * ORA_MAX_NQ];
-  double phi_pro[ORA_MAX_NQ * ORA_MAX_NQ];
+  /* per species (ns, nq, nq): with the projected equilibrium the detailed
+   * balance factors differ between species */
+  double phi_in[ORA_MAX_NS * ORA_MAX_NQ * ORA_MAX_NQ];
+  double phi_out[ORA_MAX_NS * ORA_MAX_NQ * ORA_MAX_NQ];
+  double phi_pro[ORA_MAX_NS * ORA_MAX_NQ * ORA_MAX_NQ];
   double phi_ann[ORA_MAX_NQ * ORA_MAX_NQ];
 } opac;
 
@@ -218,18 +391,34 @@ static void compute_opacities(const ora_model* m, const double* theta, double rh
   int nq = m->nq, ns = m->ns;
   o->T = T;
   o->mu = mu;
+  double odds[ORA_MAX_NS * ORA_MAX_NQ];
   for (int s = 0; s < ns; ++s) {
     int id = m->species[s];
     double mus = sp_musign(id) * mu;
+    if (m->fd_projection) {
+      double comp[ORA_MAX_NQ];
+      fd_project(m, T, mus, NULL, NULL, o->deq + s * nq, comp);
+      for (int q = 0; q < nq; ++q) odds[s * nq + q] = o->deq[s * nq + q] / comp[q];
+    }
     for (int q = 0; q < nq; ++q) {
       double shape = chi0 * pow(m->eps[q] / m->eps_ref, m->chi_power);
       /* Eq. emissivityEmAbNodal: eta^EmAb = chi^EmAb * D^Eq */
-      o->deq[s * nq + q] = ora_fermi_dirac(m->eps[q], mus, T);
+      if (!m->fd_projection) o->deq[s * nq + q] = ora_fermi_dirac(m->eps[q], mus, T);
       o->chia[s * nq + q] = ((m->flags & ORA_EMAB) && sp_emab(id)) ? theta[q] * shape : 0.0;
       o->sig[s * nq + q] = (m->flags & ORA_ISO) ? m->sigma_ratio * shape : 0.0;
     }
   }
-  ora_kernels(m, theta, rho11, T, o->phi_in, o->phi_out, o->phi_pro, o->phi_ann);
+  if (m->fd_projection) {
+    ora_kernels_odds(m, theta, rho11, T, odds, o->phi_in, o->phi_out, o->phi_pro, o->phi_ann);
+  } else {
+    /* pointwise equilibrium: one set of kernels serves every species */
+    ora_kernels(m, theta, rho11, T, o->phi_in, o->phi_out, o->phi_pro, o->phi_ann);
+    for (int s = 1; s < ns; ++s) {
+      memcpy(o->phi_in + s * nq * nq, o->phi_in, sizeof(double) * nq * nq);
+      memcpy(o->phi_out + s * nq * nq, o->phi_out, sizeof(double) * nq * nq);
+      memcpy(o->phi_pro + s * nq * nq, o->phi_pro, sizeof(double) * nq * nq);
+    }
+  }
 }
 
 /* Eqs. emissivityNodal, opacityNodal, transportOpacityNodal, nesRatesNodal,
@@ -238,17 +427,19 @@ static void rates(const ora_model* m, const opac* o, const double* D, double* et
   int nq = m->nq, ns = m->ns;
   for (int s = 0; s < ns; ++s) {
     int sb = partner_index(m, s);
+    const double *pin = o->phi_in + s * nq * nq, *pout = o->phi_out + s * nq * nq;
+    const double* ppro = o->phi_pro + s * nq * nq;
     for (int q = 0; q < nq; ++q) {
       double eta_nes = 0.0, out_nes = 0.0, eta_pair = 0.0, ann_pair = 0.0;
       if (m->flags & ORA_NES) {
         for (int p = 0; p < nq; ++p) {
-          eta_nes += m->w2[p] * o->phi_in[q * nq + p] * D[s * nq + p];
-          out_nes += m->w2[p] * o->phi_out[q * nq + p] * (1.0 - D[s * nq + p]);
+          eta_nes += m->w2[p] * pin[q * nq + p] * D[s * nq + p];
+          out_nes += m->w2[p] * pout[q * nq + p] * (1.0 - D[s * nq + p]);
         }
       }
       if ((m->flags & ORA_PAIR) && sb >= 0) {
         for (int p = 0; p < nq; ++p) {
-          eta_pair += m->w2[p] * o->phi_pro[q * nq + p] * (1.0 - D[sb * nq + p]);
+          eta_pair += m->w2[p] * ppro[q * nq + p] * (1.0 - D[sb * nq + p]);
           ann_pair += m->w2[p] * o->phi_ann[q * nq + p] * D[sb * nq + p];
         }
       }
@@ -719,6 +910,7 @@ static void jacobian_core(const ora_model* m, const double* theta, double dtau, 
 
 int ora_jacobian(const ora_model* m, const double* theta, double dtau, double rho11, double chi0,
                  const double* D, double ye, double e, double* J) {
+  if (m->fd_projection) return -2; /* derivatives of the projection: not written out */
   jwork* w = (jwork*)malloc(sizeof(jwork));
   jacobian_core(m, theta, dtau, rho11, chi0, D, ye, e, J, w);
   free(w);
@@ -788,6 +980,7 @@ static void lu_solve(const double* A, int n, const int* piv, double* x, int tran
 int ora_newton(const ora_model* m, const double* theta, double dtau, double rho11, double chi0,
                const double* Dstar, const double* Istar, double ye_star, double e_star,
                double* D, double* I, double* ye, double* e, double tol, int max_it) {
+  if (m->fd_projection) return -2; /* its Jacobian is written for the pointwise equilibrium */
   int nn = m->ns * m->nq, n = nn + 2;
   double* J = (double*)malloc(sizeof(double) * n * n);
   double* R = (double*)malloc(sizeof(double) * (2 * nn + 2));
@@ -842,6 +1035,7 @@ int ora_newton(const ora_model* m, const double* theta, double dtau, double rho1
 int ora_adjoint_batch(const ora_model* m, const double* theta, long P, double dtau, const double* rho11,
                       const double* chi0, const double* D, const double* ye, const double* e,
                       const double* gbar, double* grad_theta, double* grad_pp, int nthreads) {
+  if (m->fd_projection) return -2; /* as ora_jacobian */
   int nq = m->nq, ns = m->ns, nn = ns * nq, n = nn + 2, nt = nq + 2;
   double* gsum = (double*)calloc((size_t)nt, sizeof(double));
   int bad = 0;
@@ -1039,6 +1233,8 @@ static void phi1_terms(const ora_model* m, const opac* o, const double* D, const
   int nq = m->nq, ns = m->ns;
   for (int s = 0; s < ns; ++s) {
     int sb = partner_index(m, s);
+    const double *pin = o->phi_in + s * nq * nq, *pout = o->phi_out + s * nq * nq;
+    const double* ppro = o->phi_pro + s * nq * nq;
     for (int q = 0; q < nq; ++q) {
       double Lin[3] = {0.0, 0.0, 0.0}, Lout[3] = {0.0, 0.0, 0.0};
       double Lpro[3] = {0.0, 0.0, 0.0}, Lann[3] = {0.0, 0.0, 0.0};
@@ -1046,12 +1242,12 @@ static void phi1_terms(const ora_model* m, const opac* o, const double* D, const
         for (int p = 0; p < nq; ++p) {
           if (m->flags & ORA_NES) {
             double Ii = I[(s * 3 + i) * nq + p];
-            Lin[i] += m->w2[p] * (m->phi1_nes * o->phi_in[q * nq + p]) * Ii;
-            Lout[i] += m->w2[p] * (m->phi1_nes * o->phi_out[q * nq + p]) * Ii;
+            Lin[i] += m->w2[p] * (m->phi1_nes * pin[q * nq + p]) * Ii;
+            Lout[i] += m->w2[p] * (m->phi1_nes * pout[q * nq + p]) * Ii;
           }
           if ((m->flags & ORA_PAIR) && sb >= 0) {
             double Ib = I[(sb * 3 + i) * nq + p];
-            Lpro[i] += m->w2[p] * (m->phi1_pair * o->phi_pro[q * nq + p]) * Ib;
+            Lpro[i] += m->w2[p] * (m->phi1_pair * ppro[q * nq + p]) * Ib;
             Lann[i] += m->w2[p] * (m->phi1_pair * o->phi_ann[q * nq + p]) * Ib;
           }
         }

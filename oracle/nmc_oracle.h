@@ -56,6 +56,14 @@ typedef struct {
    * enter the O(v) solve through Eqs. zerothMomentCollisionTerm_NES/_Pair and
    * firstMomentCollisionTerm_NES/_Pair. */
   double phi1_nes, phi1_pair;
+  /* 1: the equilibrium D_eq is the weighted L2 projection of the Fermi-Dirac
+   * distribution onto each energy element with the bound-enforcing limiter
+   * into [deq_min, deq_max] (Eq. fermiDiracProjection), and the NES and pair
+   * kernels obey detailed balance with it (Eqs. detailedBalanceNES,
+   * detailedBalancePair); 0: pointwise nodal values */
+  int fd_projection;
+  double deq_min, deq_max;
+  double edges[ORA_MAX_NQ / 2 + 1]; /* element edges [MeV], nq / 2 + 1 of them */
 } ora_model;
 
 typedef struct {
@@ -64,7 +72,8 @@ typedef struct {
 } ora_params;
 
 /* grids */
-int ora_grid_loguniform(int n_elem, double eps_lo, double eps_hi, double* eps, double* w2, double* w3);
+int ora_grid_loguniform(int n_elem, double eps_lo, double eps_hi, double* edges, double* eps, double* w2,
+                        double* w3);
 int ora_grid_zoom(int n_elem, double zoom, double width, double* edges, double* eps, double* w2, double* w3);
 
 /* model default constants */
@@ -76,6 +85,20 @@ double ora_fermi_dirac_complement(double eps, double mu, double T);
 double ora_eos_energy(const ora_model* m, double T, double ye, double rho11);
 double ora_eos_temperature(const ora_model* m, double e, double ye, double rho11);
 double ora_eos_mu(const ora_model* m, double ye, double T, double rho11);
+
+/* Gauss-Legendre rule with n points on (-1, 1) */
+int ora_gauss_legendre(int n, double* x, double* w);
+/* weighted L2 projection of the Fermi-Dirac distribution f(eps; mu, T) onto
+ * the linear polynomials of every energy element (Eq. fermiDiracProjection):
+ * dtil (nq) the projection's nodal values, dlim (nq) after the
+ * bound-enforcing limiter, clim (nq) the limited complement 1 - D (any may be
+ * NULL) */
+void ora_fd_projection(const ora_model* m, double T, double mu, double* dtil, double* dlim, double* clim);
+/* NES and pair kernels of species s with detailed balance for equilibrium
+ * odds o_s = D_eq / (1 - D_eq) (Eqs. detailedBalanceNES, detailedBalancePair):
+ * odds (ns, nq) -> phi_in, phi_out, phi_pro (ns, nq, nq), phi_ann (nq, nq) */
+void ora_kernels_odds(const ora_model* m, const double* theta, double rho11, double T, const double* odds,
+                      double* phi_in, double* phi_out, double* phi_pro, double* phi_ann);
 
 /* opacities and kernels at (T, mu) for one point */
 void ora_kernels(const ora_model* m, const double* theta, double rho11, double T,
