@@ -327,6 +327,9 @@ def main():
                     help="skip the adjoint-ratio leg (its step-1 forward launches would mix into a kernel profile)")
     ap.add_argument("--all-points", action="store_true",
                     help="solve every point of the profile (no low-density pass-through), down to T ~ 0.07 MeV")
+    ap.add_argument("--fd-projection", action="store_true",
+                    help="equilibrium by projection onto the energy elements with the bound-enforcing limiter "
+                         "(the kernels' detailed balance from its odds) instead of pointwise Fermi-Dirac values")
     ap.add_argument("--chunk", type=int, default=None)
     ap.add_argument("--blocks-per-cu", type=int, default=None)
     ap.add_argument("--workload", choices=sorted(WORKLOADS) + ["profile-v"], default="profile32",
@@ -360,7 +363,13 @@ def main():
     n_elem, P_POINTS, wid, traffic_tag, kernel_label = WORKLOADS[args.workload]
     nq = 2 * n_elem
     grid = S.Grid(n_elem)
-    model = S.Model(grid, rho11_min=0.0) if args.all_points else S.Model(grid)
+    mkw = dict(rho11_min=0.0) if args.all_points else {}
+    if args.fd_projection:
+        assert nq == 32 and args.kernel_store == "chip", "--fd-projection runs in the 32-node two-point kernel"
+        mkw["fd_projection"] = 1
+        traffic_tag += "_proj"
+        kernel_label = "fwd_pair_kernel<3,true,true> (two points per wavefront, projected equilibrium)"
+    model = S.Model(grid, **mkw)
     params = S.Params()
     draws = W.radial_profile(P=P_POINTS, nq=nq, wid=wid)
     t = S.to_device(draws, dev)
@@ -505,6 +514,7 @@ def main():
             "iterations": iteration_summary(n_in, n_out),
             "status_counts": np.bincount(status.ravel(), minlength=5).tolist(),
             "all_points": bool(args.all_points),
+            "fd_projection": bool(args.fd_projection),
         },
         "roofline": {
             "kernel": kernel_label,
@@ -527,9 +537,9 @@ def main():
     fma_peak = S.probe_fma_tflops(dev)
     line["roofline"]["measured_fma_peak"] = fma_peak
     line["roofline"]["frac_of_measured_fma_peak"] = achieved / fma_peak
-    if nq == 32 and not args.no_adjoint and not args.all_points:
+    if nq == 32 and not args.no_adjoint and not args.all_points and not args.fd_projection:
         line["adjoint"] = adjoint_ratio(model, params, theta, D0, I0, t, e0, ws, launch)
-    if not args.no_cpu and args.workload == "profile32":
+    if not args.no_cpu and args.workload == "profile32" and not args.fd_projection:
         threads = int(os.environ.get("OMP_NUM_THREADS") or os.cpu_count() or 1)
         cb = cpu_baseline(args.cpu_repeats, threads, args.all_points)
         # the oracle's own iteration counts priced by the same convention:

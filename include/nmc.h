@@ -122,6 +122,19 @@ typedef struct {
    * solve, with one flux component and no closure, ignores them); each in
    * [-1/3, 1/3], the range that keeps the linear angular kernel non-negative */
   double phi1_nes, phi1_pair;
+  /* equilibrium D^Eq (Sec. 3.5.2).  0 (default): the Fermi-Dirac function at
+   * the nodes.  1: the eps^2-weighted L2 projection of the Fermi-Dirac
+   * distribution onto each energy element (Eq. fermiDiracProjection) with the
+   * bound-enforcing limiter that keeps it in [deq_min, deq_max] at the nodes
+   * and element edges without changing the element average; the NES and pair
+   * kernels then take their detailed-balance factors from its odds D / (1 -
+   * D), per species (Eqs. detailedBalanceNES, detailedBalancePair).  The
+   * projection runs in nmc_solve_batch with 32 nodes and kernel_store
+   * NMC_KERNELS_ON_CHIP or NMC_KERNELS_PAIRED; the O(v) solve, the PD-ARS
+   * step and the adjoint return NMC_E_UNSUPPORTED for it. */
+  int fd_projection;
+  double deq_min;      /* D_min, in [1e-150, 1e-3] (1e-150) */
+  double deq_max;      /* D_max, in [0.999, 1 - 1e-15] (1 - 1e-12) */
 } nmc_model_desc;
 
 typedef struct {

@@ -119,6 +119,9 @@ void nmc_model_desc_default(nmc_model_desc* d) {
   d->hc_mev_cm = 1.239841984e-10;
   d->m_u_g = 1.66053906660e-24;
   d->rho11_min = 1.0e-4;
+  d->fd_projection = 0;
+  d->deq_min = 1.0e-150;
+  d->deq_max = 1.0 - 1.0e-12;
 }
 
 void nmc_solver_params_default(nmc_solver_params* p) {
@@ -276,6 +279,48 @@ int nmc_model_create(const nmc_grid* g, const nmc_model_desc* d, nmc_model** out
     return fail(NMC_E_INVALID_ARG, "model_create: phi1_nes and phi1_pair must lie in [-1/3, 1/3]");
   m.phi1_nes = d->phi1_nes;
   m.phi1_pair = d->phi1_pair;
+  if (d->fd_projection != 0 && d->fd_projection != 1)
+    return fail(NMC_E_INVALID_ARG, "model_create: fd_projection must be 0 or 1");
+  // bounds that keep the odds D / (1 - D), their square roots and the pair
+  // products o o' normal doubles
+  if (!(d->deq_min >= 1e-150) || !(d->deq_min <= 1e-3) || !(d->deq_max >= 0.999) || !(d->deq_max <= 1.0 - 1e-15))
+    return fail(NMC_E_INVALID_ARG, "model_create: need 1e-150 <= deq_min <= 1e-3 and 0.999 <= deq_max <= 1 - 1e-15");
+  m.fd_projection = d->fd_projection;
+  m.deq_min = d->deq_min;
+  m.ceq_min = 1.0 - d->deq_max;
+  // per-node tables of the projection: eps^2 mass matrix of the element's
+  // Lagrange basis by the 3-point Gauss rule (exact for its degree-4
+  // integrands), inverted in closed form
+  for (int e = 0; 2 * e < m.nq; ++e) {
+    const double lo = g->edges[e], hi = g->edges[e + 1];
+    const double e1 = g->eps[2 * e], e2 = g->eps[2 * e + 1];
+    const double c = 0.5 * (lo + hi), r = 0.5 * (hi - lo), x3 = sqrt(0.6);
+    const double gx[3] = {c - r * x3, c, c + r * x3}, gw[3] = {r * 5.0 / 9.0, r * 8.0 / 9.0, r * 5.0 / 9.0};
+    double M11 = 0.0, M12 = 0.0, M22 = 0.0;
+    for (int k = 0; k < 3; ++k) {
+      const double x = gx[k], w = gw[k] * x * x;
+      const double l1 = (x - e2) / (e1 - e2), l2 = (x - e1) / (e2 - e1);
+      M11 += w * l1 * l1;
+      M12 += w * l1 * l2;
+      M22 += w * l2 * l2;
+    }
+    const double det = M11 * M22 - M12 * M12;
+    for (int side = 0; side < 2; ++side) {
+      const int q = 2 * e + side;
+      m.pelo[q] = lo;
+      m.pehi[q] = hi;
+      m.pl[q][0] = 1.0 / (e1 - e2);
+      m.pl[q][1] = -e2 / (e1 - e2);
+      m.pl[q][2] = 1.0 / (e2 - e1);
+      m.pl[q][3] = -e1 / (e2 - e1);
+      m.pinv[q][0] = (side == 0 ? M22 : -M12) / det;
+      m.pinv[q][1] = (side == 0 ? -M12 : M11) / det;
+      m.prm0[q] = 3.0 / (hi * hi * hi - lo * lo * lo);
+      const double eo = side == 0 ? e2 : e1, es = side == 0 ? e1 : e2;
+      m.pedge[q][0] = (lo - eo) / (es - eo);
+      m.pedge[q][1] = (hi - eo) / (es - eo);
+    }
+  }
 
   nmc_model* mm = new (std::nothrow) nmc_model();
   if (!mm) return fail(NMC_E_INVALID_ARG, "model_create: out of host memory");
@@ -360,6 +405,10 @@ static int solve_batch_impl(const char* who, const nmc_model* m, const nmc_solve
     return fail(NMC_E_UNSUPPORTED, "%s: register-resident kernel rows need 32 nodes", who);
   if ((L.kernel_store == NMC_KERNELS_PAIRED || L.kernel_store == NMC_KERNELS_WAVE) && m->host.nq != 32)
     return fail(NMC_E_UNSUPPORTED, "%s: kernel_store %d needs 32 nodes", who, L.kernel_store);
+  if (m->host.fd_projection &&
+      (m->host.nq != 32 || (L.kernel_store != NMC_KERNELS_ON_CHIP && L.kernel_store != NMC_KERNELS_PAIRED)))
+    return fail(NMC_E_UNSUPPORTED, "%s: the projected equilibrium runs in the two-points-per-wave kernel (32 nodes, "
+                "kernel_store ON_CHIP or PAIRED)", who);
   if (L.kernel_store == NMC_KERNELS_HBM) {
     if (m->host.nq != 64 || !(m->host.flags & (NMC_NES | NMC_PAIR)))
       return fail(NMC_E_UNSUPPORTED, "%s: kernels in HBM need 64 nodes and NES or pair physics", who);
@@ -412,7 +461,7 @@ static int solve_batch_impl(const char* who, const nmc_model* m, const nmc_solve
     if (e != hipSuccess) return hip_fail(e, "counter reset");
   }
   const bool coupled = (m->host.flags & (NMC_NES | NMC_PAIR)) != 0;
-  hipError_t e = nmc::launch_forward(a, m->host.nq, m->host.ns, coupled, L, m->num_cu, s);
+  hipError_t e = nmc::launch_forward(a, m->host.nq, m->host.ns, coupled, m->host.fd_projection != 0, L, m->num_cu, s);
   if (e == hipErrorInvalidValue)
     return fail(NMC_E_UNSUPPORTED, "%s: no kernel for nq=%d ns=%d", who, m->host.nq, m->host.ns);
   if (e != hipSuccess) return hip_fail(e, "forward launch");
@@ -455,6 +504,8 @@ int nmc_solve_batch_v(const nmc_model* m, const nmc_solver_params* prm, int64_t 
   if (!(dtau > 0.0) || !isfinite(dtau)) return fail(NMC_E_INVALID_ARG, "solve_batch_v: dtau must be positive");
   if (m->host.nq != 32)
     return fail(NMC_E_UNSUPPORTED, "solve_batch_v: implemented for 32 energy nodes (model has %d)", m->host.nq);
+  if (m->host.fd_projection)
+    return fail(NMC_E_UNSUPPORTED, "solve_batch_v: the projected equilibrium is implemented in nmc_solve_batch only");
   if (P == 0) return NMC_OK;
   if (!in->D0 || !in->I0 || !in->rho11 || !in->ye0 || !in->ef0 || !in->v0 || !in->theta)
     return fail(NMC_E_INVALID_ARG, "solve_batch_v: null input array");
@@ -598,6 +649,8 @@ int nmc_pdars_step_v(const nmc_model* m, const nmc_solver_params* prm, const nmc
                      double dt, const nmc_batch_v_in* in, const nmc_batch_v_out* out, void* ws, size_t ws_bytes,
                      const nmc_launch* launch, void* stream) {
   if (!m || !in || !out) return fail(NMC_E_INVALID_ARG, "pdars_step_v: null handle or descriptor");
+  if (m->host.fd_projection)
+    return fail(NMC_E_UNSUPPORTED, "pdars_step_v: the projected equilibrium is implemented in nmc_solve_batch only");
   int rc = check_c2p(cp, "pdars_step_v");
   if (rc) return rc;
   if (!(dt > 0.0) || !isfinite(dt)) return fail(NMC_E_INVALID_ARG, "pdars_step_v: dt must be positive");
@@ -664,6 +717,8 @@ int nmc_solve_batch_adjoint(const nmc_model* m, const nmc_solver_params* prm, in
   if (!(dtau > 0.0) || !isfinite(dtau)) return fail(NMC_E_INVALID_ARG, "adjoint: dtau must be positive and finite");
   if (!grad_theta) return fail(NMC_E_INVALID_ARG, "adjoint: null grad_theta");
   if (m->host.nq != 32) return fail(NMC_E_UNSUPPORTED, "adjoint: implemented for 32 energy nodes (model has %d)", m->host.nq);
+  if (m->host.fd_projection)
+    return fail(NMC_E_UNSUPPORTED, "adjoint: its Jacobian is written for the pointwise equilibrium");
   if (P == 0) return NMC_OK;
   if (!in->rho11 || !in->theta || !fwd->D || !fwd->ye || !fwd->e || !fwd->status || !fwd->n_outer || !gbar)
     return fail(NMC_E_INVALID_ARG, "adjoint: null array");

@@ -639,11 +639,12 @@ hipError_t launch_reset_counter(int* counter, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_forward(const FwdArgs& a, int nq, int ns, bool coupled, const nmc_launch& L, int num_cu,
-                          hipStream_t s) {
+hipError_t launch_forward(const FwdArgs& a, int nq, int ns, bool coupled, bool proj, const nmc_launch& L,
+                          int num_cu, hipStream_t s) {
   if (nq == 32) {
     if (L.kernel_store == NMC_KERNELS_ON_CHIP || L.kernel_store == NMC_KERNELS_PAIRED)
-      return launch_forward_pair(a, ns, coupled, L, num_cu, s);
+      return launch_forward_pair(a, ns, coupled, proj, L, num_cu, s);
+    if (proj) return hipErrorInvalidValue;
     if (coupled && L.kernel_store == NMC_KERNELS_REGEN) {
       switch (ns) {
         case 1: return launch_fwd_t<1, 32, true, 1>(a, L, num_cu, s);
@@ -670,7 +671,7 @@ hipError_t launch_forward(const FwdArgs& a, int nq, int ns, bool coupled, const 
       }
     }
   }
-  if (nq == 64) return launch_forward64(a, ns, coupled, L, num_cu, s);
+  if (nq == 64 && !proj) return launch_forward64(a, ns, coupled, L, num_cu, s);
   return hipErrorInvalidValue;
 }
 

@@ -30,6 +30,7 @@
 // its state frozen, so no barrier or cross-lane step is ever in divergent
 // control flow; every per-point decision is a per-lane value that is uniform
 // within its half.
+#include "nmc_fdproj.h"
 #include "nmc_wave.h"
 
 namespace nmc {
@@ -46,7 +47,10 @@ struct PairLds {
   ModelLds m;
   SplitExp E[2];                   // per point: exponent splits at its current temperature
   union {
-    double hist[4][2 * NS][kLanes];  // Anderson history per lane and owned moment: Q_prev, F_prev, dQ_old, dF_old
+    struct {
+      double hist[4][2 * NS][kLanes];  // Anderson history per lane and owned moment: Q_prev, F_prev, dQ_old, dF_old
+      double fac[2][NS][kLanes];       // projected equilibrium: 1 / sqrt(o) and o per species (o = D / (1 - D))
+    };
     double tile[2][NQP][NQP];        // per point, signed pair factors: [j][q] = +b if j > q, else -b
   } u;
   struct Pt {                      // per-point state of the outer (matter) loop
@@ -353,7 +357,13 @@ struct ColSym<1> {
   }
 };
 
-template <int NS, bool COUPLED>
+// PROJ: the equilibrium is the projected, limited Fermi-Dirac distribution of
+// every species (Eq. fermiDiracProjection), and the kernels take their
+// detailed-balance factors from its odds o = D / (1 - D) (Eqs.
+// detailedBalanceNES, detailedBalancePair): g = sqrt(o) and h = o of each
+// species replace exp(-e / (2T)) and exp(-e / T) of the pointwise form.  The
+// limiter bounds o, so the symmetric core serves every temperature.
+template <int NS, bool COUPLED, bool PROJ>
 struct PairSolver {
   static constexpr int NQ = NQP;
   static constexpr int KC = (3 * NS + 1) / 2;  // reduction chains of the convergence test
@@ -436,6 +446,13 @@ struct PairSolver {
       const double Tu = run ? T : 1.0, muu = run ? mu : 0.0;
       const double invT = 1.0 / Tu;
       double baseD[NS], den0D[NS];
+      // projected equilibrium and its complement at node q (every lane, both
+      // halves: the element partner exchange is a DPP)
+      double pD[PROJ ? NS : 1], pC[PROJ ? NS : 1];
+      if constexpr (PROJ) {
+#pragma unroll
+        for (int t = 0; t < NS; ++t) fdp::projected_node(a.mdl, q, Tu, md->imusign[t] * muu, pD[t], pC[t]);
+      }
       double dsig = 0.0;  // dtau sigma: 1 + dtau kappa = 1 + dtau chi + dsig
       const double epsq = mt.eps[q];
       {
@@ -445,10 +462,15 @@ struct PairSolver {
 #pragma unroll
         for (int t = 0; t < NS; ++t) {
           const double chia = md->iemab[t] * emab_q;
-          const double x = (epsq - md->imusign[t] * muu) * invT;
-          const double ex = exp(-fabs(x));
-          const double r = rcp_nr(1.0 + ex);
-          const double deq = x > 0.0 ? ex * r : r;
+          double deq;
+          if constexpr (PROJ) {
+            deq = pD[t];
+          } else {
+            const double x = (epsq - md->imusign[t] * muu) * invT;
+            const double ex = exp(-fabs(x));
+            const double r = rcp_nr(1.0 + ex);
+            deq = x > 0.0 ? ex * r : r;
+          }
           baseD[t] = Dst[t] + dtau * (chia * deq);
           den0D[t] = 1.0 + dtau * chia;
         }
@@ -477,7 +499,9 @@ struct PairSolver {
         E.n2[q] = xs.n;
         hq = ldexp(xs.R * xs.R, -2 * xs.n);  // 2^(-2x) = exp(-e / T)
         __syncthreads();
-        {
+        if constexpr (PROJ) {
+          sym = true;
+        } else {
           // g = 2^-x with x = n + f increasing along the grid
           const int nlo = E.n2[0], nhi = E.n2[NQ - 1];
           sym = __builtin_amdgcn_readfirstlane(
@@ -503,6 +527,15 @@ struct PairSolver {
 #pragma unroll
           for (int j = 0; j < NQ; ++j) B[j] = T[j][q];
           __syncthreads();
+        }
+        if constexpr (PROJ) {
+          // the tile is consumed: its space holds the lane's factors
+#pragma unroll
+          for (int t = 0; t < NS; ++t) {
+            const double o = pD[t] / pC[t];
+            S.u.fac[0][t][lane] = 1.0 / sqrt(o);
+            S.u.fac[1][t][lane] = o;
+          }
         }
       }
 
@@ -533,11 +566,17 @@ struct PairSolver {
             double AR[2][NS], BR[2][NS], CR[2][NS], DR[2][NS];
 #pragma unroll
             for (int t = 0; t < NS; ++t) {
+              double rg = rgq, g = gq, hh = hq;
+              if constexpr (PROJ) {
+                rg = S.u.fac[0][t][lane];
+                hh = S.u.fac[1][t][lane];
+                g = hh * rg;
+              }
               const double xv = w2eq * D[t], yv = w2eq - xv;
-              swap16(xv * rgq, AR[0][t], AR[1][t]);
-              swap16(yv * gq, BR[0][t], BR[1][t]);
+              swap16(xv * rg, AR[0][t], AR[1][t]);
+              swap16(yv * g, BR[0][t], BR[1][t]);
               swap16(xv, CR[0][t], CR[1][t]);
-              swap16(hq * yv, DR[0][t], DR[1][t]);
+              swap16(hh * yv, DR[0][t], DR[1][t]);
             }
             static_for<0, NQ / 4>([&](auto jj) __attribute__((always_inline)) {
               constexpr int j = 4 * decltype(jj)::value;
@@ -578,8 +617,15 @@ struct PairSolver {
         double Qx[2 * NS], Fx[2 * NS];
 #pragma unroll
         for (int t = 0; t < NS; ++t) {
-          const double eta = __builtin_fma(Aeq * gq, etaN[t], Apqh * etaP[t]);
-          const double chi = __builtin_fma(Aeq * rgq, outN[t], __builtin_fma(Apq, annP[t], eta));
+          double ag = Aeq * gq, arg = Aeq * rgq, aph = Apqh;
+          if constexpr (PROJ && COUPLED) {
+            const double rg = S.u.fac[0][t][lane], hh = S.u.fac[1][t][lane];
+            ag = Aeq * (hh * rg);
+            arg = Aeq * rg;
+            aph = Apq * hh;
+          }
+          const double eta = __builtin_fma(ag, etaN[t], aph * etaP[t]);
+          const double chi = __builtin_fma(arg, outN[t], __builtin_fma(Apq, annP[t], eta));
           const double dD = __builtin_fma(dtau, chi, den0D[t]), dI = dD + dsig;
           const double r = rcp_nr(dD * dI);
           Qx[t] = __builtin_fma(dtau, eta, baseD[t]) * (r * dI);
@@ -804,7 +850,7 @@ struct PairSolver {
   }
 };
 
-template <int NS, bool COUPLED>
+template <int NS, bool COUPLED, bool PROJ>
 __global__ __launch_bounds__(kLanes, 2) void fwd_pair_kernel(FwdArgs a) {
   __shared__ PairLds<NS> S;
   load_model(a.mdl, a.theta, S.m);
@@ -814,18 +860,18 @@ __global__ __launch_bounds__(kLanes, 2) void fwd_pair_kernel(FwdArgs a) {
     for (int64_t g; (g = wq.next()) >= 0;) {
       const int64_t b0 = uniform64(g * a.chunk);
       const int64_t end = uniform64(b0 + a.chunk < pairs ? b0 + a.chunk : pairs);
-      for (int64_t u = b0; u < end; ++u) PairSolver<NS, COUPLED>::solve(a, u, S, [&] { wq.settle(); });
+      for (int64_t u = b0; u < end; ++u) PairSolver<NS, COUPLED, PROJ>::solve(a, u, S, [&] { wq.settle(); });
     }
   } else {
     const int64_t b0 = (int64_t)blockIdx.x * a.chunk;
     const int64_t end = b0 + a.chunk < pairs ? b0 + a.chunk : pairs;
-    for (int64_t u = b0; u < end; ++u) PairSolver<NS, COUPLED>::solve(a, u, S, [] {});
+    for (int64_t u = b0; u < end; ++u) PairSolver<NS, COUPLED, PROJ>::solve(a, u, S, [] {});
   }
 }
 
-template <int NS, bool COUPLED>
+template <int NS, bool COUPLED, bool PROJ>
 hipError_t launch_pair_t(const FwdArgs& a, const nmc_launch& L, int num_cu, hipStream_t s) {
-  auto kern = fwd_pair_kernel<NS, COUPLED>;
+  auto kern = fwd_pair_kernel<NS, COUPLED, PROJ>;
   const int64_t pairs = (a.P + 1) / 2;
   const int64_t need = (pairs + a.chunk - 1) / a.chunk;
   int64_t grid;
@@ -852,24 +898,29 @@ hipError_t launch_pair_t(const FwdArgs& a, const nmc_launch& L, int num_cu, hipS
   return hipGetLastError();
 }
 
-}  // namespace
-
-hipError_t launch_forward_pair(const FwdArgs& a, int ns, bool coupled, const nmc_launch& L, int num_cu,
-                               hipStream_t s) {
+template <bool PROJ>
+hipError_t launch_pair_p(const FwdArgs& a, int ns, bool coupled, const nmc_launch& L, int num_cu, hipStream_t s) {
   if (coupled) {
     switch (ns) {
-      case 1: return launch_pair_t<1, true>(a, L, num_cu, s);
-      case 2: return launch_pair_t<2, true>(a, L, num_cu, s);
-      case 3: return launch_pair_t<3, true>(a, L, num_cu, s);
+      case 1: return launch_pair_t<1, true, PROJ>(a, L, num_cu, s);
+      case 2: return launch_pair_t<2, true, PROJ>(a, L, num_cu, s);
+      case 3: return launch_pair_t<3, true, PROJ>(a, L, num_cu, s);
     }
   } else {
     switch (ns) {
-      case 1: return launch_pair_t<1, false>(a, L, num_cu, s);
-      case 2: return launch_pair_t<2, false>(a, L, num_cu, s);
-      case 3: return launch_pair_t<3, false>(a, L, num_cu, s);
+      case 1: return launch_pair_t<1, false, PROJ>(a, L, num_cu, s);
+      case 2: return launch_pair_t<2, false, PROJ>(a, L, num_cu, s);
+      case 3: return launch_pair_t<3, false, PROJ>(a, L, num_cu, s);
     }
   }
   return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+hipError_t launch_forward_pair(const FwdArgs& a, int ns, bool coupled, bool proj, const nmc_launch& L, int num_cu,
+                               hipStream_t s) {
+  return proj ? launch_pair_p<true>(a, ns, coupled, L, num_cu, s) : launch_pair_p<false>(a, ns, coupled, L, num_cu, s);
 }
 
 }  // namespace nmc

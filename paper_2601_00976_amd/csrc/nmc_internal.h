@@ -40,6 +40,18 @@ struct DevModel {
   double kcoup;           // K * rho11 [MeV^-3]
   double rho11_min;
   double phi1_nes, phi1_pair;  // Phi_1 / Phi_0 of the NES and pair kernels
+  // projected equilibrium (Eq. fermiDiracProjection) with its limiter bounds
+  // D_min and 1 - D_max, and per-node tables of the node's element: edges,
+  // l_1 eps^2 = pl[0] eps^3 + pl[1] eps^2 and l_2 likewise (pl[2], pl[3]),
+  // the node's row of the inverse eps^2 mass matrix, 1 / int eps^2, and the
+  // node's own basis function at the element's lower and upper edge
+  int fd_projection;
+  double deq_min, ceq_min;
+  double pelo[kMaxNq], pehi[kMaxNq];
+  double pl[kMaxNq][4];
+  double pinv[kMaxNq][2];
+  double prm0[kMaxNq];
+  double pedge[kMaxNq][2];
 };
 
 struct SolverParams {
@@ -102,12 +114,12 @@ struct AdjArgs {
 };
 
 // launchers (defined in the kernel translation units)
-hipError_t launch_forward(const FwdArgs& a, int nq, int ns, bool coupled, const nmc_launch& L, int num_cu,
-                          hipStream_t s);
+hipError_t launch_forward(const FwdArgs& a, int nq, int ns, bool coupled, bool proj, const nmc_launch& L,
+                          int num_cu, hipStream_t s);
 hipError_t launch_forward64(const FwdArgs& a, int ns, bool coupled, const nmc_launch& L, int num_cu,
                             hipStream_t s);
-hipError_t launch_forward_pair(const FwdArgs& a, int ns, bool coupled, const nmc_launch& L, int num_cu,
-                               hipStream_t s);
+hipError_t launch_forward_pair(const FwdArgs& a, int ns, bool coupled, bool proj, const nmc_launch& L,
+                               int num_cu, hipStream_t s);
 hipError_t launch_forward_v(const FwdVArgs& a, int ns, bool coupled, bool phi1, const nmc_launch& L, int num_cu,
                             hipStream_t s);
 hipError_t launch_reset_counter(int* counter, hipStream_t s);

@@ -52,7 +52,8 @@ class ModelDesc(C.Structure):
                 ("sigma_ratio", C.c_double), ("eos_a", C.c_double), ("eos_b", C.c_double),
                 ("mu_a", C.c_double), ("mu_ye0", C.c_double), ("mu_b", C.c_double), ("mu_t0", C.c_double),
                 ("hc_mev_cm", C.c_double), ("m_u_g", C.c_double), ("rho11_min", C.c_double),
-                ("phi1_nes", C.c_double), ("phi1_pair", C.c_double)]
+                ("phi1_nes", C.c_double), ("phi1_pair", C.c_double),
+                ("fd_projection", C.c_int), ("deq_min", C.c_double), ("deq_max", C.c_double)]
 
 
 class SolverParams(C.Structure):

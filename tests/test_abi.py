@@ -101,3 +101,36 @@ def test_default_descriptors():
     p = N.SolverParams()
     N.lib().nmc_solver_params_default(C.byref(p))
     assert (p.tol_inner, p.m_inner, p.m_outer, p.max_inner, p.max_outer) == (1e-10, 3, 3, 100, 50)
+
+
+def test_projection_descriptor_defaults_and_bounds():
+    """The projected equilibrium is off by default with the documented bounds;
+    out-of-range bounds are rejected before any device call."""
+    d = N.ModelDesc()
+    N.lib().nmc_model_desc_default(C.byref(d))
+    assert d.fd_projection == 0 and d.deq_min == 1e-150 and d.deq_max == 1.0 - 1e-12
+    rc, g = _grid()
+    assert rc == N.NMC_OK
+    for field, val in (("deq_min", 0.0), ("deq_min", 1e-200), ("deq_min", 0.1), ("deq_max", 1.0),
+                       ("deq_max", 0.5), ("fd_projection", 2)):
+        dd = N.ModelDesc()
+        N.lib().nmc_model_desc_default(C.byref(dd))
+        dd.fd_projection = 1
+        setattr(dd, field, val)
+        h = C.c_void_p()
+        assert N.lib().nmc_model_create(g, C.byref(dd), C.byref(h)) == N.NMC_E_INVALID_ARG, (field, val)
+        assert not h.value
+    N.lib().nmc_grid_destroy(g)
+
+
+def test_projection_gauss_rule_constants():
+    """The 8-point Gauss-Legendre rule written into the projection's device
+    code is the rule numpy computes (nodes and weights to rounding)."""
+    src = open(os.path.join(ROOT, "paper_2601_00976_amd", "csrc", "nmc_fdproj.h")).read()
+    num = r"(-?\d\.\d+)"
+    gx = [float(v) for v in re.findall(num, re.search(r"kGx\[8\] = \{(.*?)\};", src, re.S).group(1))]
+    gw = [float(v) for v in re.findall(num, re.search(r"kGw\[8\] = \{(.*?)\};", src, re.S).group(1))]
+    x, w = np.polynomial.legendre.leggauss(8)
+    assert len(gx) == 8 and len(gw) == 8
+    assert np.max(np.abs(np.array(gx) - x)) <= 2e-16
+    assert np.max(np.abs(np.array(gw) - w)) <= 5e-16
