@@ -47,6 +47,18 @@ def flops_per_point(n_inner, n_outer, nq=32, ns=NS):
     return n_inner * (8 * ns * nq * nq + 40 * ns * nq) + n_outer * (4 * nq * nq + 30 * ns * nq)
 
 
+def flops_per_point_v(n_inner, n_outer, nq=32, ns=NS):
+    """Algorithmic FLOPs of one O(v) point-solve (FMA = 2), counted from the
+    two-points-per-wavefront kernel: per inner iteration the four
+    energy-coupling mat-vecs of every species (8 ns nq^2) and, per species and
+    node, the Minerbo closure with the velocity products (47), the right-hand
+    sides and quotients of the four moments (41), the Anderson step over them
+    (72) and the convergence sums (14), together 174 ns nq; per outer
+    iteration the kernel build (4 nq^2), the opacities and equilibrium (30 ns
+    nq) and the Eulerian integrals with their closure (70 ns nq)."""
+    return n_inner * (8 * ns * nq * nq + 174 * ns * nq) + n_outer * (4 * nq * nq + 100 * ns * nq)
+
+
 def bytes_per_point(nq=32, ns=NS):
     """Algorithmic HBM bytes of one point-solve: read D*, I* and 3 scalars
     (rho11, Ye*, e*), write D, I, 3 scalars (Ye, e, T) and 3 int32 counters."""
@@ -115,6 +127,14 @@ def run_velocity(args):
     D0, I0, ef0 = S.init_state_v(model, t)
     theta = model.default_theta()
     launch = S.LaunchConfig(chunk=args.chunk or 1, blocks_per_cu=args.blocks_per_cu or 0)
+    if args.kernel_store == "wave":
+        launch.kernel_store = 5
+        kernel_label, traffic_tag = ("fwd_v_kernel<3, true, false> (persistent O(v) point solve, one point per "
+                                     "wavefront)"), "fwd_v_kernel_nq32_ns3"
+    else:
+        assert args.kernel_store == "chip", "the O(v) solve runs with --kernel-store chip (default) or wave"
+        kernel_label, traffic_tag = ("fwd_vpair_kernel<3, true> (persistent O(v) point solve, two points per "
+                                     "wavefront)"), "fwd_vpair_kernel_nq32_ns3"
     work = dict(D=D0.clone(), I=I0.clone(), ye=t["ye"].clone(), ef=ef0.clone(), v=t["v"].clone())
     outs = [S.alloc_outputs_v(model, P_POINTS, dev) for _ in range(STEPS_PER_GRAPH)]
     for o in outs:
@@ -179,7 +199,7 @@ def run_velocity(args):
     n_out = np.stack([o["n_outer"].cpu().numpy() for o in outs]).astype(np.float64)
     status = np.stack([o["status"].cpu().numpy() for o in outs])
     solved = int(np.sum(n_out > 0))
-    flops = float(np.sum(flops_per_point(n_in, n_out, 32)))
+    flops = float(np.sum(flops_per_point_v(n_in, n_out, 32)))
     eager_s = kern_ms * 1e-3 / (n_timed * STEPS_PER_GRAPH)
     kern_s = (graph_ms - copy_ms) * 1e-3 / STEPS_PER_GRAPH
     achieved = flops / STEPS_PER_GRAPH / kern_s / 1e12
@@ -195,13 +215,14 @@ def run_velocity(args):
             "implicit_steps_per_step": STEPS_PER_GRAPH, "dtau_km": W.DTAU_KM, "tol_inner": params.tol_inner,
             "tol_outer": params.tol_outer, "anderson_memory": params.m_inner,
             "launch": {"chunk": launch.chunk, "blocks_per_cu": launch.blocks_per_cu, "persistent": launch.persistent},
+            "kernel_store": args.kernel_store,
             "iterations": iteration_summary(n_in, n_out),
             "status_counts": np.bincount(status.ravel(), minlength=5).tolist(),
         },
         "roofline": {
-            "kernel": "fwd_v_kernel<3, true> (persistent O(v) point solve, one point per wavefront)",
+            "kernel": kernel_label, "flop_convention": "O(v): closure and velocity work counted (flops_per_point_v)",
             "bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-            "frac": achieved / PEAK_FP64_TFLOPS, "traffic": AT.stored_traffic("fwd_v_kernel_nq32_ns3"),
+            "frac": achieved / PEAK_FP64_TFLOPS, "traffic": AT.stored_traffic(traffic_tag),
             "kernel_ms_per_launch": kern_s * 1e3,
             "kernel_ms_per_launch_from": "graph replay time (HIP events, timed region) less the pristine copy, / 10",
             "graph_ms_per_step": graph_ms, "pristine_copy_ms": copy_ms, "eager_ms_per_launch": eager_s * 1e3,

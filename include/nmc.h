@@ -322,8 +322,11 @@ typedef struct {
 } nmc_batch_v_out;
 
 /* Batched O(v) forward solve.  32-node grids only (NMC_E_UNSUPPORTED
- * otherwise); one point per wavefront with the kernel entries regenerated on
- * chip (launch->kernel_store must be NMC_KERNELS_ON_CHIP).  Workspace,
+ * otherwise).  launch->kernel_store NMC_KERNELS_ON_CHIP (default) or
+ * NMC_KERNELS_PAIRED: two points per wavefront, each lane owning the four
+ * moments of its node; NMC_KERNELS_WAVE: one point per wavefront (the mode
+ * that also carries the linear-order corrections, used whenever phi1_nes or
+ * phi1_pair is nonzero).  Other modes return NMC_E_UNSUPPORTED.  Workspace,
  * launch, stream and error rules as for nmc_solve_batch; dtau must be
  * positive. */
 int nmc_solve_batch_v(const nmc_model* m, const nmc_solver_params* prm, int64_t P, double dtau,

@@ -516,8 +516,10 @@ int nmc_solve_batch_v(const nmc_model* m, const nmc_solver_params* prm, int64_t 
   if (launch) L = *launch;
   if (L.chunk < 1 || L.chunk > 4096 || L.blocks_per_cu < 0 || L.blocks_per_cu > 64)
     return fail(NMC_E_INVALID_ARG, "solve_batch_v: bad launch configuration");
-  if (L.kernel_store != NMC_KERNELS_ON_CHIP)
-    return fail(NMC_E_UNSUPPORTED, "solve_batch_v: kernel_store must be NMC_KERNELS_ON_CHIP");
+  if (L.kernel_store != NMC_KERNELS_ON_CHIP && L.kernel_store != NMC_KERNELS_PAIRED &&
+      L.kernel_store != NMC_KERNELS_WAVE)
+    return fail(NMC_E_UNSUPPORTED, "solve_batch_v: kernel_store must be NMC_KERNELS_ON_CHIP or NMC_KERNELS_PAIRED (two "
+                "points per wavefront) or NMC_KERNELS_WAVE (one point per wavefront)");
   if (L.persistent && (!ws || !aligned256(ws) || ws_bytes < kCounterBytes))
     return fail(NMC_E_WORKSPACE, "solve_batch_v: persistent launch needs a 256-byte aligned workspace");
   nmc::FwdVArgs a;
@@ -559,7 +561,10 @@ int nmc_solve_batch_v(const nmc_model* m, const nmc_solver_params* prm, int64_t 
   }
   const bool coupled = (m->host.flags & (NMC_NES | NMC_PAIR)) != 0;
   const bool phi1 = coupled && (m->host.phi1_nes != 0.0 || m->host.phi1_pair != 0.0);
-  hipError_t e = nmc::launch_forward_v(a, m->host.ns, coupled, phi1, L, m->num_cu, s);
+  // the linear-order corrections run in the one-point-per-wavefront kernel
+  const bool one_point = phi1 || L.kernel_store == NMC_KERNELS_WAVE;
+  hipError_t e = one_point ? nmc::launch_forward_v(a, m->host.ns, coupled, phi1, L, m->num_cu, s)
+                           : nmc::launch_forward_vpair(a, m->host.ns, coupled, L, m->num_cu, s);
   if (e == hipErrorInvalidValue) return fail(NMC_E_UNSUPPORTED, "solve_batch_v: no kernel for ns=%d", m->host.ns);
   if (e != hipSuccess) return hip_fail(e, "solve_batch_v: launch");
   return NMC_OK;

@@ -1,0 +1,316 @@
+// Building blocks of the two-points-per-wavefront solve kernels (CDNA4): the
+// lane half of a wave solves one point and lane q of the half owns node q of
+// every species.  Half-wave reductions, the pair-factor tile of a point, and
+// the rate contraction over the point's 32 columns broadcast by DPP
+// row_newbcast (Eqs. nesRatesNodal, pairRatesNodal).
+#pragma once
+
+#include "nmc_wave.h"
+
+namespace nmc {
+namespace pairk {
+
+constexpr int NQP = 32;
+// widest exponent range (powers of two of exp(-e / (2T)) over the grid) of
+// the symmetric contraction: its scaled vectors and row factors then stay
+// within 2^(+-(kSymBits / 2 + 1)), far from overflow
+constexpr int kSymBits = 1800;
+
+// Sums over the lane's half-wave of 2K values, in every lane of the half:
+// rows (0, 2) carry slot k, rows (1, 3) slot K + k, then a row butterfly and
+// a row swap.  The K chains advance stage by stage.  Fixed order.
+template <int K>
+__device__ __forceinline__ void half_own_sums(const double (&v)[2 * K], double (&s)[2 * K]) {
+  double r[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) r[k] = halve16(v[k], v[K + k]);
+#pragma unroll
+  for (int k = 0; k < K; ++k) r[k] += dpp<0xB1>(r[k]);   // quad_perm [1,0,3,2]
+#pragma unroll
+  for (int k = 0; k < K; ++k) r[k] += dpp<0x4E>(r[k]);   // quad_perm [2,3,0,1]
+#pragma unroll
+  for (int k = 0; k < K; ++k) r[k] += dpp<0x141>(r[k]);  // row_half_mirror
+#pragma unroll
+  for (int k = 0; k < K; ++k) r[k] += dpp<0x140>(r[k]);  // row_mirror
+#pragma unroll
+  for (int k = 0; k < K; ++k) swap16(r[k], s[k], s[K + k]);
+}
+
+
+// max(a, -b) of two non-NaN values as one v_max_f64 with a negated operand
+__device__ __forceinline__ double max_neg_f64(double a, double b) {
+  double r;
+  asm("v_max_f64 %0, %1, -%2" : "=v"(r) : "v"(a), "v"(b));
+  return r;
+}
+
+// Pair factors of one point into its 32 x 32 tile T (row-major).  SYM: the
+// symmetric core b^2 (diagonal written by the caller).  Otherwise signed:
+// for every unordered node pair (lo, hi), T[hi][lo] = +b and T[lo][hi] = -b
+// with b = exp(-|e_lo - e_hi| / (2T)) = P_lo R_hi 2^(n_lo - n_hi).  Lane q
+// forms the pairs (q, q + d mod 32) for d = 1..15 and, if q < 16, d = 16,
+// from its own split (Pq, Rq, nq) and its partner's in LDS.  Of the two
+// orientations 2^(x_q - x_j) and 2^(x_j - x_q) the smaller is b (the other
+// is its reciprocal, or overflows), so no compare picks the formula; the
+// sign goes by whether q is the lower node.
+template <bool SYM>
+__device__ __forceinline__ void pair_tile_rows(double* __restrict__ T, const double* __restrict__ P2,
+                                               const double* __restrict__ R2, const int* __restrict__ n2, int q,
+                                               double Pq, double Rq, int nq) {
+  constexpr int N = 32;
+  double Pp[N / 2], Rp[N / 2];
+  int np[N / 2];
+#pragma unroll
+  for (int d = 1; d <= N / 2; ++d) {  // every partner load first: one LDS round trip
+    const int j = (q + d) & (N - 1);
+    Pp[d - 1] = P2[j];
+    Rp[d - 1] = R2[j];
+    np[d - 1] = n2[j];
+  }
+#pragma unroll
+  for (int d = 1; d <= N / 2; ++d) {
+    const int j = (q + d) & (N - 1);
+    const int e = nq - np[d - 1];
+    const double b = min_f64(ldexp(Pq * Rp[d - 1], e), ldexp(Pp[d - 1] * Rq, -e));
+    if (d < N / 2 || q < N / 2) {
+      if constexpr (SYM) {
+        const double b2 = b * b;
+        T[j * N + q] = b2;
+        T[q * N + j] = b2;
+      } else {
+        const double sb = q + d < N ? b : -b;  // + where j is the upper node
+        T[j * N + q] = sb;
+        T[q * N + j] = -sb;
+      }
+    }
+  }
+}
+
+// any lane of this lane's half
+__device__ __forceinline__ bool half_any(bool b) {
+  const uint64_t m = __builtin_amdgcn_ballot_w64(b);
+  return ((threadIdx.x >> 5) ? (m >> 32) : (m & 0xffffffffull)) != 0;
+}
+
+// One column of the rate contraction: the moment vectors' column L of each
+// 16-lane row is broadcast into the FMAs (v_fmac_f64_dpp row_newbcast:L, the
+// DPP operand being src0).  eN += Phi_in x_s, oN += Phi_out y_s,
+// aP += Phi_ann x_sbar, eP += Phi_ann (h y)_sbar, the last being Phi_pro y_sbar
+// by detailed balance once the row sum is scaled by h_q (h = exp(-e / T)).
+// The leading s_nop covers the VALU-write to DPP-read distance for registers
+// written just before.
+template <int NS>
+struct ColFmac;
+
+template <>
+struct ColFmac<3> {
+  template <int L>
+  __device__ __forceinline__ static void run(double (&eN)[3], double (&oN)[3], double (&aP)[3], double (&eP)[3],
+                                             const double (&x)[3], const double (&y)[3], const double (&hy)[3],
+                                             double fi, double fo, double fa) {
+    asm volatile(
+        "s_nop 1\n"
+        "v_fmac_f64_dpp %0, %12, %21 row_newbcast:%24 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %1, %13, %21 row_newbcast:%24 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %2, %14, %21 row_newbcast:%24 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %3, %15, %22 row_newbcast:%24 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %4, %16, %22 row_newbcast:%24 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %5, %17, %22 row_newbcast:%24 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %6, %13, %23 row_newbcast:%24 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %7, %12, %23 row_newbcast:%24 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %8, %14, %23 row_newbcast:%24 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %9, %19, %23 row_newbcast:%24 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %10, %18, %23 row_newbcast:%24 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %11, %20, %23 row_newbcast:%24 row_mask:0xf bank_mask:0xf\n"
+        : "+v"(eN[0]), "+v"(eN[1]), "+v"(eN[2]), "+v"(oN[0]), "+v"(oN[1]), "+v"(oN[2]), "+v"(aP[0]), "+v"(aP[1]),
+          "+v"(aP[2]), "+v"(eP[0]), "+v"(eP[1]), "+v"(eP[2])
+        : "v"(x[0]), "v"(x[1]), "v"(x[2]), "v"(y[0]), "v"(y[1]), "v"(y[2]), "v"(hy[0]), "v"(hy[1]), "v"(hy[2]),
+          "v"(fi), "v"(fo), "v"(fa), "i"(L));
+  }
+};
+
+template <>
+struct ColFmac<2> {
+  template <int L>
+  __device__ __forceinline__ static void run(double (&eN)[2], double (&oN)[2], double (&aP)[2], double (&eP)[2],
+                                             const double (&x)[2], const double (&y)[2], const double (&hy)[2],
+                                             double fi, double fo, double fa) {
+    asm volatile(
+        "s_nop 1\n"
+        "v_fmac_f64_dpp %0, %8, %14 row_newbcast:%17 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %1, %9, %14 row_newbcast:%17 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %2, %10, %15 row_newbcast:%17 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %3, %11, %15 row_newbcast:%17 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %4, %9, %16 row_newbcast:%17 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %5, %8, %16 row_newbcast:%17 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %6, %13, %16 row_newbcast:%17 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %7, %12, %16 row_newbcast:%17 row_mask:0xf bank_mask:0xf\n"
+        : "+v"(eN[0]), "+v"(eN[1]), "+v"(oN[0]), "+v"(oN[1]), "+v"(aP[0]), "+v"(aP[1]), "+v"(eP[0]), "+v"(eP[1])
+        : "v"(x[0]), "v"(x[1]), "v"(y[0]), "v"(y[1]), "v"(hy[0]), "v"(hy[1]), "v"(fi), "v"(fo), "v"(fa), "i"(L));
+  }
+};
+
+template <>
+struct ColFmac<1> {
+  template <int L>
+  __device__ __forceinline__ static void run(double (&eN)[1], double (&oN)[1], double (&aP)[1], double (&eP)[1],
+                                             const double (&x)[1], const double (&y)[1], const double (&hy)[1],
+                                             double fi, double fo, double fa) {
+    asm volatile(
+        "s_nop 1\n"
+        "v_fmac_f64_dpp %0, %4, %7 row_newbcast:%10 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %1, %5, %8 row_newbcast:%10 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %2, %4, %9 row_newbcast:%10 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %3, %6, %9 row_newbcast:%10 row_mask:0xf bank_mask:0xf\n"
+        : "+v"(eN[0]), "+v"(oN[0]), "+v"(aP[0]), "+v"(eP[0])
+        : "v"(x[0]), "v"(y[0]), "v"(hy[0]), "v"(fi), "v"(fo), "v"(fa), "i"(L));
+  }
+};
+
+// Four columns L0 .. L0 + 3 of the rate contraction on the symmetric core
+// B2 = b^2 of the kernels (the per-node exponential factors ride on the
+// vectors, see the solver): eN += B2 a_s, oN += B2 b_s, aP += B2 c_sbar,
+// eP += B2 d_sbar, the vectors' column broadcast into the FMAs
+// (row_newbcast) and B2 from VGPRs m0 .. m3.  12 FMAs per column for three
+// species and nothing else; one leading s_nop per four columns covers the
+// VALU-write to DPP-read distance of the vectors.
+template <int NS>
+struct ColSym;
+
+template <>
+struct ColSym<3> {
+  template <int L0>
+  __device__ __forceinline__ static void run(double (&eN)[3], double (&oN)[3], double (&aP)[3], double (&eP)[3],
+                                             const double (&a)[3], const double (&b)[3], const double (&c)[3],
+                                             const double (&d)[3], double m0, double m1, double m2, double m3) {
+    asm volatile(
+        "s_nop 1\n"
+        "v_fmac_f64_dpp %0, %12, %24 row_newbcast:%28 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %1, %13, %24 row_newbcast:%28 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %2, %14, %24 row_newbcast:%28 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %3, %15, %24 row_newbcast:%28 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %4, %16, %24 row_newbcast:%28 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %5, %17, %24 row_newbcast:%28 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %6, %19, %24 row_newbcast:%28 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %7, %18, %24 row_newbcast:%28 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %8, %20, %24 row_newbcast:%28 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %9, %22, %24 row_newbcast:%28 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %10, %21, %24 row_newbcast:%28 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %11, %23, %24 row_newbcast:%28 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %0, %12, %25 row_newbcast:%29 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %1, %13, %25 row_newbcast:%29 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %2, %14, %25 row_newbcast:%29 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %3, %15, %25 row_newbcast:%29 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %4, %16, %25 row_newbcast:%29 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %5, %17, %25 row_newbcast:%29 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %6, %19, %25 row_newbcast:%29 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %7, %18, %25 row_newbcast:%29 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %8, %20, %25 row_newbcast:%29 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %9, %22, %25 row_newbcast:%29 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %10, %21, %25 row_newbcast:%29 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %11, %23, %25 row_newbcast:%29 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %0, %12, %26 row_newbcast:%30 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %1, %13, %26 row_newbcast:%30 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %2, %14, %26 row_newbcast:%30 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %3, %15, %26 row_newbcast:%30 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %4, %16, %26 row_newbcast:%30 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %5, %17, %26 row_newbcast:%30 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %6, %19, %26 row_newbcast:%30 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %7, %18, %26 row_newbcast:%30 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %8, %20, %26 row_newbcast:%30 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %9, %22, %26 row_newbcast:%30 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %10, %21, %26 row_newbcast:%30 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %11, %23, %26 row_newbcast:%30 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %0, %12, %27 row_newbcast:%31 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %1, %13, %27 row_newbcast:%31 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %2, %14, %27 row_newbcast:%31 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %3, %15, %27 row_newbcast:%31 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %4, %16, %27 row_newbcast:%31 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %5, %17, %27 row_newbcast:%31 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %6, %19, %27 row_newbcast:%31 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %7, %18, %27 row_newbcast:%31 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %8, %20, %27 row_newbcast:%31 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %9, %22, %27 row_newbcast:%31 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %10, %21, %27 row_newbcast:%31 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %11, %23, %27 row_newbcast:%31 row_mask:0xf bank_mask:0xf\n"
+        : "+v"(eN[0]), "+v"(eN[1]), "+v"(eN[2]), "+v"(oN[0]), "+v"(oN[1]), "+v"(oN[2]), "+v"(aP[0]), "+v"(aP[1]), "+v"(aP[2]), "+v"(eP[0]), "+v"(eP[1]), "+v"(eP[2])
+        : "v"(a[0]), "v"(a[1]), "v"(a[2]), "v"(b[0]), "v"(b[1]), "v"(b[2]), "v"(c[0]), "v"(c[1]), "v"(c[2]), "v"(d[0]), "v"(d[1]), "v"(d[2]), "v"(m0), "v"(m1), "v"(m2), "v"(m3), "i"(L0 + 0), "i"(L0 + 1), "i"(L0 + 2), "i"(L0 + 3));
+  }
+};
+
+template <>
+struct ColSym<2> {
+  template <int L0>
+  __device__ __forceinline__ static void run(double (&eN)[2], double (&oN)[2], double (&aP)[2], double (&eP)[2],
+                                             const double (&a)[2], const double (&b)[2], const double (&c)[2],
+                                             const double (&d)[2], double m0, double m1, double m2, double m3) {
+    asm volatile(
+        "s_nop 1\n"
+        "v_fmac_f64_dpp %0, %8, %16 row_newbcast:%20 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %1, %9, %16 row_newbcast:%20 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %2, %10, %16 row_newbcast:%20 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %3, %11, %16 row_newbcast:%20 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %4, %13, %16 row_newbcast:%20 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %5, %12, %16 row_newbcast:%20 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %6, %15, %16 row_newbcast:%20 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %7, %14, %16 row_newbcast:%20 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %0, %8, %17 row_newbcast:%21 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %1, %9, %17 row_newbcast:%21 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %2, %10, %17 row_newbcast:%21 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %3, %11, %17 row_newbcast:%21 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %4, %13, %17 row_newbcast:%21 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %5, %12, %17 row_newbcast:%21 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %6, %15, %17 row_newbcast:%21 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %7, %14, %17 row_newbcast:%21 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %0, %8, %18 row_newbcast:%22 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %1, %9, %18 row_newbcast:%22 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %2, %10, %18 row_newbcast:%22 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %3, %11, %18 row_newbcast:%22 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %4, %13, %18 row_newbcast:%22 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %5, %12, %18 row_newbcast:%22 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %6, %15, %18 row_newbcast:%22 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %7, %14, %18 row_newbcast:%22 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %0, %8, %19 row_newbcast:%23 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %1, %9, %19 row_newbcast:%23 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %2, %10, %19 row_newbcast:%23 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %3, %11, %19 row_newbcast:%23 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %4, %13, %19 row_newbcast:%23 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %5, %12, %19 row_newbcast:%23 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %6, %15, %19 row_newbcast:%23 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %7, %14, %19 row_newbcast:%23 row_mask:0xf bank_mask:0xf\n"
+        : "+v"(eN[0]), "+v"(eN[1]), "+v"(oN[0]), "+v"(oN[1]), "+v"(aP[0]), "+v"(aP[1]), "+v"(eP[0]), "+v"(eP[1])
+        : "v"(a[0]), "v"(a[1]), "v"(b[0]), "v"(b[1]), "v"(c[0]), "v"(c[1]), "v"(d[0]), "v"(d[1]), "v"(m0), "v"(m1), "v"(m2), "v"(m3), "i"(L0 + 0), "i"(L0 + 1), "i"(L0 + 2), "i"(L0 + 3));
+  }
+};
+
+template <>
+struct ColSym<1> {
+  template <int L0>
+  __device__ __forceinline__ static void run(double (&eN)[1], double (&oN)[1], double (&aP)[1], double (&eP)[1],
+                                             const double (&a)[1], const double (&b)[1], const double (&c)[1],
+                                             const double (&d)[1], double m0, double m1, double m2, double m3) {
+    asm volatile(
+        "s_nop 1\n"
+        "v_fmac_f64_dpp %0, %4, %8 row_newbcast:%12 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %1, %5, %8 row_newbcast:%12 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %2, %6, %8 row_newbcast:%12 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %3, %7, %8 row_newbcast:%12 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %0, %4, %9 row_newbcast:%13 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %1, %5, %9 row_newbcast:%13 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %2, %6, %9 row_newbcast:%13 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %3, %7, %9 row_newbcast:%13 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %0, %4, %10 row_newbcast:%14 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %1, %5, %10 row_newbcast:%14 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %2, %6, %10 row_newbcast:%14 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %3, %7, %10 row_newbcast:%14 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %0, %4, %11 row_newbcast:%15 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %1, %5, %11 row_newbcast:%15 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %2, %6, %11 row_newbcast:%15 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f64_dpp %3, %7, %11 row_newbcast:%15 row_mask:0xf bank_mask:0xf\n"
+        : "+v"(eN[0]), "+v"(oN[0]), "+v"(aP[0]), "+v"(eP[0])
+        : "v"(a[0]), "v"(b[0]), "v"(c[0]), "v"(d[0]), "v"(m0), "v"(m1), "v"(m2), "v"(m3), "i"(L0 + 0), "i"(L0 + 1), "i"(L0 + 2), "i"(L0 + 3));
+  }
+};
+
+}  // namespace pairk
+}  // namespace nmc

@@ -9,11 +9,12 @@ Two steps, each run on a machine with the GPU:
 
 `run` launches a plain device-to-device copy of a known size (the
 calibration: it must read and write exactly that many bytes), the forward
-solve (default and one-point-per-wave kernels) and the adjoint on the first
-step of the 2^16-point radial profile, the O(v) solve on the first step of
-the 2^16-point moving profile, and the 64-node solves (kernels on
-chip and in HBM) on the first step of the 2^18-point profile, each at the
-launch shape of the autotune cache.
+solve (default and one-point-per-wave kernels, and the default with the
+projected equilibrium) and the adjoint on the first step of the 2^16-point
+radial profile, the O(v) solve (two points and one point per wavefront) on
+the first step of the 2^16-point moving profile, and the 64-node solves
+(kernels on chip and in HBM) on the first step of the 2^18-point profile,
+each at the launch shape of the autotune cache.
 `summarize` scales each kernel's per-dispatch counter by copy bytes / copy
 counter and writes profiles/traffic_<kernel>.txt with the source hash of the
 kernels, so that stale measurements are recognised.
@@ -28,12 +29,16 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 COPY_BYTES = 1 << 28  # 256 MiB calibration copy
 KERNELS = {
-    "fwd_pair_kernel<3, true>": ("fwd_pair_kernel_nq32_ns3", "radial profile, 2^16 points, 32 nodes, step 1"),
+    "fwd_pair_kernel<3, true, false>": ("fwd_pair_kernel_nq32_ns3", "radial profile, 2^16 points, 32 nodes, step 1"),
+    "fwd_pair_kernel<3, true, true>": ("fwd_pair_kernel_nq32_ns3_proj", "radial profile, 2^16 points, 32 nodes, "
+                                       "step 1, projected equilibrium"),
     "fwd_kernel<3, 32, true, 2>": ("fwd_kernel_nq32_ns3", "radial profile, 2^16 points, 32 nodes, step 1, "
                                    "one point per wavefront"),
     "adj_kernel<3>": ("adj_kernel_nq32_ns3", "radial profile, 2^16 points, 32 nodes, step 1"),
-    "fwd_v_kernel<3, true>": ("fwd_v_kernel_nq32_ns3", "moving radial profile (O(v) solve), 2^16 points, "
-                              "32 nodes, step 1"),
+    "fwd_v_kernel<3, true, false>": ("fwd_v_kernel_nq32_ns3", "moving radial profile (O(v) solve), 2^16 points, "
+                                     "32 nodes, step 1, one point per wavefront"),
+    "fwd_vpair_kernel<3, true>": ("fwd_vpair_kernel_nq32_ns3", "moving radial profile (O(v) solve), 2^16 "
+                                  "points, 32 nodes, step 1, two points per wavefront"),
     "fwd64_kernel<3, true, false>": ("fwd64_kernel_nq64_ns3", "radial profile, 2^18 points, 64 nodes, step 1"),
     "fwd64_kernel<3, true, true>": ("fwd64_kernel_nq64_ns3_hbm",
                                     "radial profile, 2^18 points, 64 nodes, step 1, kernels in HBM"),
@@ -71,12 +76,18 @@ def run():
     gbar = torch.ones(1 << 16, 2, dtype=torch.float64, device=dev)
     S.adjoint(model, W.DTAU_KM, t["rho11"], theta, out, gbar, workspace=ws)
     torch.cuda.synchronize()
+    # the projected equilibrium, at the same launch shape
+    mp = S.Model(S.Grid(16), fd_projection=1)
+    S.solve(mp, S.Params(), W.DTAU_KM, D0, I0, t["rho11"], t["ye"], e0, theta, out=out, workspace=ws,
+            launch=AT.best_launch(model, 1 << 16))
+    torch.cuda.synchronize()
     # the O(v) solve on the moving profile, at the launch shape bench.py uses
     tv = S.to_device(W.radial_profile_v(P=1 << 16, wid=6), dev)
     Dv, Iv, efv = S.init_state_v(model, tv)
     outv = S.alloc_outputs_v(model, 1 << 16, dev)
-    S.solve_v(model, S.Params(tol_inner=1e-12, tol_outer=1e-10), W.DTAU_KM, Dv, Iv, tv["rho11"], tv["ye"], efv,
-              tv["v"], theta, out=outv, workspace=ws, launch=S.LaunchConfig(chunk=1))
+    for store in (0, 5):  # two points per wavefront (default), then one
+        S.solve_v(model, S.Params(tol_inner=1e-12, tol_outer=1e-10), W.DTAU_KM, Dv, Iv, tv["rho11"], tv["ye"], efv,
+                  tv["v"], theta, out=outv, workspace=ws, launch=S.LaunchConfig(chunk=1, kernel_store=store))
     torch.cuda.synchronize()
     del ws, out, gbar, D0, I0, e0, t, tv, Dv, Iv, efv, outv
     # 64 nodes, 2^18 points: kernels on chip, then precomputed in HBM
