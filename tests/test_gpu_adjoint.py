@@ -134,33 +134,42 @@ def test_adjoint_deterministic_and_autograd():
 
 def test_adjoint_against_gpu_finite_differences():
     """Central differences of the GPU forward solve (tolerances 1e-14) on 64
-    profile points drawn without replacement, h = 1e-3 |theta_j|.
+    profile points drawn without replacement, every component of theta.
 
-    A difference quotient is only meaningful where the change it measures,
-    |dL/dtheta_j| 2h, stands well above the noise of L: the solver tolerance
-    and rounding leave ~4e-14 max(|e*|, 1) in L_E (|Ye*| for L_Y).  Components
-    with a change below 1e5 times that floor are skipped (weak kernels at low
-    density move L by less than an ulp); on the rest the FD quotient carries
-    ~1e-5 relative noise plus O(h^2) ~ 1e-6 truncation.  Bound: per point,
-    max |g_IFT - g_FD| <= 1e-4 max |g_FD| over resolvable components, and the
-    median of that error <= 1e-6."""
+    The components of theta carry different units (per-node opacity scales
+    ~1, NES and pair amplitudes ~1e-10), so the gradient is compared as the
+    elasticities E_j = theta_j dL/dtheta_j, in each point's infinity norm:
+    max_j |E_IFT - E_FD| <= 1e-6 max_j |E_FD|.  The losses are taken through
+    the neutrino side, L_E = e* - e = K sum d W3 (D - D*) and L_Y = Ye - Ye* =
+    -K sum g W2 (D - D*) (equal by conservation), which avoids cancelling
+    against e*.  Steps h_j = 1e-2 |theta_j| and h_j / 2 with Richardson
+    extrapolation remove the O(h^2) term.  With h = 1e-6 |theta_j| the
+    change of L lies at the solve's rounding floor for the weakly coupled
+    components: that floor is measured and printed (median ~3e-6, max ~2e-3
+    in the oracle's arithmetic), not asserted at 1e-6."""
     import torch
-    _say("adjoint vs GPU central differences, 64 sampled profile points, 8 components of theta")
+    _say("adjoint vs GPU central differences, 64 sampled profile points, all 34 components of theta")
     full = W.radial_profile(P=1 << 16)
     d = full.take(W.fd_sample(1 << 16, 64))
     d = d.take(np.where(d.rho11 >= 1e-4)[0])  # points below the coupling threshold have zero gradient
     P = len(d.rho11)
     mg = S.Model(S.Grid(16))
+    om = O.Model()
     t = S.to_device(d)
     D0, I0, e0 = S.init_state(mg, t["T"], t["rho11"], t["ye"], t["uD"], t["uI"])
+    D0n = D0.cpu().numpy()
     prm = S.Params(tol_inner=1e-14, tol_outer=1e-14, max_inner=400, max_outer=400)
     theta0 = torch.as_tensor(_theta(), device="cuda")
+    K = om.c.kcoup / d.rho11
+    gs = np.array([1.0, -1.0, 0.0])[None, :, None]
+    ds = np.array([1.0, 1.0, 4.0])[None, :, None]
 
     def losses(theta):
         out = S.solve(mg, prm, W.DTAU_KM, D0, I0, t["rho11"], t["ye"], e0, theta)
         torch.cuda.synchronize()
         assert int(out["status"].abs().sum()) == 0
-        return out, (e0 - out["e"]).cpu().numpy(), (out["ye"] - t["ye"]).cpu().numpy()
+        dD = out["D"].cpu().numpy() - D0n
+        return out, K * np.sum(ds * om.w3 * dD, axis=(1, 2)), -K * np.sum(gs * om.w2 * dD, axis=(1, 2))
 
     out, _, _ = losses(theta0)
     grads = {}
@@ -168,30 +177,33 @@ def test_adjoint_against_gpu_finite_differences():
         gbar = torch.tensor([gb] * P, dtype=torch.float64, device="cuda")
         _, gpp = S.adjoint(mg, W.DTAU_KM, t["rho11"], theta0, out, gbar, per_point=True)
         grads[name] = gpp.cpu().numpy()
-    comps = [0, 7, 12, 15, 23, 31, 32, 33]
     th_np = theta0.cpu().numpy()
-    hs = 1e-3 * np.abs(th_np[comps])
-    fd = {"E": np.zeros((P, len(comps))), "Y": np.zeros((P, len(comps)))}
-    for c, j in enumerate(comps):
-        tp, tm = theta0.clone(), theta0.clone()
-        tp[j] += hs[c]
-        tm[j] -= hs[c]
-        _, LEp, LYp = losses(tp)
-        _, LEm, LYm = losses(tm)
-        fd["E"][:, c] = (LEp - LEm) / (2 * hs[c])
-        fd["Y"][:, c] = (LYp - LYm) / (2 * hs[c])
-    checked = 0
-    for name, ref in (("E", e0.cpu().numpy()), ("Y", d.ye)):
-        floor = 4e-14 * np.maximum(np.abs(ref), 1.0)
-        res = np.abs(fd[name]) * 2 * hs[None, :] >= 1e5 * floor[:, None]
-        g = grads[name][:, comps]
-        scale = np.max(np.where(res, np.abs(fd[name]), 0.0), axis=1)
-        rows = scale > 0
-        err = np.max(np.where(res, np.abs(g - fd[name]), 0.0), axis=1)[rows] / scale[rows]
-        checked += int(res.sum())
-        assert err.max() <= 1e-4, f"L_{name}: FD mismatch {err.max():.3e}"
-        assert np.median(err) <= 1e-6, f"L_{name}: median FD mismatch {np.median(err):.3e}"
-    assert checked >= 100
+    nt = len(th_np)
+
+    def elasticities(r):
+        EE, EY = np.zeros((P, nt)), np.zeros((P, nt))
+        for j in range(nt):
+            tp, tm = theta0.clone(), theta0.clone()
+            tp[j] += r * abs(th_np[j])
+            tm[j] -= r * abs(th_np[j])
+            _, LEp, LYp = losses(tp)
+            _, LEm, LYm = losses(tm)
+            EE[:, j] = (LEp - LEm) / (2 * r)
+            EY[:, j] = (LYp - LYm) / (2 * r)
+        return {"E": EE, "Y": EY}
+
+    F1, F2, F6 = elasticities(1e-2), elasticities(5e-3), elasticities(1e-6)
+    for name in ("E", "Y"):
+        A = grads[name] * th_np[None, :]
+        FR = (4 * F2[name] - F1[name]) / 3
+        scale = np.max(np.abs(FR), axis=1)
+        assert np.all(scale > 0)
+        err = np.max(np.abs(A - FR), axis=1) / scale
+        err6 = np.max(np.abs(A - F6[name]), axis=1) / scale
+        print(f"L_{name}: Richardson (h = 1e-2, 5e-3) max {err.max():.2e} median {np.median(err):.2e}; "
+              f"h = 1e-6 plain max {err6.max():.2e} median {np.median(err6):.2e}", flush=True)
+        assert err.max() <= 1e-6, f"L_{name}: FD mismatch {err.max():.3e}"
+        assert np.median(err6) <= 3e-5
 
 
 def test_adjoint_full_size_every_point():
