@@ -48,6 +48,7 @@ struct PairLds {
       double fac[2][NS][kLanes];       // projected equilibrium: 1 / sqrt(o) and o per species (o = D / (1 - D))
     };
     double tile[2][NQP][NQP];        // per point, signed pair factors: [j][q] = +b if j > q, else -b
+    double2 ht[2][NQP];              // per point and node: (h 2^2c, 2^-2c / h), h = exp(-e / T)
   } u;
   struct Pt {                      // per-point state of the outer (matter) loop
     double dref[NS];               // ||D_s^[k,1]||_W^2 of the current inner loop
@@ -187,6 +188,10 @@ struct PairSolver {
       // two in g, T above ~0.12 MeV).  Otherwise (colder points) the signed
       // orientation form: +b(q, j) for j > q (q the lower node), -b(q, j)
       // otherwise, every entry a product of factors <= 1.
+      // Where the grid spans at most kDirectBits powers of two in g (T above
+      // ~0.22 MeV) every lane forms its whole row from the point's table of
+      // the scaled h and 1 / h (direct_row); otherwise the lanes fill the
+      // point's LDS tile, each unordered pair once, and read their rows back.
       double B[COUPLED ? NQ : 1];
       double hq = 0.0;  // exp(-e_q / T)
       double gq = 1.0, rgq = 1.0;  // g_q 2^c and 2^-c / g_q (symmetric form)
@@ -199,21 +204,32 @@ struct PairSolver {
         E.n2[q] = xs.n;
         hq = ldexp(xs.R * xs.R, -2 * xs.n);  // 2^(-2x) = exp(-e / T)
         __syncthreads();
+        // g = 2^-x with x = n + f increasing along the grid
+        const int nlo = E.n2[0], nhi = E.n2[NQ - 1];
+        const int c = (nlo + nhi) >> 1;
+        const bool direct = __builtin_amdgcn_readfirstlane((uint32_t)(
+                                __builtin_amdgcn_ballot_w64(run && nhi - nlo > kDirectBits) == 0)) != 0;
         if constexpr (PROJ) {
           sym = true;
         } else {
-          // g = 2^-x with x = n + f increasing along the grid
-          const int nlo = E.n2[0], nhi = E.n2[NQ - 1];
           sym = __builtin_amdgcn_readfirstlane(
                     (uint32_t)(__builtin_amdgcn_ballot_w64(run && nhi - nlo > kSymBits) == 0)) != 0;
-          const int c = (nlo + nhi) >> 1;
           gq = sym ? ldexp(xs.R, c - xs.n) : 1.0;
           rgq = sym ? ldexp(xs.P, xs.n - c) : 1.0;
         }
-        // pair factors of the point, each unordered pair (q, q + d mod 32)
-        // once: d = 1..15 by every lane, d = 16 by lanes q < 16 (the Anderson
-        // history is dead between inner loops, its space holds them)
-        {
+        if (direct) {
+          // the Anderson history is dead between inner loops: its space
+          // holds the point's table
+          const double gt = PROJ ? ldexp(xs.R, c - xs.n) : gq;
+          const double rgt = PROJ ? ldexp(xs.P, xs.n - c) : rgq;
+          const double ht = gt * gt, rht = rgt * rgt;
+          S.u.ht[h][q] = make_double2(ht, rht);
+          __syncthreads();
+          direct_row(S.u.ht[h], ht, rht, B);
+          __syncthreads();
+        } else {
+          // pair factors of the point, each unordered pair (q, q + d mod 32)
+          // once: d = 1..15 by every lane, d = 16 by lanes q < 16
           double (*T)[NQ] = S.u.tile[h];
           if (sym) {
             pair_tile_rows<true>(&T[0][0], E.P2, E.R2, E.n2, q, xs.P, xs.R, xs.n);

@@ -15,6 +15,24 @@ constexpr int NQP = 32;
 // the symmetric contraction: its scaled vectors and row factors then stay
 // within 2^(+-(kSymBits / 2 + 1)), far from overflow
 constexpr int kSymBits = 1800;
+// widest exponent range of g for which a lane forms its row of the
+// symmetric core directly from the squared scaled factors h = g^2 and 1 / h
+// (within 2^(+-(kDirectBits + 4)), inside the normal range)
+constexpr int kDirectBits = 1000;
+
+// Row q of the symmetric core B2(q, j) = exp(-|e_q - e_j| / T), q this
+// lane's node, from the point's table HT[j] = (h_j, 1 / h_j) of the scaled
+// h = exp(-e / T) 2^2c: of the two orientations h_j / h_q and h_q / h_j the
+// smaller is B2 (the other is its reciprocal, or overflows to +inf).  Every
+// lane of a half reads the same table entry (an LDS broadcast).  The
+// diagonal comes out as h_q / h_q, one to within two roundings.
+__device__ __forceinline__ void direct_row(const double2* __restrict__ HT, double hq, double rhq, double (&B)[32]) {
+#pragma unroll
+  for (int j = 0; j < 32; ++j) {
+    const double2 v = HT[j];
+    B[j] = min_f64(v.x * rhq, hq * v.y);
+  }
+}
 
 // Sums over the lane's half-wave of 2K values, in every lane of the half:
 // rows (0, 2) carry slot k, rows (1, 3) slot K + k, then a row butterfly and
