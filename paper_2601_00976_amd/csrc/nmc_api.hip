@@ -271,6 +271,7 @@ int nmc_model_create(const nmc_grid* g, const nmc_model_desc* d, nmc_model** out
   m.mu_ye0 = d->mu_ye0;
   m.mu_b = d->mu_b;
   m.mu_t0 = d->mu_t0;
+  m.inv_mu_t0 = 1.0 / d->mu_t0;
   const double pi = 3.14159265358979323846;
   const double hc = d->hc_mev_cm;
   m.kcoup = 4.0 * pi / (hc * hc * hc) * d->m_u_g / 1.0e11;

@@ -133,10 +133,13 @@ struct PairSolver {
       // ---- ComputeOpacities(y^[k]) --------------------------------------
       const double r3 = pt.r3;
       const double y0 = pt.y[0], y1 = pt.y[1];
-      const double T = fixedT ? pt.T_fix : (y1 - md->eos_b * ye43(y0) * r3) / (md->eos_a * (1.0 + y0));
+      // reciprocals by refined estimates (no IEEE division): the EOS is
+      // evaluated per lane once per outer iteration
+      const double T = fixedT ? pt.T_fix
+                              : (y1 - md->eos_b * ye43(y0) * r3) * rcp_nr(md->eos_a * (1.0 + y0));
       const double mu = (a.prm.fixed_matter && a.mu_fixed)
                             ? pt.mu_fix
-                            : md->mu_a * (y0 - md->mu_ye0) * r3 + md->mu_b * log(T / md->mu_t0);
+                            : md->mu_a * (y0 - md->mu_ye0) * r3 + md->mu_b * log_pos(T * md->inv_mu_t0);
       if (run && (!(T > 0.0) || !(y0 >= 0.0) || !isfinite(T) || !isfinite(mu))) {
         status = NMC_STATUS_EOS_DOMAIN;
         fatal = true;
@@ -145,7 +148,7 @@ struct PairSolver {
       if (run) pt.T_last = T;
       // a finished half keeps a harmless temperature
       const double Tu = run ? T : 1.0, muu = run ? mu : 0.0;
-      const double invT = 1.0 / Tu;
+      const double invT = rcp_nr(Tu);
       double baseD[NS], den0D[NS];
       // projected equilibrium and its complement at node q (every lane, both
       // halves: the element partner exchange is a DPP)
@@ -163,10 +166,12 @@ struct PairSolver {
 #pragma unroll
         for (int t = 0; t < NS; ++t) {
           const double chia = md->iemab[t] * emab_q;
-          double deq;
+          double deq = 0.0;
           if constexpr (PROJ) {
             deq = pD[t];
-          } else {
+          } else if (!(NS == 3 && t == 2)) {
+            // three species are nu_e, anti-nu_e, nu_x in this order, and
+            // nu_x has no emission or absorption (chia = 0): no equilibrium
             const double x = (epsq - md->imusign[t] * muu) * invT;
             const double ex = exp(-fabs(x));
             const double r = rcp_nr(1.0 + ex);

@@ -37,6 +37,7 @@ struct DevModel {
   double shape[kMaxNq];   // (eps / eps_ref)^chi_power
   double chi_ref, sigma_ratio;
   double eos_a, eos_b, mu_a, mu_ye0, mu_b, mu_t0;
+  double inv_mu_t0;       // 1 / mu_t0
   double kcoup;           // K * rho11 [MeV^-3]
   double rho11_min;
   double phi1_nes, phi1_pair;  // Phi_1 / Phi_0 of the NES and pair kernels

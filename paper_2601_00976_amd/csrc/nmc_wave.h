@@ -325,6 +325,37 @@ __device__ __forceinline__ double rcp_nr(double x) {
   return __builtin_fma(r, e, r);
 }
 
+// Natural logarithm of a positive finite double: x = m 2^e with m in
+// [sqrt(1/2), sqrt(2)), ln m = 2 atanh(s) = 2 (s + s^3 / 3 + ... + s^19 / 19)
+// with s = (m - 1) / (m + 1), |s| <= 0.1716 (the remainder of the series is
+// below 2^-53 of its sum), and e ln 2 split in a high part exact in the
+// product and a low part (Cody and Waite).  Within 2 ulp of the correctly
+// rounded value.  Not for x <= 0, inf or NaN.
+__device__ __forceinline__ double log_pos(double x) {
+  double m = __builtin_amdgcn_frexp_mant(x);  // [0.5, 1)
+  int e = __builtin_amdgcn_frexp_exp(x);
+  const bool lo = m < 0.70710678118654752440;
+  m = lo ? m + m : m;
+  e = lo ? e - 1 : e;
+  const double num = m - 1.0, den = m + 1.0;  // m - 1 exact
+  const double r = rcp_nr(den);
+  double s = num * r;
+  s = __builtin_fma(__builtin_fma(-s, den, num), r, s);
+  const double z = s * s;
+  double p = 1.0 / 19.0;
+  p = __builtin_fma(p, z, 1.0 / 17.0);
+  p = __builtin_fma(p, z, 1.0 / 15.0);
+  p = __builtin_fma(p, z, 1.0 / 13.0);
+  p = __builtin_fma(p, z, 1.0 / 11.0);
+  p = __builtin_fma(p, z, 1.0 / 9.0);
+  p = __builtin_fma(p, z, 1.0 / 7.0);
+  p = __builtin_fma(p, z, 1.0 / 5.0);
+  p = __builtin_fma(p, z, 1.0 / 3.0);
+  const double s2 = s + s, ef = (double)e;
+  constexpr double kLn2Hi = 6.93147180369123816490e-01, kLn2Lo = 1.90821492927058770002e-10;
+  return __builtin_fma(ef, kLn2Hi, s2 + __builtin_fma(ef, kLn2Lo, (s2 * z) * p));
+}
+
 // Coefficients (g1, g2) of an Anderson step over two difference columns
 // (1 the older, 2 the newer) from their normal equations, by LDL^T (the
 // Cholesky pivots G11 and G22 - G12^2 / G11, without square roots).  A pivot
