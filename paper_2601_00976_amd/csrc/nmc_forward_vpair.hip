@@ -34,6 +34,7 @@ struct VPairLds {
   union {
     double hist[4][4 * NS][kLanes];  // Anderson history per owned moment: Q_prev, F_prev, dQ_old, dF_old
     double tile[2][NQP][NQP];        // per point, pair factors (see the static two-point kernel)
+    double2 ht[2][NQP];              // per point and node: (h 2^2c, 2^-2c / h), h = exp(-e / T)
   } u;
   struct Pt {  // per-point state of the outer (matter) loop
     double dref[NS];  // ||D_s^[k,1]||_W^2 of the current inner loop
@@ -47,7 +48,7 @@ struct VPairLds {
 __device__ __forceinline__ double temperature_v(const_ptr<DevModel> md, const double* y, double r3) {
   const double v2 = y[2] * y[2] + y[3] * y[3] + y[4] * y[4];
   const double e = y[1] - 0.5 * kMuC2v * v2;
-  return (e - md->eos_b * ye43(y[0]) * r3) / (md->eos_a * (1.0 + y[0]));
+  return (e - md->eos_b * ye43(y[0]) * r3) * rcp_nr(md->eos_a * (1.0 + y[0]));
 }
 
 // The lane's contributions to the Eulerian integrals (N, E, F_1, F_2, F_3) of
@@ -190,10 +191,10 @@ struct VPairSolver {
       if (run) k_done = k;
       // ---- ComputeOpacities(y^[k]) --------------------------------------
       const double v[3] = {pt.y[2], pt.y[3], pt.y[4]};
-      const double lam = 1.0 / (1.0 + sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]));
+      const double lam = rcp_nr(1.0 + sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]));
       const double T = temperature_v(md, a.prm.fixed_matter ? pt.yst : pt.y, pt.r3);
       const double y0 = pt.y[0];
-      const double mu = md->mu_a * (y0 - md->mu_ye0) * pt.r3 + md->mu_b * log(T / md->mu_t0);
+      const double mu = md->mu_a * (y0 - md->mu_ye0) * pt.r3 + md->mu_b * log_pos(T * md->inv_mu_t0);
       if (run && (!(T > 0.0) || !(y0 >= 0.0) || !isfinite(T) || !isfinite(mu))) {
         status = NMC_STATUS_EOS_DOMAIN;
         fatal = true;
@@ -206,7 +207,7 @@ struct VPairSolver {
       }
       // a finished half keeps a harmless temperature
       const double Tu = run ? T : 1.0, muu = run ? mu : 0.0;
-      const double invT = 1.0 / Tu;
+      const double invT = rcp_nr(Tu);
       const double ldt = lam * dtau, oml = 1.0 - lam;
       const double epsq = mt.eps[q];
       // per species: lam (N* + dtau chi^EmAb D_eq), 1 + lam dtau chi^EmAb and
@@ -219,10 +220,15 @@ struct VPairSolver {
 #pragma unroll
         for (int t = 0; t < NS; ++t) {
           const double chia = md->iemab[t] * emab_q;
-          const double x = (epsq - md->imusign[t] * muu) * invT;
-          const double ex = exp(-fabs(x));
-          const double r = rcp_nr(1.0 + ex);
-          const double deq = x > 0.0 ? ex * r : r;
+          double deq = 0.0;
+          if (!(NS == 3 && t == 2)) {
+            // three species are nu_e, anti-nu_e, nu_x in this order, and
+            // nu_x has no emission or absorption (chia = 0): no equilibrium
+            const double x = (epsq - md->imusign[t] * muu) * invT;
+            const double ex = exp(-fabs(x));
+            const double r = rcp_nr(1.0 + ex);
+            deq = x > 0.0 ? ex * r : r;
+          }
           baseD[t] = lam * (Nst[t] + dtau * (chia * deq));
           denD[t] = 1.0 + ldt * chia;
           denI[t] = 1.0 + ldt * (chia + sig);
@@ -241,15 +247,22 @@ struct VPairSolver {
         E.n2[q] = xs.n;
         hq = ldexp(xs.R * xs.R, -2 * xs.n);  // exp(-e / T)
         __syncthreads();
-        {
-          const int nlo = E.n2[0], nhi = E.n2[NQ - 1];
-          sym = __builtin_amdgcn_readfirstlane(
-                    (uint32_t)(__builtin_amdgcn_ballot_w64(run && nhi - nlo > kSymBits) == 0)) != 0;
-          const int c = (nlo + nhi) >> 1;
-          gq = sym ? ldexp(xs.R, c - xs.n) : 1.0;
-          rgq = sym ? ldexp(xs.P, xs.n - c) : 1.0;
-        }
-        {
+        const int nlo = E.n2[0], nhi = E.n2[NQ - 1];
+        const int c = (nlo + nhi) >> 1;
+        sym = __builtin_amdgcn_readfirstlane(
+                  (uint32_t)(__builtin_amdgcn_ballot_w64(run && nhi - nlo > kSymBits) == 0)) != 0;
+        const bool direct = __builtin_amdgcn_readfirstlane((uint32_t)(
+                                __builtin_amdgcn_ballot_w64(run && nhi - nlo > kDirectBits) == 0)) != 0;
+        gq = sym ? ldexp(xs.R, c - xs.n) : 1.0;
+        rgq = sym ? ldexp(xs.P, xs.n - c) : 1.0;
+        if (direct) {
+          // rows of the symmetric core from the point's table of scaled h
+          const double ht = gq * gq, rht = rgq * rgq;
+          S.u.ht[h][q] = make_double2(ht, rht);
+          __syncthreads();
+          direct_row(S.u.ht[h], ht, rht, B);
+          __syncthreads();
+        } else {
           double (*Tt)[NQ] = S.u.tile[h];
           if (sym) {
             pair_tile_rows<true>(&Tt[0][0], E.P2, E.R2, E.n2, q, xs.P, xs.R, xs.n);
