@@ -59,6 +59,27 @@ __device__ __forceinline__ void lds_write2_f64(uint32_t base, double a, double b
                : "memory");
 }
 
+// R[J + i] += bcast_{L + i}(u) b + bcast_{L + i}(w) a for i = 0..3, the
+// column values u, w taken from lane L + i of the lane's 16-lane row
+// (v_fmac_f64_dpp row_newbcast): the b term first, then the a term, each one
+// rounding.  The leading s_nop covers a VALU write of u or w just before.
+template <int L>
+__device__ __forceinline__ void elim_cols4(double& r0, double& r1, double& r2, double& r3, double u, double w,
+                                           double a, double b) {
+  asm volatile(
+      "s_nop 1\n"
+      "v_fmac_f64_dpp %0, %5, %7 row_newbcast:%8 row_mask:0xf bank_mask:0xf\n"
+      "v_fmac_f64_dpp %1, %5, %7 row_newbcast:%9 row_mask:0xf bank_mask:0xf\n"
+      "v_fmac_f64_dpp %2, %5, %7 row_newbcast:%10 row_mask:0xf bank_mask:0xf\n"
+      "v_fmac_f64_dpp %3, %5, %7 row_newbcast:%11 row_mask:0xf bank_mask:0xf\n"
+      "v_fmac_f64_dpp %0, %4, %6 row_newbcast:%8 row_mask:0xf bank_mask:0xf\n"
+      "v_fmac_f64_dpp %1, %4, %6 row_newbcast:%9 row_mask:0xf bank_mask:0xf\n"
+      "v_fmac_f64_dpp %2, %4, %6 row_newbcast:%10 row_mask:0xf bank_mask:0xf\n"
+      "v_fmac_f64_dpp %3, %4, %6 row_newbcast:%11 row_mask:0xf bank_mask:0xf\n"
+      : "+v"(r0), "+v"(r1), "+v"(r2), "+v"(r3)
+      : "v"(u), "v"(w), "v"(a), "v"(b), "i"(L), "i"(L + 1), "i"(L + 2), "i"(L + 3));
+}
+
 // Solves A^T z = c for one diagonal block of size N (lanes 0..N-1 active):
 // lane r enters with R = row r of A^T and c = (c0, c1) its right-hand sides
 // and leaves with (z0, z1) = entry r of the two solutions.  Returns false if
@@ -73,22 +94,28 @@ __device__ __forceinline__ void lds_write2_f64(uint32_t base, double a, double b
 // leaving a margin W_p (1 + dtau chi^EmAb_p)); elimination without pivoting is
 // stable for such matrices, and their diagonal blocks and Schur complements
 // stay dominant, so every 2 x 2 pivot block is nonsingular.  Step k (even)
-// broadcasts rows k and k+1 of A^T (lanes k and k+1) through two LDS row
-// buffers: the two lanes write their entries k+2..N-1 and right-hand sides,
-// every lane reads them back as 16-byte broadcasts and removes both rows with
-// the multipliers [R[k], R[k+1]] B^-1 of the pivot block B.  A single
-// wavefront runs the work-group, so its LDS accesses complete in program
-// order and no barrier is needed.  Back substitution solves the 2 x 2
-// diagonal blocks from the last.
+// removes rows k and k+1 of A^T (lanes k and k+1) from the rows below with
+// the multipliers [R[k], R[k+1]] B^-1 of the pivot block B.  The two lanes
+// write their rows (from column k on) and right-hand sides to two LDS row
+// buffers; every lane then loads, per group of 16 columns, one entry of each
+// pivot row (lane L of a 16-lane row loads column 16 g + L), and the update
+// FMAs take column 16 g + L from lane L of the lane's row by DPP broadcast.
+// All lanes run the FMAs (a DPP source lane must be active); rows k + 1 and
+// above have zero multipliers, so their entries are unchanged.  The columns
+// of a group left of k + 2 are updated too: for rows below the pivot they are
+// the eliminated part, never read again.  A single wavefront runs the
+// work-group, so its LDS accesses complete in program order and no barrier is
+// needed.  Back substitution solves the 2 x 2 diagonal blocks from the last.
 template <int N>
 __device__ __forceinline__ bool solve_block_transposed(double (&R)[N], double c0, double c1, double& z0,
                                                        double& z1, double* prow_generic) {
-  static_assert(N % 2 == 0, "2 x 2 pivot blocks");
+  static_assert(N % 16 == 0, "2 x 2 pivot blocks, 16-column groups");
   typedef double f64x2 __attribute__((ext_vector_type(2)));
   typedef __attribute__((address_space(3))) double lds_f64;
   typedef __attribute__((address_space(3))) f64x2 lds_f64x2;
   constexpr int RS = N + 2;  // doubles per row buffer: entries 0..N-1, right-hand sides at N, N+1
   const int lane = opaque((int)threadIdx.x);
+  const int col = lane & 15;
   static_for<0, N / 2>([&](auto kk) __attribute__((always_inline)) {
     constexpr int k = 2 * decltype(kk)::value;
     lds_f64* prow = (lds_f64*)prow_generic;
@@ -97,29 +124,30 @@ __device__ __forceinline__ bool solve_block_transposed(double (&R)[N], double c0
     const double a00 = readlane_f64(R[k], k), a01 = readlane_f64(R[k + 1], k);
     const double a10 = readlane_f64(R[k], k + 1), a11 = readlane_f64(R[k + 1], k + 1);
     if (lane == k || lane == k + 1) {
-      // rows k and k+1 to their buffers: ds_write2_b64 from one base register
-      // per lane with 8-byte-unit offsets
+      // rows k and k+1 (columns k..N-1) to their buffers: ds_write2_b64 from
+      // one base register per lane with 8-byte-unit offsets
       const uint32_t base = (uint32_t)(uintptr_t)prow + (uint32_t)((lane - k) * RS * 8);
-      static_for<0, (N - k - 2) / 2>([&](auto ii) __attribute__((always_inline)) {
-        constexpr int j = k + 2 + 2 * decltype(ii)::value;
+      static_for<0, (N - k) / 2>([&](auto ii) __attribute__((always_inline)) {
+        constexpr int j = k + 2 * decltype(ii)::value;
         lds_write2_f64<j>(base, R[j], R[j + 1]);
       });
       lds_write2_f64<N>(base, c0, c1);
     }
-    if (lane > k + 1) {
-      const double rdet = rcp_nr(a00 * a11 - a01 * a10);
-      const double l0 = (R[k] * a11 - R[k + 1] * a10) * rdet;
-      const double l1 = (R[k + 1] * a00 - R[k] * a01) * rdet;
-#pragma unroll
-      for (int j = k + 2; j < N; j += 2) {
-        const f64x2 u = prow2[j / 2], v = prow2[(RS + j) / 2];
-        R[j] = __builtin_fma(-l0, u.x, __builtin_fma(-l1, v.x, R[j]));
-        R[j + 1] = __builtin_fma(-l0, u.y, __builtin_fma(-l1, v.y, R[j + 1]));
-      }
-      const f64x2 cu = prow2[N / 2], cv = prow2[(RS + N) / 2];
-      c0 = __builtin_fma(-l0, cu.x, __builtin_fma(-l1, cv.x, c0));
-      c1 = __builtin_fma(-l0, cu.y, __builtin_fma(-l1, cv.y, c1));
-    }
+    const double rdet = rcp_nr(a00 * a11 - a01 * a10);
+    const bool below = lane > k + 1;
+    const double nl0 = below ? -((R[k] * a11 - R[k + 1] * a10) * rdet) : 0.0;
+    const double nl1 = below ? -((R[k + 1] * a00 - R[k] * a01) * rdet) : 0.0;
+    static_for<(k + 2) / 16, N / 16>([&](auto gg) __attribute__((always_inline)) {
+      constexpr int g = decltype(gg)::value;
+      const double u = prow[16 * g + col], w = prow[RS + 16 * g + col];
+      static_for<0, 4>([&](auto qq) __attribute__((always_inline)) {
+        constexpr int j = 16 * g + 4 * decltype(qq)::value;
+        elim_cols4<j % 16>(R[j], R[j + 1], R[j + 2], R[j + 3], u, w, nl0, nl1);
+      });
+    });
+    const f64x2 cu = prow2[N / 2], cv = prow2[(RS + N) / 2];
+    c0 = __builtin_fma(nl0, cu.x, __builtin_fma(nl1, cv.x, c0));
+    c1 = __builtin_fma(nl0, cu.y, __builtin_fma(nl1, cv.y, c1));
   });
   // back substitution by 2 x 2 blocks from the last: z of rows k, k+1 from
   // their (reduced) right-hand sides, then every row above removes its terms
