@@ -448,32 +448,44 @@ struct PairSolver {
       }
       if (ran) total_inner += l_done;
       if (run && !cvd) inner_failed = true;
-      // the reference norms of the next inner loop (applied after a failed
-      // loop: the norm of the current moments) and the sums of the matter
-      // right-hand side (Eq. implicitFluidNodal at v = 0) in one reduction
+      // the sums of the matter right-hand side (Eq. implicitFluidNodal at
+      // v = 0) and, where a running point's inner loop failed, the reference
+      // norms of its next inner loop (the norm of the current moments) in one
+      // reduction.  A converged loop took its reference from the convergence
+      // test's norm of the same moments, which this reduction would reproduce
+      // bit for bit (every slot of the half-wave sums runs the same tree).
       double yq0, yq1;
       {
-        constexpr int KR = (NS + 3) / 2;
         const double w3 = mt.w3[q];
-        double v[2 * KR], s[2 * KR], m0 = 0.0, m1 = 0.0;
+        double m0 = 0.0, m1 = 0.0;
 #pragma unroll
         for (int t = 0; t < NS; ++t) {
-          v[t] = w2q * D[t] * D[t];
           const double dd = D[t] - Dst[t];
           m0 += md->ig[t] * w2q * dd;
           m1 += md->imult[t] * w3 * dd;
         }
-        v[NS] = m0;
-        v[NS + 1] = m1;
+        if (__builtin_amdgcn_ballot_w64(run && !cvd) != 0) {
+          constexpr int KR = (NS + 3) / 2;
+          double v[2 * KR], s[2 * KR];
 #pragma unroll
-        for (int t = NS + 2; t < 2 * KR; ++t) v[t] = 0.0;
-        half_own_sums<KR>(v, s);
-        if (run && !cvd) {
+          for (int t = 0; t < NS; ++t) v[t] = w2q * D[t] * D[t];
+          v[NS] = m0;
+          v[NS + 1] = m1;
 #pragma unroll
-          for (int t = 0; t < NS; ++t) pt.dref[t] = s[t];
+          for (int t = NS + 2; t < 2 * KR; ++t) v[t] = 0.0;
+          half_own_sums<KR>(v, s);
+          if (run && !cvd) {
+#pragma unroll
+            for (int t = 0; t < NS; ++t) pt.dref[t] = s[t];
+          }
+          yq0 = pt.ye_st - pt.K * s[NS];
+          yq1 = pt.e_st - pt.K * s[NS + 1];
+        } else {
+          double v[2] = {m0, m1}, s[2];
+          half_own_sums<1>(v, s);
+          yq0 = pt.ye_st - pt.K * s[0];
+          yq1 = pt.e_st - pt.K * s[1];
         }
-        yq0 = pt.ye_st - pt.K * s[NS];
-        yq1 = pt.e_st - pt.K * s[NS + 1];
       }
       if (a.prm.fixed_matter) {
         if (run) outer_conv = true;
