@@ -291,13 +291,25 @@ def cpu_baseline(repeats: int, threads: int, all_points: bool = False):
     t1 = time.perf_counter()
     solved1, _ = chain(sub, 1)
     dt1 = time.perf_counter() - t1
+    # the oracle's own operation count (counting build) on every 64th profile
+    # point of the first step, beside the convention's FLOPs for the same
+    # point-solves
+    O.build_tally(force=False)
+    tp = d.take(np.arange(0, P_POINTS, 64))
+    D0, I0, e0 = m.init_state(tp.T, tp.rho11, tp.ye, tp.uD, tp.uI)
+    r, c = O.flop_tally(m, O.Params(), theta, W.DTAU_KM, D0, I0, tp.rho11, tp.ye, e0)
+    conv = float(np.sum(flops_per_point(r["n_inner"].astype(np.float64), r["n_outer"].astype(np.float64), 32)))
+    ora = c["add"] + c["mul"] + c["div"]
+    tally = {"sample": f"every 64th profile point, step 1: {int(np.sum(r['n_outer'] > 0))} solves",
+             "oracle_flops": ora, "convention_flops": conv, "oracle_over_convention": ora / conv,
+             "oracle_sqrt": c["sqrt"], "oracle_transcendental_calls": c["trans"]}
     return dict(value=solved / dt, unit="point-solves/s", cores=threads, kind="oracle",
                 sample=f"all {P_POINTS} profile points, {STEPS_PER_GRAPH} chained steps x {repeats}, "
                        f"{solved} solves in {dt:.1f} s",
                 one_core={"value": solved1 / dt1, "unit": "point-solves/s", "cores": 1,
                           "sample": f"every 16th profile point, {STEPS_PER_GRAPH} chained steps, {solved1} solves "
                                     f"in {dt1:.1f} s"},
-                _flops_per_chain=flops_chain)
+                flop_tally=tally, _flops_per_chain=flops_chain)
 
 
 def adjoint_ratio(model, params, theta, D0, I0, t, e0, ws, launch, reps=5):

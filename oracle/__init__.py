@@ -17,6 +17,8 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liboracle_nmc.so")
 SRC = os.path.join(HERE, "nmc_oracle.c")
+TALLY_PATH = os.path.join(HERE, "liboracle_tally.so")
+TALLY_SRC = os.path.join(HERE, "flop_tally.cpp")
 
 MAX_NQ = 64
 MAX_NS = 3
@@ -61,7 +63,20 @@ class _Params(C.Structure):
     ]
 
 
+def build_tally(force: bool = True) -> str:
+    """Compile the counting build of the oracle (flop_tally.cpp: the same
+    source with every double replaced by an operation-counting wrapper)."""
+    if force or not os.path.exists(TALLY_PATH):
+        tmp = TALLY_PATH + ".tmp"
+        cmd = ["g++", "-O2", "-ffp-contract=off", "-fopenmp", "-fpermissive", "-std=c++17", "-w",
+               "-shared", "-fPIC", TALLY_SRC, "-o", tmp, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, TALLY_PATH)
+    return TALLY_PATH
+
+
 _lib = None
+_tally = None
 
 
 def lib():
@@ -69,7 +84,26 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             build()
-        L = C.CDLL(LIB_PATH)
+        _lib = _load(LIB_PATH)
+    return _lib
+
+
+def tally_lib():
+    """The counting build (same C ABI, plus ora_tally_read / ora_tally_reset)."""
+    global _tally
+    if _tally is None:
+        if not os.path.exists(TALLY_PATH):
+            build_tally()
+        L = _load(TALLY_PATH)
+        L.ora_tally_read.argtypes = [np.ctypeslib.ndpointer(dtype=np.uint64, flags="C_CONTIGUOUS")]
+        L.ora_tally_reset.argtypes = []
+        _tally = L
+    return _tally
+
+
+def _load(path):
+    if True:
+        L = C.CDLL(path)
         dp = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
         ip = np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS")
         vp = C.c_void_p
@@ -121,8 +155,7 @@ def lib():
         L.ora_solve_batch_v.argtypes = [C.POINTER(_Model), C.POINTER(_Params), dp, C.c_long, C.c_double,
                                         dp, dp, dp, dp, dp, dp, vp,
                                         dp, dp, dp, dp, dp, dp, ip, ip, ip, C.c_int]
-        _lib = L
-    return _lib
+    return L
 
 
 def _vp(a):
@@ -311,8 +344,10 @@ def anderson(Qh, Fh):
 
 
 def solve_batch(model: Model, params: Params, theta, dtau, D0, I0, rho11, ye0, e0, chi0=None,
-                T_fixed=None, mu_fixed=None, nthreads: int = 0):
-    """Batched forward solve (Algorithm neutrinoMatterCoupling), one point per item."""
+                T_fixed=None, mu_fixed=None, nthreads: int = 0, library=None):
+    """Batched forward solve (Algorithm neutrinoMatterCoupling), one point per item.
+    ``library``: the loaded oracle build to run (default lib(); tally_lib()
+    for the operation count, with nthreads = 1)."""
     D0 = _f64(D0)
     P = D0.shape[0]
     nn = model.ns * model.nq
@@ -323,13 +358,26 @@ def solve_batch(model: Model, params: Params, theta, dtau, D0, I0, rho11, ye0, e
     T_fixed = None if T_fixed is None else _f64(T_fixed)
     mu_fixed = None if mu_fixed is None else _f64(mu_fixed)
     pc = params.c()
-    rc = lib().ora_solve_batch(model.ref(), C.byref(pc), _f64(theta), P, dtau, D0.ravel(),
+    rc = (library or lib()).ora_solve_batch(model.ref(), C.byref(pc), _f64(theta), P, dtau, D0.ravel(),
                                _f64(I0).ravel(), _f64(rho11), _f64(ye0), _f64(e0), _vp(chi0),
                                _vp(T_fixed), _vp(mu_fixed), D, I, ye, e, T, no, ni, st, nthreads)
     if rc != 0:
         raise ValueError("oracle rejected the arguments")
     shp = (P, model.ns, model.nq)
     return dict(D=D.reshape(shp), I=I.reshape(shp), ye=ye, e=e, T=T, n_outer=no, n_inner=ni, status=st)
+
+
+def flop_tally(model: Model, params: Params, theta, dtau, D0, I0, rho11, ye0, e0):
+    """Runs the forward solve through the counting build on one thread and
+    returns (result, counts) with counts = {add, mul, div, sqrt, trans}:
+    the additions/subtractions, products, quotients, square roots and
+    transcendental calls the oracle performed."""
+    L = tally_lib()
+    L.ora_tally_reset()
+    r = solve_batch(model, params, theta, dtau, D0, I0, rho11, ye0, e0, nthreads=1, library=L)
+    c = np.zeros(5, dtype=np.uint64)
+    L.ora_tally_read(c)
+    return r, dict(zip(("add", "mul", "div", "sqrt", "trans"), (int(x) for x in c)))
 
 
 def adjoint_batch(model: Model, theta, dtau, rho11, D, ye, e, gbar, chi0=None, per_point=False,
