@@ -230,7 +230,8 @@ def run_velocity(args):
             "algorithmic_hbm_gbs": bytes_per_point_v() * P_POINTS / kern_s / 1e9,
         },
     }
-    fma_peak = S.probe_fma_tflops(dev)
+    from paper_2601_00976_amd import probe as PR
+    fma_peak = PR.fma_tflops(dev)
     line["roofline"]["measured_fma_peak"] = fma_peak
     line["roofline"]["frac_of_measured_fma_peak"] = achieved / fma_peak
     if not args.no_cpu:
@@ -567,7 +568,8 @@ def main():
         },
     }
     # the denominator checked on this device: a pure FP64 FMA probe
-    fma_peak = S.probe_fma_tflops(dev)
+    from paper_2601_00976_amd import probe as PR
+    fma_peak = PR.fma_tflops(dev)
     line["roofline"]["measured_fma_peak"] = fma_peak
     line["roofline"]["frac_of_measured_fma_peak"] = achieved / fma_peak
     if nq == 32 and not args.no_adjoint and not args.all_points and not args.fd_projection:

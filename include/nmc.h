@@ -381,17 +381,6 @@ int nmc_init_state(const nmc_model* m, int64_t P, const double* T, const double*
                    const double* rho11, const double* ye, const double* uD, const double* uI,
                    double a, double b, double c, double* D0, double* I0, double* e0, void* stream);
 
-/* FP64 FMA throughput probe (measurement of the roofline denominator, not
- * part of the solve).  Launches `waves` work-groups of one wavefront each;
- * every lane runs R rounds of 16 independent FMA chains (x <- x a + b), R =
- * `iters` rounded up to a multiple of 8 (8 rounds per loop trip), i.e.
- * 32 R FLOP per lane and waves * 64 * 32 * R FLOP in total, and writes its
- * 16 chain values' sum to out[lane] (out: device array of waves * 64
- * doubles, caller-owned), so that no FMA is dead.  The caller times the launch on `stream`.
- * NMC_E_INVALID_ARG for waves < 1, waves > 2^20, iters < 1, iters > 2^24 or
- * a null out. */
-int nmc_probe_fma_f64(int64_t waves, int iters, double* out, void* stream);
-
 const char* nmc_error_string(int code);
 const char* nmc_last_error(void);
 

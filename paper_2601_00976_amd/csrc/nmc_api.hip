@@ -769,38 +769,11 @@ int nmc_init_state(const nmc_model* m, int64_t P, const double* T, const double*
   return e == hipSuccess ? NMC_OK : hip_fail(e, "init_state: launch");
 }
 
-int nmc_probe_fma_f64(int64_t waves, int iters, double* out, void* stream) {
-  if (waves < 1 || waves > (int64_t(1) << 20) || iters < 1 || iters > (1 << 24) || !out)
-    return fail(NMC_E_INVALID_ARG, "probe_fma_f64: waves in [1, 2^20], iters in [1, 2^24], out non-null");
-  hipError_t e = nmc::launch_probe_fma(waves, iters, out, (hipStream_t)stream);
-  return e == hipSuccess ? NMC_OK : hip_fail(e, "probe_fma_f64: launch");
-}
-
 }  // extern "C"
 
 // ---------------------------------------------------------------------------
 namespace nmc {
 namespace {
-
-// 16 independent FMA chains per lane, 8 rounds per loop trip
-__global__ __launch_bounds__(64) void probe_fma_kernel(int iters, double* __restrict__ out) {
-  const int64_t l = (int64_t)blockIdx.x * 64 + threadIdx.x;
-  double x[16];
-#pragma unroll
-  for (int k = 0; k < 16; ++k) x[k] = 1.0 + 1e-3 * k + 1e-9 * (double)threadIdx.x;
-  const double a = 0.9999999, b = 1e-7;
-  for (int i = 0; i < iters; i += 8) {
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
-#pragma unroll
-      for (int k = 0; k < 16; ++k) x[k] = __builtin_fma(x[k], a, b);
-    }
-  }
-  double s = 0.0;
-#pragma unroll
-  for (int k = 0; k < 16; ++k) s += x[k];
-  out[l] = s;
-}
 
 // one thread per (point, species, node)
 __global__ void init_state_kernel(const DevModel* __restrict__ md, int ns, int nq, int64_t P,
@@ -829,12 +802,6 @@ __global__ void init_state_kernel(const DevModel* __restrict__ md, int ns, int n
 }
 
 }  // namespace
-
-hipError_t launch_probe_fma(int64_t waves, int iters, double* out, hipStream_t s) {
-  const int rounds = (iters + 7) / 8 * 8;
-  hipLaunchKernelGGL(probe_fma_kernel, dim3((unsigned)waves), dim3(64), 0, s, rounds, out);
-  return hipGetLastError();
-}
 
 hipError_t launch_init_state(const DevModel* mdl, int ns, int nq, int64_t P, const double* T, const double* mu,
                              const double* rho11, const double* ye, const double* uD, const double* uI, double a,

@@ -132,8 +132,7 @@ hipError_t launch_pdars_stage3(const PdarsArgs& a, int num_cu, hipStream_t s);
 hipError_t launch_pdars_merge(int64_t P, int nn, const int32_t* no2, const int32_t* ni2, const int32_t* st2,
                               const int32_t* iters, int32_t* n_outer, int32_t* n_inner, int32_t* status, int num_cu,
                               hipStream_t s);
-// FP64 FMA throughput probe (measurement only)
-hipError_t launch_probe_fma(int64_t waves, int iters, double* out, hipStream_t s);
+// near-equilibrium initial state from raw draws
 hipError_t launch_init_state(const DevModel* mdl, int ns, int nq, int64_t P, const double* T, const double* mu,
                              const double* rho11, const double* ye, const double* uD, const double* uI, double a,
                              double b, double c, double* D0, double* I0, double* e0, hipStream_t s);

@@ -11,6 +11,7 @@ import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libnmc.so")
+PROBE_LIB_PATH = os.path.join(HERE, "libnmc_probe.so")
 
 NMC_OK = 0
 NMC_E_INVALID_ARG = -1
@@ -30,7 +31,7 @@ EXPORTED = (
     "nmc_grid_destroy", "nmc_model_create", "nmc_model_destroy", "nmc_workspace_bytes", "nmc_kernel_store_bytes",
     "nmc_solve_batch", "nmc_solve_batch_noalloc", "nmc_solve_batch_v", "nmc_solve_batch_adjoint",
     "nmc_c2p_params_default", "nmc_primitive_recovery", "nmc_pdars_workspace_bytes", "nmc_pdars_step_v",
-    "nmc_init_state", "nmc_probe_fma_f64", "nmc_error_string",
+    "nmc_init_state", "nmc_error_string",
     "nmc_last_error",
 )
 
@@ -128,14 +129,13 @@ def lib():
                                               C.POINTER(BatchOut), vp, vp, vp, vp, C.c_size_t, vp]
         L.nmc_init_state.argtypes = [vp, C.c_int64, vp, vp, vp, vp, vp, vp, C.c_double, C.c_double, C.c_double,
                                      vp, vp, vp, vp]
-        L.nmc_probe_fma_f64.argtypes = [C.c_int64, C.c_int, vp, vp]
         L.nmc_error_string.argtypes = [C.c_int]
         L.nmc_error_string.restype = C.c_char_p
         L.nmc_last_error.argtypes = []
         L.nmc_last_error.restype = C.c_char_p
         for f in ("nmc_grid_create", "nmc_grid_query", "nmc_grid_destroy", "nmc_model_create", "nmc_model_destroy",
                   "nmc_solve_batch", "nmc_solve_batch_noalloc", "nmc_solve_batch_v", "nmc_solve_batch_adjoint", "nmc_init_state",
-                  "nmc_primitive_recovery", "nmc_pdars_step_v", "nmc_probe_fma_f64"):
+                  "nmc_primitive_recovery", "nmc_pdars_step_v"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib

@@ -409,28 +409,6 @@ def init_state(model: Model, T, rho11, ye, uD, uI, a=1.0, b=0.1, c=0.1, mu=None,
     return D0, I0, e0
 
 
-def probe_fma_tflops(device="cuda", waves=None, iters=4096, reps=3):
-    """Measured FP64 FMA throughput of the device (TFLOP/s, best of `reps`):
-    nmc_probe_fma_f64 with 8 one-wavefront work-groups per SIMD, timed with
-    HIP events on the current stream."""
-    props = torch.cuda.get_device_properties(device)
-    if waves is None:
-        waves = props.multi_processor_count * 4 * 8
-    iters = (iters + 7) // 8 * 8
-    out = torch.empty(waves * 64, dtype=torch.float64, device=device)
-    stream = torch.cuda.current_stream(device)
-    best = 0.0
-    for _ in range(reps + 1):
-        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        a.record(stream)
-        N.check(N.lib().nmc_probe_fma_f64(waves, iters, out.data_ptr(), _stream_handle(stream)))
-        b.record(stream)
-        b.synchronize()
-        flops = waves * 64.0 * 32.0 * iters
-        best = max(best, flops / (a.elapsed_time(b) * 1e-3) / 1e12)
-    return best
-
-
 def to_device(draws, device="cuda"):
     """Move a workloads.Draws bundle to the GPU as float64 tensors."""
     f = lambda x: None if x is None else torch.as_tensor(x, dtype=torch.float64, device=device).contiguous()

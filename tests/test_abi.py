@@ -1,6 +1,7 @@
 """C-ABI checks that need no GPU: the library loads, exports every function
 declared in include/nmc.h, builds energy grids on the host and rejects bad
-arguments before touching the device."""
+arguments before touching the device; likewise the measurement library of the
+FMA probe (include/nmc_probe.h), which the solver library does not export."""
 import ctypes as C
 import os
 import re
@@ -13,8 +14,8 @@ from paper_2601_00976_amd import native as N
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
-def declared_functions():
-    src = open(os.path.join(ROOT, "include", "nmc.h")).read()
+def declared_functions(header="nmc.h"):
+    src = open(os.path.join(ROOT, "include", header)).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
     return sorted(set(re.findall(r"\b(nmc_[a-z_0-9]+)\s*\(", src)))
 
@@ -26,6 +27,15 @@ def test_exports_every_declared_symbol():
     for n in names:
         assert hasattr(L, n), n
     assert set(names) == set(N.EXPORTED)
+    assert not hasattr(L, "nmc_probe_fma_f64")
+
+
+def test_probe_library_exports_and_checks():
+    from paper_2601_00976_amd import probe as PR
+    L = PR.lib()
+    assert declared_functions("nmc_probe.h") == ["nmc_probe_fma_f64"]
+    for waves, iters, out in ((0, 8, 1), (1, 0, 1), (1, 8, None), (1 << 21, 8, 1)):
+        assert L.nmc_probe_fma_f64(waves, iters, out, None) == N.NMC_E_INVALID_ARG
 
 
 def _grid(**kw):
@@ -90,8 +100,6 @@ def test_solve_rejects_null_arguments_before_launch():
     assert L.nmc_error_string(N.NMC_E_UNSUPPORTED) == b"unsupported configuration"
     rc = L.nmc_init_state(None, 1, None, None, None, None, None, None, 1.0, 0.1, 0.1, None, None, None, None)
     assert rc == N.NMC_E_INVALID_ARG
-    for waves, iters, out in ((0, 8, 1), (1, 0, 1), (1, 8, None), (1 << 21, 8, 1)):
-        assert L.nmc_probe_fma_f64(waves, iters, out, None) == N.NMC_E_INVALID_ARG
 
 
 def test_default_descriptors():

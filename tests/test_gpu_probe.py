@@ -11,13 +11,12 @@ pytestmark = pytest.mark.gpu
 def test_probe_values_and_rate():
     import torch
 
-    from paper_2601_00976_amd import native as N
-    from paper_2601_00976_amd import solver as S
+    from paper_2601_00976_amd import probe as PR
 
     print("probe: 4 waves x 64 lanes, 64 rounds; then the default rate probe", flush=True)
     waves, iters = 4, 64
     out = torch.empty(waves * 64, dtype=torch.float64, device="cuda")
-    N.check(N.lib().nmc_probe_fma_f64(waves, iters, out.data_ptr(), None))
+    PR.fma_f64(waves, iters, out)
     torch.cuda.synchronize()
     lane = np.arange(waves * 64) % 64
     a, b = 0.9999999, 1e-7
@@ -28,5 +27,5 @@ def test_probe_values_and_rate():
             x = x * a + b
         ref += x
     assert np.allclose(out.cpu().numpy(), ref, rtol=1e-13, atol=0)
-    tf = S.probe_fma_tflops("cuda")
+    tf = PR.fma_tflops("cuda")
     assert 20.0 < tf < 100.0, tf
