@@ -265,6 +265,11 @@ struct PairSolver {
       const double Aeq = pt.An * epsq, Apq = pt.Ap * epsq, Apqh = Apq * hq;
 
       double G11 = 0.0;
+      // the reference norms of this inner loop, in registers (constant within
+      // the loop: a converged loop sets the next loop's and ends)
+      double dref0[NS];
+#pragma unroll
+      for (int t = 0; t < NS; ++t) dref0[t] = pt.dref[t];
       const bool ran = run;  // this half runs this outer iteration
       bool act = run;        // this half is still iterating the inner loop
       bool cvd = false;      // this half's inner loop converged
@@ -424,7 +429,7 @@ struct PairSolver {
 #pragma unroll
           for (int t = 0; t < NS; ++t) {
             const double dm2 = s[t] > s[NS + t] ? s[t] : s[NS + t];
-            const double d0 = pt.dref[t], dn2 = s[2 * NS + t];
+            const double d0 = dref0[t], dn2 = s[2 * NS + t];
             const double dref2 = d0 > dn2 ? d0 : dn2;
             if (!(dm2 <= a.tol_inner2 * dref2)) conv = false;
           }
