@@ -48,7 +48,6 @@ struct PairLds {
       double fac[2][NS][kLanes];       // projected equilibrium: 1 / sqrt(o) and o per species (o = D / (1 - D))
     };
     double tile[2][NQP][NQP];        // per point, signed pair factors: [j][q] = +b if j > q, else -b
-    double2 ht[2][NQP];              // per point and node: (h 2^2c, 2^-2c / h), h = exp(-e / T)
   } u;
   struct Pt {                      // per-point state of the outer (matter) loop
     double dref[NS];               // ||D_s^[k,1]||_W^2 of the current inner loop
@@ -194,9 +193,10 @@ struct PairSolver {
       // orientation form: +b(q, j) for j > q (q the lower node), -b(q, j)
       // otherwise, every entry a product of factors <= 1.
       // Where the grid spans at most kDirectBits powers of two in g (T above
-      // ~0.22 MeV) every lane forms its whole row from the point's table of
-      // the scaled h and 1 / h (direct_row); otherwise the lanes fill the
-      // point's LDS tile, each unordered pair once, and read their rows back.
+      // ~0.22 MeV) every lane forms its whole row from the point's scaled h
+      // and 1 / h, broadcast from registers (direct_row_regs); otherwise the
+      // lanes fill the point's LDS tile, each unordered pair once, and read
+      // their rows back.
       double B[COUPLED ? NQ : 1];
       double hq = 0.0;  // exp(-e_q / T)
       double gq = 1.0, rgq = 1.0;  // g_q 2^c and 2^-c / g_q (symmetric form)
@@ -223,15 +223,10 @@ struct PairSolver {
           rgq = sym ? ldexp(xs.P, xs.n - c) : 1.0;
         }
         if (direct) {
-          // the Anderson history is dead between inner loops: its space
-          // holds the point's table
           const double gt = PROJ ? ldexp(xs.R, c - xs.n) : gq;
           const double rgt = PROJ ? ldexp(xs.P, xs.n - c) : rgq;
           const double ht = gt * gt, rht = rgt * rgt;
-          S.u.ht[h][q] = make_double2(ht, rht);
-          __syncthreads();
-          direct_row(S.u.ht[h], ht, rht, B);
-          __syncthreads();
+          direct_row_regs(ht, rht, B);
         } else {
           // pair factors of the point, each unordered pair (q, q + d mod 32)
           // once: d = 1..15 by every lane, d = 16 by lanes q < 16

@@ -34,7 +34,6 @@ struct VPairLds {
   union {
     double hist[4][4 * NS][kLanes];  // Anderson history per owned moment: Q_prev, F_prev, dQ_old, dF_old
     double tile[2][NQP][NQP];        // per point, pair factors (see the static two-point kernel)
-    double2 ht[2][NQP];              // per point and node: (h 2^2c, 2^-2c / h), h = exp(-e / T)
   } u;
   struct Pt {  // per-point state of the outer (matter) loop
     double dref[NS];  // ||D_s^[k,1]||_W^2 of the current inner loop
@@ -256,12 +255,9 @@ struct VPairSolver {
         gq = sym ? ldexp(xs.R, c - xs.n) : 1.0;
         rgq = sym ? ldexp(xs.P, xs.n - c) : 1.0;
         if (direct) {
-          // rows of the symmetric core from the point's table of scaled h
-          const double ht = gq * gq, rht = rgq * rgq;
-          S.u.ht[h][q] = make_double2(ht, rht);
-          __syncthreads();
-          direct_row(S.u.ht[h], ht, rht, B);
-          __syncthreads();
+          // rows of the symmetric core from the point's scaled h, broadcast
+          // from registers
+          direct_row_regs(gq * gq, rgq * rgq, B);
         } else {
           double (*Tt)[NQ] = S.u.tile[h];
           if (sym) {

@@ -21,17 +21,21 @@ constexpr int kSymBits = 1800;
 constexpr int kDirectBits = 1000;
 
 // Row q of the symmetric core B2(q, j) = exp(-|e_q - e_j| / T), q this
-// lane's node, from the point's table HT[j] = (h_j, 1 / h_j) of the scaled
-// h = exp(-e / T) 2^2c: of the two orientations h_j / h_q and h_q / h_j the
-// smaller is B2 (the other is its reciprocal, or overflows to +inf).  Every
-// lane of a half reads the same table entry (an LDS broadcast).  The
-// diagonal comes out as h_q / h_q, one to within two roundings.
-__device__ __forceinline__ void direct_row(const double2* __restrict__ HT, double hq, double rhq, double (&B)[32]) {
-#pragma unroll
-  for (int j = 0; j < 32; ++j) {
-    const double2 v = HT[j];
-    B[j] = min_f64(v.x * rhq, hq * v.y);
-  }
+// lane's node, from the scaled h = exp(-e / T) 2^2c of every node of the
+// point and their reciprocals, held in registers: after swap16, H[g] and
+// RH[g] carry nodes [16 g, 16 g + 16) in every 16-lane row, and column j is
+// taken from lane j % 16 of the row by DPP broadcast.  Of the two
+// orientations h_j / h_q and h_q / h_j the smaller is B2 (the other is its
+// reciprocal, or overflows to +inf).  The diagonal comes out as h_q / h_q,
+// one to within two roundings.
+__device__ __forceinline__ void direct_row_regs(double hq, double rhq, double (&B)[32]) {
+  double H[2], RH[2];
+  swap16(hq, H[0], H[1]);
+  swap16(rhq, RH[0], RH[1]);
+  static_for<0, 32>([&](auto jj) __attribute__((always_inline)) {
+    constexpr int j = decltype(jj)::value;
+    B[j] = min_f64(row_bcast<j % 16>(H[j / 16]) * rhq, hq * row_bcast<j % 16>(RH[j / 16]));
+  });
 }
 
 // Sums over the lane's half-wave of 2K values, in every lane of the half:
