@@ -66,7 +66,6 @@ struct PairLds {
 template <int NS, bool COUPLED, bool PROJ>
 struct PairSolver {
   static constexpr int NQ = NQP;
-  static constexpr int KC = (3 * NS + 1) / 2;  // reduction chains of the convergence test
 
   // settle() is called once the pair's inputs are loaded (work-queue hook)
   template <class Settle>
@@ -260,11 +259,11 @@ struct PairSolver {
       const double Aeq = pt.An * epsq, Apq = pt.Ap * epsq, Apqh = Apq * hq;
 
       double G11 = 0.0;
-      // the reference norms of this inner loop, in registers (constant within
-      // the loop: a converged loop sets the next loop's and ends)
-      double dref0[NS];
-#pragma unroll
-      for (int t = 0; t < NS; ++t) dref0[t] = pt.dref[t];
+      // the reference norm of this lane's species class in this inner loop,
+      // in a register (constant within the loop: a converged loop sets the
+      // next loop's and ends)
+      const int cls = spread_class(lane);
+      const double dref0 = cls < NS ? pt.dref[cls < NS ? cls : 0] : 0.0;
       const bool ran = run;  // this half runs this outer iteration
       bool act = run;        // this half is still iterating the inner loop
       bool cvd = false;      // this half's inner loop converged
@@ -382,7 +381,7 @@ struct PairSolver {
             v4[3] += dF2[x] * Fx[x];
           }
           double gs[4];
-          half_own_sums<2>(v4, gs);
+          half_sums4(v4, gs);
           double g1, g2;
           anderson2(mem == 3, G11, gs[0], gs[1], gs[2], gs[3], g1, g2);
 #pragma unroll
@@ -409,30 +408,22 @@ struct PairSolver {
         // Algorithm innerConverged (weighted per species, reference guarded
         // by the new norm), compared squared
         {
-          double v[2 * KC], s[2 * KC];
+          // the sums are spread over the half (lane class c holds species c,
+          // spread_conv_sums); the half has converged when every lane passes
+          double vd[NS], vi[NS], vn[NS];
 #pragma unroll
           for (int t = 0; t < NS; ++t) {
             const double dd = Xn[t] - D[t], di = Xn[NS + t] - I[t];
-            v[t] = w2q * dd * dd;
-            v[NS + t] = w2q * di * di;
-            v[2 * NS + t] = w2q * Xn[t] * Xn[t];
+            vd[t] = w2q * dd * dd;
+            vi[t] = w2q * di * di;
+            vn[t] = w2q * Xn[t] * Xn[t];
           }
-#pragma unroll
-          for (int i = 3 * NS; i < 2 * KC; ++i) v[i] = 0.0;
-          half_own_sums<KC>(v, s);
-          bool conv = true;
-#pragma unroll
-          for (int t = 0; t < NS; ++t) {
-            const double dm2 = s[t] > s[NS + t] ? s[t] : s[NS + t];
-            const double d0 = dref0[t], dn2 = s[2 * NS + t];
-            const double dref2 = d0 > dn2 ? d0 : dn2;
-            if (!(dm2 <= a.tol_inner2 * dref2)) conv = false;
-          }
-          if (act && conv) {
-            // ||D^[k,*]|| is the reference of the next inner loop
-#pragma unroll
-            for (int t = 0; t < NS; ++t) pt.dref[t] = s[2 * NS + t];
-          }
+          double dm2, dn2;
+          spread_conv_sums<NS>(vd, vi, vn, dm2, dn2);
+          const double dref2 = dref0 > dn2 ? dref0 : dn2;
+          const bool conv = !half_any(!(dm2 <= a.tol_inner2 * dref2));
+          // ||D^[k,*]|| is the reference of the next inner loop
+          if (act && conv && cls < NS) pt.dref[cls < NS ? cls : 0] = dn2;
           if (act) {
 #pragma unroll
             for (int t = 0; t < NS; ++t) {
@@ -452,8 +443,7 @@ struct PairSolver {
       // v = 0) and, where a running point's inner loop failed, the reference
       // norms of its next inner loop (the norm of the current moments) in one
       // reduction.  A converged loop took its reference from the convergence
-      // test's norm of the same moments, which this reduction would reproduce
-      // bit for bit (every slot of the half-wave sums runs the same tree).
+      // test's norm of the same moments (the same sum in another fixed order).
       double yq0, yq1;
       {
         const double w3 = mt.w3[q];

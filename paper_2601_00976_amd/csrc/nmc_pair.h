@@ -59,6 +59,86 @@ __device__ __forceinline__ void half_own_sums(const double (&v)[2 * K], double (
 }
 
 
+// Lanes whose DPP bank (4-lane group of a 16-lane row, bit b of BANKS for
+// lanes 4b..4b+3) is enabled take src from their DPP source lane of CTRL; the
+// others keep old.
+template <int CTRL, int BANKS>
+__device__ __forceinline__ double dpp_banks(double old, double src) {
+  const long v = __builtin_amdgcn_update_dpp(__builtin_bit_cast(long, old), __builtin_bit_cast(long, src), CTRL,
+                                             0xF, BANKS, false);
+  return __builtin_bit_cast(double, v);
+}
+
+// A butterfly stage that folds the sums of two values into one register:
+// CTRL pairs every lane of the banks in A with a lane outside them
+// (row_mirror with A = banks 0, 1; row_half_mirror with A = banks 0, 2), and
+// after it lanes in A hold a + a(partner), the others b + b(partner).  Two
+// masked moves and one add, where two separate stages cost four moves and
+// two adds; the next stages then carry one value instead of two.
+template <int CTRL, int A>
+__device__ __forceinline__ double fold_pair(double a, double b) {
+  const double x = dpp_banks<CTRL, A>(b, a);
+  const double y = dpp_banks<CTRL, 0xF ^ A>(a, b);
+  return x + y;
+}
+
+// Species class of a lane for the spread sums below: c = 2 r + m with r the
+// row of the lane within its half and m = 1 for lanes 8..15 of the row.
+__device__ __forceinline__ int spread_class(int lane) { return ((lane >> 4) & 1) * 2 + ((lane >> 3) & 1); }
+
+// Sums over the half-wave of the inner convergence test, spread over its
+// lanes instead of copied into all of them: lane class c (spread_class)
+// holds species c, or zeros where c >= NS.  d is the squared change of D_c
+// in lanes with bit 2 clear and of I_c in the others; n is the squared norm
+// of the new D_c.  Terms: dd (change of D), di (change of I), xn (new D),
+// per species.  The rows of a half first split the species pairs (0, 1) and
+// (2, 3), row_mirror folds the pairs apart, row_half_mirror folds d with i,
+// and two quad stages finish.  Fixed order; every lane of a class holds the
+// same bits.
+template <int NS>
+__device__ __forceinline__ void spread_conv_sums(const double (&dd)[NS], const double (&di)[NS],
+                                                 const double (&xn)[NS], double& d, double& n) {
+  double pd[4], pi[4], pn[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    pd[c] = c < NS ? dd[c < NS ? c : 0] : 0.0;
+    pi[c] = c < NS ? di[c < NS ? c : 0] : 0.0;
+    pn[c] = c < NS ? xn[c < NS ? c : 0] : 0.0;
+  }
+  // even row of the half: species 0 and 1; odd row: species 2 and 3
+  const double dP = halve16(pd[0], pd[2]), dQ = halve16(pd[1], pd[3]);
+  const double iP = halve16(pi[0], pi[2]), iQ = halve16(pi[1], pi[3]);
+  const double nP = halve16(pn[0], pn[2]), nQ = halve16(pn[1], pn[3]);
+  const double fd = fold_pair<0x140, 0x3>(dP, dQ);  // row_mirror: lanes 0..7 keep P
+  const double fi = fold_pair<0x140, 0x3>(iP, iQ);
+  double x = fold_pair<0x140, 0x3>(nP, nQ);
+  double y = fold_pair<0x141, 0x5>(fd, fi);  // row_half_mirror: lanes 0..3, 8..11 keep D
+  x += dpp<0x141>(x);
+  y += dpp<0xB1>(y);  // quad_perm [1,0,3,2]
+  x += dpp<0xB1>(x);
+  y += dpp<0x4E>(y);  // quad_perm [2,3,0,1]
+  x += dpp<0x4E>(x);
+  d = y;
+  n = x;
+}
+
+// Four sums over the half-wave, in every lane of the half: folded pairwise
+// by row_mirror and row_half_mirror (lanes 0..3 of a row carry v0, 4..7 v2,
+// 8..11 v1, 12..15 v3), two quad stages, the half's two rows added, and each
+// sum broadcast from its bank.  Fixed order.
+__device__ __forceinline__ void half_sums4(const double (&v)[4], double (&s)[4]) {
+  const double x01 = fold_pair<0x140, 0x3>(v[0], v[1]);
+  const double x23 = fold_pair<0x140, 0x3>(v[2], v[3]);
+  double z = fold_pair<0x141, 0x5>(x01, x23);
+  z += dpp<0xB1>(z);
+  z += dpp<0x4E>(z);
+  z = halve16(z, z);
+  s[0] = row_bcast<0>(z);
+  s[1] = row_bcast<8>(z);
+  s[2] = row_bcast<4>(z);
+  s[3] = row_bcast<12>(z);
+}
+
 // max(a, -b) of two non-NaN values as one v_max_f64 with a negated operand
 __device__ __forceinline__ double max_neg_f64(double a, double b) {
   double r;
