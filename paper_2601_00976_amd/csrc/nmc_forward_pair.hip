@@ -410,18 +410,18 @@ struct PairSolver {
         {
           // the sums are spread over the half (lane class c holds species c,
           // spread_conv_sums); the half has converged when every lane passes
-          double vd[NS], vi[NS], vn[NS];
+          double vm[2][NS], vn[NS];
 #pragma unroll
           for (int t = 0; t < NS; ++t) {
             const double dd = Xn[t] - D[t], di = Xn[NS + t] - I[t];
-            vd[t] = w2q * dd * dd;
-            vi[t] = w2q * di * di;
+            vm[0][t] = w2q * dd * dd;
+            vm[1][t] = w2q * di * di;
             vn[t] = w2q * Xn[t] * Xn[t];
           }
-          double dm2, dn2;
-          spread_conv_sums<NS>(vd, vi, vn, dm2, dn2);
+          double dm2[1], dn2;
+          spread_conv_sums<NS, 2>(vm, vn, dm2, dn2);
           const double dref2 = dref0 > dn2 ? dref0 : dn2;
-          const bool conv = !half_any(!(dm2 <= a.tol_inner2 * dref2));
+          const bool conv = !half_any(!(dm2[0] <= a.tol_inner2 * dref2));
           // ||D^[k,*]|| is the reference of the next inner loop
           if (act && conv && cls < NS) pt.dref[cls < NS ? cls : 0] = dn2;
           if (act) {

@@ -98,7 +98,6 @@ template <int NS, bool COUPLED>
 struct VPairSolver {
   static constexpr int NQ = NQP;
   static constexpr int NM = 4 * NS;            // owned moments per lane
-  static constexpr int KC = (5 * NS + 1) / 2;  // reduction chains of the convergence test
 
   // matter right-hand side q(M, y) of Eq. implicitFluidNodal from the
   // integrals X of the current moments
@@ -377,7 +376,7 @@ struct VPairSolver {
             v4[3] += dF2 * Fx;
           }
           double gs[4];
-          half_own_sums<2>(v4, gs);
+          half_sums4(v4, gs);
           double g1, g2;
           anderson2(mem == 3, G11, gs[0], gs[1], gs[2], gs[3], g1, g2);
 #pragma unroll
@@ -406,33 +405,26 @@ struct VPairSolver {
         // Algorithm innerConverged over the four moments of each species:
         // max_m sum_q W dM_m^2 <= tol^2 max(||D^[k,1]||^2, ||D^[k,l+1]||^2)
         {
-          double vv[2 * KC], s[2 * KC];
+          // the sums are spread over the half (lane class c holds species c,
+          // spread_conv_sums); the half has converged when every lane passes
+          double vm[4][NS], vn[NS];
 #pragma unroll
           for (int t = 0; t < NS; ++t) {
 #pragma unroll
             for (int m = 0; m < 4; ++m) {
               const double d = Xn[4 * t + m] - cur(4 * t + m);
-              vv[4 * t + m] = w2q * d * d;
+              vm[m][t] = w2q * d * d;
             }
-            vv[4 * NS + t] = w2q * Xn[4 * t] * Xn[4 * t];
+            vn[t] = w2q * Xn[4 * t] * Xn[4 * t];
           }
-#pragma unroll
-          for (int i = 5 * NS; i < 2 * KC; ++i) vv[i] = 0.0;
-          half_own_sums<KC>(vv, s);
-          bool conv = true;
-#pragma unroll
-          for (int t = 0; t < NS; ++t) {
-            const double m01 = s[4 * t] > s[4 * t + 1] ? s[4 * t] : s[4 * t + 1];
-            const double m23 = s[4 * t + 2] > s[4 * t + 3] ? s[4 * t + 2] : s[4 * t + 3];
-            const double dm2 = m01 > m23 ? m01 : m23;
-            const double d0 = pt.dref[t], dn2 = s[4 * NS + t];
-            const double dref2 = d0 > dn2 ? d0 : dn2;
-            if (!(dm2 <= a.tol_inner2 * dref2)) conv = false;
-          }
-          if (act && conv) {
-#pragma unroll
-            for (int t = 0; t < NS; ++t) pt.dref[t] = s[4 * NS + t];
-          }
+          double dm2[2], dn2;
+          spread_conv_sums<NS, 4>(vm, vn, dm2, dn2);
+          const int cls = spread_class(lane);
+          const double d0 = cls < NS ? pt.dref[cls < NS ? cls : 0] : 0.0;
+          const double tr2 = a.tol_inner2 * (d0 > dn2 ? d0 : dn2);
+          const bool conv = !half_any(!(dm2[0] <= tr2 && dm2[1] <= tr2));
+          // ||D^[k,*]|| is the reference of the next inner loop
+          if (act && conv && cls < NS) pt.dref[cls < NS ? cls : 0] = dn2;
           if (act) {
 #pragma unroll
             for (int t = 0; t < NS; ++t) {

@@ -86,39 +86,42 @@ __device__ __forceinline__ double fold_pair(double a, double b) {
 // row of the lane within its half and m = 1 for lanes 8..15 of the row.
 __device__ __forceinline__ int spread_class(int lane) { return ((lane >> 4) & 1) * 2 + ((lane >> 3) & 1); }
 
+// One value per species folded to its lane class (spread_class): the rows
+// of a half split the species pairs (0, 1) and (2, 3), and row_mirror folds
+// the pairs apart.  Species at or beyond NS count as zero.
+template <int NS>
+__device__ __forceinline__ double species_fold(const double (&v)[NS]) {
+  double p[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) p[c] = c < NS ? v[c < NS ? c : 0] : 0.0;
+  return fold_pair<0x140, 0x3>(halve16(p[0], p[2]), halve16(p[1], p[3]));
+}
+
 // Sums over the half-wave of the inner convergence test, spread over its
 // lanes instead of copied into all of them: lane class c (spread_class)
-// holds species c, or zeros where c >= NS.  d is the squared change of D_c
-// in lanes with bit 2 clear and of I_c in the others; n is the squared norm
-// of the new D_c.  Terms: dd (change of D), di (change of I), xn (new D),
-// per species.  The rows of a half first split the species pairs (0, 1) and
-// (2, 3), row_mirror folds the pairs apart, row_half_mirror folds d with i,
-// and two quad stages finish.  Fixed order; every lane of a class holds the
-// same bits.
-template <int NS>
-__device__ __forceinline__ void spread_conv_sums(const double (&dd)[NS], const double (&di)[NS],
-                                                 const double (&xn)[NS], double& d, double& n) {
-  double pd[4], pi[4], pn[4];
+// holds species c, or zeros where c >= NS.  Terms: dm[m] the squared change
+// of owned moment m of each species (M of them, M even), xn the squared new
+// D.  On return y[j] holds moment 2j's sum in lanes with bit 2 clear and
+// moment 2j + 1's in the others (row_half_mirror folds each pair), and n the
+// sum of xn; all over the half's 32 nodes.  Fixed order; every lane of a
+// class and bank pair holds the same bits.
+template <int NS, int M>
+__device__ __forceinline__ void spread_conv_sums(const double (&dm)[M][NS], const double (&xn)[NS],
+                                                 double (&y)[M / 2], double& n) {
+  static_assert(M % 2 == 0, "moments are folded in pairs");
+  double f[M];
 #pragma unroll
-  for (int c = 0; c < 4; ++c) {
-    pd[c] = c < NS ? dd[c < NS ? c : 0] : 0.0;
-    pi[c] = c < NS ? di[c < NS ? c : 0] : 0.0;
-    pn[c] = c < NS ? xn[c < NS ? c : 0] : 0.0;
-  }
-  // even row of the half: species 0 and 1; odd row: species 2 and 3
-  const double dP = halve16(pd[0], pd[2]), dQ = halve16(pd[1], pd[3]);
-  const double iP = halve16(pi[0], pi[2]), iQ = halve16(pi[1], pi[3]);
-  const double nP = halve16(pn[0], pn[2]), nQ = halve16(pn[1], pn[3]);
-  const double fd = fold_pair<0x140, 0x3>(dP, dQ);  // row_mirror: lanes 0..7 keep P
-  const double fi = fold_pair<0x140, 0x3>(iP, iQ);
-  double x = fold_pair<0x140, 0x3>(nP, nQ);
-  double y = fold_pair<0x141, 0x5>(fd, fi);  // row_half_mirror: lanes 0..3, 8..11 keep D
+  for (int m = 0; m < M; ++m) f[m] = species_fold<NS>(dm[m]);
+  double x = species_fold<NS>(xn);
+#pragma unroll
+  for (int j = 0; j < M / 2; ++j) y[j] = fold_pair<0x141, 0x5>(f[2 * j], f[2 * j + 1]);  // lanes 0..3, 8..11 keep 2j
   x += dpp<0x141>(x);
-  y += dpp<0xB1>(y);  // quad_perm [1,0,3,2]
+#pragma unroll
+  for (int j = 0; j < M / 2; ++j) y[j] += dpp<0xB1>(y[j]);  // quad_perm [1,0,3,2]
   x += dpp<0xB1>(x);
-  y += dpp<0x4E>(y);  // quad_perm [2,3,0,1]
+#pragma unroll
+  for (int j = 0; j < M / 2; ++j) y[j] += dpp<0x4E>(y[j]);  // quad_perm [2,3,0,1]
   x += dpp<0x4E>(x);
-  d = y;
   n = x;
 }
 
