@@ -84,28 +84,34 @@ __device__ __forceinline__ void elim_cols4(double& r0, double& r1, double& r2, d
 // lane r enters with R = row r of A^T and c = (c0, c1) its right-hand sides
 // and leaves with (z0, z1) = entry r of the two solutions.  Returns false if
 // a pivot block was singular or non-finite, detected as a non-finite
-// solution entry (such a block turns the multipliers or a quotient of the
-// back substitution into inf or NaN, which propagate into z).
+// solution entry (such a block turns the multipliers or the final quotients
+// into inf or NaN, which propagate into z).
 //
-// Block Gaussian elimination with 2 x 2 pivot blocks and no row exchanges:
-// with D in [0, 1] and non-negative kernels, diag(W) A is strictly
+// Block Gauss-Jordan elimination with 2 x 2 pivot blocks and no row
+// exchanges: with D in [0, 1] and non-negative kernels, diag(W) A is strictly
 // diagonally dominant by columns (the off-diagonal column sums of the
 // W-scaled NES and pair terms equal the kernel part of the diagonal opacity,
-// leaving a margin W_p (1 + dtau chi^EmAb_p)); elimination without pivoting is
-// stable for such matrices, and their diagonal blocks and Schur complements
-// stay dominant, so every 2 x 2 pivot block is nonsingular.  Step k (even)
-// removes rows k and k+1 of A^T (lanes k and k+1) from the rows below with
-// the multipliers [R[k], R[k+1]] B^-1 of the pivot block B.  The two lanes
-// write their rows (from column k on) and right-hand sides to two LDS row
-// buffers; every lane then loads, per group of 16 columns, one entry of each
-// pivot row (lane L of a 16-lane row loads column 16 g + L), and the update
-// FMAs take column 16 g + L from lane L of the lane's row by DPP broadcast.
-// All lanes run the FMAs (a DPP source lane must be active); rows k + 1 and
-// above have zero multipliers, so their entries are unchanged.  The columns
-// of a group left of k + 2 are updated too: for rows below the pivot they are
-// the eliminated part, never read again.  A single wavefront runs the
-// work-group, so its LDS accesses complete in program order and no barrier is
-// needed.  Back substitution solves the 2 x 2 diagonal blocks from the last.
+// leaving a margin W_p (1 + dtau chi^EmAb_p)), so A^T with its columns scaled
+// by W is dominant by rows; elimination without pivoting, Gauss-Jordan
+// included, is stable for such matrices, and their diagonal blocks and Schur
+// complements stay dominant, so every 2 x 2 pivot block is nonsingular.
+// Step k (even) removes columns k and k+1 from every row but k and k+1 (lanes
+// k and k+1) with the multipliers [R[k], R[k+1]] B^-1 of the pivot block B.
+// The two lanes write their rows (from column k on) and right-hand sides to
+// two LDS row buffers; every lane then loads, per group of 16 columns, one
+// entry of each pivot row (lane L of a 16-lane row loads column 16 g + L), and
+// the update FMAs take column 16 g + L from lane L of the lane's row by DPP
+// broadcast.  All lanes run the FMAs (a DPP source lane must be active); the
+// pivot rows have zero multipliers, so their entries are unchanged.  The
+// columns of a group left of k + 2 are updated too: they are eliminated
+// columns or the row's own pivot block, which the row keeps in registers
+// when it is eliminated, and are never read again.  Rows above the pivot are
+// updated by the same instructions as the rows below, so the elimination
+// costs no more than a one-sided one, and at the end every pivot pair holds
+// only its own block: z = B^-1 c for each pair, from the partner's
+// right-hand sides by DPP, with no back substitution.  A single wavefront
+// runs the work-group, so its LDS accesses complete in program order and no
+// barrier is needed.
 template <int N>
 __device__ __forceinline__ bool solve_block_transposed(double (&R)[N], double c0, double c1, double& z0,
                                                        double& z1, double* prow_generic) {
@@ -116,6 +122,10 @@ __device__ __forceinline__ bool solve_block_transposed(double (&R)[N], double c0
   constexpr int RS = N + 2;  // doubles per row buffer: entries 0..N-1, right-hand sides at N, N+1
   const int lane = opaque((int)threadIdx.x);
   const int col = lane & 15;
+  // the lane's pivot block, kept when its pair is eliminated: lane k (even)
+  // solves z_k = (a11 c_k - a01 c_k+1) / det, lane k+1 z_k+1 = (a00 c_k+1 -
+  // a10 c_k) / det, so each keeps its (x, y) = (a11, a01) or (a00, a10)
+  double bx = 0.0, by = 0.0, brd = 0.0;
   static_for<0, N / 2>([&](auto kk) __attribute__((always_inline)) {
     constexpr int k = 2 * decltype(kk)::value;
     lds_f64* prow = (lds_f64*)prow_generic;
@@ -134,9 +144,19 @@ __device__ __forceinline__ bool solve_block_transposed(double (&R)[N], double c0
       lds_write2_f64<N>(base, c0, c1);
     }
     const double rdet = rcp_nr(a00 * a11 - a01 * a10);
-    const bool below = lane > k + 1;
-    const double nl0 = below ? -((R[k] * a11 - R[k + 1] * a10) * rdet) : 0.0;
-    const double nl1 = below ? -((R[k + 1] * a00 - R[k] * a01) * rdet) : 0.0;
+    if (lane == k) {
+      bx = a11;
+      by = a01;
+      brd = rdet;
+    }
+    if (lane == k + 1) {
+      bx = a00;
+      by = a10;
+      brd = rdet;
+    }
+    const bool other = lane != k && lane != k + 1;
+    const double nl0 = other ? -((R[k] * a11 - R[k + 1] * a10) * rdet) : 0.0;
+    const double nl1 = other ? -((R[k + 1] * a00 - R[k] * a01) * rdet) : 0.0;
     static_for<(k + 2) / 16, N / 16>([&](auto gg) __attribute__((always_inline)) {
       constexpr int g = decltype(gg)::value;
       const double u = prow[16 * g + col], w = prow[RS + 16 * g + col];
@@ -149,31 +169,11 @@ __device__ __forceinline__ bool solve_block_transposed(double (&R)[N], double c0
     c0 = __builtin_fma(nl0, cu.x, __builtin_fma(nl1, cv.x, c0));
     c1 = __builtin_fma(nl0, cu.y, __builtin_fma(nl1, cv.y, c1));
   });
-  // back substitution by 2 x 2 blocks from the last: z of rows k, k+1 from
-  // their (reduced) right-hand sides, then every row above removes its terms
-  z0 = z1 = 0.0;
-  static_for<0, N / 2>([&](auto kk) __attribute__((always_inline)) {
-    constexpr int k = N - 2 - 2 * decltype(kk)::value;
-    const double a00 = readlane_f64(R[k], k), a01 = readlane_f64(R[k + 1], k);
-    const double a10 = readlane_f64(R[k], k + 1), a11 = readlane_f64(R[k + 1], k + 1);
-    const double rdet = rcp_nr(a00 * a11 - a01 * a10);
-    const double p0 = readlane_f64(c0, k), p1 = readlane_f64(c0, k + 1);
-    const double q0 = readlane_f64(c1, k), q1 = readlane_f64(c1, k + 1);
-    const double zk0 = (a11 * p0 - a01 * p1) * rdet, zl0 = (a00 * p1 - a10 * p0) * rdet;
-    const double zk1 = (a11 * q0 - a01 * q1) * rdet, zl1 = (a00 * q1 - a10 * q0) * rdet;
-    if (lane == k) {
-      z0 = zk0;
-      z1 = zk1;
-    }
-    if (lane == k + 1) {
-      z0 = zl0;
-      z1 = zl1;
-    }
-    if (lane < k) {
-      c0 = __builtin_fma(-R[k], zk0, __builtin_fma(-R[k + 1], zl0, c0));
-      c1 = __builtin_fma(-R[k], zk1, __builtin_fma(-R[k + 1], zl1, c1));
-    }
-  });
+  // each pivot pair (k, k+1) now solves its own block; the partner lane is
+  // lane ^ 1 (quad_perm [1,0,3,2])
+  const double o0 = dpp<0xB1>(c0), o1 = dpp<0xB1>(c1);
+  z0 = (bx * c0 - by * o0) * brd;
+  z1 = (bx * c1 - by * o1) * brd;
   // a singular or non-finite pivot block makes some entry of the solution
   // non-finite
   return __builtin_amdgcn_ballot_w64(lane < N && !(isfinite(z0) && isfinite(z1))) == 0;
