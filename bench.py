@@ -59,6 +59,33 @@ def flops_per_point_v(n_inner, n_outer, nq=32, ns=NS):
     return n_inner * (8 * ns * nq * nq + 174 * ns * nq) + n_outer * (4 * nq * nq + 100 * ns * nq)
 
 
+def flops_per_point_v_phi1(n_inner, n_outer, nq=32, ns=NS):
+    """Algorithmic FLOPs of one O(v) point-solve with the linear-order Phi_1
+    corrections (FMA = 2): the O(v) count plus, per inner iteration, the four
+    Phi_1 contractions of every species against each of the three flux
+    components (24 ns nq^2) and, per species and node, the two combinations
+    of the contracted vectors per component (18) and the Phi_1 collision terms
+    of the closure (52), together 70 ns nq."""
+    return flops_per_point_v(n_inner, n_outer, nq, ns) + n_inner * (24 * ns * nq * nq + 70 * ns * nq)
+
+
+def flops_per_node_c2p(iters):
+    """Algorithmic FLOPs of one primitive-moment recovery (FMA = 2), per
+    iteration of the fixed-point map: the Minerbo closure with the velocity
+    products (47), the relaxed map (16) and residual (4), the Anderson step
+    over the 4-vector (79: differences, Gram sums, the 2 x 2 solve, mixing)
+    and the convergence test (12), together 158; per node the scaling, the
+    step parameter and the reference norm (30)."""
+    return 158 * iters + 30
+
+
+def bytes_per_node_c2p(ns=NS, nq=32):
+    """Algorithmic HBM bytes of one node recovery: read N and G (4 doubles),
+    write D and I (4 doubles) and the iteration count (int32), plus the
+    point's velocity (3 doubles) shared by its ns * nq nodes."""
+    return 4 * 8 + 4 * 8 + 4 + 3 * 8 / (ns * nq)
+
+
 def bytes_per_point(nq=32, ns=NS):
     """Algorithmic HBM bytes of one point-solve: read D*, I* and 3 scalars
     (rho11, Ye*, e*), write D, I, 3 scalars (Ye, e, T) and 3 int32 counters."""
@@ -78,11 +105,14 @@ def bytes_per_point_v(nq=32, ns=NS):
 # the profile, would otherwise exceed the outer tolerance there)
 V_TOL_INNER, V_TOL_OUTER = 1e-12, 1e-10
 V_WID = 6
+# linear-order corrections of the Phi_1 workload: Phi_1 = r Phi_0 per process
+PHI1_NES, PHI1_PAIR = 0.3, -0.25
 
 
-def cpu_baseline_v(steps: int, threads: int):
-    """The oracle's O(v) solve on the moving profile: all 2^16 points, `steps`
-    chained implicit steps from the initial state."""
+def cpu_baseline_v(steps: int, threads: int, mode: str = "solve"):
+    """The oracle's O(v) solve (mode "solve"), the same with the Phi_1
+    corrections ("phi1") or its PD-ARS step ("pdars") on the moving profile:
+    all 2^16 points, `steps` chained steps from the initial state."""
     import numpy as np
 
     import oracle as O
@@ -91,7 +121,7 @@ def cpu_baseline_v(steps: int, threads: int):
 
     O.build(force=False)
     d = W.radial_profile_v(P=P_POINTS, wid=V_WID)
-    m = O.Model(n_elem=16)
+    m = O.Model(n_elem=16, overrides=dict(phi1_nes=PHI1_NES, phi1_pair=PHI1_PAIR) if mode == "phi1" else {})
     theta = m.default_theta(S.DEFAULT_A_NES, S.DEFAULT_A_PAIR)
     D, _, e0 = m.init_state(d.T, d.rho11, d.ye, d.uD, d.uI)
     I = 0.1 * D[:, :, None, :] * d.uI3
@@ -101,18 +131,52 @@ def cpu_baseline_v(steps: int, threads: int):
     solved = 0
     t0 = time.perf_counter()
     for _ in range(steps):
-        r = O.solve_batch_v(m, prm, theta, W.DTAU_KM, D, I, d.rho11, ye, ef, v, nthreads=threads)
+        if mode == "pdars":
+            r = O.pdars_step_v(m, prm, theta, W.DTAU_KM, D, I, d.rho11, ye, ef, v, nthreads=threads)
+        else:
+            r = O.solve_batch_v(m, prm, theta, W.DTAU_KM, D, I, d.rho11, ye, ef, v, nthreads=threads)
         D, I, ye, ef, v = r["D"], r["I"], r["ye"], r["ef"], r["v"]
         solved += int(np.sum(r["n_outer"] > 0))
     dt = time.perf_counter() - t0
-    return dict(value=solved / dt, unit="point-solves/s", cores=threads, kind="oracle",
-                sample=f"all {P_POINTS} moving-profile points, {steps} chained steps, {solved} solves in {dt:.1f} s")
+    unit = "point-steps/s" if mode == "pdars" else "point-solves/s"
+    return dict(value=solved / dt, unit=unit, cores=threads, kind="oracle",
+                sample=f"all {P_POINTS} moving-profile points, {steps} chained steps, {solved} solved point-steps "
+                       f"in {dt:.1f} s")
 
 
-def run_velocity(args):
+def cpu_baseline_c2p(threads: int, min_seconds: float = 10.0):
+    """The oracle's primitive-moment recovery of the same conserved moments
+    (every node of the profile), repeated until `min_seconds` have passed."""
+    import numpy as np
+
+    import oracle as O
+    from paper_2601_00976_amd import workloads as W
+
+    O.build(force=False)
+    d = W.radial_profile_v(P=P_POINTS, wid=V_WID)
+    m = O.Model(n_elem=16)
+    D, _, _ = m.init_state(d.T, d.rho11, d.ye, d.uD, d.uI)
+    I = 0.1 * D[:, :, None, :] * d.uI3
+    N, G, v = D, np.ascontiguousarray(I), np.ascontiguousarray(d.v)
+    done, reps = 0, 0
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < min_seconds:
+        _, _, it = O.primitive_batch(m, N, G, v, nthreads=threads)
+        done += it.size
+        reps += 1
+    dt = time.perf_counter() - t0
+    return dict(value=done / dt, unit="node-recoveries/s", cores=threads, kind="oracle",
+                sample=f"every node of the moving profile ({it.size}) x {reps}: {done} recoveries in {dt:.1f} s")
+
+
+def run_velocity(args, mode: str = "solve"):
     """The O(v) solve (nonzero fluid velocity) on the moving radial profile:
     2^16 points, 3 species, 32 nodes, 10 chained in-place steps per captured
-    graph, timed and accounted as the static workload."""
+    graph, timed and accounted as the static workload.  mode "phi1": the same
+    solve with the linear-order Phi_1 corrections (Phi_1 = r Phi_0, r = 0.3
+    for NES and -0.25 for pair); mode "pdars": each step is one PD-ARS IMEX
+    step of the coupling (two solves, dt and dt / 2, with the primitive
+    recovery between them)."""
     import numpy as np
     import torch
 
@@ -121,13 +185,17 @@ def run_velocity(args):
     from paper_2601_00976_amd import workloads as W
 
     dev = torch.device("cuda:0")
-    model = S.Model(S.Grid(16))
+    model = S.Model(S.Grid(16), **(dict(phi1_nes=PHI1_NES, phi1_pair=PHI1_PAIR) if mode == "phi1" else {}))
     params = S.Params(tol_inner=V_TOL_INNER, tol_outer=V_TOL_OUTER)
     t = S.to_device(W.radial_profile_v(P=P_POINTS, wid=V_WID), dev)
     D0, I0, ef0 = S.init_state_v(model, t)
     theta = model.default_theta()
     launch = S.LaunchConfig(chunk=args.chunk or 1, blocks_per_cu=args.blocks_per_cu or 0)
-    if args.kernel_store == "wave":
+    if mode == "phi1":
+        assert args.kernel_store == "chip", "the Phi_1 solve runs in the one-point kernel (--kernel-store chip)"
+        kernel_label, traffic_tag = ("fwd_v_kernel<3, true, true> (persistent O(v) point solve with the Phi_1 "
+                                     "corrections, one point per wavefront)"), "fwd_v_kernel_nq32_ns3_phi1"
+    elif args.kernel_store == "wave":
         launch.kernel_store = 5
         kernel_label, traffic_tag = ("fwd_v_kernel<3, true, false> (persistent O(v) point solve, one point per "
                                      "wavefront)"), "fwd_v_kernel_nq32_ns3"
@@ -140,9 +208,10 @@ def run_velocity(args):
     for o in outs:
         for k in work:
             o[k] = work[k]
-    ws = S.Workspace(model, P_POINTS, dev)
+    ws = S.PdarsWorkspace(model, P_POINTS, dev) if mode == "pdars" else S.Workspace(model, P_POINTS, dev)
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
           for _ in range(STEPS_PER_GRAPH)]
+    step_fn = S.pdars_step_v if mode == "pdars" else S.solve_v
 
     def one_pass(record=False):
         work["D"].copy_(D0)
@@ -153,8 +222,8 @@ def run_velocity(args):
         for i in range(STEPS_PER_GRAPH):
             if record:
                 ev[i][0].record()
-            S.solve_v(model, params, W.DTAU_KM, work["D"], work["I"], t["rho11"], work["ye"], work["ef"],
-                      work["v"], theta, out=outs[i], workspace=ws, launch=launch)
+            step_fn(model, params, W.DTAU_KM, work["D"], work["I"], t["rho11"], work["ye"], work["ef"],
+                    work["v"], theta, out=outs[i], workspace=ws, launch=launch)
             if record:
                 ev[i][1].record()
 
@@ -199,18 +268,31 @@ def run_velocity(args):
     n_out = np.stack([o["n_outer"].cpu().numpy() for o in outs]).astype(np.float64)
     status = np.stack([o["status"].cpu().numpy() for o in outs])
     solved = int(np.sum(n_out > 0))
-    flops = float(np.sum(flops_per_point_v(n_in, n_out, 32)))
+    flops = float(np.sum((flops_per_point_v_phi1 if mode == "phi1" else flops_per_point_v)(n_in, n_out, 32)))
     eager_s = kern_ms * 1e-3 / (n_timed * STEPS_PER_GRAPH)
     kern_s = (graph_ms - copy_ms) * 1e-3 / STEPS_PER_GRAPH
     achieved = flops / STEPS_PER_GRAPH / kern_s / 1e12
+    metric, unit, wl = {
+        "solve": ("implicit O(v) point-solves/sec at 32 energy nodes, 3 species (FP64)", "point-solves/s",
+                  "moving radial-profile (O(v) solve, fluid velocity up to 0.1 c), 2^16 points, 3 species, "
+                  "32 energy nodes, full physics, 10 chained implicit steps per captured graph"),
+        "phi1": ("implicit O(v) point-solves/sec with the Phi_1 corrections at 32 energy nodes, 3 species (FP64)",
+                 "point-solves/s",
+                 "moving radial-profile (O(v) solve with the linear-order Phi_1 NES and pair corrections, "
+                 "Phi_1 = 0.3 / -0.25 Phi_0), 2^16 points, 3 species, 32 energy nodes, full physics, 10 chained "
+                 "implicit steps per captured graph"),
+        "pdars": ("PD-ARS coupling point-steps/sec at 32 energy nodes, 3 species (FP64)", "point-steps/s",
+                  "moving radial-profile, one PD-ARS IMEX step of the coupling per step (O(v) solves with dt and "
+                  "dt / 2, primitive recovery between them), 2^16 points, 3 species, 32 energy nodes, full physics, "
+                  "10 chained steps per captured graph"),
+    }[mode]
     line = {
-        "metric": "implicit O(v) point-solves/sec at 32 energy nodes, 3 species (FP64)",
-        "value": solved / (ms_per_step * 1e-3), "unit": "point-solves/s", "n_gpus": 1, "steps": args.steps,
+        "metric": metric,
+        "value": solved / (ms_per_step * 1e-3), "unit": unit, "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {
-            "workload": "moving radial-profile (O(v) solve, fluid velocity up to 0.1 c), 2^16 points, 3 species, "
-                        "32 energy nodes, full physics, 10 chained implicit steps per captured graph",
+            "workload": wl,
             "points": P_POINTS, "solved_point_steps_per_step": solved, "species": NS, "energy_nodes": 32,
             "implicit_steps_per_step": STEPS_PER_GRAPH, "dtau_km": W.DTAU_KM, "tol_inner": params.tol_inner,
             "tol_outer": params.tol_outer, "anderson_memory": params.m_inner,
@@ -220,11 +302,17 @@ def run_velocity(args):
             "status_counts": np.bincount(status.ravel(), minlength=5).tolist(),
         },
         "roofline": {
-            "kernel": kernel_label, "flop_convention": "O(v): closure and velocity work counted (flops_per_point_v)",
+            "kernel": kernel_label + (" x 2 solves, with the recovery and stage kernels" if mode == "pdars" else ""),
+            "flop_convention": {"solve": "O(v): closure and velocity work counted (flops_per_point_v)",
+                                "phi1": "O(v) with the Phi_1 contractions and collision terms "
+                                        "(flops_per_point_v_phi1)",
+                                "pdars": "O(v) convention over both solves of the step (flops_per_point_v of the "
+                                         "summed iteration counts); the recovery and stage work is not counted"}[mode],
             "bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP64_TFLOPS, "traffic": AT.stored_traffic(traffic_tag),
             "kernel_ms_per_launch": kern_s * 1e3,
-            "kernel_ms_per_launch_from": "graph replay time (HIP events, timed region) less the pristine copy, / 10",
+            "kernel_ms_per_launch_from": ("graph replay time (HIP events, timed region) less the pristine copy, / 10"
+                                          + ("; a launch is a whole PD-ARS step" if mode == "pdars" else "")),
             "graph_ms_per_step": graph_ms, "pristine_copy_ms": copy_ms, "eager_ms_per_launch": eager_s * 1e3,
             "flops_per_launch": flops / STEPS_PER_GRAPH,
             "algorithmic_hbm_gbs": bytes_per_point_v() * P_POINTS / kern_s / 1e9,
@@ -236,7 +324,101 @@ def run_velocity(args):
     line["roofline"]["frac_of_measured_fma_peak"] = achieved / fma_peak
     if not args.no_cpu:
         threads = int(os.environ.get("OMP_NUM_THREADS") or os.cpu_count() or 1)
-        line["cpu_baseline"] = cpu_baseline_v(args.cpu_steps_v, threads)
+        line["cpu_baseline"] = cpu_baseline_v(args.cpu_steps_v, threads, mode)
+    print(json.dumps(line), flush=True)
+
+
+def run_c2p(args):
+    """Primitive-moment recovery (Sec. 3.4) of every node of the moving
+    profile: 2^16 points x 3 species x 32 nodes, the conserved moments (N, G)
+    being the profile's drawn near-equilibrium moments at its fluid velocity
+    (|v| up to 0.1), memory 3, tolerance 1e-8; 10 recoveries per captured
+    graph."""
+    import numpy as np
+    import torch
+
+    from paper_2601_00976_amd import solver as S
+    from paper_2601_00976_amd import workloads as W
+
+    dev = torch.device("cuda:0")
+    model = S.Model(S.Grid(16))
+    t = S.to_device(W.radial_profile_v(P=P_POINTS, wid=V_WID), dev)
+    Nc, G, _ = S.init_state_v(model, t)
+    v = t["v"]
+    cp = S.C2pParams()
+    outs = [(torch.empty_like(Nc), torch.empty_like(G), torch.empty(Nc.shape, dtype=torch.int32, device=dev))
+            for _ in range(STEPS_PER_GRAPH)]
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(STEPS_PER_GRAPH)]
+
+    def one_pass(record=False):
+        for i in range(STEPS_PER_GRAPH):
+            if record:
+                ev[i][0].record()
+            S.primitive_recovery(model, Nc, G, v, cp, out=outs[i])
+            if record:
+                ev[i][1].record()
+
+    one_pass()
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        one_pass()
+    for _ in range(args.warmup):
+        g.replay()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream(dev)
+    g0, g1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    g0.record(stream)
+    for _ in range(args.steps):
+        g.replay()
+    g1.record(stream)
+    torch.cuda.synchronize()
+    ms_per_step = 1e3 * (time.perf_counter() - t0) / args.steps
+    graph_ms = g0.elapsed_time(g1) / args.steps
+    kern_ms = 0.0
+    n_timed = max(2, min(args.steps, 5))
+    for _ in range(n_timed):
+        one_pass(record=True)
+        torch.cuda.synchronize()
+        kern_ms += sum(a.elapsed_time(b) for a, b in ev)
+    it = outs[0][2].cpu().numpy().astype(np.int64)
+    nodes = int(it.size)
+    assert np.all(it > 0), "a recovery hit its cap or went non-finite"
+    kern_s = graph_ms * 1e-3 / STEPS_PER_GRAPH
+    flops = float(np.sum(flops_per_node_c2p(it.astype(np.float64))))
+    achieved = flops / kern_s / 1e12
+    gbs = bytes_per_node_c2p() * nodes / kern_s / 1e9
+    alu = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+           "frac": achieved / PEAK_FP64_TFLOPS}
+    hbm = {"bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": gbs / PEAK_HBM_GBS}
+    roof = alu if alu["frac"] >= hbm["frac"] else hbm
+    other = hbm if roof is alu else alu
+    line = {
+        "metric": "primitive-moment recoveries/sec (nodes) at 32 energy nodes, 3 species (FP64)",
+        "value": STEPS_PER_GRAPH * nodes / (ms_per_step * 1e-3), "unit": "node-recoveries/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {
+            "workload": "primitive-moment recovery of every node of the moving radial profile (2^16 points x 3 "
+                        "species x 32 nodes, |v| up to 0.1), Anderson memory 3, tolerance 1e-8, 10 recoveries per "
+                        "captured graph",
+            "nodes": nodes, "recoveries_per_step": STEPS_PER_GRAPH, "anderson_memory": cp.mem, "tol": cp.tol,
+            "iterations": {"min": int(it.min()), "median": float(np.median(it)), "max": int(it.max()),
+                           "hist": np.bincount(it.ravel()).tolist()},
+        },
+        "roofline": dict(roof, kernel="c2p_kernel (one thread per node)",
+                         flop_convention="flops_per_node_c2p: 158 per iteration + 30 per node",
+                         traffic=None, kernel_ms_per_launch=kern_s * 1e3,
+                         kernel_ms_per_launch_from="graph replay time (HIP events, timed region) / 10",
+                         eager_ms_per_launch=kern_ms / (n_timed * STEPS_PER_GRAPH), flops_per_launch=flops,
+                         algorithmic_bytes_per_launch=bytes_per_node_c2p() * nodes,
+                         other_bound={k: other[k] for k in ("bound", "achieved", "peak", "unit", "frac")}),
+    }
+    if not args.no_cpu:
+        threads = int(os.environ.get("OMP_NUM_THREADS") or os.cpu_count() or 1)
+        line["cpu_baseline"] = cpu_baseline_c2p(threads)
     print(json.dumps(line), flush=True)
 
 
@@ -366,9 +548,13 @@ def main():
                          "(the kernels' detailed balance from its odds) instead of pointwise Fermi-Dirac values")
     ap.add_argument("--chunk", type=int, default=None)
     ap.add_argument("--blocks-per-cu", type=int, default=None)
-    ap.add_argument("--workload", choices=sorted(WORKLOADS) + ["profile-v"], default="profile32",
+    ap.add_argument("--workload", choices=sorted(WORKLOADS) + ["profile-v", "profile-v-phi1", "pdars", "c2p"],
+                    default="profile32",
                     help="profile32: the headline (2^16 points, 32 nodes); profile64: 2^18 points, 64 nodes; "
-                         "profile-v: the O(v) solve on the moving profile (2^16 points, 32 nodes)")
+                         "profile-v: the O(v) solve on the moving profile (2^16 points, 32 nodes); profile-v-phi1: "
+                         "the same with the linear-order Phi_1 corrections; pdars: PD-ARS IMEX steps of the "
+                         "coupling on the moving profile; c2p: primitive-moment recovery of every node of the "
+                         "moving profile")
     ap.add_argument("--cpu-steps-v", type=int, default=4, help="chained steps of the O(v) oracle baseline")
     ap.add_argument("--kernel-store", choices=("chip", "wave", "regen", "registers", "hbm"), default="chip",
                     help="chip: library default (32 nodes: two points per wavefront); wave (32 nodes): one point "
@@ -393,6 +579,12 @@ def main():
     torch.cuda.set_device(dev)
     if args.workload == "profile-v":
         return run_velocity(args)
+    if args.workload == "profile-v-phi1":
+        return run_velocity(args, "phi1")
+    if args.workload == "pdars":
+        return run_velocity(args, "pdars")
+    if args.workload == "c2p":
+        return run_c2p(args)
 
     n_elem, P_POINTS, wid, traffic_tag, kernel_label = WORKLOADS[args.workload]
     nq = 2 * n_elem

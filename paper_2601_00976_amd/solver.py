@@ -263,18 +263,26 @@ class C2pParams:
         return N.C2pParams(self.mem, self.tol, self.max_it)
 
 
-def primitive_recovery(model: Model, Nc, G, v, params: C2pParams | None = None, stream=None):
+def primitive_recovery(model: Model, Nc, G, v, params: C2pParams | None = None, stream=None, out=None):
     """Primitive moments (D (P, ns, nq), I (P, ns, 3, nq)) of conserved ones
     Nc (P, ns, nq), G (P, ns, 3, nq) at velocity v (P, 3), with the iteration
-    counts (P, ns, nq) int32 (-1 at the cap, -2 non-finite).  Not synchronized."""
+    counts (P, ns, nq) int32 (-1 at the cap, -2 non-finite).  ``out`` = (D, I,
+    it) to write into (allocated if None; D and I must not alias Nc and G).
+    Not synchronized."""
     P = Nc.shape[0]
     ns, nq = model.ns, model.nq
     _req(Nc, "N", (P, ns, nq))
     _req(G, "G", (P, ns, 3, nq))
     _req(v, "v", (P, 3))
-    D = torch.empty_like(Nc)
-    I = torch.empty_like(G)
-    it = torch.empty(P, ns, nq, dtype=torch.int32, device=Nc.device)
+    if out is None:
+        D = torch.empty_like(Nc)
+        I = torch.empty_like(G)
+        it = torch.empty(P, ns, nq, dtype=torch.int32, device=Nc.device)
+    else:
+        D, I, it = out
+        _req(D, "D", (P, ns, nq))
+        _req(I, "I", (P, ns, 3, nq))
+        _req(it, "iters", (P, ns, nq), torch.int32)
     pc = (params or C2pParams()).c()
     N.check(N.lib().nmc_primitive_recovery(model._h, C.byref(pc), P, Nc.data_ptr(), G.data_ptr(), v.data_ptr(),
                                            D.data_ptr(), I.data_ptr(), it.data_ptr(), _stream_handle(stream)))

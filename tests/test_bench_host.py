@@ -27,6 +27,15 @@ def test_flop_and_byte_conventions():
     assert bench.bytes_per_point(32, 3) == 2 * 96 * 8 + 24 + 2 * 96 * 8 + 24 + 12
     # O(v): D and three flux components each way, six scalars each way
     assert bench.bytes_per_point_v(32, 3) == 2 * 4 * 96 * 8 + 48 + 48 + 12
+    # Phi_1: four contractions per species against each of three flux
+    # components (24 Ns Nq^2) and 70 Ns Nq pointwise, per inner iteration
+    assert (bench.flops_per_point_v_phi1(1, 0, 32, 3) - bench.flops_per_point_v(1, 0, 32, 3)
+            == 24 * 3 * 1024 + 70 * 96)
+    assert bench.flops_per_point_v_phi1(0, 1, 32, 3) == bench.flops_per_point_v(0, 1, 32, 3)
+    # recovery: 158 per iteration and 30 per node; 68 bytes per node plus the
+    # velocity shared by the point's 96 nodes
+    assert bench.flops_per_node_c2p(5) == 5 * 158 + 30
+    assert bench.bytes_per_node_c2p(3, 32) == 68 + 24 / 96
 
 
 def test_iteration_summary_histograms():
