@@ -337,6 +337,7 @@ def run_c2p(args):
     import numpy as np
     import torch
 
+    from paper_2601_00976_amd import autotune as AT
     from paper_2601_00976_amd import solver as S
     from paper_2601_00976_amd import workloads as W
 
@@ -410,7 +411,7 @@ def run_c2p(args):
         },
         "roofline": dict(roof, kernel="c2p_kernel (one thread per node)",
                          flop_convention="flops_per_node_c2p: 158 per iteration + 30 per node",
-                         traffic=None, kernel_ms_per_launch=kern_s * 1e3,
+                         traffic=AT.stored_traffic("c2p_kernel_nq32_ns3"), kernel_ms_per_launch=kern_s * 1e3,
                          kernel_ms_per_launch_from="graph replay time (HIP events, timed region) / 10",
                          eager_ms_per_launch=kern_ms / (n_timed * STEPS_PER_GRAPH), flops_per_launch=flops,
                          algorithmic_bytes_per_launch=bytes_per_node_c2p() * nodes,

@@ -12,7 +12,9 @@ calibration: it must read and write exactly that many bytes), the forward
 solve (default and one-point-per-wave kernels, and the default with the
 projected equilibrium) and the adjoint on the first step of the 2^16-point
 radial profile, the O(v) solve (two points and one point per wavefront) on
-the first step of the 2^16-point moving profile, and the 64-node solves
+the first step of the 2^16-point moving profile (and with the Phi_1
+corrections), the primitive recovery of that profile's moments, and the
+64-node solves
 (kernels on chip and in HBM) on the first step of the 2^18-point profile,
 each at the launch shape of the autotune cache.
 `summarize` scales each kernel's per-dispatch counter by copy bytes / copy
@@ -39,6 +41,10 @@ KERNELS = {
                                      "32 nodes, step 1, one point per wavefront"),
     "fwd_vpair_kernel<3, true>": ("fwd_vpair_kernel_nq32_ns3", "moving radial profile (O(v) solve), 2^16 "
                                   "points, 32 nodes, step 1, two points per wavefront"),
+    "fwd_v_kernel<3, true, true>": ("fwd_v_kernel_nq32_ns3_phi1", "moving radial profile (O(v) solve with the "
+                                    "Phi_1 corrections), 2^16 points, 32 nodes, step 1"),
+    "c2p_kernel": ("c2p_kernel_nq32_ns3", "primitive recovery of every node of the moving radial profile, "
+                   "2^16 points x 3 species x 32 nodes"),
     "fwd64_kernel<3, true, false>": ("fwd64_kernel_nq64_ns3", "radial profile, 2^18 points, 64 nodes, step 1"),
     "fwd64_kernel<3, true, true>": ("fwd64_kernel_nq64_ns3_hbm",
                                     "radial profile, 2^18 points, 64 nodes, step 1, kernels in HBM"),
@@ -88,6 +94,12 @@ def run():
     for store in (0, 5):  # two points per wavefront (default), then one
         S.solve_v(model, S.Params(tol_inner=1e-12, tol_outer=1e-10), W.DTAU_KM, Dv, Iv, tv["rho11"], tv["ye"], efv,
                   tv["v"], theta, out=outv, workspace=ws, launch=S.LaunchConfig(chunk=1, kernel_store=store))
+    # the same with the Phi_1 corrections (the one-point kernel), and the
+    # primitive recovery of the profile's moments at its velocity
+    m1 = S.Model(S.Grid(16), phi1_nes=0.3, phi1_pair=-0.25)
+    S.solve_v(m1, S.Params(tol_inner=1e-12, tol_outer=1e-10), W.DTAU_KM, Dv, Iv, tv["rho11"], tv["ye"], efv,
+              tv["v"], theta, out=outv, workspace=ws, launch=S.LaunchConfig(chunk=1))
+    S.primitive_recovery(model, Dv, Iv, tv["v"])
     torch.cuda.synchronize()
     del ws, out, gbar, D0, I0, e0, t, tv, Dv, Iv, efv, outv
     # 64 nodes, 2^18 points: kernels on chip, then precomputed in HBM
