@@ -191,17 +191,21 @@ def run_velocity(args, mode: str = "solve"):
     D0, I0, ef0 = S.init_state_v(model, t)
     theta = model.default_theta()
     launch = S.LaunchConfig(chunk=args.chunk or 1, blocks_per_cu=args.blocks_per_cu or 0)
-    if mode == "phi1":
-        assert args.kernel_store == "chip", "the Phi_1 solve runs in the one-point kernel (--kernel-store chip)"
+    if mode == "phi1" and args.kernel_store == "wave":
+        launch.kernel_store = 5
         kernel_label, traffic_tag = ("fwd_v_kernel<3, true, true> (persistent O(v) point solve with the Phi_1 "
                                      "corrections, one point per wavefront)"), "fwd_v_kernel_nq32_ns3_phi1"
+    elif mode == "phi1":
+        assert args.kernel_store == "chip", "the Phi_1 solve runs with --kernel-store chip (default) or wave"
+        kernel_label, traffic_tag = ("fwd_vpair_kernel<3, true, true> (persistent O(v) point solve with the Phi_1 "
+                                     "corrections, two points per wavefront)"), "fwd_vpair_kernel_nq32_ns3_phi1"
     elif args.kernel_store == "wave":
         launch.kernel_store = 5
         kernel_label, traffic_tag = ("fwd_v_kernel<3, true, false> (persistent O(v) point solve, one point per "
                                      "wavefront)"), "fwd_v_kernel_nq32_ns3"
     else:
         assert args.kernel_store == "chip", "the O(v) solve runs with --kernel-store chip (default) or wave"
-        kernel_label, traffic_tag = ("fwd_vpair_kernel<3, true> (persistent O(v) point solve, two points per "
+        kernel_label, traffic_tag = ("fwd_vpair_kernel<3, true, false> (persistent O(v) point solve, two points per "
                                      "wavefront)"), "fwd_vpair_kernel_nq32_ns3"
     work = dict(D=D0.clone(), I=I0.clone(), ye=t["ye"].clone(), ef=ef0.clone(), v=t["v"].clone())
     outs = [S.alloc_outputs_v(model, P_POINTS, dev) for _ in range(STEPS_PER_GRAPH)]

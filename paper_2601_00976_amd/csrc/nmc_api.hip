@@ -562,10 +562,11 @@ int nmc_solve_batch_v(const nmc_model* m, const nmc_solver_params* prm, int64_t 
   }
   const bool coupled = (m->host.flags & (NMC_NES | NMC_PAIR)) != 0;
   const bool phi1 = coupled && (m->host.phi1_nes != 0.0 || m->host.phi1_pair != 0.0);
-  // the linear-order corrections run in the one-point-per-wavefront kernel
-  const bool one_point = phi1 || L.kernel_store == NMC_KERNELS_WAVE;
+  // two points per wavefront unless the one-point kernel is asked for; both
+  // carry the linear-order corrections
+  const bool one_point = L.kernel_store == NMC_KERNELS_WAVE;
   hipError_t e = one_point ? nmc::launch_forward_v(a, m->host.ns, coupled, phi1, L, m->num_cu, s)
-                           : nmc::launch_forward_vpair(a, m->host.ns, coupled, L, m->num_cu, s);
+                           : nmc::launch_forward_vpair(a, m->host.ns, coupled, phi1, L, m->num_cu, s);
   if (e == hipErrorInvalidValue) return fail(NMC_E_UNSUPPORTED, "solve_batch_v: no kernel for ns=%d", m->host.ns);
   if (e != hipSuccess) return hip_fail(e, "solve_batch_v: launch");
   return NMC_OK;

@@ -84,29 +84,6 @@ __device__ __forceinline__ void phi1_half(const L& S, int q, int j0, const doubl
   }
 }
 
-// Linear-order collision terms of one species at one node (Eqs.
-// zerothMomentCollisionTerm_NES/_Pair, firstMomentCollisionTerm_NES/_Pair):
-// with P = L_in - L_pro and R = L_out - L_ann (vectors over i),
-//   number equation: (R - P).I
-//   flux equation j: P_j / 3 + (K (R - P))_j,  K = D ((1 - psi) 1 + (3 psi - 1) n n) / 2
-// (the Minerbo tensor of the node, as in closure_terms)
-__device__ __forceinline__ void phi1_collision(double D, const double (&I)[3], const double (&P)[3],
-                                               const double (&R)[3], double& c0, double (&c1)[3]) {
-  const double Imag = sqrt(I[0] * I[0] + I[1] * I[1] + I[2] * I[2]);
-  double h = 0.0;
-  if (Imag > 0.0) h = Imag < D ? Imag * rcp_nr(D) : 1.0;
-  const double psi = 1.0 / 3.0 + (2.0 / 15.0) * (3.0 - h + 3.0 * h * h) * h * h;
-  const double a = 0.5 * (1.0 - psi), b = 0.5 * (3.0 * psi - 1.0);
-  const double rI = Imag > 0.0 ? rcp_nr(Imag) : 0.0;
-  const double n0 = I[0] * rI, n1 = I[1] * rI, n2 = I[2] * rI;
-  const double d0 = R[0] - P[0], d1 = R[1] - P[1], d2 = R[2] - P[2];
-  const double bnd = b * (n0 * d0 + n1 * d1 + n2 * d2);
-  c0 = d0 * I[0] + d1 * I[1] + d2 * I[2];
-  c1[0] = P[0] * (1.0 / 3.0) + D * (a * d0 + bnd * n0);
-  c1[1] = P[1] * (1.0 / 3.0) + D * (a * d1 + bnd * n1);
-  c1[2] = P[2] * (1.0 / 3.0) + D * (a * d2 + bnd * n2);
-}
-
 template <int NS, bool COUPLED, bool PHI1>
 struct PointSolverV {
   static constexpr int NQ = 32;

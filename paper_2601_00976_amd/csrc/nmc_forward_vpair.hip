@@ -16,7 +16,10 @@
 // the columns broadcast by DPP, or the signed orientation form for very cold
 // points).  The Anderson history of the 4 NS owned moments lives in LDS,
 // sharing its space with the pair-factor tile, which is dead during the
-// inner loop.
+// inner loop.  PHI1: the linear-order corrections (Eqs.
+// zerothMomentCollisionTerm_NES/_Pair, firstMomentCollisionTerm_NES/_Pair with
+// Eqs. linearCorrectionsNES/Pair, Phi_1 = r Phi_0 per process), contracted
+// against each flux component on the same core as the isotropic rates.
 #include "nmc_closure.h"
 #include "nmc_pair.h"
 
@@ -94,7 +97,7 @@ __device__ __forceinline__ void dnorms(double w2, const double (&D)[NS], double 
   for (int t = 0; t < NS; ++t) n[t] = s[t];
 }
 
-template <int NS, bool COUPLED>
+template <int NS, bool COUPLED, bool PHI1>
 struct VPairSolver {
   static constexpr int NQ = NQP;
   static constexpr int NM = 4 * NS;            // owned moments per lane
@@ -108,6 +111,62 @@ struct VPairSolver {
     const double Kv = pt.K * (1.0 / kMuC2v);
 #pragma unroll
     for (int j = 0; j < 3; ++j) yq[2 + j] = pt.yst[2 + j] - Kv * (X[2 + j] - pt.X0[2 + j]);
+  }
+
+  // Phi_1 contraction of flux component x_t = W e I_t,i (one component, all
+  // species) on the row B of pair factors: L_in, L_out (own species), L_ann,
+  // L_pro (partner species) at node q.  Symmetric core: the g and h factors
+  // ride on the vectors and the row sums as in the isotropic rates; the
+  // orientation form carries the entries directly.
+  __device__ __forceinline__ static void phi1_pass(bool sym, const double (&B)[NQ], const double (&x)[NS], double gq,
+                                                   double rgq, double hq, double (&Lin)[NS], double (&Lout)[NS],
+                                                   double (&Lann)[NS], double (&Lpro)[NS]) {
+    double eN[NS], oN[NS], aP[NS], eP[NS];
+#pragma unroll
+    for (int t = 0; t < NS; ++t) eN[t] = oN[t] = aP[t] = eP[t] = 0.0;
+    if (sym) {
+      double AR[2][NS], BR[2][NS], CR[2][NS], DR[2][NS];
+#pragma unroll
+      for (int t = 0; t < NS; ++t) {
+        swap16(x[t] * rgq, AR[0][t], AR[1][t]);
+        swap16(x[t] * gq, BR[0][t], BR[1][t]);
+        swap16(x[t], CR[0][t], CR[1][t]);
+        swap16(hq * x[t], DR[0][t], DR[1][t]);
+      }
+      static_for<0, NQ / 4>([&](auto jj) __attribute__((always_inline)) {
+        constexpr int j = 4 * decltype(jj)::value;
+        ColSym<NS>::template run<j % 16>(eN, oN, aP, eP, AR[j / 16], BR[j / 16], CR[j / 16], DR[j / 16], B[j],
+                                         B[j + 1], B[j + 2], B[j + 3]);
+      });
+#pragma unroll
+      for (int t = 0; t < NS; ++t) {
+        Lin[t] = gq * eN[t];
+        Lout[t] = rgq * oN[t];
+      }
+    } else {
+      double XR[2][NS], HR[2][NS];
+#pragma unroll
+      for (int t = 0; t < NS; ++t) {
+        swap16(x[t], XR[0][t], XR[1][t]);
+        swap16(hq * x[t], HR[0][t], HR[1][t]);
+      }
+      static_for<0, NQ>([&](auto jj) __attribute__((always_inline)) {
+        constexpr int j = decltype(jj)::value;
+        const double sb = B[j], b2 = sb * sb, c3 = sb * b2;
+        ColFmac<NS>::template run<j % 16>(eN, oN, aP, eP, XR[j / 16], XR[j / 16], HR[j / 16],
+                                          max_neg_f64(sb, c3), max_neg_f64(c3, sb), b2);
+      });
+#pragma unroll
+      for (int t = 0; t < NS; ++t) {
+        Lin[t] = eN[t];
+        Lout[t] = oN[t];
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < NS; ++t) {
+      Lann[t] = aP[t];
+      Lpro[t] = hq * eP[t];
+    }
   }
 
   template <class Settle>
@@ -325,10 +384,34 @@ struct VPairSolver {
             });
           }
         }
+        // linear-order corrections at the current iterate (PHI1): with
+        // P = r_N L_in - r_P L_pro and R = r_N L_out - r_P L_ann per flux
+        // component, the number equation gains (R - P).I and flux component j
+        // P_j / 3 + (K (R - P))_j (phi1_collision), added like the emissivity
+        double cN[PHI1 ? NS : 1], cI[PHI1 ? NS : 1][3];
+        if constexpr (PHI1) {
+          double Pc[NS][3], Rc[NS][3];
+          const double rN = md->phi1_nes * Aeq, rP = md->phi1_pair * Apq;
+          static_for<0, 3>([&](auto ii) __attribute__((always_inline)) {
+            constexpr int i = decltype(ii)::value;
+            double x[NS], Lin[NS], Lout[NS], Lann[NS], Lpro[NS];
+#pragma unroll
+            for (int t = 0; t < NS; ++t) x[t] = w2eq * I[t][i];
+            phi1_pass(sym, B, x, gq, rgq, hq, Lin, Lout, Lann, Lpro);
+#pragma unroll
+            for (int t = 0; t < NS; ++t) {
+              Pc[t][i] = __builtin_fma(rN, Lin[t], -rP * Lpro[t]);
+              Rc[t][i] = __builtin_fma(rN, Lout[t], -rP * Lann[t]);
+            }
+          });
+#pragma unroll
+          for (int t = 0; t < NS; ++t) phi1_collision(D[t], I[t], Pc[t], Rc[t], cN[t], cI[t]);
+        }
         // Q and residual of the owned moments (Eq. implicitMomentsNodal):
-        //   Q_D  = ((1 - lam) D - lam v.I + lam (N* + dtau eta)) / (1 + lam dtau chi)
-        //   Q_Ij = ((1 - lam) I_j - lam v^i K_ij + lam G*_j) / (1 + lam dtau kappa)
-        // one reciprocal of the product of the two denominators serves both
+        //   Q_D  = ((1 - lam) D - lam v.I + lam (N* + dtau (eta + c))) / (1 + lam dtau chi)
+        //   Q_Ij = ((1 - lam) I_j - lam v^i K_ij + lam (G*_j + dtau c_j)) / (1 + lam dtau kappa)
+        // (c, c_j the linear-order terms, zero without PHI1); one reciprocal
+        // of the product of the two denominators serves both
         double Qx[NM];
 #pragma unroll
         for (int t = 0; t < NS; ++t) {
@@ -338,11 +421,13 @@ struct VPairSolver {
           closure_terms(D[t], I[t], v, vI, vK);
           const double dD = __builtin_fma(ldt, chi, denD[t]), dI = __builtin_fma(ldt, chi, denI[t]);
           const double r = rcp_nr(dD * dI);
-          const double nD = __builtin_fma(oml, D[t], baseD[t]) - lam * vI + ldt * eta;
+          double nD = __builtin_fma(oml, D[t], baseD[t]) - lam * vI + ldt * eta;
+          if constexpr (PHI1) nD = __builtin_fma(ldt, cN[t], nD);
           Qx[4 * t] = nD * (r * dI);
 #pragma unroll
           for (int j = 0; j < 3; ++j) {
-            const double nI = __builtin_fma(oml, I[t][j], lam * Gst[t][j]) - lam * vK[j];
+            double nI = __builtin_fma(oml, I[t][j], lam * Gst[t][j]) - lam * vK[j];
+            if constexpr (PHI1) nI = __builtin_fma(ldt, cI[t][j], nI);
             Qx[4 * t + 1 + j] = nI * (r * dD);
           }
         }
@@ -571,7 +656,7 @@ struct VPairSolver {
   }
 };
 
-template <int NS, bool COUPLED>
+template <int NS, bool COUPLED, bool PHI1>
 __global__ __launch_bounds__(kLanes, COUPLED ? 1 : 2) void fwd_vpair_kernel(FwdVArgs a) {
   __shared__ VPairLds<NS> S;
   load_model(a.mdl, a.theta, S.m);
@@ -581,18 +666,18 @@ __global__ __launch_bounds__(kLanes, COUPLED ? 1 : 2) void fwd_vpair_kernel(FwdV
     for (int64_t g; (g = wq.next()) >= 0;) {
       const int64_t b0 = uniform64(g * a.chunk);
       const int64_t end = uniform64(b0 + a.chunk < pairs ? b0 + a.chunk : pairs);
-      for (int64_t u = b0; u < end; ++u) VPairSolver<NS, COUPLED>::solve(a, u, S, [&] { wq.settle(); });
+      for (int64_t u = b0; u < end; ++u) VPairSolver<NS, COUPLED, PHI1>::solve(a, u, S, [&] { wq.settle(); });
     }
   } else {
     const int64_t b0 = (int64_t)blockIdx.x * a.chunk;
     const int64_t end = b0 + a.chunk < pairs ? b0 + a.chunk : pairs;
-    for (int64_t u = b0; u < end; ++u) VPairSolver<NS, COUPLED>::solve(a, u, S, [] {});
+    for (int64_t u = b0; u < end; ++u) VPairSolver<NS, COUPLED, PHI1>::solve(a, u, S, [] {});
   }
 }
 
-template <int NS, bool COUPLED>
+template <int NS, bool COUPLED, bool PHI1>
 hipError_t launch_vpair_t(const FwdVArgs& a, const nmc_launch& L, int num_cu, hipStream_t s) {
-  auto kern = fwd_vpair_kernel<NS, COUPLED>;
+  auto kern = fwd_vpair_kernel<NS, COUPLED, PHI1>;
   const int64_t pairs = (a.P + 1) / 2;
   const int64_t need = (pairs + a.chunk - 1) / a.chunk;
   int64_t grid;
@@ -619,19 +704,25 @@ hipError_t launch_vpair_t(const FwdVArgs& a, const nmc_launch& L, int num_cu, hi
 
 }  // namespace
 
-hipError_t launch_forward_vpair(const FwdVArgs& a, int ns, bool coupled, const nmc_launch& L, int num_cu,
-                                hipStream_t s) {
-  if (coupled) {
+hipError_t launch_forward_vpair(const FwdVArgs& a, int ns, bool coupled, bool phi1, const nmc_launch& L,
+                                int num_cu, hipStream_t s) {
+  if (coupled && phi1) {
     switch (ns) {
-      case 1: return launch_vpair_t<1, true>(a, L, num_cu, s);
-      case 2: return launch_vpair_t<2, true>(a, L, num_cu, s);
-      case 3: return launch_vpair_t<3, true>(a, L, num_cu, s);
+      case 1: return launch_vpair_t<1, true, true>(a, L, num_cu, s);
+      case 2: return launch_vpair_t<2, true, true>(a, L, num_cu, s);
+      case 3: return launch_vpair_t<3, true, true>(a, L, num_cu, s);
+    }
+  } else if (coupled) {
+    switch (ns) {
+      case 1: return launch_vpair_t<1, true, false>(a, L, num_cu, s);
+      case 2: return launch_vpair_t<2, true, false>(a, L, num_cu, s);
+      case 3: return launch_vpair_t<3, true, false>(a, L, num_cu, s);
     }
   } else {
     switch (ns) {
-      case 1: return launch_vpair_t<1, false>(a, L, num_cu, s);
-      case 2: return launch_vpair_t<2, false>(a, L, num_cu, s);
-      case 3: return launch_vpair_t<3, false>(a, L, num_cu, s);
+      case 1: return launch_vpair_t<1, false, false>(a, L, num_cu, s);
+      case 2: return launch_vpair_t<2, false, false>(a, L, num_cu, s);
+      case 3: return launch_vpair_t<3, false, false>(a, L, num_cu, s);
     }
   }
   return hipErrorInvalidValue;

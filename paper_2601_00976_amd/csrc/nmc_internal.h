@@ -123,7 +123,7 @@ hipError_t launch_forward_pair(const FwdArgs& a, int ns, bool coupled, bool proj
                                int num_cu, hipStream_t s);
 hipError_t launch_forward_v(const FwdVArgs& a, int ns, bool coupled, bool phi1, const nmc_launch& L, int num_cu,
                             hipStream_t s);
-hipError_t launch_forward_vpair(const FwdVArgs& a, int ns, bool coupled, const nmc_launch& L, int num_cu,
+hipError_t launch_forward_vpair(const FwdVArgs& a, int ns, bool coupled, bool phi1, const nmc_launch& L, int num_cu,
                                 hipStream_t s);
 hipError_t launch_reset_counter(int* counter, hipStream_t s);
 hipError_t launch_c2p(int64_t P, int ns, int nq, const double* N, const double* G, const double* v, int mem,

@@ -39,10 +39,11 @@ KERNELS = {
     "adj_kernel<3>": ("adj_kernel_nq32_ns3", "radial profile, 2^16 points, 32 nodes, step 1"),
     "fwd_v_kernel<3, true, false>": ("fwd_v_kernel_nq32_ns3", "moving radial profile (O(v) solve), 2^16 points, "
                                      "32 nodes, step 1, one point per wavefront"),
-    "fwd_vpair_kernel<3, true>": ("fwd_vpair_kernel_nq32_ns3", "moving radial profile (O(v) solve), 2^16 "
+    "fwd_vpair_kernel<3, true, false>": ("fwd_vpair_kernel_nq32_ns3", "moving radial profile (O(v) solve), 2^16 "
                                   "points, 32 nodes, step 1, two points per wavefront"),
-    "fwd_v_kernel<3, true, true>": ("fwd_v_kernel_nq32_ns3_phi1", "moving radial profile (O(v) solve with the "
-                                    "Phi_1 corrections), 2^16 points, 32 nodes, step 1"),
+    "fwd_vpair_kernel<3, true, true>": ("fwd_vpair_kernel_nq32_ns3_phi1", "moving radial profile (O(v) solve "
+                                        "with the Phi_1 corrections), 2^16 points, 32 nodes, step 1, two points "
+                                        "per wavefront"),
     "c2p_kernel": ("c2p_kernel_nq32_ns3", "primitive recovery of every node of the moving radial profile, "
                    "2^16 points x 3 species x 32 nodes"),
     "fwd64_kernel<3, true, false>": ("fwd64_kernel_nq64_ns3", "radial profile, 2^18 points, 64 nodes, step 1"),
@@ -94,7 +95,7 @@ def run():
     for store in (0, 5):  # two points per wavefront (default), then one
         S.solve_v(model, S.Params(tol_inner=1e-12, tol_outer=1e-10), W.DTAU_KM, Dv, Iv, tv["rho11"], tv["ye"], efv,
                   tv["v"], theta, out=outv, workspace=ws, launch=S.LaunchConfig(chunk=1, kernel_store=store))
-    # the same with the Phi_1 corrections (the one-point kernel), and the
+    # the same with the Phi_1 corrections (two points per wavefront), and the
     # primitive recovery of the profile's moments at its velocity
     m1 = S.Model(S.Grid(16), phi1_nes=0.3, phi1_pair=-0.25)
     S.solve_v(m1, S.Params(tol_inner=1e-12, tol_outer=1e-10), W.DTAU_KM, Dv, Iv, tv["rho11"], tv["ye"], efv,

@@ -1,8 +1,9 @@
 """GPU parity of the O(v) solve with the linear-order (Phi_1) NES and pair
 corrections (Eqs. zerothMomentCollisionTerm_NES/_Pair,
 firstMomentCollisionTerm_NES/_Pair with Eqs. linearCorrectionsNES/Pair)
-against the oracle: the moving profile with pass-through, fast flow, species
-subsets, and a full-size launch sampled along the profile."""
+against the oracle: the moving profile with pass-through (both kernels: two
+points per wavefront, the default, and one point per wavefront), fast flow,
+species subsets."""
 import numpy as np
 import pytest
 
@@ -50,10 +51,12 @@ def _compare(om, ref, got, rho11, species=(0, 1, 2)):
     assert max(eD.max(), eI.max(), eY.max(), eE.max(), eV.max()) <= TOL
 
 
-def test_phi1_moving_profile_parity():
-    print("[case] Phi_1 terms, O(v) moving profile sample with pass-through, P=400", flush=True)
+@pytest.mark.parametrize("store", [0, 5], ids=["two_points_per_wave", "one_point_per_wave"])
+def test_phi1_moving_profile_parity(store):
+    print(f"[case] Phi_1 terms, O(v) moving profile sample with pass-through, P=400, kernel_store {store}",
+          flush=True)
     d = W.radial_profile_v(P=1 << 16).take(np.linspace(0, 45000, 400).astype(np.int64))
-    om, ref, got = _run(d)
+    om, ref, got = _run(d, launch=S.LaunchConfig(chunk=1, kernel_store=store))
     _compare(om, ref, got, d.rho11)
     # the corrections act: the isotropic solve of the same inputs differs
     _, iso, _ = _run(d.take(np.arange(0, 400, 8)), r=(0.0, 0.0))
