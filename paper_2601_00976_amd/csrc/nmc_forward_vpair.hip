@@ -14,9 +14,10 @@
 // of a node are lane-local.  The collision rates depend on the number moments
 // only and are contracted as in the static kernel (symmetric b^2 core with
 // the columns broadcast by DPP, or the signed orientation form for very cold
-// points).  The Anderson history of the 4 NS owned moments lives in LDS,
-// sharing its space with the pair-factor tile, which is dead during the
-// inner loop.  PHI1: the linear-order corrections (Eqs.
+// points).  The Anderson history of the 4 NS owned moments lives in
+// registers in the coupled kernel (one wave per SIMD leaves them to spare),
+// otherwise in LDS, sharing its space with the pair-factor tile, which is dead
+// during the inner loop.  PHI1: the linear-order corrections (Eqs.
 // zerothMomentCollisionTerm_NES/_Pair, firstMomentCollisionTerm_NES/_Pair with
 // Eqs. linearCorrectionsNES/Pair, Phi_1 = r Phi_0 per process), contracted
 // against each flux component on the same core as the isotropic rates.
@@ -101,6 +102,9 @@ template <int NS, bool COUPLED, bool PHI1>
 struct VPairSolver {
   static constexpr int NQ = NQP;
   static constexpr int NM = 4 * NS;            // owned moments per lane
+  // the inner Anderson history in registers (the coupled isotropic kernel
+  // runs one wave per SIMD and has the registers to spare); otherwise in LDS
+  static constexpr bool HREG = COUPLED && !PHI1;
 
   // matter right-hand side q(M, y) of Eq. implicitFluidNodal from the
   // integrals X of the current moments
@@ -337,6 +341,7 @@ struct VPairSolver {
       const double Aeq = pt.An * epsq, Apq = pt.Ap * epsq, Apqh = Apq * hq;
 
       double G11 = 0.0;
+      double H[4][NM];  // Q_prev, F_prev, dQ_old, dF_old per owned moment (HREG)
       const bool ran = run;
       bool act = run;
       bool cvd = false;
@@ -436,48 +441,92 @@ struct VPairSolver {
         // Anderson step over min(l, M_inner) residuals (difference form)
         const int mem = l < a.prm.m_inner ? l : a.prm.m_inner;
         double Xn[NM];
-        if (mem == 1) {
-          // the older difference column is weighted zero at the second
-          // iterate: clear it, so that no stale LDS word enters that product
+        if constexpr (HREG) {
+          // history in registers
+          if (mem == 1) {
+            // the older difference column is weighted zero at the second
+            // iterate: clear it, so that no stale value enters that product
+#pragma unroll
+            for (int x = 0; x < NM; ++x) {
+              Xn[x] = Qx[x];
+              H[2][x] = 0.0;
+              H[3][x] = 0.0;
+            }
+          } else {
+            const double use1 = (mem == 3) ? 1.0 : 0.0;
+            double v4[4] = {0.0, 0.0, 0.0, 0.0}, dF2[NM];
+#pragma unroll
+            for (int x = 0; x < NM; ++x) {
+              const double Fx = Qx[x] - cur(x);
+              dF2[x] = Fx - H[1][x];
+              const double dF1 = use1 * H[3][x];
+              v4[0] += dF1 * dF2[x];
+              v4[1] += dF2[x] * dF2[x];
+              v4[2] += dF1 * Fx;
+              v4[3] += dF2[x] * Fx;
+            }
+            double gs[4];
+            half_sums4(v4, gs);
+            double g1, g2;
+            anderson2(mem == 3, G11, gs[0], gs[1], gs[2], gs[3], g1, g2);
+#pragma unroll
+            for (int x = 0; x < NM; ++x) {
+              const double dQ2 = Qx[x] - H[0][x];
+              Xn[x] = Qx[x] - g2 * dQ2 - g1 * H[2][x];
+              H[2][x] = dQ2;
+              H[3][x] = dF2[x];
+            }
+            G11 = gs[1];
+          }
 #pragma unroll
           for (int x = 0; x < NM; ++x) {
-            Xn[x] = Qx[x];
-            S.u.hist[2][x][lane] = 0.0;
-            S.u.hist[3][x][lane] = 0.0;
+            H[1][x] = Qx[x] - cur(x);
+            H[0][x] = Qx[x];
           }
         } else {
-          // two passes over the owned moments: the Gram sums, then the step
-          // (the differences are formed again from LDS rather than held)
-          const double use1 = (mem == 3) ? 1.0 : 0.0;
-          double v4[4] = {0.0, 0.0, 0.0, 0.0};
+          if (mem == 1) {
+            // the older difference column is weighted zero at the second
+            // iterate: clear it, so that no stale LDS word enters that product
+#pragma unroll
+            for (int x = 0; x < NM; ++x) {
+              Xn[x] = Qx[x];
+              S.u.hist[2][x][lane] = 0.0;
+              S.u.hist[3][x][lane] = 0.0;
+            }
+          } else {
+            // two passes over the owned moments: the Gram sums, then the step
+            // (the differences are formed again from LDS rather than held)
+            const double use1 = (mem == 3) ? 1.0 : 0.0;
+            double v4[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int x = 0; x < NM; ++x) {
+              const double Fx = Qx[x] - cur(x);
+              const double dF2 = Fx - S.u.hist[1][x][lane];
+              const double dF1 = use1 * S.u.hist[3][x][lane];
+              v4[0] += dF1 * dF2;
+              v4[1] += dF2 * dF2;
+              v4[2] += dF1 * Fx;
+              v4[3] += dF2 * Fx;
+            }
+            double gs[4];
+            half_sums4(v4, gs);
+            double g1, g2;
+            anderson2(mem == 3, G11, gs[0], gs[1], gs[2], gs[3], g1, g2);
+#pragma unroll
+            for (int x = 0; x < NM; ++x) {
+              const double dQ2 = Qx[x] - S.u.hist[0][x][lane];
+              const double dF2 = (Qx[x] - cur(x)) - S.u.hist[1][x][lane];
+              Xn[x] = Qx[x] - g2 * dQ2 - g1 * S.u.hist[2][x][lane];
+              S.u.hist[2][x][lane] = dQ2;
+              S.u.hist[3][x][lane] = dF2;
+            }
+            G11 = gs[1];
+          }
 #pragma unroll
           for (int x = 0; x < NM; ++x) {
-            const double Fx = Qx[x] - cur(x);
-            const double dF2 = Fx - S.u.hist[1][x][lane];
-            const double dF1 = use1 * S.u.hist[3][x][lane];
-            v4[0] += dF1 * dF2;
-            v4[1] += dF2 * dF2;
-            v4[2] += dF1 * Fx;
-            v4[3] += dF2 * Fx;
+            S.u.hist[0][x][lane] = Qx[x];
+            S.u.hist[1][x][lane] = Qx[x] - cur(x);
           }
-          double gs[4];
-          half_sums4(v4, gs);
-          double g1, g2;
-          anderson2(mem == 3, G11, gs[0], gs[1], gs[2], gs[3], g1, g2);
-#pragma unroll
-          for (int x = 0; x < NM; ++x) {
-            const double dQ2 = Qx[x] - S.u.hist[0][x][lane];
-            const double dF2 = (Qx[x] - cur(x)) - S.u.hist[1][x][lane];
-            Xn[x] = Qx[x] - g2 * dQ2 - g1 * S.u.hist[2][x][lane];
-            S.u.hist[2][x][lane] = dQ2;
-            S.u.hist[3][x][lane] = dF2;
-          }
-          G11 = gs[1];
-        }
-#pragma unroll
-        for (int x = 0; x < NM; ++x) {
-          S.u.hist[0][x][lane] = Qx[x];
-          S.u.hist[1][x][lane] = Qx[x] - cur(x);
         }
         bool bad = false;
 #pragma unroll
