@@ -103,9 +103,10 @@ __device__ __forceinline__ void elim_cols4(double& r0, double& r1, double& r2, d
 // the update FMAs take column 16 g + L from lane L of the lane's row by DPP
 // broadcast.  All lanes run the FMAs (a DPP source lane must be active); the
 // pivot rows have zero multipliers, so their entries are unchanged.  The
-// columns of a group left of k + 2 are updated too: they are eliminated
-// columns or the row's own pivot block, which the row keeps in registers
-// when it is eliminated, and are never read again.  Rows above the pivot are
+// update starts at the 4-column block of column k + 2; the columns of that
+// block left of k + 2 are updated too: they are eliminated columns or the
+// row's own pivot block, which the row keeps in registers when it is
+// eliminated, and are never read again.  Rows above the pivot are
 // updated by the same instructions as the rows below, so the elimination
 // costs no more than a one-sided one, and at the end every pivot pair holds
 // only its own block: z = B^-1 c for each pair, from the partner's
@@ -160,7 +161,11 @@ __device__ __forceinline__ bool solve_block_transposed(double (&R)[N], double c0
     static_for<(k + 2) / 16, N / 16>([&](auto gg) __attribute__((always_inline)) {
       constexpr int g = decltype(gg)::value;
       const double u = prow[16 * g + col], w = prow[RS + 16 * g + col];
-      static_for<0, 4>([&](auto qq) __attribute__((always_inline)) {
+      // in the group of column k + 2, the 4-column blocks left of it hold
+      // only dead entries (eliminated columns, or the pivot blocks kept in
+      // registers): skipped
+      constexpr int q0 = g == (k + 2) / 16 ? ((k + 2) % 16) / 4 : 0;
+      static_for<q0, 4>([&](auto qq) __attribute__((always_inline)) {
         constexpr int j = 16 * g + 4 * decltype(qq)::value;
         elim_cols4<j % 16>(R[j], R[j + 1], R[j + 2], R[j + 3], u, w, nl0, nl1);
       });
