@@ -367,14 +367,13 @@ struct PairSolver {
             S.u.hist[3][x][lane] = 0.0;
           }
         } else {
-          const double use1 = (mem == 3) ? 1.0 : 0.0;
           double dQ2[2 * NS], dF2[2 * NS];
           double v4[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
           for (int x = 0; x < 2 * NS; ++x) {
             dQ2[x] = Qx[x] - S.u.hist[0][x][lane];
             dF2[x] = Fx[x] - S.u.hist[1][x][lane];
-            const double dF1 = use1 * S.u.hist[3][x][lane];
+            const double dF1 = S.u.hist[3][x][lane];
             v4[0] += dF1 * dF2[x];
             v4[1] += dF2[x] * dF2[x];
             v4[2] += dF1 * Fx[x];

@@ -453,13 +453,12 @@ struct VPairSolver {
               H[3][x] = 0.0;
             }
           } else {
-            const double use1 = (mem == 3) ? 1.0 : 0.0;
             double v4[4] = {0.0, 0.0, 0.0, 0.0}, dF2[NM];
 #pragma unroll
             for (int x = 0; x < NM; ++x) {
               const double Fx = Qx[x] - cur(x);
               dF2[x] = Fx - H[1][x];
-              const double dF1 = use1 * H[3][x];
+              const double dF1 = H[3][x];
               v4[0] += dF1 * dF2[x];
               v4[1] += dF2[x] * dF2[x];
               v4[2] += dF1 * Fx;
@@ -496,13 +495,12 @@ struct VPairSolver {
           } else {
             // two passes over the owned moments: the Gram sums, then the step
             // (the differences are formed again from LDS rather than held)
-            const double use1 = (mem == 3) ? 1.0 : 0.0;
             double v4[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
             for (int x = 0; x < NM; ++x) {
               const double Fx = Qx[x] - cur(x);
               const double dF2 = Fx - S.u.hist[1][x][lane];
-              const double dF1 = use1 * S.u.hist[3][x][lane];
+              const double dF1 = S.u.hist[3][x][lane];
               v4[0] += dF1 * dF2;
               v4[1] += dF2 * dF2;
               v4[2] += dF1 * Fx;

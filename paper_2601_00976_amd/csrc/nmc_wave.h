@@ -360,7 +360,9 @@ __device__ __forceinline__ double log_pos(double x) {
 // (1 the older, 2 the newer) from their normal equations, by LDL^T (the
 // Cholesky pivots G11 and G22 - G12^2 / G11, without square roots).  A pivot
 // <= 1e-14 trace drops the older column, and with no column left the step is
-// Picard (g = 0).  two_cols says whether the older column exists.
+// Picard (g = 0).  two_cols says whether the older column exists; without
+// it G12 and b1 are not used (any value, NaN included, gives the same g2 and
+// g1 = 0), so callers need not zero the older column's products.
 // Branch-free, with Newton-refined reciprocals of the positive pivots.
 __device__ __forceinline__ void anderson2(bool two_cols, double G11, double G12, double G22, double b1, double b2,
                                           double& g1, double& g2) {
