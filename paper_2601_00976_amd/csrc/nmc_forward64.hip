@@ -393,29 +393,25 @@ struct PointSolver64 {
           fatal = true;
           break;
         }
-        // Algorithm innerConverged, compared squared
+        // Algorithm innerConverged, compared squared; the sums are spread over
+        // the wave (row c of 16 lanes holds species c, spread_conv_sums64) and
+        // the point has converged when every lane passes
         {
-          double v[3 * NS], s[3 * NS];
+          double vd[NS], vi[NS], vn[NS];
 #pragma unroll
           for (int t = 0; t < NS; ++t) {
             const double dd = Xn[t] - D[t], di = Xn[NS + t] - I[t];
-            v[t] = w2q * dd * dd;
-            v[NS + t] = w2q * di * di;
-            v[2 * NS + t] = w2q * Xn[t] * Xn[t];
+            vd[t] = w2q * dd * dd;
+            vi[t] = w2q * di * di;
+            vn[t] = w2q * Xn[t] * Xn[t];
           }
-          wave_sums<3 * NS>(v, s);
-          conv = true;
-#pragma unroll
-          for (int t = 0; t < NS; ++t) {
-            const double dm2 = s[t] > s[NS + t] ? s[t] : s[NS + t];
-            const double d0 = S.dref[t], dn2 = s[2 * NS + t];
-            const double dref2 = d0 > dn2 ? d0 : dn2;
-            if (!(dm2 <= a.tol_inner2 * dref2)) conv = false;
-          }
-          if (conv) {
-#pragma unroll
-            for (int t = 0; t < NS; ++t) S.dref[t] = s[2 * NS + t];
-          }
+          double dm2, dn2;
+          spread_conv_sums64<NS>(vd, vi, vn, dm2, dn2);
+          const int cls = lane >> 4;
+          const double d0 = cls < NS ? S.dref[cls < NS ? cls : 0] : 0.0;
+          const double dref2 = d0 > dn2 ? d0 : dn2;
+          conv = __builtin_amdgcn_ballot_w64(!(dm2 <= a.tol_inner2 * dref2)) == 0;
+          if (conv && cls < NS) S.dref[cls < NS ? cls : 0] = dn2;
         }
 #pragma unroll
         for (int t = 0; t < NS; ++t) {

@@ -59,29 +59,6 @@ __device__ __forceinline__ void half_own_sums(const double (&v)[2 * K], double (
 }
 
 
-// Lanes whose DPP bank (4-lane group of a 16-lane row, bit b of BANKS for
-// lanes 4b..4b+3) is enabled take src from their DPP source lane of CTRL; the
-// others keep old.
-template <int CTRL, int BANKS>
-__device__ __forceinline__ double dpp_banks(double old, double src) {
-  const long v = __builtin_amdgcn_update_dpp(__builtin_bit_cast(long, old), __builtin_bit_cast(long, src), CTRL,
-                                             0xF, BANKS, false);
-  return __builtin_bit_cast(double, v);
-}
-
-// A butterfly stage that folds the sums of two values into one register:
-// CTRL pairs every lane of the banks in A with a lane outside them
-// (row_mirror with A = banks 0, 1; row_half_mirror with A = banks 0, 2), and
-// after it lanes in A hold a + a(partner), the others b + b(partner).  Two
-// masked moves and one add, where two separate stages cost four moves and
-// two adds; the next stages then carry one value instead of two.
-template <int CTRL, int A>
-__device__ __forceinline__ double fold_pair(double a, double b) {
-  const double x = dpp_banks<CTRL, A>(b, a);
-  const double y = dpp_banks<CTRL, 0xF ^ A>(a, b);
-  return x + y;
-}
-
 // Species class of a lane for the spread sums below: c = 2 r + m with r the
 // row of the lane within its half and m = 1 for lanes 8..15 of the row.
 __device__ __forceinline__ int spread_class(int lane) { return ((lane >> 4) & 1) * 2 + ((lane >> 3) & 1); }

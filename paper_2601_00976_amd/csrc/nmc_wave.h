@@ -135,6 +135,64 @@ __device__ __forceinline__ double halve16(double a, double b) {
   return mk64(x[0], y[0]) + mk64(x[1], y[1]);
 }
 
+// Lanes whose DPP bank (4-lane group of a 16-lane row, bit b of BANKS for
+// lanes 4b..4b+3) is enabled take src from their DPP source lane of CTRL; the
+// others keep old.
+template <int CTRL, int BANKS>
+__device__ __forceinline__ double dpp_banks(double old, double src) {
+  const long v = __builtin_amdgcn_update_dpp(__builtin_bit_cast(long, old), __builtin_bit_cast(long, src), CTRL,
+                                             0xF, BANKS, false);
+  return __builtin_bit_cast(double, v);
+}
+
+// A butterfly stage that folds the sums of two values into one register:
+// CTRL pairs every lane of the banks in A with a lane outside them
+// (row_mirror with A = banks 0, 1; row_half_mirror with A = banks 0, 2), and
+// after it lanes in A hold a + a(partner), the others b + b(partner).  Two
+// masked moves and one add, where two separate stages cost four moves and
+// two adds; the next stages then carry one value instead of two.
+template <int CTRL, int A>
+__device__ __forceinline__ double fold_pair(double a, double b) {
+  const double x = dpp_banks<CTRL, A>(b, a);
+  const double y = dpp_banks<CTRL, 0xF ^ A>(a, b);
+  return x + y;
+}
+
+// Sums over the whole wave of the inner convergence test of a one-point
+// kernel (64 nodes, lane = node), spread over the lanes: the 16-lane row c
+// (lane >> 4) holds species c (zeros where c >= NS).  d is the squared change
+// of D_c in lanes with bit 3 clear and of I_c in the others; n is the squared
+// norm of the new D_c.  The wave halves split the species pairs (0, 1) and
+// (2, 3), the rows of a half split the pairs, row_mirror folds the D and I
+// changes apart, and three more DPP stages finish.  Fixed order; every lane
+// of a row and bank pair holds the same bits.
+template <int NS>
+__device__ __forceinline__ void spread_conv_sums64(const double (&dd)[NS], const double (&di)[NS],
+                                                   const double (&xn)[NS], double& d, double& n) {
+  double pd[4], pi[4], pn[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    pd[c] = c < NS ? dd[c < NS ? c : 0] : 0.0;
+    pi[c] = c < NS ? di[c < NS ? c : 0] : 0.0;
+    pn[c] = c < NS ? xn[c < NS ? c : 0] : 0.0;
+  }
+  // halve32: lanes 0..31 carry species (0, 1), lanes 32..63 (2, 3); halve16:
+  // the even row of a half the first of its pair, the odd row the second
+  const double fd = halve16(halve32(pd[0], pd[2]), halve32(pd[1], pd[3]));
+  const double fi = halve16(halve32(pi[0], pi[2]), halve32(pi[1], pi[3]));
+  double x = halve16(halve32(pn[0], pn[2]), halve32(pn[1], pn[3]));
+  double y = fold_pair<0x140, 0x3>(fd, fi);  // row_mirror: lanes 0..7 keep D
+  x += dpp<0x140>(x);
+  y += dpp<0x141>(y);  // row_half_mirror
+  x += dpp<0x141>(x);
+  y += dpp<0xB1>(y);  // quad_perm [1,0,3,2]
+  x += dpp<0xB1>(x);
+  y += dpp<0x4E>(y);  // quad_perm [2,3,0,1]
+  x += dpp<0x4E>(x);
+  d = y;
+  n = x;
+}
+
 // Sums of 4 values over all 64 lanes, returned in every lane.
 __device__ __forceinline__ void wave_sums4(const double (&v)[4], double (&out)[4]) {
   // lanes 0..31: (v0, v1) over the wave halves; lanes 32..63: (v2, v3)
