@@ -324,11 +324,10 @@ typedef struct {
 /* Batched O(v) forward solve.  32-node grids only (NMC_E_UNSUPPORTED
  * otherwise).  launch->kernel_store NMC_KERNELS_ON_CHIP (default) or
  * NMC_KERNELS_PAIRED: two points per wavefront, each lane owning the four
- * moments of its node; NMC_KERNELS_WAVE: one point per wavefront (the mode
- * that also carries the linear-order corrections, used whenever phi1_nes or
- * phi1_pair is nonzero).  Other modes return NMC_E_UNSUPPORTED.  Workspace,
- * launch, stream and error rules as for nmc_solve_batch; dtau must be
- * positive. */
+ * moments of its node; NMC_KERNELS_WAVE: one point per wavefront.  Both
+ * carry the linear-order corrections when phi1_nes or phi1_pair is nonzero.
+ * Other modes return NMC_E_UNSUPPORTED.  Workspace, launch, stream and error
+ * rules as for nmc_solve_batch; dtau must be positive. */
 int nmc_solve_batch_v(const nmc_model* m, const nmc_solver_params* prm, int64_t P, double dtau,
                       const nmc_batch_v_in* in, const nmc_batch_v_out* out, void* ws, size_t ws_bytes,
                       const nmc_launch* launch, void* stream);
