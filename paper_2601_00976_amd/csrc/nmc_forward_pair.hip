@@ -52,7 +52,7 @@ struct PairLds {
   struct Pt {                      // per-point state of the outer (matter) loop
     double dref[NS];               // ||D_s^[k,1]||_W^2 of the current inner loop
     double y[2], oq[2], of[2], odq[2], odf[2];
-    double T_last, r3, K, An, Ap;
+    double r3, K, An, Ap;
     double ye_st, e_st, chi0, T_fix, mu_fix;
   } pt[2];
 };
@@ -108,7 +108,6 @@ struct PairSolver {
     if (a.prm.fixed_matter && a.mu_fixed) pt.mu_fix = a.mu_fixed[p];
 #pragma unroll
     for (int i = 0; i < 2; ++i) pt.oq[i] = pt.of[i] = pt.odq[i] = pt.odf[i] = 0.0;
-    pt.T_last = 0.0;
     {
       const double w2q = mt.w2[q0];
       double v[2 * ((NS + 1) / 2)], s[2 * ((NS + 1) / 2)];
@@ -123,6 +122,7 @@ struct PairSolver {
     bool fatal = false, inner_failed = false, outer_conv = false;
     bool run = !skip;  // this half's point is still iterating the outer loop
     int k_done = 0, total_inner = 0;
+    double T_last = 0.0;  // temperature of the last outer iteration this half ran
 
     for (int k = 1; k <= a.prm.max_outer && __builtin_amdgcn_ballot_w64(run) != 0; ++k) {
       const_ptr<DevModel> md = scalar_ptr(a.mdl);
@@ -143,10 +143,14 @@ struct PairSolver {
         fatal = true;
         run = false;
       }
-      if (run) pt.T_last = T;
+      T_last = run ? T : T_last;
       // a finished half keeps a harmless temperature
       const double Tu = run ? T : 1.0, muu = run ? mu : 0.0;
       const double invT = rcp_nr(Tu);
+      // the exponent split of this lane's node (pair factors below), issued
+      // here so that it overlaps the equilibrium's exponentials
+      const double epsq = mt.eps[q];
+      const ExpSplit xs = exp_split(epsq, invT);
       double baseD[NS], den0D[NS];
       // projected equilibrium and its complement at node q (every lane, both
       // halves: the element partner exchange is a DPP)
@@ -156,7 +160,6 @@ struct PairSolver {
         for (int t = 0; t < NS; ++t) fdp::projected_node(a.mdl, q, Tu, md->imusign[t] * muu, pD[t], pC[t]);
       }
       double dsig = 0.0;  // dtau sigma: 1 + dtau kappa = 1 + dtau chi + dsig
-      const double epsq = mt.eps[q];
       {
         const double shape = pt.chi0 * mt.shape[q];
         const double sig = (md->flags & NMC_ISO) ? md->sigma_ratio * shape : 0.0;
@@ -202,7 +205,6 @@ struct PairSolver {
       bool sym = false;  // wave-uniform
       if constexpr (COUPLED) {
         SplitExp& E = S.E[h];
-        const ExpSplit xs = exp_split(epsq, invT);
         E.P2[q] = xs.P;
         E.R2[q] = xs.R;
         E.n2[q] = xs.n;
@@ -531,7 +533,7 @@ struct PairSolver {
 
     // ---- outputs --------------------------------------------------------
     const double ye_st = pt.ye_st, e_st = pt.e_st;
-    double ye_out = ye_st, e_out = e_st, T_out = pt.T_last;
+    double ye_out = ye_st, e_out = e_st, T_out = T_last;
     {
       const double w2 = mt.w2[q0], w3 = mt.w3[q0];
       double mv[2] = {0.0, 0.0}, s[2];
