@@ -50,7 +50,6 @@ struct PairLds {
     double tile[2][NQP][NQP];        // per point, signed pair factors: [j][q] = +b if j > q, else -b
   } u;
   struct Pt {                      // per-point state of the outer (matter) loop
-    double dref[NS];               // ||D_s^[k,1]||_W^2 of the current inner loop
     double y[2], oq[2], of[2], odq[2], odf[2];
     double r3, K, An, Ap;
     double ye_st, e_st, chi0, T_fix, mu_fix;
@@ -84,6 +83,10 @@ struct PairSolver {
     const double rho = a.rho11[p];
     const bool fixedT = a.prm.fixed_matter && a.T_fixed;
     typename PairLds<NS>::Pt& pt = S.pt[h];
+    // ||D_c^[k,1]||_W^2 of the current inner loop for this lane's species
+    // class c (spread_conv_sums; zero beyond NS), in a register
+    const int cls = spread_class(lane);
+    double dref = 0.0;
 
     double Dst[NS], Ist[NS], D[NS], I[NS];
 #pragma unroll
@@ -114,8 +117,7 @@ struct PairSolver {
 #pragma unroll
       for (int t = 0; t < 2 * ((NS + 1) / 2); ++t) v[t] = t < NS ? w2q * D[t < NS ? t : 0] * D[t < NS ? t : 0] : 0.0;
       half_own_sums<(NS + 1) / 2>(v, s);
-#pragma unroll
-      for (int t = 0; t < NS; ++t) pt.dref[t] = s[t];
+      dref = class_pick<NS>(s, cls);
     }
 
     int status = NMC_STATUS_OK;
@@ -261,11 +263,9 @@ struct PairSolver {
       const double Aeq = pt.An * epsq, Apq = pt.Ap * epsq, Apqh = Apq * hq;
 
       double G11 = 0.0;
-      // the reference norm of this lane's species class in this inner loop,
-      // in a register (constant within the loop: a converged loop sets the
-      // next loop's and ends)
-      const int cls = spread_class(lane);
-      const double dref0 = cls < NS ? pt.dref[cls < NS ? cls : 0] : 0.0;
+      // the reference norm of this inner loop (constant within the loop: a
+      // converged loop sets the next loop's and ends)
+      const double dref0 = dref;
       const bool ran = run;  // this half runs this outer iteration
       bool act = run;        // this half is still iterating the inner loop
       bool cvd = false;      // this half's inner loop converged
@@ -424,7 +424,7 @@ struct PairSolver {
           const double dref2 = dref0 > dn2 ? dref0 : dn2;
           const bool conv = !half_any(!(dm2[0] <= a.tol_inner2 * dref2));
           // ||D^[k,*]|| is the reference of the next inner loop
-          if (act && conv && cls < NS) pt.dref[cls < NS ? cls : 0] = dn2;
+          dref = (act && conv) ? dn2 : dref;
           if (act) {
 #pragma unroll
             for (int t = 0; t < NS; ++t) {
@@ -465,10 +465,7 @@ struct PairSolver {
 #pragma unroll
           for (int t = NS + 2; t < 2 * KR; ++t) v[t] = 0.0;
           half_own_sums<KR>(v, s);
-          if (run && !cvd) {
-#pragma unroll
-            for (int t = 0; t < NS; ++t) pt.dref[t] = s[t];
-          }
+          dref = (run && !cvd) ? class_pick<NS>(s, cls) : dref;
           yq0 = pt.ye_st - pt.K * s[NS];
           yq1 = pt.e_st - pt.K * s[NS + 1];
         } else {

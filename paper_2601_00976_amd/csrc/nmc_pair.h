@@ -59,6 +59,17 @@ __device__ __forceinline__ void half_own_sums(const double (&v)[2 * K], double (
 }
 
 
+// The value of species class c (spread_class) from per-species values s[t]
+// held in every lane; zero beyond NS.
+template <int NS, int N>
+__device__ __forceinline__ double class_pick(const double (&s)[N], int c) {
+  static_assert(N >= NS, "one value per species");
+  double r = 0.0;
+#pragma unroll
+  for (int t = 0; t < NS; ++t) r = c == t ? s[t] : r;
+  return r;
+}
+
 // Species class of a lane for the spread sums below: c = 2 r + m with r the
 // row of the lane within its half and m = 1 for lanes 8..15 of the row.
 __device__ __forceinline__ int spread_class(int lane) { return ((lane >> 4) & 1) * 2 + ((lane >> 3) & 1); }
