@@ -28,7 +28,7 @@ __device__ __forceinline__ int c2p_scaled(double N, const double (&G)[3], const 
   for (int k = 1; k <= max_it; ++k) {
     double vI, vK[3];
     const double I3[3] = {M[1], M[2], M[3]};
-    closure_terms(M[0], I3, v, vI, vK);
+    closure_terms_unit(M[0], I3, v, vI, vK);
     double g[4], F[4], Mn[4];
     g[0] = oml * M[0] + lam * (N - vI);
 #pragma unroll
