@@ -10,15 +10,17 @@ namespace nmc {
 // k_ij = ((1 - psi) delta_ij + (3 psi - 1) n_i n_j) / 2, n = I / |I|, psi the
 // polynomial Eddington factor of the flux factor h = |I| / D, taken as 0
 // without flux and limited to [0, 1] (1 when D <= 0 carries a flux).
-// The closure from |I| (Imag) and 1 / |I| (rI, 0 without flux).
-__device__ __forceinline__ void closure_terms_norm(double D, const double (&I)[3], const double (&v)[3], double Imag,
-                                                   double rI, double& vI, double (&vK)[3]) {
+// The closure from |I| (Imag); rinv() gives 1 / |I| (0 without flux).
+template <class RInv>
+__device__ __forceinline__ void closure_from_norm(double D, const double (&I)[3], const double (&v)[3], double Imag,
+                                                  RInv&& rinv, double& vI, double (&vK)[3]) {
   double h = 0.0;
   // Imag < D keeps D normal where its reciprocal is taken (a nonzero Imag is
   // at least ~1e-162: its components' squares underflow below that)
   if (Imag > 0.0) h = Imag < D ? Imag * rcp_nr(D) : 1.0;
   const double psi = 1.0 / 3.0 + (2.0 / 15.0) * (3.0 - h + 3.0 * h * h) * h * h;
   const double a = 0.5 * (1.0 - psi), b = 0.5 * (3.0 * psi - 1.0);
+  const double rI = rinv();
   const double n0 = I[0] * rI, n1 = I[1] * rI, n2 = I[2] * rI;
   const double bvn = b * (v[0] * n0 + v[1] * n1 + v[2] * n2);
   vI = v[0] * I[0] + v[1] * I[1] + v[2] * I[2];
@@ -30,7 +32,7 @@ __device__ __forceinline__ void closure_terms_norm(double D, const double (&I)[3
 __device__ __forceinline__ void closure_terms(double D, const double (&I)[3], const double (&v)[3], double& vI,
                                               double (&vK)[3]) {
   const double Imag = sqrt(I[0] * I[0] + I[1] * I[1] + I[2] * I[2]);
-  closure_terms_norm(D, I, v, Imag, Imag > 0.0 ? rcp_nr(Imag) : 0.0, vI, vK);
+  closure_from_norm(D, I, v, Imag, [&] { return Imag > 0.0 ? rcp_nr(Imag) : 0.0; }, vI, vK);
 }
 
 // The same for moments of order one (a flux whose squared norm is at least
@@ -56,7 +58,7 @@ __device__ __forceinline__ void closure_terms_unit(double D, const double (&I)[3
     Imag = sqrt(s);
     rI = Imag > 0.0 ? rcp_nr(Imag) : 0.0;
   }
-  closure_terms_norm(D, I, v, Imag, rI, vI, vK);
+  closure_from_norm(D, I, v, Imag, [&] { return rI; }, vI, vK);
 }
 
 // Linear-order collision terms of one species at one node (Eqs.
