@@ -118,10 +118,14 @@ __global__ __launch_bounds__(256) void c2p_kernel(int64_t P, int ns, int nq, con
                                                   int mem, double tol2, int max_it, double* __restrict__ D,
                                                   double* __restrict__ I, int32_t* __restrict__ iters) {
   const int64_t n = P * ns * nq;
+  // nq is a power of two (32 or 64) and ns is 1..3: the node, (point,
+  // species) and point indices by shifts, a mask and a division by the
+  // constant 3
+  const int lq = 31 - __builtin_clz(nq);
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t ps = i / nq;
-    const int q = (int)(i - ps * nq);
-    const int64_t p = ps / ns;
+    const int64_t ps = i >> lq;
+    const int q = (int)(i & (nq - 1));
+    const int64_t p = ns == 3 ? ps / 3 : ps >> (ns - 1);
     const double vv[3] = {v[3 * p], v[3 * p + 1], v[3 * p + 2]};
     const double Gq[3] = {G[(ps * 3 + 0) * nq + q], G[(ps * 3 + 1) * nq + q], G[(ps * 3 + 2) * nq + q]};
     double M[4];
@@ -212,6 +216,8 @@ int64_t grid_for(int64_t n, int num_cu) {
 
 hipError_t launch_c2p(int64_t P, int ns, int nq, const double* N, const double* G, const double* v, int mem,
                       double tol, int max_it, double* D, double* I, int32_t* iters, int num_cu, hipStream_t s) {
+  // the kernel's index arithmetic takes nq a power of two and ns in 1..3
+  if (nq <= 0 || (nq & (nq - 1)) != 0 || ns < 1 || ns > 3) return hipErrorInvalidValue;
   const int64_t n = P * ns * nq;
   hipLaunchKernelGGL(c2p_kernel, dim3((unsigned)grid_for(n, num_cu)), dim3(256), 0, s, P, ns, nq, N, G, v, mem,
                      tol * tol, max_it, D, I, iters);
